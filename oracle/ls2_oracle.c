@@ -1,0 +1,643 @@
+/*
+ * ls2_oracle.c -- plain, slow, obviously-correct FP64 CPU reference for the
+ * sparse-coefficient Gaussian splatting path of LangSplatV2 (arXiv 2507.07136).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline do.  It shares no code, header, table or constant generator with
+ * the HIP library.
+ *
+ * What is computed, and where the paper defines it:
+ *   - Gaussian kernel and covariance Sigma = R S S^T R^T: Section 3.1, Eqs. 1-2.
+ *   - Projection to the image plane: Section 3.1 cites EWA splatting
+ *     (Zwicker et al. 2001) and 3D Gaussian Splatting without restating the
+ *     formula; this file uses the local-affine Jacobian of the perspective map
+ *     at the mean, a 0.3 px^2 low-pass dilation and a 3-sigma radius (the
+ *     readings are listed in the design notes).
+ *   - Front-to-back alpha compositing over the depth-ordered Gaussians of a
+ *     tile: Section 3.1, Eq. 3, with alpha_i = o_i G2D_i(v).
+ *   - Sparse coefficient field and the blend of only the K non-zero
+ *     coefficients: Section 3.3 Eq. 5, Section 3.4 and Appendix A (Algorithm 1):
+ *     W[j] += w_ij * alpha_i * prod_{m<i}(1 - alpha_m).
+ *   - Dense D-dim rendering of f_i = w_i S (Eq. 6) for the linearity identity
+ *     of Eq. 7: sum_i e_i w_i S = (sum_i e_i w_i) S.
+ *   - Decode as one matrix product with the global codebook: Section 3.3, Eq. 7.
+ *   - Relevancy: Section 3.2 says it follows LERF; LERF's score is the minimum
+ *     over canonical negatives of the pairwise softmax between the query and
+ *     the negative cosine similarities.
+ *
+ * Parity status per function is stated in the header comment of each.
+ * All arithmetic is double precision except where a floating-point value
+ * decides an integer (tile rectangle, depth order): there the float32 value is
+ * used, as the GPU kernel does.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_TILE 16
+
+/* thresholds of the compositing rule, as float32 constants promoted to double */
+static const double ALPHA_MAX = (double)0.99f;
+static const double ALPHA_MIN = (double)(1.0f / 255.0f);
+static const double T_MIN = (double)1e-4f;
+static const double DILATION = (double)0.3f;
+
+/* camera array: [W, H, fx, fy, cx, cy, R00..R22, t0..t2, znear] */
+typedef struct {
+    int W, H, tx, ty;
+    double fx, fy, cx, cy;
+    double R[9], t[3];
+    double znear;
+} cam_t;
+
+static cam_t cam_from(const double* c) {
+    cam_t k;
+    k.W = (int)c[0];
+    k.H = (int)c[1];
+    k.fx = c[2]; k.fy = c[3]; k.cx = c[4]; k.cy = c[5];
+    for (int i = 0; i < 9; ++i) k.R[i] = c[6 + i];
+    for (int i = 0; i < 3; ++i) k.t[i] = c[15 + i];
+    k.znear = c[18];
+    k.tx = (k.W + ORC_TILE - 1) / ORC_TILE;
+    k.ty = (k.H + ORC_TILE - 1) / ORC_TILE;
+    return k;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Eq. 2: rotation matrix from a quaternion (w, x, y, z), normalised.  */
+/* ------------------------------------------------------------------ */
+static void quat_to_rot(const double q_in[4], double R[9]) {
+    double n = sqrt(q_in[0] * q_in[0] + q_in[1] * q_in[1] + q_in[2] * q_in[2] + q_in[3] * q_in[3]);
+    double w = q_in[0] / n, x = q_in[1] / n, y = q_in[2] / n, z = q_in[3] / n;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static void matmul3(const double A[9], const double B[9], double C[9]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+            C[3 * i + j] = s;
+        }
+}
+
+static void transpose3(const double A[9], double B[9]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B[3 * j + i] = A[3 * i + j];
+}
+
+/* Tile rectangle of a projected Gaussian, evaluated in float32 exactly as the
+ * kernel does: tiles [floor((u - r)/16), floor((u + r)/16)] clipped to the
+ * grid.  Returns 0 if empty. */
+static int rect_f32(float u, float v, int r, int tx, int ty, int* x0, int* y0, int* x1, int* y1) {
+    float rf = (float)r;
+    float lox = floorf((u - rf) * 0.0625f), hix = floorf((u + rf) * 0.0625f);
+    float loy = floorf((v - rf) * 0.0625f), hiy = floorf((v + rf) * 0.0625f);
+    if (lox < 0.0f) lox = 0.0f;
+    if (loy < 0.0f) loy = 0.0f;
+    if (hix > (float)(tx - 1)) hix = (float)(tx - 1);
+    if (hiy > (float)(ty - 1)) hiy = (float)(ty - 1);
+    if (!(lox <= hix) || !(loy <= hiy)) return 0;
+    *x0 = (int)lox; *x1 = (int)hix; *y0 = (int)loy; *y1 = (int)hiy;
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Projection (Eqs. 1-2 and the EWA reading).                          */
+/* Outputs per Gaussian i:                                             */
+/*   mean2d[2i..]  pixel-space mean (u, v)                             */
+/*   cov2d[3i..]   dilated screen covariance (a, b, c)                 */
+/*   conic[3i..]   its inverse (A, B, C) = (c, -b, a) / det            */
+/*   depth[i]      camera-space z                                      */
+/*   extent[i]     3 * sqrt(lambda_max) (radius before ceil)           */
+/*   radius[i]     ceil(extent), 0 if culled                           */
+/*   rect[4i..]    x0, y0, x1, y1 tile rectangle (inclusive)           */
+/*   touched[i]    number of tiles in the rectangle                    */
+/* Culled (radius 0, zeros elsewhere): z <= znear, non-finite values,  */
+/* det <= 0, or an empty tile rectangle.                               */
+/* Parity pinned by closed forms (on-axis / axis-aligned Gaussians),   */
+/* the image-edge pixel of the 60-degree field of view and a numerical */
+/* Jacobian of the perspective map.                                    */
+/* ------------------------------------------------------------------ */
+void orc_project(const double* cam_arr, int n, const float* means, const float* scales,
+                 const float* quats, double* mean2d, double* cov2d, double* conic,
+                 double* depth, double* extent, int32_t* radius, int32_t* rect, int32_t* touched) {
+    cam_t cam = cam_from(cam_arr);
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        mean2d[2 * i] = mean2d[2 * i + 1] = 0;
+        cov2d[3 * i] = cov2d[3 * i + 1] = cov2d[3 * i + 2] = 0;
+        conic[3 * i] = conic[3 * i + 1] = conic[3 * i + 2] = 0;
+        depth[i] = 0; extent[i] = 0; radius[i] = 0; touched[i] = 0;
+        rect[4 * i] = rect[4 * i + 1] = rect[4 * i + 2] = rect[4 * i + 3] = 0;
+
+        double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+        double p[3];
+        for (int r = 0; r < 3; ++r)
+            p[r] = cam.R[3 * r] * mu[0] + cam.R[3 * r + 1] * mu[1] + cam.R[3 * r + 2] * mu[2] + cam.t[r];
+        double x = p[0], y = p[1], z = p[2];
+        if (!(z > cam.znear) || !isfinite(x) || !isfinite(y)) continue;
+
+        /* Eq. 2: Sigma = R S S^T R^T */
+        double q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+        double Rq[9];
+        quat_to_rot(q, Rq);
+        double M[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * (double)scales[3 * i + c];
+        double Mt[9], Sig[9];
+        transpose3(M, Mt);
+        matmul3(M, Mt, Sig);
+
+        /* world -> camera covariance */
+        double Rt[9], tmp[9], Sc[9];
+        transpose3(cam.R, Rt);
+        matmul3(cam.R, Sig, tmp);
+        matmul3(tmp, Rt, Sc);
+
+        /* EWA: local affine approximation of the perspective map at the mean */
+        double J[6] = {cam.fx / z, 0.0, -cam.fx * x / (z * z),
+                       0.0, cam.fy / z, -cam.fy * y / (z * z)};
+        double JS[6];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0;
+                for (int k = 0; k < 3; ++k) s += J[3 * r + k] * Sc[3 * k + c];
+                JS[3 * r + c] = s;
+            }
+        double cv[4];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                double s = 0;
+                for (int k = 0; k < 3; ++k) s += JS[3 * r + k] * J[3 * c + k];
+                cv[2 * r + c] = s;
+            }
+        double a = cv[0] + DILATION, b = cv[1], c = cv[3] + DILATION;
+        double det = a * c - b * b;
+        if (!(det > 0) || !isfinite(det)) continue;
+
+        double mid = 0.5 * (a + c);
+        double disc = mid * mid - det;
+        double lam = mid + sqrt(disc > 0 ? disc : 0);
+        double ext = 3.0 * sqrt(lam);
+        if (!isfinite(ext) || ext > 1e7) continue;
+        int r = (int)ceil(ext);
+
+        double u = cam.fx * x / z + cam.cx;
+        double v = cam.fy * y / z + cam.cy;
+        int x0, y0, x1, y1;
+        if (!rect_f32((float)u, (float)v, r, cam.tx, cam.ty, &x0, &y0, &x1, &y1)) continue;
+
+        mean2d[2 * i] = u; mean2d[2 * i + 1] = v;
+        cov2d[3 * i] = a; cov2d[3 * i + 1] = b; cov2d[3 * i + 2] = c;
+        conic[3 * i] = c / det; conic[3 * i + 1] = -b / det; conic[3 * i + 2] = a / det;
+        depth[i] = z; extent[i] = ext; radius[i] = r;
+        rect[4 * i] = x0; rect[4 * i + 1] = y0; rect[4 * i + 2] = x1; rect[4 * i + 3] = y1;
+        touched[i] = (x1 - x0 + 1) * (y1 - y0 + 1);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Tile binning and depth order (the "ordered Gaussian points within a  */
+/* tile" of Eq. 3).  One (tile, Gaussian) pair per tile of the         */
+/* rectangle; pairs ordered by tile, then float32 depth, then id.       */
+/* Outputs keys = tile << 32 | float32 bits of depth, ids, and per-tile */
+/* [start, end) ranges.  Returns 0, or -2 when cap < P (num_pairs = P). */
+/* Parity pinned against numpy's lexsort of the same triples and a    */
+/* brute-force per-pixel renderer.                                     */
+/* ------------------------------------------------------------------ */
+typedef struct { uint32_t tile, dbits, id; } pair_t;
+
+static int pair_cmp(const void* a, const void* b) {
+    const pair_t* p = (const pair_t*)a;
+    const pair_t* q = (const pair_t*)b;
+    if (p->tile != q->tile) return p->tile < q->tile ? -1 : 1;
+    if (p->dbits != q->dbits) return p->dbits < q->dbits ? -1 : 1;
+    if (p->id != q->id) return p->id < q->id ? -1 : 1;
+    return 0;
+}
+
+static uint32_t f32_bits(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+int orc_tile_lists(const double* cam_arr, int n, const float* mean2d, const int32_t* radius,
+                   const float* depth, int64_t cap, uint64_t* keys, uint32_t* ids,
+                   uint32_t* ranges, int64_t* num_pairs) {
+    cam_t cam = cam_from(cam_arr);
+    int64_t P = 0;
+    for (int i = 0; i < n; ++i) {
+        int x0, y0, x1, y1;
+        if (radius[i] <= 0) continue;
+        if (!rect_f32(mean2d[2 * i], mean2d[2 * i + 1], radius[i], cam.tx, cam.ty, &x0, &y0, &x1, &y1))
+            continue;
+        P += (int64_t)(x1 - x0 + 1) * (y1 - y0 + 1);
+    }
+    *num_pairs = P;
+    int ntiles = cam.tx * cam.ty;
+    if (P > cap) return -2;
+    pair_t* pairs = (pair_t*)malloc(sizeof(pair_t) * (size_t)(P > 0 ? P : 1));
+    int64_t k = 0;
+    for (int i = 0; i < n; ++i) {
+        int x0, y0, x1, y1;
+        if (radius[i] <= 0) continue;
+        if (!rect_f32(mean2d[2 * i], mean2d[2 * i + 1], radius[i], cam.tx, cam.ty, &x0, &y0, &x1, &y1))
+            continue;
+        for (int ty = y0; ty <= y1; ++ty)
+            for (int tx = x0; tx <= x1; ++tx) {
+                pairs[k].tile = (uint32_t)(ty * cam.tx + tx);
+                pairs[k].dbits = f32_bits(depth[i]);
+                pairs[k].id = (uint32_t)i;
+                ++k;
+            }
+    }
+    qsort(pairs, (size_t)P, sizeof(pair_t), pair_cmp);
+    for (int t = 0; t < ntiles; ++t) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
+    for (int64_t j = 0; j < P; ++j) {
+        if (keys) keys[j] = ((uint64_t)pairs[j].tile << 32) | pairs[j].dbits;
+        ids[j] = pairs[j].id;
+    }
+    /* ranges: first and one-past-last position of each tile */
+    for (int64_t j = 0; j < P; ++j) {
+        uint32_t t = pairs[j].tile;
+        if (j == 0 || pairs[j - 1].tile != t) ranges[2 * t] = (uint32_t)j;
+        if (j == P - 1 || pairs[j + 1].tile != t) ranges[2 * t + 1] = (uint32_t)(j + 1);
+    }
+    free(pairs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Per-pixel front-to-back walk (Eq. 3).  For the ordered list of the  */
+/* pixel's tile, compute the blending weights e_i = alpha_i prod_{j<i}  */
+/* (1 - alpha_j) of Eq. 7 for the Gaussians that contribute.           */
+/*   alpha = min(0.99, o * exp(-0.5 d^T conic d)); skip alpha < 1/255;  */
+/*   stop (without blending) once T (1 - alpha) < 1e-4.                 */
+/* Writes contributing list positions and their e_i; returns count.    */
+/* *T_out = final transmittance, *last_out = 1 + position of the last   */
+/* contributing entry relative to the tile start (0 if none),          */
+/* *margin = smallest relative distance of any decision to its         */
+/* threshold (clamp, skip, stop).                                      */
+/* ------------------------------------------------------------------ */
+static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, const uint32_t* ids,
+                      const double* mean2d, const double* conic, const double* opacity,
+                      int32_t* pos_out, double* e_out, double* T_before_out, double* alpha_out,
+                      double* T_out, int32_t* last_out, double* margin) {
+    double T = 1.0;
+    int cnt = 0;
+    int32_t last = 0;
+    double mg = INFINITY;
+    for (uint32_t pos = start; pos < end; ++pos) {
+        uint32_t i = ids[pos];
+        double dx = mean2d[2 * i] - pxc;
+        double dy = mean2d[2 * i + 1] - pyc;
+        double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
+        double power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
+        if (power > 0) continue;
+        double g = opacity[i] * exp(power);
+        double m1 = fabs(g - ALPHA_MAX) / ALPHA_MAX;
+        if (m1 < mg) mg = m1;
+        double alpha = g < ALPHA_MAX ? g : ALPHA_MAX;
+        double m2 = fabs(alpha - ALPHA_MIN) / ALPHA_MIN;
+        if (m2 < mg) mg = m2;
+        if (alpha < ALPHA_MIN) continue;
+        double testT = T * (1.0 - alpha);
+        double m3 = fabs(testT - T_MIN) / T_MIN;
+        if (m3 < mg) mg = m3;
+        if (testT < T_MIN) break;
+        if (pos_out) pos_out[cnt] = (int32_t)(pos - start);
+        if (e_out) e_out[cnt] = alpha * T;
+        if (T_before_out) T_before_out[cnt] = T;
+        if (alpha_out) alpha_out[cnt] = alpha;
+        ++cnt;
+        T = testT;
+        last = (int32_t)(pos - start + 1);
+    }
+    *T_out = T;
+    *last_out = last;
+    *margin = mg;
+    return cnt;
+}
+
+static uint32_t max_range(const uint32_t* ranges, int ntiles) {
+    uint32_t m = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+        if (len > m) m = len;
+    }
+    return m;
+}
+
+/* ------------------------------------------------------------------ */
+/* Sparse coefficient splatting (Section 3.4, Algorithm 1): for every   */
+/* level l and pixel v, W_l(v)[j] = sum_i e_i(v) w_{i,l,j}, blending    */
+/* only the K stored (index, coefficient) pairs of each Gaussian.      */
+/* coef: [levels, H, W, L]; final_T, margin: [H, W]; last: [H, W].      */
+/* Parity pinned by closed forms (one and two Gaussians, the T stop    */
+/* rule), invariants (T in [1e-4, 1] non-increasing, sum W + T = 1),    */
+/* the dense-L and dense-D (Eq. 6/7) renderers and a brute-force       */
+/* per-pixel binning.                                                  */
+/* ------------------------------------------------------------------ */
+void orc_composite(const double* cam_arr, int levels, int K, int L, const uint32_t* ranges,
+                   const uint32_t* ids, const double* mean2d, const double* conic,
+                   const double* opacity, const int32_t* topk_idx, const double* topk_w,
+                   double* coef, double* final_T, int32_t* last, double* margin) {
+    cam_t cam = cam_from(cam_arr);
+    int ntiles = cam.tx * cam.ty;
+    size_t HW = (size_t)cam.W * cam.H;
+    memset(coef, 0, sizeof(double) * (size_t)levels * HW * L);
+    uint32_t maxlen = max_range(ranges, ntiles);
+    #pragma omp parallel
+    {
+        int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (maxlen + 1));
+        double* e = (double*)malloc(sizeof(double) * (maxlen + 1));
+        #pragma omp for schedule(dynamic, 1)
+        for (int t = 0; t < ntiles; ++t) {
+            int tx = t % cam.tx, ty = t / cam.tx;
+            for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < cam.H; ++py)
+                for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < cam.W; ++px) {
+                    size_t pix = (size_t)py * cam.W + px;
+                    double T;
+                    int32_t lst;
+                    double mg;
+                    int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids,
+                                         mean2d, conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg);
+                    for (int c = 0; c < cnt; ++c) {
+                        uint32_t i = ids[ranges[2 * t] + pos[c]];
+                        for (int lv = 0; lv < levels; ++lv) {
+                            double* W = coef + ((size_t)lv * HW + pix) * L;
+                            for (int k = 0; k < K; ++k) {
+                                size_t o = ((size_t)i * levels + lv) * K + k;
+                                W[topk_idx[o]] += topk_w[o] * e[c];
+                            }
+                        }
+                    }
+                    final_T[pix] = T;
+                    last[pix] = lst;
+                    margin[pix] = mg;
+                }
+        }
+        free(pos);
+        free(e);
+    }
+}
+
+/* Dense renderer (Eqs. 4 and 6): out(v) = sum_i e_i(v) feat_i for a dense  */
+/* per-Gaussian vector of C channels.  With feat_i = w_i S it is the   */
+/* D-dimensional rendering of Eq. 6; with feat_i = the dense L-vector w_i */
+/* it is the unsparsified coefficient rendering.  out: [H, W, C].       */
+void orc_composite_dense(const double* cam_arr, int C, const uint32_t* ranges, const uint32_t* ids,
+                         const double* mean2d, const double* conic, const double* opacity,
+                         const double* feat, double* out) {
+    cam_t cam = cam_from(cam_arr);
+    int ntiles = cam.tx * cam.ty;
+    memset(out, 0, sizeof(double) * (size_t)cam.W * cam.H * C);
+    uint32_t maxlen = max_range(ranges, ntiles);
+    #pragma omp parallel
+    {
+        int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (maxlen + 1));
+        double* e = (double*)malloc(sizeof(double) * (maxlen + 1));
+        #pragma omp for schedule(dynamic, 1)
+        for (int t = 0; t < ntiles; ++t) {
+            int tx = t % cam.tx, ty = t / cam.tx;
+            for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < cam.H; ++py)
+                for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < cam.W; ++px) {
+                    double T, mg;
+                    int32_t lst;
+                    int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids,
+                                         mean2d, conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg);
+                    double* o = out + ((size_t)py * cam.W + px) * C;
+                    for (int c = 0; c < cnt; ++c) {
+                        const double* f = feat + (size_t)ids[ranges[2 * t] + pos[c]] * C;
+                        for (int ch = 0; ch < C; ++ch) o[ch] += e[c] * f[ch];
+                    }
+                }
+        }
+        free(pos);
+        free(e);
+    }
+}
+
+/* Composite only the listed pixels (flat indices py * W + px), for     */
+/* sampled parity checks at full size.  coef: [npix, levels, L].        */
+void orc_composite_pixels(const double* cam_arr, int levels, int K, int L, const uint32_t* ranges,
+                          const uint32_t* ids, const double* mean2d, const double* conic,
+                          const double* opacity, const int32_t* topk_idx, const double* topk_w,
+                          int64_t npix, const int64_t* pix, double* coef, double* final_T,
+                          int32_t* last, double* margin) {
+    cam_t cam = cam_from(cam_arr);
+    uint32_t maxlen = max_range(ranges, cam.tx * cam.ty);
+    memset(coef, 0, sizeof(double) * (size_t)npix * levels * L);
+    #pragma omp parallel
+    {
+        int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (maxlen + 1));
+        double* e = (double*)malloc(sizeof(double) * (maxlen + 1));
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < npix; ++q) {
+            int px = (int)(pix[q] % cam.W), py = (int)(pix[q] / cam.W);
+            int t = (py / ORC_TILE) * cam.tx + px / ORC_TILE;
+            double T, mg;
+            int32_t lst;
+            int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids, mean2d,
+                                 conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg);
+            for (int c = 0; c < cnt; ++c) {
+                uint32_t i = ids[ranges[2 * t] + pos[c]];
+                for (int lv = 0; lv < levels; ++lv) {
+                    double* W = coef + ((size_t)q * levels + lv) * L;
+                    for (int k = 0; k < K; ++k) {
+                        size_t o = ((size_t)i * levels + lv) * K + k;
+                        W[topk_idx[o]] += topk_w[o] * e[c];
+                    }
+                }
+            }
+            final_T[q] = T;
+            last[q] = lst;
+            margin[q] = mg;
+        }
+        free(pos);
+        free(e);
+    }
+}
+
+/* Brute-force renderer: for every pixel, gather all Gaussians whose tile */
+/* rectangle (float32 rule) contains the pixel's tile, order them by     */
+/* (float32 depth, id) and composite.  No tile lists involved; used to   */
+/* pin the binning.  coef: [levels, H, W, L].                           */
+typedef struct { uint32_t dbits, id; } dkey_t;
+static int dkey_cmp(const void* a, const void* b) {
+    const dkey_t* p = (const dkey_t*)a;
+    const dkey_t* q = (const dkey_t*)b;
+    if (p->dbits != q->dbits) return p->dbits < q->dbits ? -1 : 1;
+    return p->id < q->id ? -1 : (p->id > q->id ? 1 : 0);
+}
+
+void orc_composite_bruteforce(const double* cam_arr, int n, int levels, int K, int L,
+                              const float* mean2d_f32, const int32_t* radius, const float* depth_f32,
+                              const double* mean2d, const double* conic, const double* opacity,
+                              const int32_t* topk_idx, const double* topk_w, double* coef,
+                              double* final_T) {
+    cam_t cam = cam_from(cam_arr);
+    size_t HW = (size_t)cam.W * cam.H;
+    memset(coef, 0, sizeof(double) * (size_t)levels * HW * L);
+    #pragma omp parallel
+    {
+        dkey_t* list = (dkey_t*)malloc(sizeof(dkey_t) * (size_t)(n > 0 ? n : 1));
+        #pragma omp for schedule(dynamic, 1)
+        for (int py = 0; py < cam.H; ++py)
+            for (int px = 0; px < cam.W; ++px) {
+                int tx = px / ORC_TILE, ty = py / ORC_TILE;
+                int cnt = 0;
+                for (int i = 0; i < n; ++i) {
+                    int x0, y0, x1, y1;
+                    if (radius[i] <= 0) continue;
+                    if (!rect_f32(mean2d_f32[2 * i], mean2d_f32[2 * i + 1], radius[i], cam.tx, cam.ty,
+                                  &x0, &y0, &x1, &y1))
+                        continue;
+                    if (tx < x0 || tx > x1 || ty < y0 || ty > y1) continue;
+                    list[cnt].dbits = f32_bits(depth_f32[i]);
+                    list[cnt].id = (uint32_t)i;
+                    ++cnt;
+                }
+                qsort(list, (size_t)cnt, sizeof(dkey_t), dkey_cmp);
+                double T = 1.0;
+                size_t pix = (size_t)py * cam.W + px;
+                for (int c = 0; c < cnt; ++c) {
+                    uint32_t i = list[c].id;
+                    double dx = mean2d[2 * i] - (px + 0.5), dy = mean2d[2 * i + 1] - (py + 0.5);
+                    double power = -0.5 * (conic[3 * i] * dx * dx + conic[3 * i + 2] * dy * dy)
+                                   - conic[3 * i + 1] * dx * dy;
+                    if (power > 0) continue;
+                    double alpha = fmin(ALPHA_MAX, opacity[i] * exp(power));
+                    if (alpha < ALPHA_MIN) continue;
+                    if (T * (1.0 - alpha) < T_MIN) break;
+                    for (int lv = 0; lv < levels; ++lv)
+                        for (int k = 0; k < K; ++k) {
+                            size_t o = ((size_t)i * levels + lv) * K + k;
+                            coef[((size_t)lv * HW + pix) * L + topk_idx[o]] += topk_w[o] * alpha * T;
+                        }
+                    T *= 1.0 - alpha;
+                }
+                final_T[pix] = T;
+            }
+        free(list);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Decode (Eq. 7): F = W S, one plain triple loop per pixel row.        */
+/* coef [M, L], dict [L, D], out [M, D].  Pinned against a library      */
+/* float64 matrix product.                                             */
+/* ------------------------------------------------------------------ */
+void orc_decode(int64_t M, int L, int D, const double* coef, const double* dict, double* out) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < M; ++m) {
+        double* o = out + m * D;
+        for (int d = 0; d < D; ++d) o[d] = 0.0;
+        for (int l = 0; l < L; ++l) {
+            double c = coef[m * L + l];
+            const double* s = dict + (size_t)l * D;
+            for (int d = 0; d < D; ++d) o[d] += c * s[d];
+        }
+    }
+}
+
+/* float32 -> bfloat16 -> float32, round to nearest, ties to even (IEEE).  */
+static float round_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) {          /* inf / nan */
+        if (u & 0x007fffffu) u |= 0x00400000u;        /* keep nan quiet */
+        u &= 0xffff0000u;
+    } else {
+        uint32_t lsb = (u >> 16) & 1u;
+        u += 0x7fffu + lsb;
+        u &= 0xffff0000u;
+    }
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+void orc_round_bf16(int64_t n, const float* in, float* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = round_bf16(in[i]);
+}
+
+/* Decode with both operands rounded to bfloat16 first (the precision form:
+ * bf16 inputs, exact products, wide accumulation).  If round_out, the
+ * result is rounded to float32 and then to bfloat16.  Pinned by the
+ * rounding routine against a library bf16 conversion and by reduction to
+ * orc_decode when inputs are already bf16-representable. */
+void orc_decode_bf16(int64_t M, int L, int D, const float* coef, const float* dict, int round_out,
+                     double* out) {
+    float* sb = (float*)malloc(sizeof(float) * (size_t)L * D);
+    for (size_t j = 0; j < (size_t)L * D; ++j) sb[j] = round_bf16(dict[j]);
+    #pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < M; ++m) {
+        double* o = out + m * D;
+        for (int d = 0; d < D; ++d) o[d] = 0.0;
+        for (int l = 0; l < L; ++l) {
+            double c = (double)round_bf16(coef[m * L + l]);
+            const float* s = sb + (size_t)l * D;
+            for (int d = 0; d < D; ++d) o[d] += c * (double)s[d];
+        }
+        if (round_out)
+            for (int d = 0; d < D; ++d) o[d] = (double)round_bf16((float)o[d]);
+    }
+    free(sb);
+}
+
+/* ------------------------------------------------------------------ */
+/* Relevancy (Section 3.2, "following LERF"): with cosine similarities  */
+/* s_q = cos(F, q) and s_j = cos(F, c_j) against the canonical          */
+/* negatives, r = min_j exp(tau s_q) / (exp(tau s_q) + exp(tau s_j)).  */
+/* A zero feature (norm below 1e-12) has cosine 0 with everything.     */
+/* Pinned by the closed form sigmoid(tau (s_q - max_j s_j)), F = q and  */
+/* F = 0 special cases.                                                 */
+/* ------------------------------------------------------------------ */
+static double cosine(const double* f, const float* e, int D) {
+    double fe = 0, ff = 0, ee = 0;
+    for (int d = 0; d < D; ++d) {
+        fe += f[d] * (double)e[d];
+        ff += f[d] * f[d];
+        ee += (double)e[d] * (double)e[d];
+    }
+    double nf = sqrt(ff), ne = sqrt(ee);
+    if (nf < 1e-12) nf = 1e-12;
+    if (ne < 1e-12) ne = 1e-12;
+    return fe / (nf * ne);
+}
+
+void orc_query(int64_t M, int D, const double* feat, const float* pos, int n_neg, const float* neg,
+               double tau, double* out) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < M; ++m) {
+        const double* f = feat + m * D;
+        double sq = cosine(f, pos, D);
+        double r = INFINITY;
+        for (int j = 0; j < n_neg; ++j) {
+            double sj = cosine(f, neg + (size_t)j * D, D);
+            double eq = exp(tau * sq), ej = exp(tau * sj);
+            double pj = eq / (eq + ej);
+            if (pj < r) r = pj;
+        }
+        out[m] = r;
+    }
+}

@@ -1,0 +1,237 @@
+"""ctypes shim over the FP64 CPU oracle (``ls2_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.  It marshals
+numpy arrays; all arithmetic happens in the C file (plus the numpy loss and
+finite-difference helpers that the tests define themselves).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ls2_oracle.c")
+_LIB = os.path.join(_HERE, "libls2_oracle.so")
+
+_CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA
+    contraction, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+_P = ctypes.c_void_p
+
+
+def _declare(L):
+    i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.orc_num_threads.restype = ctypes.c_int
+    L.orc_project.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_project.restype = None
+    L.orc_tile_lists.argtypes = [_P, ctypes.c_int, _P, _P, _P, i64, _P, _P, _P, _P]
+    L.orc_tile_lists.restype = ctypes.c_int
+    L.orc_composite.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P,
+                                _P, _P, _P, _P]
+    L.orc_composite.restype = None
+    L.orc_composite_dense.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_composite_dense.restype = None
+    L.orc_composite_pixels.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P,
+                                       _P, _P, i64, _P, _P, _P, _P, _P]
+    L.orc_composite_pixels.restype = None
+    L.orc_composite_bruteforce.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_composite_bruteforce.restype = None
+    L.orc_decode.argtypes = [i64, ctypes.c_int, ctypes.c_int, _P, _P, _P]
+    L.orc_decode.restype = None
+    L.orc_decode_bf16.argtypes = [i64, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, _P]
+    L.orc_decode_bf16.restype = None
+    L.orc_round_bf16.argtypes = [i64, _P, _P]
+    L.orc_round_bf16.restype = None
+    L.orc_query.argtypes = [i64, ctypes.c_int, _P, _P, ctypes.c_int, _P, f64, _P]
+    L.orc_query.restype = None
+    for name, args in _BACKWARD_DECLS.items():
+        if hasattr(L, name):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = None
+    del i32
+
+
+_BACKWARD_DECLS: dict = {}
+
+
+def _c(a, dtype):
+    """Contiguous array of dtype (copy only if needed)."""
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def cam_array(cam) -> np.ndarray:
+    return _c(cam.as_array() if hasattr(cam, "as_array") else cam, np.float64)
+
+
+# --------------------------------------------------------------------------
+def project(cam, means, scales, quats):
+    """Projection of every Gaussian (Eqs. 1-2, EWA reading).  Returns a dict
+    of float64/int32 arrays: mean2d (N,2), cov2d (N,3), conic (N,3), depth,
+    extent, radius, rect (N,4), touched."""
+    means, scales, quats = _c(means, np.float32), _c(scales, np.float32), _c(quats, np.float32)
+    n = means.shape[0]
+    out = dict(mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
+               depth=np.zeros(n), extent=np.zeros(n), radius=np.zeros(n, np.int32),
+               rect=np.zeros((n, 4), np.int32), touched=np.zeros(n, np.int32))
+    ca = cam_array(cam)
+    lib().orc_project(_p(ca), n, _p(means), _p(scales), _p(quats), _p(out["mean2d"]), _p(out["cov2d"]),
+                      _p(out["conic"]), _p(out["depth"]), _p(out["extent"]), _p(out["radius"]),
+                      _p(out["rect"]), _p(out["touched"]))
+    return out
+
+
+def tile_lists(cam, mean2d_f32, radius, depth_f32, cap=None):
+    """Per-tile depth-ordered lists from float32 mean2d/depth and int radius.
+    Returns (keys u64 [P], ids u32 [P], ranges u32 [tiles, 2])."""
+    n = radius.shape[0]
+    m2 = _c(mean2d_f32, np.float32)
+    rd = _c(radius, np.int32)
+    dp = _c(depth_f32, np.float32)
+    ca = cam_array(cam)
+    ntiles = cam.tiles_x * cam.tiles_y
+    P = ctypes.c_int64(0)
+    ranges = np.zeros((ntiles, 2), np.uint32)
+    if cap is None:
+        st = lib().orc_tile_lists(_p(ca), n, _p(m2), _p(rd), _p(dp), 0, None, None, _p(ranges),
+                                  ctypes.byref(P))
+        cap = P.value
+    keys = np.zeros(max(cap, 1), np.uint64)
+    ids = np.zeros(max(cap, 1), np.uint32)
+    st = lib().orc_tile_lists(_p(ca), n, _p(m2), _p(rd), _p(dp), cap, _p(keys), _p(ids), _p(ranges),
+                              ctypes.byref(P))
+    if st != 0:
+        raise RuntimeError("tile_lists capacity %d < %d" % (cap, P.value))
+    return keys[:P.value], ids[:P.value], ranges
+
+
+def composite(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L):
+    """Sparse coefficient splatting (Algorithm 1).  topk_idx/topk_w: (N, levels, K).
+    Returns coef (levels, H, W, L), final_T (H, W), last (H, W), margin (H, W)."""
+    n, levels, K = topk_idx.shape
+    H, W = cam.height, cam.width
+    coef = np.zeros((levels, H, W, L))
+    fT = np.zeros((H, W))
+    last = np.zeros((H, W), np.int32)
+    margin = np.zeros((H, W))
+    ids = _c(ids, np.uint32)
+    args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
+            _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64)]
+    lib().orc_composite(_p(cam_array(cam)), levels, K, L, *[_p(a) for a in args], _p(coef), _p(fT),
+                        _p(last), _p(margin))
+    return coef, fT, last, margin
+
+
+def composite_pixels(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L, pix):
+    """Composite only the flat pixel indices ``pix``.  Returns coef
+    (npix, levels, L), final_T, last, margin (npix,)."""
+    n, levels, K = topk_idx.shape
+    pix = _c(pix, np.int64)
+    npix = pix.shape[0]
+    coef = np.zeros((npix, levels, L))
+    fT = np.zeros(npix)
+    last = np.zeros(npix, np.int32)
+    margin = np.zeros(npix)
+    ids = _c(ids, np.uint32)
+    args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
+            _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64)]
+    lib().orc_composite_pixels(_p(cam_array(cam)), levels, K, L, *[_p(a) for a in args], npix, _p(pix),
+                               _p(coef), _p(fT), _p(last), _p(margin))
+    return coef, fT, last, margin
+
+
+def composite_dense(cam, ranges, ids, mean2d, conic, opacity, feat):
+    """Dense renderer (Eqs. 4/6): feat (N, C) -> (H, W, C)."""
+    feat = _c(feat, np.float64)
+    C = feat.shape[1]
+    out = np.zeros((cam.height, cam.width, C))
+    ids = _c(ids, np.uint32)
+    args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
+            _c(conic, np.float64), _c(opacity, np.float64), feat]
+    lib().orc_composite_dense(_p(cam_array(cam)), C, *[_p(a) for a in args], _p(out))
+    return out
+
+
+def composite_bruteforce(cam, mean2d_f32, radius, depth_f32, mean2d, conic, opacity, topk_idx, topk_w, L):
+    """Brute-force per-pixel renderer (no tile lists).  Returns (coef, final_T)."""
+    n, levels, K = topk_idx.shape
+    coef = np.zeros((levels, cam.height, cam.width, L))
+    fT = np.zeros((cam.height, cam.width))
+    args = [_c(mean2d_f32, np.float32), _c(radius, np.int32), _c(depth_f32, np.float32),
+            _c(mean2d, np.float64), _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32),
+            _c(topk_w, np.float64)]
+    lib().orc_composite_bruteforce(_p(cam_array(cam)), n, levels, K, L, *[_p(a) for a in args], _p(coef),
+                                   _p(fT))
+    return coef, fT
+
+
+def decode(coef, dictionary):
+    """F = W S in float64.  coef (..., L), dictionary (L, D) -> (..., D)."""
+    L, D = dictionary.shape
+    c = _c(coef, np.float64).reshape(-1, L)
+    s = _c(dictionary, np.float64)
+    out = np.zeros((c.shape[0], D))
+    lib().orc_decode(c.shape[0], L, D, _p(c), _p(s), _p(out))
+    return out.reshape(*coef.shape[:-1], D)
+
+
+def decode_bf16(coef_f32, dictionary_f32, round_out=False):
+    """Decode with bf16-rounded operands, float64 accumulation; optionally
+    bf16-rounded output.  Inputs float32."""
+    L, D = dictionary_f32.shape
+    c = _c(coef_f32, np.float32).reshape(-1, L)
+    s = _c(dictionary_f32, np.float32)
+    out = np.zeros((c.shape[0], D))
+    lib().orc_decode_bf16(c.shape[0], L, D, _p(c), _p(s), int(bool(round_out)), _p(out))
+    return out.reshape(*coef_f32.shape[:-1], D)
+
+
+def round_bf16(x):
+    x = _c(x, np.float32)
+    out = np.empty_like(x)
+    lib().orc_round_bf16(x.size, _p(x), _p(out))
+    return out
+
+
+def query(feat, pos, neg, tau=1.0):
+    """LERF relevancy per pixel.  feat (..., D) float64; pos (D,), neg (J, D)."""
+    D = feat.shape[-1]
+    f = _c(feat, np.float64).reshape(-1, D)
+    pos = _c(pos, np.float32)
+    neg = _c(neg, np.float32).reshape(-1, D)
+    out = np.zeros(f.shape[0])
+    lib().orc_query(f.shape[0], D, _p(f), _p(pos), neg.shape[0], _p(neg), float(tau), _p(out))
+    return out.reshape(feat.shape[:-1])
