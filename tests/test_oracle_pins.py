@@ -278,9 +278,11 @@ def test_two_gaussians_front_to_back(orc):
 
 
 def test_transmittance_stop_rule_closed_form(orc):
-    """Twenty identical opaque Gaussians with alpha = 1/2 at the centre pixel:
-    T halves each time; the 14th would take T to 2^-14 < 1e-4 and is not
-    blended, so W = w (1 - 2^-13) and T = 2^-13."""
+    """Fourteen Gaussians with alpha = 1/2 at the centre pixel, then six with
+    alpha = 1/10 behind them: T halves each time; the 14th would take T to
+    2^-14 < 1e-4, so compositing stops there (the weaker ones behind, which
+    alone would keep T above 1e-4, are not blended either): W = w (1 - 2^-13)
+    and T = 2^-13."""
     cam = gen.make_camera(128, 128)
     n = 20
     mus = [[0.0, 0.0, 0.01 * k] for k in range(n)]
@@ -290,6 +292,7 @@ def test_transmittance_stop_rule_closed_form(orc):
     mean2d = pr["mean2d"].copy()
     mean2d[:] = [64.5, 64.5]
     op = np.full(n, 0.5)
+    op[14:] = 0.1
     keys, ids, ranges = orc.tile_lists(cam, mean2d.astype(np.float32), pr["radius"], pr["depth"].astype(np.float32))
     coef, fT, last, mg = orc.composite(cam, ranges, ids, mean2d, pr["conic"], op, sc.topk_idx, sc.topk_w, 64)
     w = np.float32([0.1, 0.2, 0.3, 0.4]).astype(float)
