@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Feature-map benchmark of the sparse-coefficient splatting path on one GPU.
+
+One step = one feature-map frame of the whole forward hot path over the
+synthetic 1440x1080 scene (300k Gaussians, L=64, K=4, D=512, one level):
+project -> bin_sort -> splat_sparse -> dict_decode (bf16 matrix cores,
+bf16 output), with the scene already resident in HBM.  Prints one JSON line.
+
+Also reported: per-stage times (HIP events on the launch stream), the query
+rate (frame + relevancy), the plain FP32 path's rate, the roofline of the
+dominant kernel and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+BF16_PEAK_TFLOPS = 2500.0      # dense MFMA bf16
+F32_MFMA_PEAK_TFLOPS = 157.3   # MFMA fp32
+METRIC = "feature-map FPS at 1440x1080, L=64 K=4 D=512; fwd+bwd ms; % HBM/MFMA peak"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(stage, n, P, H, W, L, D, K, levels, feat_bytes):
+    """HBM bytes the method itself must move per launch of each stage."""
+    M = levels * H * W
+    if stage == "project":
+        return n * (12 + 12 + 16) + n * (8 + 12 + 4 + 4 + 4)
+    if stage == "bin_sort":
+        # count + emit read the projection (mean2d, radius, depth); emit writes
+        # 8-byte keys; the sort reads them and writes 4-byte ids
+        return n * (8 + 4) * 2 + n * 4 + P * 8 + P * 8 + P * 4
+    if stage == "splat":
+        rec = 8 + 12 + 4 + levels * K * 8
+        return M * L * 4 + H * W * 8 + P * 4 + n * rec
+    if stage == "decode":
+        return M * L * 4 + L * D * 4 + M * D * feat_bytes
+    if stage == "query":
+        return M * D * feat_bytes + M * 4
+    return 0
+
+
+def cpu_baseline(cam, scene, frac):
+    """The FP64 oracle, untuned, on a bounded sample of the same frame:
+    projection and binning of the full scene, compositing + decode of a random
+    fraction of the pixels; the frame time is extrapolated."""
+    import numpy as np
+    from oracle import oracle as orc
+    orc.build()
+    t0 = time.perf_counter()
+    pr = orc.project(cam, scene.means, scene.scales, scene.quats)
+    t1 = time.perf_counter()
+    keys, ids, ranges = orc.tile_lists(cam, pr["mean2d"].astype(np.float32), pr["radius"],
+                                       pr["depth"].astype(np.float32))
+    t2 = time.perf_counter()
+    npx = cam.width * cam.height
+    pix = np.random.default_rng(0).choice(npx, max(1, int(frac * npx)), replace=False)
+    coef, fT, last, margin = orc.composite_pixels(cam, ranges, ids, pr["mean2d"], pr["conic"], scene.opacity,
+                                                  scene.topk_idx, scene.topk_w, scene.L, pix)
+    t3 = time.perf_counter()
+    orc.decode(coef.reshape(-1, scene.L), scene.dictionary)
+    t4 = time.perf_counter()
+    scale = npx / len(pix)
+    frame_s = (t1 - t0) + (t2 - t1) + ((t3 - t2) + (t4 - t3)) * scale
+    return dict(value=1.0 / frame_s, unit="FPS", cores=orc.num_threads(), kind="oracle",
+                sample="full-scene projection + binning; compositing + decode of %d random pixels (%.1f%% of the "
+                       "frame), extrapolated; measured %.2f s of CPU work" % (len(pix), 100.0 * len(pix) / npx,
+                                                                             t4 - t0),
+                frame_s=frame_s, stages_s=dict(project=t1 - t0, bin_sort=t2 - t1, composite=(t3 - t2) * scale,
+                                               decode=(t4 - t3) * scale))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--cpu-frac", type=float, default=0.05, help="pixel fraction for the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path measurement")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the splatting path runs on a single MI355X here "
+              "(multi-GPU sharding is described in DESIGN.md but not run); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2507_07136_amd as ls2
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = gen.CONFIGS[args.config]
+    log("generating scene", args.config, cfg)
+    scene, cam = gen.config_scene(args.config)
+    pos, neg = gen.make_text(cfg["seed"] + 7, D=cfg["D"])
+    t = ls2.to_device(scene)
+    post, negt = torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda()
+    n, H, W, L, D, K, levels = scene.n, cam.height, cam.width, scene.L, scene.D, scene.K, scene.levels
+
+    pipe = ls2.Pipeline(cam, n, levels=levels, K=K, L=L, D=D)
+    # first frame sizes the pair buffers (one host sync); later frames run without host syncs
+    pipe.project(t["means"], t["scales"], t["quats"])
+    P = pipe.bin_sort(sync=True)
+    log("P =", P, "pairs")
+
+    def frame(compute, out_dtype, ev=None, query=False):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        pipe.project(t["means"], t["scales"], t["quats"])
+        mark(1)
+        pipe.bin_sort(sync=False)
+        mark(2)
+        pipe.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+        mark(3)
+        pipe.decode(t["dictionary"], compute, out_dtype)
+        mark(4)
+        if query:
+            pipe.query(post, negt)
+            mark(5)
+
+    stages = ["project", "bin_sort", "splat", "decode", "query"]
+
+    def run(compute, out_dtype, steps, warmup, query=False):
+        for _ in range(warmup):
+            frame(compute, out_dtype, query=query)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            frame(compute, out_dtype, evs[s], query=query)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        nst = 5 if query else 4
+        per = {stages[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
+               for i in range(nst)}
+        return wall, per
+
+    # headline: f32 splat + bf16 decode (bf16 feature map)
+    wall, per = run(ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
+    assert ls2.ls2_bin_sort_count(pipe.workspace) == P
+    fps = args.steps / wall
+    ms = 1000.0 * wall / args.steps
+    log("bf16 path: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
+
+    qwall, qper = run(ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
+    query_fps = max(5, args.steps // 2) / qwall
+
+    f32 = None
+    if not args.no_f32:
+        fwall, fper = run(ls2.LS2_F32, torch.float32, max(5, args.steps // 2), 3)
+        f32 = dict(fps=max(5, args.steps // 2) / fwall, stages_ms=fper)
+        log("f32 path: %.1f FPS" % f32["fps"])
+
+    # roofline per stage (bf16 path); the dominant kernel is the slowest stage
+    roof_all = {}
+    for st, tms in qper.items():
+        fb = 2
+        b = algorithmic_bytes(st, n, P, H, W, L, D, K, levels, fb)
+        gbs = b / (tms * 1e-3) / 1e9
+        roof_all[st] = dict(ms=tms, bytes=b, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
+    dom = max(per, key=per.get)
+    b = algorithmic_bytes(dom, n, P, H, W, L, D, K, levels, 2)
+    ach = b / (per[dom] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+                    traffic=None, kernel=dom, kernel_ms=round(per[dom], 4), algorithmic_bytes=int(b))
+    M = levels * H * W
+    decode_flops = 2.0 * M * L * D
+    mfma = dict(decode_tflops=decode_flops / (per["decode"] * 1e-3) / 1e12,
+                decode_frac_bf16_peak=decode_flops / (per["decode"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        cpu = cpu_baseline(cam, scene, args.cpu_frac)
+        log("cpu oracle: %.4f FPS (%d threads)" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": METRIC,
+        "value": round(fps, 2),
+        "unit": "FPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 splat, bf16 decode (fp32 accumulate)",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d Gaussians, %dx%d, L=%d, K=%d, D=%d, %d level(s), 16x16 tiles"
+                               % (args.config, n, W, H, L, K, D, levels),
+                   "pairs": P},
+        "stages_ms": {k: round(v, 4) for k, v in per.items()},
+        "query_fps": round(query_fps, 2),
+        "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
+                                               "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},
+        "fwd_bwd_ms": None,
+        "roofline": roofline,
+        "roofline_stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                            for k, v in roof_all.items()},
+        "mfma": {k: round(v, 4) for k, v in mfma.items()},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

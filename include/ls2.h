@@ -1,0 +1,177 @@
+/*
+ * ls2.h -- C ABI of libls2, the MI355X (gfx950) sparse-coefficient Gaussian
+ * splatting library (LangSplatV2, arXiv 2507.07136).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE pointers unless marked (host).  Arrays are
+ *     row-major and contiguous.  The caller owns all memory; the library
+ *     never allocates or frees (scratch comes in through a caller-sized
+ *     workspace where one is needed).
+ *   - Calls are asynchronous on `stream` unless documented otherwise.  There
+ *     is no global state: calls on different streams do not interact.
+ *   - Invalid sizes or null required pointers return LS2_ERR_ARG before any
+ *     work is enqueued.  Shapes outside the compiled kernel set return
+ *     LS2_ERR_UNSUPPORTED.  A HIP launch failure returns LS2_ERR_DEVICE.
+ *   - Pixel (px, py) is sampled at (px + 0.5, py + 0.5).  Screen tiles are
+ *     16 x 16 pixels, numbered row-major: tile = ty * ceil(W/16) + tx.
+ */
+#ifndef LS2_H
+#define LS2_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LS2_TILE 16
+
+enum {
+    LS2_OK = 0,
+    LS2_ERR_ARG = -1,          /* invalid argument (null pointer, negative size, K > L, ...) */
+    LS2_ERR_CAPACITY = -2,     /* ls2_bin_sort: more pairs than max_pairs */
+    LS2_ERR_UNSUPPORTED = -3,  /* shape outside the compiled set */
+    LS2_ERR_DEVICE = -4        /* HIP runtime error */
+};
+
+enum { LS2_F32 = 0, LS2_BF16 = 1 };
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  world_to_cam is
+ * the 3x4 row-major [R | t]; a world point X maps to p = R X + t.  Passed by
+ * (host) pointer. */
+typedef struct ls2_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float world_to_cam[12];
+    float znear;               /* Gaussians with camera z <= znear are culled */
+} ls2_camera;
+
+/* Human-readable text for a status code (static storage). */
+const char* ls2_status_string(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int ls2_version(void);
+
+/*
+ * ls2_project -- per-Gaussian projection to the image plane.
+ *
+ * Section 3.1, Eqs. 1-2: Sigma = R S S^T R^T with R from the unit quaternion
+ * q = (w, x, y, z) (normalised here) and S = diag(scales).  The paper cites
+ * EWA splatting for the projection; this library uses the local affine
+ * Jacobian J of the perspective map at the camera-space mean p = (x, y, z),
+ * J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]], the screen covariance
+ * Sigma2D = J R_wc Sigma R_wc^T J^T + 0.3 I, and a radius of
+ * ceil(3 sqrt(lambda_max(Sigma2D))) pixels.
+ *
+ * In:  means [n,3], scales [n,3] (> 0), quats [n,4] (w, x, y, z).
+ * Out: mean2d [n,2] = (fx x/z + cx, fy y/z + cy); conic [n,3] = the inverse of
+ *      Sigma2D as (A, B, C) with Sigma2D^-1 = [[A, B], [B, C]]; depth [n] = z;
+ *      radius [n]; tiles_touched [n] = number of 16x16 tiles in the rectangle
+ *      [floor((u-r)/16), floor((u+r)/16)] x [floor((v-r)/16), floor((v+r)/16)]
+ *      clipped to the grid (evaluated in float32).
+ * A Gaussian is culled (radius = 0, tiles_touched = 0, other outputs 0) if
+ * z <= znear, any value is non-finite, det(Sigma2D) <= 0, or its rectangle
+ * is empty.  n = 0 is a no-op.
+ */
+int ls2_project(const ls2_camera* cam, int32_t n, const float* means, const float* scales,
+                const float* quats, float* mean2d, float* conic, float* depth, int32_t* radius,
+                int32_t* tiles_touched, hipStream_t stream);
+
+/*
+ * ls2_bin_sort -- tile binning and per-tile depth order.
+ *
+ * Eq. 3 composites "the ordered Gaussian points within a tile": every visible
+ * Gaussian contributes one (tile, Gaussian) pair per tile of its rectangle
+ * (same float32 rule as ls2_project), and each tile's pairs are ordered by
+ * float32 depth, ties broken by Gaussian id (a unique, total order).
+ *
+ * In:  mean2d [n,2], radius [n], depth [n] from ls2_project.
+ * Out: ids [P] (Gaussian id of each pair, grouped by tile, depth-ordered);
+ *      keys [P] = (tile << 32) | float32 bits of depth (optional: may be NULL);
+ *      tile_ranges [tiles,2] = [start, end) of each tile in ids; start is the
+ *      number of pairs in all tiles before it (an empty tile has start = end).
+ *      P is at most max_pairs.
+ * workspace: device scratch of at least ls2_bin_sort_workspace() bytes,
+ *      256-byte aligned, owned by the caller, not shared between concurrent
+ *      calls.
+ * num_pairs (host, optional): if non-NULL the call synchronises the stream
+ *      once and stores P; if P > max_pairs it returns LS2_ERR_CAPACITY (grow
+ *      the buffers and call again).  If NULL the call does not synchronise;
+ *      on overflow every tile range is left empty and P can be read later
+ *      with ls2_bin_sort_count().
+ */
+int ls2_bin_sort_workspace(const ls2_camera* cam, int32_t n, int64_t max_pairs, size_t* bytes);
+int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2d, const int32_t* radius,
+                 const float* depth, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
+                 uint32_t* tile_ranges, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+/* P of the last ls2_bin_sort that used this workspace (synchronises stream). */
+int ls2_bin_sort_count(const void* workspace, int64_t* num_pairs, hipStream_t stream);
+
+/*
+ * ls2_splat_sparse -- efficient sparse coefficient splatting.
+ *
+ * Section 3.4 and Appendix A (Algorithm 1), with the compositing rule of
+ * Eq. 3: for each pixel v, walk its tile's ordered list front to back with
+ * alpha_i = min(0.99, o_i exp(-0.5 d^T conic_i d)), d = mean2d_i - v; skip
+ * alpha_i < 1/255; stop (without blending) once T (1 - alpha_i) < 1e-4;
+ * otherwise for every level l and each of the K stored pairs (j, w_ilj):
+ *     coef_l(v)[j] += w_ilj * alpha_i * T,   then T *= 1 - alpha_i.
+ * Only the K non-zero coefficients are touched (O(K) per Gaussian, not O(L)).
+ * Levels share alpha and T (one traversal renders every level).
+ *
+ * In:  tile_ranges, ids from ls2_bin_sort; mean2d [n,2], conic [n,3] from
+ *      ls2_project; opacity [n] in (0,1); topk_idx [n,levels,K] int32 in
+ *      [0, L); topk_w [n,levels,K].
+ * Out: coef [levels,H,W,L]; final_T [H,W] (optional) = transmittance after
+ *      the last blended Gaussian; last [H,W] (optional) = 1 + position in the
+ *      tile list of the last blended Gaussian (0 if none).
+ * Supported: L in {32, 64, 128}, 1 <= K <= 8, levels in {1, 2, 3} with
+ * levels * L <= 192.  Out-of-range indices are wrapped modulo L (garbage
+ * result, never out-of-bounds access).
+ */
+int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                     const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                     const float* conic, const float* opacity, const int32_t* topk_idx,
+                     const float* topk_w, float* coef, float* final_T, int32_t* last,
+                     hipStream_t stream);
+
+/*
+ * ls2_dict_decode -- feature map F = W S (Eq. 7: rendering the sparse
+ * coefficients and multiplying by the global codebook S equals rendering
+ * the D-dimensional features).  One product shared by all levels.
+ *
+ * In:  coef [m,L] f32 (m = levels*H*W rows), dict [L,D] f32.
+ * compute: LS2_F32 (float32 products and accumulation) or LS2_BF16 (both
+ *      operands rounded to bfloat16, nearest-even; float32 accumulation on
+ *      the matrix cores).
+ * Out: feat [m,D], float32 (out_dtype LS2_F32) or bfloat16 (LS2_BF16,
+ *      rounded nearest-even from the float32 accumulator).
+ * Supported: L in {32, 64, 128}; D in {128, 256, 384, 512, 1024}.
+ */
+int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                    int32_t compute, int32_t out_dtype, void* feat, hipStream_t stream);
+
+/*
+ * ls2_query -- relevancy of each feature to a text query.
+ *
+ * Section 3.2 computes relevancy "following LERF": with cosine similarities
+ * s_q = cos(F, pos), s_j = cos(F, neg_j) against n_neg canonical negatives,
+ *     r = min_j exp(tau s_q) / (exp(tau s_q) + exp(tau s_j))
+ *       = sigmoid(tau (s_q - max_j s_j)).
+ * Norms are guarded below by 1e-12 (a zero feature scores 0.5).
+ *
+ * In:  feat [m,D] f32 or bf16 (feat_dtype); pos [D]; neg [n_neg,D] f32.
+ * Out: relevancy [m] f32.  Arithmetic is float32.
+ * Supported: D a multiple of 64 up to 1024, 1 <= n_neg <= 8.
+ */
+int ls2_query(int64_t m, int32_t D, const void* feat, int32_t feat_dtype, const float* pos,
+              int32_t n_neg, const float* neg, float tau, float* relevancy, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LS2_H */

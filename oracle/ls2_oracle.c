@@ -270,16 +270,20 @@ int orc_tile_lists(const double* cam_arr, int n, const float* mean2d, const int3
             }
     }
     qsort(pairs, (size_t)P, sizeof(pair_t), pair_cmp);
-    for (int t = 0; t < ntiles; ++t) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
     for (int64_t j = 0; j < P; ++j) {
         if (keys) keys[j] = ((uint64_t)pairs[j].tile << 32) | pairs[j].dbits;
         ids[j] = pairs[j].id;
     }
-    /* ranges: first and one-past-last position of each tile */
-    for (int64_t j = 0; j < P; ++j) {
-        uint32_t t = pairs[j].tile;
-        if (j == 0 || pairs[j - 1].tile != t) ranges[2 * t] = (uint32_t)j;
-        if (j == P - 1 || pairs[j + 1].tile != t) ranges[2 * t + 1] = (uint32_t)(j + 1);
+    /* ranges: [start, end) of each tile; start = number of pairs in the tiles
+     * before it (so an empty tile has start = end = that count) */
+    for (int t = 0; t < ntiles; ++t) ranges[2 * t + 1] = 0;
+    for (int64_t j = 0; j < P; ++j) ranges[2 * pairs[j].tile + 1] += 1;
+    uint32_t acc = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        uint32_t c = ranges[2 * t + 1];
+        ranges[2 * t] = acc;
+        acc += c;
+        ranges[2 * t + 1] = acc;
     }
     free(pairs);
     return 0;
@@ -294,17 +298,18 @@ int orc_tile_lists(const double* cam_arr, int n, const float* mean2d, const int3
 /* Writes contributing list positions and their e_i; returns count.    */
 /* *T_out = final transmittance, *last_out = 1 + position of the last   */
 /* contributing entry relative to the tile start (0 if none),          */
-/* *margin = smallest relative distance of any decision to its         */
-/* threshold (clamp, skip, stop).                                      */
+/* *margin = smallest relative distance of an alpha decision (clamp,    */
+/* skip) to its threshold, *margin_T = the same for the stop decision   */
+/* (transmittance against 1e-4).                                        */
 /* ------------------------------------------------------------------ */
 static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, const uint32_t* ids,
                       const double* mean2d, const double* conic, const double* opacity,
                       int32_t* pos_out, double* e_out, double* T_before_out, double* alpha_out,
-                      double* T_out, int32_t* last_out, double* margin) {
+                      double* T_out, int32_t* last_out, double* margin, double* margin_T) {
     double T = 1.0;
     int cnt = 0;
     int32_t last = 0;
-    double mg = INFINITY;
+    double mg = INFINITY, mgT = INFINITY;
     for (uint32_t pos = start; pos < end; ++pos) {
         uint32_t i = ids[pos];
         double dx = mean2d[2 * i] - pxc;
@@ -321,7 +326,7 @@ static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, cons
         if (alpha < ALPHA_MIN) continue;
         double testT = T * (1.0 - alpha);
         double m3 = fabs(testT - T_MIN) / T_MIN;
-        if (m3 < mg) mg = m3;
+        if (m3 < mgT) mgT = m3;
         if (testT < T_MIN) break;
         if (pos_out) pos_out[cnt] = (int32_t)(pos - start);
         if (e_out) e_out[cnt] = alpha * T;
@@ -334,6 +339,7 @@ static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, cons
     *T_out = T;
     *last_out = last;
     *margin = mg;
+    if (margin_T) *margin_T = mgT;
     return cnt;
 }
 
@@ -359,7 +365,7 @@ static uint32_t max_range(const uint32_t* ranges, int ntiles) {
 void orc_composite(const double* cam_arr, int levels, int K, int L, const uint32_t* ranges,
                    const uint32_t* ids, const double* mean2d, const double* conic,
                    const double* opacity, const int32_t* topk_idx, const double* topk_w,
-                   double* coef, double* final_T, int32_t* last, double* margin) {
+                   double* coef, double* final_T, int32_t* last, double* margin, double* margin_T) {
     cam_t cam = cam_from(cam_arr);
     int ntiles = cam.tx * cam.ty;
     size_t HW = (size_t)cam.W * cam.H;
@@ -377,9 +383,9 @@ void orc_composite(const double* cam_arr, int levels, int K, int L, const uint32
                     size_t pix = (size_t)py * cam.W + px;
                     double T;
                     int32_t lst;
-                    double mg;
+                    double mg, mgT;
                     int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids,
-                                         mean2d, conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg);
+                                         mean2d, conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg, &mgT);
                     for (int c = 0; c < cnt; ++c) {
                         uint32_t i = ids[ranges[2 * t] + pos[c]];
                         for (int lv = 0; lv < levels; ++lv) {
@@ -393,6 +399,7 @@ void orc_composite(const double* cam_arr, int levels, int K, int L, const uint32
                     final_T[pix] = T;
                     last[pix] = lst;
                     margin[pix] = mg;
+                    margin_T[pix] = mgT;
                 }
         }
         free(pos);
@@ -423,7 +430,7 @@ void orc_composite_dense(const double* cam_arr, int C, const uint32_t* ranges, c
                     double T, mg;
                     int32_t lst;
                     int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids,
-                                         mean2d, conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg);
+                                         mean2d, conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg, NULL);
                     double* o = out + ((size_t)py * cam.W + px) * C;
                     for (int c = 0; c < cnt; ++c) {
                         const double* f = feat + (size_t)ids[ranges[2 * t] + pos[c]] * C;
@@ -442,7 +449,7 @@ void orc_composite_pixels(const double* cam_arr, int levels, int K, int L, const
                           const uint32_t* ids, const double* mean2d, const double* conic,
                           const double* opacity, const int32_t* topk_idx, const double* topk_w,
                           int64_t npix, const int64_t* pix, double* coef, double* final_T,
-                          int32_t* last, double* margin) {
+                          int32_t* last, double* margin, double* margin_T) {
     cam_t cam = cam_from(cam_arr);
     uint32_t maxlen = max_range(ranges, cam.tx * cam.ty);
     memset(coef, 0, sizeof(double) * (size_t)npix * levels * L);
@@ -454,10 +461,10 @@ void orc_composite_pixels(const double* cam_arr, int levels, int K, int L, const
         for (int64_t q = 0; q < npix; ++q) {
             int px = (int)(pix[q] % cam.W), py = (int)(pix[q] / cam.W);
             int t = (py / ORC_TILE) * cam.tx + px / ORC_TILE;
-            double T, mg;
+            double T, mg, mgT;
             int32_t lst;
             int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids, mean2d,
-                                 conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg);
+                                 conic, opacity, pos, e, NULL, NULL, &T, &lst, &mg, &mgT);
             for (int c = 0; c < cnt; ++c) {
                 uint32_t i = ids[ranges[2 * t] + pos[c]];
                 for (int lv = 0; lv < levels; ++lv) {
@@ -471,6 +478,7 @@ void orc_composite_pixels(const double* cam_arr, int levels, int K, int L, const
             final_T[q] = T;
             last[q] = lst;
             margin[q] = mg;
+            margin_T[q] = mgT;
         }
         free(pos);
         free(e);

@@ -52,12 +52,12 @@ def _declare(L):
     L.orc_tile_lists.argtypes = [_P, ctypes.c_int, _P, _P, _P, i64, _P, _P, _P, _P]
     L.orc_tile_lists.restype = ctypes.c_int
     L.orc_composite.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P,
-                                _P, _P, _P, _P]
+                                _P, _P, _P, _P, _P]
     L.orc_composite.restype = None
     L.orc_composite_dense.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]
     L.orc_composite_dense.restype = None
     L.orc_composite_pixels.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P,
-                                       _P, _P, i64, _P, _P, _P, _P, _P]
+                                       _P, _P, i64, _P, _P, _P, _P, _P, _P]
     L.orc_composite_pixels.restype = None
     L.orc_composite_bruteforce.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
@@ -138,26 +138,31 @@ def tile_lists(cam, mean2d_f32, radius, depth_f32, cap=None):
     return keys[:P.value], ids[:P.value], ranges
 
 
-def composite(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L):
+def composite(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L, with_margin_T=False):
     """Sparse coefficient splatting (Algorithm 1).  topk_idx/topk_w: (N, levels, K).
-    Returns coef (levels, H, W, L), final_T (H, W), last (H, W), margin (H, W)."""
+    Returns coef (levels, H, W, L), final_T (H, W), last (H, W), margin (H, W)
+    and, if with_margin_T, margin_T (H, W): the relative distances of the
+    alpha decisions (clamp, skip) and of the stop decision to their thresholds."""
     n, levels, K = topk_idx.shape
     H, W = cam.height, cam.width
     coef = np.zeros((levels, H, W, L))
     fT = np.zeros((H, W))
     last = np.zeros((H, W), np.int32)
     margin = np.zeros((H, W))
+    margin_T = np.zeros((H, W))
     ids = _c(ids, np.uint32)
     args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
             _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64)]
     lib().orc_composite(_p(cam_array(cam)), levels, K, L, *[_p(a) for a in args], _p(coef), _p(fT),
-                        _p(last), _p(margin))
+                        _p(last), _p(margin), _p(margin_T))
+    if with_margin_T:
+        return coef, fT, last, margin, margin_T
     return coef, fT, last, margin
 
 
-def composite_pixels(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L, pix):
+def composite_pixels(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L, pix, with_margin_T=False):
     """Composite only the flat pixel indices ``pix``.  Returns coef
-    (npix, levels, L), final_T, last, margin (npix,)."""
+    (npix, levels, L), final_T, last, margin (npix,) [, margin_T]."""
     n, levels, K = topk_idx.shape
     pix = _c(pix, np.int64)
     npix = pix.shape[0]
@@ -165,11 +170,14 @@ def composite_pixels(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
     fT = np.zeros(npix)
     last = np.zeros(npix, np.int32)
     margin = np.zeros(npix)
+    margin_T = np.zeros(npix)
     ids = _c(ids, np.uint32)
     args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
             _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64)]
     lib().orc_composite_pixels(_p(cam_array(cam)), levels, K, L, *[_p(a) for a in args], npix, _p(pix),
-                               _p(coef), _p(fT), _p(last), _p(margin))
+                               _p(coef), _p(fT), _p(last), _p(margin), _p(margin_T))
+    if with_margin_T:
+        return coef, fT, last, margin, margin_T
     return coef, fT, last, margin
 
 

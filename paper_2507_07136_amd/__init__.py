@@ -1,0 +1,28 @@
+"""MI355X-native sparse-coefficient Gaussian splatting (LangSplatV2 hot path).
+
+The HIP library ``libls2.so`` (C ABI in ``include/ls2.h``) does all the work;
+this package marshals torch tensors into it.  Importing fails if the library
+has not been built (there is no fallback path).
+"""
+from ._lib import (  # noqa: F401
+    LS2_BF16,
+    LS2_ERR_ARG,
+    LS2_ERR_CAPACITY,
+    LS2_ERR_DEVICE,
+    LS2_ERR_UNSUPPORTED,
+    LS2_F32,
+    LS2_OK,
+    LS2Error,
+    LIB_PATH,
+    ls2_bin_sort,
+    ls2_bin_sort_count,
+    ls2_bin_sort_workspace,
+    ls2_dict_decode,
+    ls2_project,
+    ls2_query,
+    ls2_splat_sparse,
+    make_camera,
+    status_string,
+    version,
+)
+from .render import Pipeline, to_device  # noqa: F401

@@ -1,0 +1,209 @@
+"""ctypes binding of libls2 (include/ls2.h).
+
+Argument marshalling only: tensors are checked for device, dtype, shape and
+contiguity, converted to raw device pointers, and handed to the C ABI together
+with the current HIP stream.  Every step of the path runs in the HIP library;
+there is no CPU or PyTorch fallback.  If the library is missing the import
+fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libls2.so")
+
+LS2_OK, LS2_ERR_ARG, LS2_ERR_CAPACITY, LS2_ERR_UNSUPPORTED, LS2_ERR_DEVICE = 0, -1, -2, -3, -4
+LS2_F32, LS2_BF16 = 0, 1
+TILE = 16
+
+
+class LS2Error(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__("%s failed: %s (%d)" % (fn, status_string(status), status))
+        self.status = status
+
+
+class ls2_camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("world_to_cam", ctypes.c_float * 12), ("znear", ctypes.c_float)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libls2.so not built at %s: run `python -m paper_2507_07136_amd.build` "
+                          "(or __graft_entry__.build())" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    cam = ctypes.POINTER(ls2_camera)
+    sig = {
+        "ls2_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "ls2_version": ([], ctypes.c_int),
+        "ls2_project": ([cam, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "ls2_bin_sort_workspace": ([cam, i32, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_bin_sort": ([cam, i32, P, P, P, i64, P, P, P, ctypes.POINTER(ctypes.c_int64), P, ctypes.c_size_t, P],
+                         ctypes.c_int),
+        "ls2_bin_sort_count": ([P, ctypes.POINTER(ctypes.c_int64), P], ctypes.c_int),
+        "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "ls2_dict_decode": ([i64, i32, i32, P, P, i32, i32, P, P], ctypes.c_int),
+        "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return _lib.ls2_status_string(int(status)).decode()
+
+
+def version() -> int:
+    return int(_lib.ls2_version())
+
+
+def _check(fn, status):
+    if status != LS2_OK:
+        raise LS2Error(fn, status)
+
+
+def make_camera(cam) -> ls2_camera:
+    """ctypes camera from an object with width, height, fx, fy, cx, cy,
+    world_to_cam (3x4) and znear (e.g. ``gen.Camera``)."""
+    c = ls2_camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    w2c = [float(x) for x in torch.as_tensor(cam.world_to_cam, dtype=torch.float64).reshape(-1).tolist()]
+    for i in range(12):
+        c.world_to_cam[i] = w2c[i]
+    c.znear = float(getattr(cam, "znear", 0.2))
+    return c
+
+
+def _ptr(t, dtype=None, name="tensor", numel=None, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError("%s is required" % name)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor (the library has no CPU path)" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ C ABI, one wrapper per entry point
+def ls2_project(cam, means, scales, quats, mean2d, conic, depth, radius, tiles_touched=None, stream=None):
+    n = means.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    f32, i32 = torch.float32, torch.int32
+    st = _lib.ls2_project(ctypes.byref(c), n, _ptr(means, f32, "means", 3 * n), _ptr(scales, f32, "scales", 3 * n),
+                          _ptr(quats, f32, "quats", 4 * n), _ptr(mean2d, f32, "mean2d", 2 * n),
+                          _ptr(conic, f32, "conic", 3 * n), _ptr(depth, f32, "depth", n),
+                          _ptr(radius, i32, "radius", n),
+                          _ptr(tiles_touched, i32, "tiles_touched", n, allow_none=True), _stream(stream))
+    _check("ls2_project", st)
+
+
+def ls2_bin_sort_workspace(cam, n, max_pairs) -> int:
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    b = ctypes.c_size_t(0)
+    _check("ls2_bin_sort_workspace", _lib.ls2_bin_sort_workspace(ctypes.byref(c), int(n), int(max_pairs),
+                                                                 ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_bin_sort(cam, mean2d, radius, depth, max_pairs, keys, ids, tile_ranges, workspace, sync=True, stream=None):
+    """Returns P (synchronising once) if sync, else None.  Raises LS2Error
+    with status LS2_ERR_CAPACITY when P > max_pairs (sync mode)."""
+    n = radius.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    P = ctypes.c_int64(-1)
+    ntiles = ((c.width + TILE - 1) // TILE) * ((c.height + TILE - 1) // TILE)
+    st = _lib.ls2_bin_sort(ctypes.byref(c), n, _ptr(mean2d, torch.float32, "mean2d", 2 * n),
+                           _ptr(radius, torch.int32, "radius", n), _ptr(depth, torch.float32, "depth", n),
+                           int(max_pairs), _ptr(keys, torch.int64, "keys", int(max_pairs), allow_none=True),
+                           _ptr(ids, torch.int32, "ids", int(max_pairs)),
+                           _ptr(tile_ranges, torch.int32, "tile_ranges", 2 * ntiles),
+                           ctypes.byref(P) if sync else None, _ptr(workspace, torch.uint8, "workspace"),
+                           workspace.numel(), _stream(stream))
+    if st == LS2_ERR_CAPACITY:
+        err = LS2Error("ls2_bin_sort", st)
+        err.num_pairs = int(P.value)
+        raise err
+    _check("ls2_bin_sort", st)
+    return int(P.value) if sync else None
+
+
+def ls2_bin_sort_count(workspace, stream=None) -> int:
+    P = ctypes.c_int64(-1)
+    _check("ls2_bin_sort_count", _lib.ls2_bin_sort_count(_ptr(workspace, torch.uint8, "workspace"),
+                                                         ctypes.byref(P), _stream(stream)))
+    return int(P.value)
+
+
+def ls2_splat_sparse(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, coef,
+                     final_T=None, last=None, stream=None):
+    n = opacity.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    HW = c.width * c.height
+    f32, i32 = torch.float32, torch.int32
+    st = _lib.ls2_splat_sparse(ctypes.byref(c), n, int(levels), int(K), int(L), _ptr(tile_ranges, i32, "tile_ranges"),
+                               _ptr(ids, i32, "ids"), _ptr(mean2d, f32, "mean2d", 2 * n),
+                               _ptr(conic, f32, "conic", 3 * n), _ptr(opacity, f32, "opacity", n),
+                               _ptr(topk_idx, i32, "topk_idx", n * levels * K),
+                               _ptr(topk_w, f32, "topk_w", n * levels * K),
+                               _ptr(coef, f32, "coef", levels * HW * L),
+                               _ptr(final_T, f32, "final_T", HW, allow_none=True),
+                               _ptr(last, i32, "last", HW, allow_none=True), _stream(stream))
+    _check("ls2_splat_sparse", st)
+
+
+def _dtype_code(t):
+    if t.dtype == torch.float32:
+        return LS2_F32
+    if t.dtype == torch.bfloat16:
+        return LS2_BF16
+    raise TypeError("expected float32 or bfloat16, got %s" % t.dtype)
+
+
+def ls2_dict_decode(coef, dictionary, feat, compute=LS2_F32, stream=None):
+    L, D = dictionary.shape
+    m = coef.numel() // L
+    st = _lib.ls2_dict_decode(m, L, D, _ptr(coef, torch.float32, "coef", m * L),
+                              _ptr(dictionary, torch.float32, "dict", L * D), int(compute), _dtype_code(feat),
+                              _ptr(feat, None, "feat", m * D), _stream(stream))
+    _check("ls2_dict_decode", st)
+
+
+def ls2_query(feat, pos, neg, relevancy, tau=1.0, stream=None):
+    D = pos.shape[-1]
+    m = feat.numel() // D
+    n_neg = neg.numel() // D
+    st = _lib.ls2_query(m, D, _ptr(feat, None, "feat", m * D), _dtype_code(feat), _ptr(pos, torch.float32, "pos", D),
+                        n_neg, _ptr(neg, torch.float32, "neg", n_neg * D), float(tau),
+                        _ptr(relevancy, torch.float32, "relevancy", m), _stream(stream))
+    _check("ls2_query", st)

@@ -1,0 +1,287 @@
+// ls2_dict_decode: F = W S (Eq. 7), one dense [m x L] x [L x D] product per
+// call, on the CDNA4 matrix cores.
+//
+// The product has only L = 32..128 terms per output, so it is bound by the
+// HBM write of F (about 51 flop per byte in bf16), not by the matrix cores.
+// The kernel is built around streaming F out at full bandwidth:
+//   - persistent workgroups, one wave per D/(waves) feature slice; the wave's
+//     slice of S stays in VGPRs for the whole kernel (read once);
+//   - per block of 32 pixels each wave computes the transposed tile
+//     F^T[features x pixels] so that every lane ends up holding 4 consecutive
+//     features of one pixel, which it writes as one 8/16-byte LDS store;
+//   - the workgroup then writes the 32 x D tile to HBM as contiguous rows
+//     (every store instruction covers whole 1-2 KB rows).
+// bf16 compute: v_mfma_f32_32x32x16_bf16 (operands rounded to nearest even).
+// f32 compute:  v_mfma_f32_32x32x2_f32.
+#include "ls2_internal.h"
+
+namespace ls2 {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+struct DecodeArgs {
+    long long m;
+    int D;
+    int FC;        // features per workgroup chunk (min(D, 512))
+    int nchunks;   // D / FC
+    const float* coef;
+    const float* dict;
+    void* feat;
+    long long nblocks;
+};
+
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
+    __bf16 x = (__bf16)a, y = (__bf16)b;
+    return (unsigned)__builtin_bit_cast(unsigned short, x) | ((unsigned)__builtin_bit_cast(unsigned short, y) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// bf16 compute.  MFMA 32x32x16: A (32 x 16) lane l holds row l%32, k =
+// (l/32)*8 + [0,8); B (16 x 32) lane l holds column l%32, same k; C (32 x 32)
+// lane l holds column l%32, rows (r/4)*8 + (l/32)*4 + r%4 for register r.
+// A = S^T slice (features x k), B = W^T (k x pixels), C = F^T tile.
+// Each wave owns FW = 128 features (4 row tiles of 32).
+template <int L, bool OUT_BF16>
+__global__ __launch_bounds__(256) void k_decode_bf16(DecodeArgs a) {
+    constexpr int KS = L / 16;   // k-steps
+    constexpr int MT = 4;        // 32-feature tiles per wave
+    constexpr int OSZ = OUT_BF16 ? 2 : 4;
+    extern __shared__ float4 smem4[];
+    char* smem = reinterpret_cast<char*>(smem4);
+
+    const int D = a.D;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int chunk = blockIdx.x % a.nchunks;          // this workgroup's feature chunk
+    const int row_bytes = a.FC * OSZ;                  // bytes of one row inside the chunk
+    const int srow = row_bytes + 16;                   // padded LDS row (bytes)
+    const int col = lane & 31, half = lane >> 5;
+    const int f_wave = chunk * a.FC + wave * (MT * 32);
+
+    // S^T fragments for this wave: features f_wave + mt*32 + col, k = ks*16 + half*8 + [0,8)
+    bf16x8 sa[MT][KS];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int f = f_wave + mt * 32 + col;
+            bf16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (__bf16)a.dict[(size_t)(ks * 16 + half * 8 + e) * D + f];
+            sa[mt][ks] = v;
+        }
+
+    for (long long blk = blockIdx.x / a.nchunks; blk < a.nblocks; blk += gridDim.x / a.nchunks) {
+        const long long p0 = blk * 32;
+        const long long p = p0 + col;
+        // W^T fragments: pixel p, k = ks*16 + half*8 + [0,8)
+        bf16x8 wb[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            float4 u0 = make_float4(0.f, 0.f, 0.f, 0.f), u1 = u0;
+            if (p < a.m) {
+                const float4* src = reinterpret_cast<const float4*>(a.coef + p * L + ks * 16 + half * 8);
+                u0 = src[0];
+                u1 = src[1];
+            }
+            bf16x8 v;
+            v[0] = (__bf16)u0.x; v[1] = (__bf16)u0.y; v[2] = (__bf16)u0.z; v[3] = (__bf16)u0.w;
+            v[4] = (__bf16)u1.x; v[5] = (__bf16)u1.y; v[6] = (__bf16)u1.z; v[7] = (__bf16)u1.w;
+            wb[ks] = v;
+        }
+        f32x16 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            acc[mt] = (f32x16){};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+                acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sa[mt][ks], wb[ks], acc[mt], 0, 0, 0);
+        }
+        // stage: lane holds pixel col, features f_wave + mt*32 + g*8 + half*4 + [0,4)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int f = f_wave - chunk * a.FC + mt * 32 + g * 8 + half * 4;  // within the chunk
+                char* dst = smem + col * srow + f * OSZ;
+                if (OUT_BF16) {
+                    uint2 v;
+                    v.x = pack_bf16x2(acc[mt][4 * g], acc[mt][4 * g + 1]);
+                    v.y = pack_bf16x2(acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+                    *reinterpret_cast<uint2*>(dst) = v;
+                } else {
+                    *reinterpret_cast<float4*>(dst) =
+                        make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+                }
+            }
+        __syncthreads();
+        // write the 32 x D tile as contiguous rows
+        const int chunks_per_row = row_bytes / 16;
+        const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
+        const int nvec = (int)rows * chunks_per_row;
+        const long long out_row = (long long)D * OSZ;
+        char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
+        for (int c = threadIdx.x; c < nvec; c += nwaves * 64) {
+            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// f32 compute.  MFMA 32x32x2 f32: A (32 x 2) lane l holds row l%32, k = l/32;
+// B (2 x 32) lane l holds column l%32, k = l/32; C as above.  The reduction
+// index is permuted so that lane half h covers k in [h*L/2, (h+1)*L/2): step s
+// pairs k = s (half 0) with k = L/2 + s (half 1), letting each lane read its
+// pixel's coefficients as contiguous float4s.  Each wave owns FW = 64
+// features (2 row tiles).
+template <int L, bool OUT_BF16>
+__global__ __launch_bounds__(512) void k_decode_f32(DecodeArgs a) {
+    constexpr int KS = L / 2;
+    constexpr int MT = 2;
+    constexpr int OSZ = OUT_BF16 ? 2 : 4;
+    extern __shared__ float4 smem4[];
+    char* smem = reinterpret_cast<char*>(smem4);
+
+    const int D = a.D;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int chunk = blockIdx.x % a.nchunks;
+    const int row_bytes = a.FC * OSZ;
+    const int srow = row_bytes + 16;
+    const int col = lane & 31, half = lane >> 5;
+    const int f_wave = chunk * a.FC + wave * (MT * 32);
+
+    float sa[MT][KS];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) sa[mt][s] = a.dict[(size_t)(half * KS + s) * D + f_wave + mt * 32 + col];
+
+    for (long long blk = blockIdx.x / a.nchunks; blk < a.nblocks; blk += gridDim.x / a.nchunks) {
+        const long long p0 = blk * 32;
+        const long long p = p0 + col;
+        float wv[KS];
+#pragma unroll
+        for (int q = 0; q < KS / 4; ++q) {
+            float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (p < a.m) u = reinterpret_cast<const float4*>(a.coef + p * L + half * KS)[q];
+            wv[4 * q] = u.x; wv[4 * q + 1] = u.y; wv[4 * q + 2] = u.z; wv[4 * q + 3] = u.w;
+        }
+        f32x16 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            acc[mt] = (f32x16){};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[mt][s], wv[s], acc[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int f = f_wave - chunk * a.FC + mt * 32 + g * 8 + half * 4;  // within the chunk
+                char* dst = smem + col * srow + f * OSZ;
+                if (OUT_BF16) {
+                    uint2 v;
+                    v.x = pack_bf16x2(acc[mt][4 * g], acc[mt][4 * g + 1]);
+                    v.y = pack_bf16x2(acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+                    *reinterpret_cast<uint2*>(dst) = v;
+                } else {
+                    *reinterpret_cast<float4*>(dst) =
+                        make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+                }
+            }
+        __syncthreads();
+        const int chunks_per_row = row_bytes / 16;
+        const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
+        const int nvec = (int)rows * chunks_per_row;
+        const long long out_row = (long long)D * OSZ;
+        char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
+        for (int c = threadIdx.x; c < nvec; c += nwaves * 64) {
+            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+        }
+        __syncthreads();
+    }
+}
+
+static int g_num_cus = 0;
+
+static int num_cus() {
+    if (g_num_cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        g_num_cus = n;
+    }
+    return g_num_cus;
+}
+
+template <int L, bool OB>
+static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) {
+    DecodeArgs a = a0;
+    a.FC = a.D < 512 ? a.D : 512;
+    a.nchunks = a.D / a.FC;
+    const int osz = OB ? 2 : 4;
+    const size_t lds = (size_t)32 * (a.FC * osz + 16);
+    const int per_cu = lds <= 40 * 1024 ? 4 : (lds <= 80 * 1024 ? 2 : 1);
+    long long grid = (long long)num_cus() * per_cu;
+    grid -= grid % a.nchunks;
+    const long long need = a.nblocks * a.nchunks;
+    if (grid > need) grid = need;
+    if (compute == LS2_BF16) {
+        const int threads = (a.FC / 128) * 64;
+        static bool attr = false;
+        if (!attr) {
+            if (hipFuncSetAttribute((const void*)k_decode_bf16<L, OB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    96 * 1024) != hipSuccess)
+                return LS2_ERR_DEVICE;
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_decode_bf16<L, OB>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+    } else {
+        const int threads = (a.FC / 64) * 64;
+        static bool attr = false;
+        if (!attr) {
+            if (hipFuncSetAttribute((const void*)k_decode_f32<L, OB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    96 * 1024) != hipSuccess)
+                return LS2_ERR_DEVICE;
+            attr = true;
+        }
+        hipLaunchKernelGGL((k_decode_f32<L, OB>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+    }
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
+}
+
+}  // namespace ls2
+
+using namespace ls2;
+
+extern "C" int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict, int32_t compute,
+                               int32_t out_dtype, void* feat, hipStream_t stream) {
+    if (m < 0 || L < 1 || D < 1 || !dict || !feat || !coef) return LS2_ERR_ARG;
+    if ((compute != LS2_F32 && compute != LS2_BF16) || (out_dtype != LS2_F32 && out_dtype != LS2_BF16))
+        return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || D % 128 != 0 || (D > 512 && D != 1024)) return LS2_ERR_UNSUPPORTED;
+    if (m == 0) return LS2_OK;
+    DecodeArgs a;
+    a.m = m;
+    a.D = D;
+    a.coef = coef;
+    a.dict = dict;
+    a.feat = feat;
+    a.nblocks = (m + 31) / 32;
+    const bool ob = out_dtype == LS2_BF16;
+    switch (L) {
+        case 32: return ob ? launch_decode<32, true>(a, compute, stream) : launch_decode<32, false>(a, compute, stream);
+        case 64: return ob ? launch_decode<64, true>(a, compute, stream) : launch_decode<64, false>(a, compute, stream);
+        default: return ob ? launch_decode<128, true>(a, compute, stream) : launch_decode<128, false>(a, compute, stream);
+    }
+}

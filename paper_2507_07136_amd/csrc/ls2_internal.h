@@ -1,0 +1,88 @@
+// Internal helpers of libls2 (device and host).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ls2.h"
+
+namespace ls2 {
+
+constexpr int kTile = LS2_TILE;
+
+// Camera passed to kernels by value.
+struct CamK {
+    int W, H, tx, ty;
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    float znear;
+};
+
+inline CamK cam_k(const ls2_camera& c) {
+    CamK k;
+    k.W = c.width;
+    k.H = c.height;
+    k.tx = (c.width + kTile - 1) / kTile;
+    k.ty = (c.height + kTile - 1) / kTile;
+    k.fx = c.fx; k.fy = c.fy; k.cx = c.cx; k.cy = c.cy;
+    for (int r = 0; r < 3; ++r) {
+        for (int j = 0; j < 3; ++j) k.R[3 * r + j] = c.world_to_cam[4 * r + j];
+        k.t[r] = c.world_to_cam[4 * r + 3];
+    }
+    k.znear = c.znear;
+    return k;
+}
+
+inline bool cam_valid(const ls2_camera* c) {
+    return c && c->width > 0 && c->height > 0 && c->width <= (1 << 15) && c->height <= (1 << 15);
+}
+
+// Tile rectangle [x0,x1] x [y0,y1] of a Gaussian with float32 mean (u, v) and
+// integer radius r: [floor((u - r)/16), floor((u + r)/16)] clipped to the
+// grid.  Every step is an explicit round-to-nearest float32 operation so the
+// decision is identical wherever it is evaluated.  Returns false if empty.
+__host__ __device__ inline bool tile_rect(float u, float v, int r, int tx, int ty, int& x0, int& y0,
+                                          int& x1, int& y1) {
+    const float rf = (float)r;
+#if defined(__HIP_DEVICE_COMPILE__)
+    float lox = floorf(__fmul_rn(__fsub_rn(u, rf), 0.0625f));
+    float hix = floorf(__fmul_rn(__fadd_rn(u, rf), 0.0625f));
+    float loy = floorf(__fmul_rn(__fsub_rn(v, rf), 0.0625f));
+    float hiy = floorf(__fmul_rn(__fadd_rn(v, rf), 0.0625f));
+#else
+    float lox = floorf((u - rf) * 0.0625f);
+    float hix = floorf((u + rf) * 0.0625f);
+    float loy = floorf((v - rf) * 0.0625f);
+    float hiy = floorf((v + rf) * 0.0625f);
+#endif
+    lox = lox < 0.0f ? 0.0f : lox;
+    loy = loy < 0.0f ? 0.0f : loy;
+    hix = hix > (float)(tx - 1) ? (float)(tx - 1) : hix;
+    hiy = hiy > (float)(ty - 1) ? (float)(ty - 1) : hiy;
+    if (!(lox <= hix) || !(loy <= hiy)) return false;
+    x0 = (int)lox; x1 = (int)hix; y0 = (int)loy; y1 = (int)hiy;
+    return true;
+}
+
+// Map a linear block index to (work item, slot).  Blocks are dispatched
+// round-robin over the 8 XCDs, so block b runs on XCD b % 8.  The remap gives
+// each XCD one contiguous range of the linear order: the `per` blocks of one
+// work item share an XCD, and spatially adjacent tiles share its L2.  The
+// grid must be a multiple of 8; linear indices past the work are returned as
+// item >= the caller's item count.
+__device__ inline void xcd_remap(int b, int grid, int per, int& item, int& slot) {
+    const int per_xcd = grid >> 3;
+    const int lin = (b & 7) * per_xcd + (b >> 3);
+    item = lin / per;
+    slot = lin - item * per;
+}
+
+inline int round_up8(int x) { return (x + 7) & ~7; }
+
+#define LS2_LAUNCH_CHECK()                                              \
+    do {                                                                \
+        if (hipGetLastError() != hipSuccess) return LS2_ERR_DEVICE;     \
+    } while (0)
+
+}  // namespace ls2

@@ -1,0 +1,109 @@
+"""Feature-map pipeline over the libls2 C ABI.
+
+``Pipeline`` owns the device buffers of one camera / scene size and chains the
+ABI calls of the inference path of Section 3 (Table 1's rendering and
+decoding stages, then the relevancy of the post-processing stage):
+project -> bin_sort -> splat_sparse -> dict_decode -> query.  PyTorch supplies
+device memory and the stream; every step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+from ._lib import LS2_BF16, LS2_F32, LS2Error
+
+_TILE = _lib.TILE
+
+
+class Pipeline:
+    def __init__(self, cam, n: int, levels: int = 1, K: int = 4, L: int = 64, D: int = 512,
+                 max_pairs: int | None = None, device="cuda", keep_keys: bool = False):
+        self.cam = _lib.make_camera(cam)
+        self.n, self.levels, self.K, self.L, self.D = n, levels, K, L, D
+        self.H, self.W = self.cam.height, self.cam.width
+        self.tiles_x = (self.W + _TILE - 1) // _TILE
+        self.tiles_y = (self.H + _TILE - 1) // _TILE
+        self.device = torch.device(device)
+        dev = self.device
+        f32, i32 = torch.float32, torch.int32
+        self.mean2d = torch.empty((n, 2), dtype=f32, device=dev)
+        self.conic = torch.empty((n, 3), dtype=f32, device=dev)
+        self.depth = torch.empty((n,), dtype=f32, device=dev)
+        self.radius = torch.empty((n,), dtype=i32, device=dev)
+        self.tiles_touched = torch.empty((n,), dtype=i32, device=dev)
+        self.tile_ranges = torch.empty((self.tiles_x * self.tiles_y, 2), dtype=i32, device=dev)
+        self.keep_keys = keep_keys
+        self.num_pairs = None
+        self._alloc_pairs(max_pairs if max_pairs is not None else max(1024, 64 * n))
+        self.coef = torch.empty((levels, self.H, self.W, L), dtype=f32, device=dev)
+        self.final_T = torch.empty((self.H, self.W), dtype=f32, device=dev)
+        self.last = torch.empty((self.H, self.W), dtype=i32, device=dev)
+        self.feat = None
+        self.relevancy = None
+
+    def _alloc_pairs(self, cap: int):
+        dev = self.device
+        self.max_pairs = int(cap)
+        self.ids = torch.empty((self.max_pairs,), dtype=torch.int32, device=dev)
+        self.keys = torch.empty((self.max_pairs,), dtype=torch.int64, device=dev) if self.keep_keys else None
+        ws = _lib.ls2_bin_sort_workspace(self.cam, self.n, self.max_pairs)
+        self.workspace = torch.empty((ws,), dtype=torch.uint8, device=dev)
+
+    # ---------------------------------------------------------------- stages
+    def project(self, means, scales, quats):
+        _lib.ls2_project(self.cam, means, scales, quats, self.mean2d, self.conic, self.depth, self.radius,
+                         self.tiles_touched)
+
+    def bin_sort(self, sync: bool = True):
+        """Bins and sorts; with sync=True grows the pair buffers if needed and
+        returns P.  With sync=False no host synchronisation happens (the
+        capacity must already suffice)."""
+        while True:
+            try:
+                P = _lib.ls2_bin_sort(self.cam, self.mean2d, self.radius, self.depth, self.max_pairs, self.keys,
+                                      self.ids, self.tile_ranges, self.workspace, sync=sync)
+                if sync:
+                    self.num_pairs = P
+                return P
+            except LS2Error as e:
+                if e.status != _lib.LS2_ERR_CAPACITY:
+                    raise
+                self._alloc_pairs(int(e.num_pairs * 1.25) + 1024)
+
+    def splat(self, opacity, topk_idx, topk_w):
+        _lib.ls2_splat_sparse(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids, self.mean2d,
+                              self.conic, opacity, topk_idx, topk_w, self.coef, self.final_T, self.last)
+
+    def decode(self, dictionary, compute=LS2_BF16, out_dtype=torch.bfloat16):
+        m = self.levels * self.H * self.W
+        if self.feat is None or self.feat.dtype != out_dtype:
+            self.feat = torch.empty((self.levels, self.H, self.W, self.D), dtype=out_dtype, device=self.device)
+        _lib.ls2_dict_decode(self.coef.view(m, self.L), dictionary, self.feat.view(m, self.D), compute)
+        return self.feat
+
+    def query(self, pos, neg, tau: float = 1.0):
+        if self.relevancy is None:
+            self.relevancy = torch.empty((self.levels, self.H, self.W), dtype=torch.float32, device=self.device)
+        _lib.ls2_query(self.feat, pos, neg, self.relevancy, tau)
+        return self.relevancy
+
+    def feature_map(self, means, scales, quats, opacity, topk_idx, topk_w, dictionary, compute=LS2_BF16,
+                    out_dtype=torch.bfloat16, sync: bool = True):
+        """One feature-map frame: project, bin and sort, splat, decode."""
+        self.project(means, scales, quats)
+        self.bin_sort(sync=sync)
+        self.splat(opacity, topk_idx, topk_w)
+        return self.decode(dictionary, compute, out_dtype)
+
+
+def to_device(scene, device="cuda"):
+    """Scene arrays (numpy, from ``gen``) as contiguous device tensors."""
+    t = lambda a, dt: torch.from_numpy(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
+    return dict(means=t(scene.means, torch.float32), scales=t(scene.scales, torch.float32),
+                quats=t(scene.quats, torch.float32), opacity=t(scene.opacity, torch.float32),
+                topk_idx=t(scene.topk_idx, torch.int32), topk_w=t(scene.topk_w, torch.float32),
+                dictionary=t(scene.dictionary, torch.float32))
+
+
+__all__ = ["Pipeline", "to_device", "LS2_F32", "LS2_BF16"]

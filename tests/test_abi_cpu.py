@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/ls2.h declares, and rejects invalid arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ls2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ls2_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_07136_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["ls2_project", "ls2_bin_sort", "ls2_splat_sparse", "ls2_dict_decode", "ls2_query"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings(L):
+    from paper_2507_07136_amd import _lib
+    assert _lib.status_string(0) == "ok"
+    assert "capacity" in _lib.status_string(-2)
+    assert _lib.version() >= 100
+
+
+def _cam(w=128, h=128):
+    import gen
+    from paper_2507_07136_amd import _lib
+    return _lib.make_camera(gen.make_camera(w, h))
+
+
+def test_argument_validation_without_device(L):
+    c = _cam()
+    V = ctypes.c_void_p
+    # negative n, bad camera
+    assert L.ls2_project(ctypes.byref(c), -1, None, None, None, None, None, None, None, None, None) == -1
+    bad = _cam()
+    bad.width = 0
+    assert L.ls2_project(ctypes.byref(bad), 1, V(16), V(16), V(16), V(16), V(16), V(16), V(16), None, None) == -1
+    # n = 0 is a no-op
+    assert L.ls2_project(ctypes.byref(c), 0, None, None, None, None, None, None, None, None, None) == 0
+    # splat: K > L, unsupported L, too many levels, null outputs
+    args = [V(16)] * 11
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 9, 8, *args) == -1
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 4, 48, *args) == -3
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 9, 64, *args) == -3
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 4, 4, 64, *args) == -3
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 3, 4, 128, *args) == -3
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 4, 64, None, *args[1:]) == -1
+    # decode: bad dtype codes, unsupported D / L
+    assert L.ls2_dict_decode(10, 64, 512, V(16), V(16), 7, 0, V(16), None) == -1
+    assert L.ls2_dict_decode(10, 64, 500, V(16), V(16), 0, 0, V(16), None) == -3
+    assert L.ls2_dict_decode(10, 48, 512, V(16), V(16), 0, 0, V(16), None) == -3
+    assert L.ls2_dict_decode(-1, 64, 512, V(16), V(16), 0, 0, V(16), None) == -1
+    assert L.ls2_dict_decode(0, 64, 512, V(16), V(16), 0, 0, V(16), None) == 0
+    # query: bad n_neg, unsupported D
+    assert L.ls2_query(10, 512, V(16), 0, V(16), 0, V(16), ctypes.c_float(1.0), V(16), None) == -1
+    assert L.ls2_query(10, 500, V(16), 0, V(16), 4, V(16), ctypes.c_float(1.0), V(16), None) == -3
+    assert L.ls2_query(10, 512, V(16), 0, V(16), 9, V(16), ctypes.c_float(1.0), V(16), None) == -3
+
+
+def test_bin_sort_workspace_and_validation(L):
+    c = _cam()
+    b = ctypes.c_size_t(0)
+    assert L.ls2_bin_sort_workspace(ctypes.byref(c), 100, 1000, ctypes.byref(b)) == 0
+    assert b.value >= 1000 * 8
+    assert L.ls2_bin_sort_workspace(ctypes.byref(c), 100, -1, ctypes.byref(b)) == -1
+    assert L.ls2_bin_sort_workspace(ctypes.byref(c), 100, 1 << 33, ctypes.byref(b)) == -3
+    P = ctypes.c_int64(0)
+    V = ctypes.c_void_p
+    # misaligned workspace, too small workspace
+    assert L.ls2_bin_sort(ctypes.byref(c), 10, V(256), V(256), V(256), 1000, None, V(256), V(256), ctypes.byref(P),
+                          V(257), b.value, None) == -1
+    assert L.ls2_bin_sort(ctypes.byref(c), 10, V(256), V(256), V(256), 1000, None, V(256), V(256), ctypes.byref(P),
+                          V(256), 16, None) == -1

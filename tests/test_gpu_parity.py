@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (float32 kernels vs float64 oracle):
+  - binning and per-tile order (stage-isolated: the oracle sorts the GPU's
+    own float32 projection): bit-exact keys, ids and ranges;
+  - projection: mean2d and depth to a few float32 ulps, conic to 1e-4
+    relative (the 2x2 inverse divides by det = ac - b^2), radius exact except
+    where 3 sqrt(lambda_max) is within 1e-4 of an integer;
+  - compositing (stage-isolated): |dW| <= 2e-5 absolute on the coefficient
+    map, excluding pixels where a decision lies near its threshold: an alpha
+    clamp / skip within 1e-5 (relative; alpha carries ~2e-6 relative error
+    from the float32 exponent), or the transmittance stop within 1e-3 (the
+    float32 transmittance multiplies factors 1 - alpha whose relative error is
+    the absolute error of alpha divided by 1 - alpha >= 0.01, up to ~2e-4 per
+    near-opaque Gaussian).  Excluded pixels are counted and must stay below
+    0.1 % of the image (or 2 pixels on tiny images);
+  - FP32 feature map: |dF| <= 1e-5 absolute (end to end);
+  - BF16 decode: within 1e-5 of the bf16-emulated oracle (float32 output) /
+    one bf16 ulp (bf16 output), and per-pixel ||dF|| / ||F|| <= 1e-2 against
+    the exact float64 product;
+  - relevancy: 1e-5 absolute (float32 features), 2e-3 (bfloat16 features,
+    whose text embeddings are rounded to bf16 for the matrix cores).
+"""
+import numpy as np
+import pytest
+import torch
+
+import gen
+from gpu_common import oracle_composite_from_gpu, oracle_lists_from_gpu, run_forward, small_scene
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-5      # alpha clamp / skip decisions
+MARGIN_T = 1e-3    # transmittance stop decision
+
+
+def _ok(margin, margin_T):
+    ok = (margin >= MARGIN) & (margin_T >= MARGIN_T)
+    assert (~ok).sum() <= max(2, 1e-3 * ok.size), "too many near-threshold pixels: %d" % (~ok).sum()
+    return ok
+
+
+def _check_lists(orc, cam, g):
+    keys, ids, ranges = oracle_lists_from_gpu(orc, cam, g)
+    assert g["P"] == len(ids)
+    assert np.array_equal(g["ranges"], ranges)
+    assert np.array_equal(g["ids"], ids)
+    if g["keys"] is not None:
+        assert np.array_equal(g["keys"], keys)
+
+
+def _check_coef(orc, cam, scene, g, atol=2e-5):
+    coef, fT, last, margin, margin_T = oracle_composite_from_gpu(orc, cam, scene, g)
+    ok = _ok(margin, margin_T)
+    err = np.abs(g["coef"] - coef).max(axis=(0, 3))
+    print("coef max err (clean px) %.3e, near-threshold px %d" % (err[ok].max() if ok.any() else 0, (~ok).sum()))
+    assert err[ok].max() <= atol
+    assert np.abs(g["final_T"] - fT)[ok].max() <= atol
+    assert np.array_equal(g["last"][ok], last[ok])
+    return coef, fT, last, margin, margin_T
+
+
+@pytest.fixture(scope="module")
+def c1(orc):
+    scene, cam = gen.config_scene("c1")
+    g = run_forward(cam, scene)
+    return scene, cam, g
+
+
+def test_project_parity_c1(orc, c1):
+    scene, cam, g = c1
+    pr = orc.project(cam, scene.means, scene.scales, scene.quats)
+    near = np.abs(pr["extent"] - np.round(pr["extent"])) < 1e-4
+    same_r = (g["radius"] == pr["radius"]) | near
+    assert same_r.all()
+    vis = (pr["radius"] > 0) & (g["radius"] > 0)
+    assert vis.sum() > 1900
+    np.testing.assert_allclose(g["mean2d"][vis], pr["mean2d"][vis], rtol=2e-6, atol=2e-5)
+    np.testing.assert_allclose(g["depth"][vis], pr["depth"][vis], rtol=1e-6)
+    np.testing.assert_allclose(g["conic"][vis], pr["conic"][vis], rtol=1e-4, atol=1e-6 * np.abs(pr["conic"]).max())
+    exact = vis & ~near
+    assert np.array_equal(g["touched"][exact], pr["touched"][exact])
+
+
+def test_bin_sort_bit_exact_c1(orc, c1):
+    scene, cam, g = c1
+    _check_lists(orc, cam, g)
+
+
+def test_splat_parity_c1(orc, c1):
+    scene, cam, g = c1
+    _check_coef(orc, cam, scene, g)
+
+
+def test_feature_map_end_to_end_c1(orc, c1):
+    """Full FP64 oracle (its own projection, lists and compositing) against the
+    GPU FP32 path: the 512-d feature map within 1e-5 absolute."""
+    scene, cam, g = c1
+    pr = orc.project(cam, scene.means, scene.scales, scene.quats)
+    keys, ids, ranges = orc.tile_lists(cam, pr["mean2d"].astype(np.float32), pr["radius"],
+                                       pr["depth"].astype(np.float32))
+    coef, fT, last, margin, margin_T = orc.composite(cam, ranges, ids, pr["mean2d"], pr["conic"], scene.opacity,
+                                                     scene.topk_idx, scene.topk_w, scene.L, with_margin_T=True)
+    F = orc.decode(coef, scene.dictionary)
+    ok = _ok(margin, margin_T)
+    err = np.abs(g["feat"] - F).max(axis=(0, 3))
+    print("end-to-end feature max err %.3e (ref max %.3e)" % (err[ok].max(), np.abs(F).max()))
+    assert err[ok].max() <= 1e-5
+
+
+def test_decode_f32_parity(orc, c1):
+    scene, cam, g = c1
+    F = orc.decode(g["coef"].astype(np.float64), scene.dictionary)
+    err = np.abs(g["feat"] - F).max()
+    print("decode f32 max err %.3e" % err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("L,D", [(64, 512), (32, 256), (128, 1024), (64, 128)])
+@pytest.mark.parametrize("out_bf16", [False, True])
+def test_decode_bf16_parity(orc, L, D, out_bf16):
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(L + D)
+    m = 32 * 37 + 13  # ragged: not a multiple of the 32-row block
+    W = (rng.random((m, L)) * (rng.random((m, 1)) < 0.9)).astype(np.float32)
+    S = rng.normal(size=(L, D))
+    S = (S / np.linalg.norm(S, axis=1, keepdims=True)).astype(np.float32)
+    Wt, St = torch.from_numpy(W).cuda(), torch.from_numpy(S).cuda()
+    out = torch.empty((m, D), dtype=torch.bfloat16 if out_bf16 else torch.float32, device="cuda")
+    ls2.ls2_dict_decode(Wt, St, out, compute=ls2.LS2_BF16)
+    got = out.float().cpu().numpy()
+    emu = orc.decode_bf16(W, S, round_out=out_bf16)
+    # float32 accumulation of L exact bf16 products: |error| <= L 2^-24 sum|terms|
+    acc_bound = 1e-5 * orc.decode(np.abs(orc.round_bf16(W)), np.abs(orc.round_bf16(S))) + 1e-12
+    if out_bf16:
+        # the float32 accumulator may sit on the other side of a bf16 rounding
+        # boundary than the exact sum: one bf16 ulp (<= 2^-7 relative) plus the
+        # accumulation error
+        assert np.all(np.abs(got - emu) <= 2.0 ** -7 * np.maximum(np.abs(emu), np.abs(got)) + acc_bound)
+    else:
+        assert np.all(np.abs(got - emu) <= acc_bound)
+    exact = orc.decode(W.astype(np.float64), S)
+    nrm = np.linalg.norm(exact, axis=1)
+    rel = np.linalg.norm(got - exact, axis=1)[nrm > 1e-6] / nrm[nrm > 1e-6]
+    print("bf16 decode L=%d D=%d rel err max %.3e" % (L, D, rel.max()))
+    assert rel.max() <= 1e-2
+
+
+@pytest.mark.parametrize("L,D", [(64, 512), (32, 128), (128, 1024)])
+def test_decode_f32_shapes(orc, L, D):
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(3 * L + D)
+    m = 32 * 11 + 7
+    W = rng.random((m, L)).astype(np.float32)
+    S = rng.normal(size=(L, D)).astype(np.float32)
+    out = torch.empty((m, D), dtype=torch.float32, device="cuda")
+    ls2.ls2_dict_decode(torch.from_numpy(W).cuda(), torch.from_numpy(S).cuda(), out, compute=ls2.LS2_F32)
+    ref = orc.decode(W.astype(np.float64), S.astype(np.float64))
+    bound = 4e-7 * orc.decode(np.abs(W), np.abs(S)) * L ** 0.5 + 1e-7
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("D,n_neg", [(512, 4), (256, 1), (1024, 8), (64, 3)])
+def test_query_parity(orc, dtype, D, n_neg):
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(D + n_neg)
+    m = 16 * 53 + 5
+    F = (rng.normal(size=(m, D)) * 0.05).astype(np.float32)
+    F[3] = 0.0  # zero feature scores 0.5
+    pos, neg = gen.make_text(5, D=D, n_neg=n_neg)
+    F[4] = 2.0 * pos  # parallel to the query
+    Ft = torch.from_numpy(F).cuda().to(dtype)
+    out = torch.empty(m, dtype=torch.float32, device="cuda")
+    for tau in (1.0, 10.0):
+        ls2.ls2_query(Ft, torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda(), out, tau)
+        ref = orc.query(Ft.float().cpu().numpy().astype(np.float64), pos, neg, tau)
+        err = np.abs(out.cpu().numpy() - ref).max()
+        print("query %s D=%d tau=%g max err %.3e" % (dtype, D, tau, err))
+        assert err <= (1e-5 if dtype == torch.float32 else 2e-3) * max(1.0, tau / 4)
+        assert out[3].item() == 0.5
+
+
+def test_query_end_to_end_c1(orc, c1):
+    import paper_2507_07136_amd as ls2
+    scene, cam, g = c1
+    pos, neg = gen.make_text(9)
+    pipe = g["pipe"]
+    r = pipe.query(torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda()).cpu().numpy()
+    ref = orc.query(orc.decode(g["coef"].astype(np.float64), scene.dictionary), pos, neg)
+    assert np.abs(r - ref).max() <= 1e-5
+
+
+def test_forward_deterministic(c1):
+    scene, cam, g = c1
+    g2 = run_forward(cam, scene)
+    for k in ("mean2d", "conic", "radius", "ranges", "ids", "coef", "final_T", "last", "feat"):
+        assert np.array_equal(g[k], g2[k]), k
+
+
+# ---------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("w,h", [(100, 75), (16, 16), (33, 17)])
+def test_ragged_image(orc, w, h):
+    scene, cam = small_scene(2024 + w, 700, w, h)
+    g = run_forward(cam, scene)
+    _check_lists(orc, cam, g)
+    _check_coef(orc, cam, scene, g)
+
+
+@pytest.mark.parametrize("L,K,levels", [(64, 4, 3), (128, 8, 1), (32, 2, 2), (128, 4, 1), (64, 8, 1), (64, 1, 1),
+                                        (32, 8, 3)])
+def test_shapes_levels(orc, L, K, levels):
+    scene, cam = small_scene(7 + L + K + levels, 900, 96, 80, L=L, K=K, levels=levels, D=128)
+    g = run_forward(cam, scene)
+    _check_lists(orc, cam, g)
+    _check_coef(orc, cam, scene, g)
+
+
+def test_duplicate_indices_are_additive(orc):
+    scene, cam = small_scene(99, 600, 64, 64)
+    scene.topk_idx[:, :, 1] = scene.topk_idx[:, :, 0]
+    g = run_forward(cam, scene)
+    _check_coef(orc, cam, scene, g)
+
+
+def test_empty_and_culled(orc):
+    # no Gaussians at all
+    scene, cam = small_scene(5, 0, 64, 48)
+    g = run_forward(cam, scene)
+    assert g["P"] == 0 and np.all(g["coef"] == 0) and np.all(g["final_T"] == 1) and np.all(g["last"] == 0)
+    # every Gaussian behind the camera or NaN
+    scene, cam = small_scene(6, 300, 64, 48)
+    scene.means[:150, 2] = -5.0
+    scene.means[150:, 0] = np.nan
+    g = run_forward(cam, scene)
+    assert g["P"] == 0 and np.all(g["radius"] == 0) and np.all(g["coef"] == 0)
+
+
+def test_capacity_overflow(orc):
+    import paper_2507_07136_amd as ls2
+    scene, cam = gen.config_scene("c1")
+    t = ls2.to_device(scene)
+    pipe = ls2.Pipeline(cam, scene.n, max_pairs=100)
+    pipe.project(t["means"], t["scales"], t["quats"])
+    with pytest.raises(ls2.LS2Error) as e:
+        ls2.ls2_bin_sort(pipe.cam, pipe.mean2d, pipe.radius, pipe.depth, 100, None, pipe.ids, pipe.tile_ranges,
+                         pipe.workspace, sync=True)
+    assert e.value.status == ls2.LS2_ERR_CAPACITY and e.value.num_pairs > 100
+    # without sync: no error, every range empty, count readable afterwards
+    ls2.ls2_bin_sort(pipe.cam, pipe.mean2d, pipe.radius, pipe.depth, 100, None, pipe.ids, pipe.tile_ranges,
+                     pipe.workspace, sync=False)
+    assert ls2.ls2_bin_sort_count(pipe.workspace) == e.value.num_pairs
+    assert int(pipe.tile_ranges.abs().sum().item()) == 0
+    # the pipeline grows its buffers and retries
+    assert pipe.bin_sort(sync=True) == e.value.num_pairs
+
+
+def test_long_tile_lists(orc):
+    """Thousands of Gaussians piled onto one tile exercise the large LDS sort
+    class and the global-memory fallback."""
+    rng = np.random.default_rng(12)
+    n = 40000
+    scene = gen.make_scene(12, n, D=128)
+    scene.means[:] = rng.normal(0, 0.01, (n, 3)).astype(np.float32)
+    scene.scales[:] = 0.004
+    cam = gen.make_camera(64, 64)
+    g = run_forward(cam, scene)
+    lens = g["ranges"][:, 1] - g["ranges"][:, 0]
+    assert lens.max() > 16384
+    _check_lists(orc, cam, g)
+    _check_coef(orc, cam, scene, g)
+
+
+# ---------------------------------------------------------------- full size, sampled
+@pytest.mark.slow
+def test_c2_full_size_sampled(orc):
+    """1440x1080, 300k Gaussians (the benchmark workload): binning bit-exact
+    at full size; compositing, decode and relevancy checked on sampled pixels."""
+    scene, cam = gen.config_scene("c2")
+    g = run_forward(cam, scene, keep_keys=True)
+    print("P =", g["P"])
+    _check_lists(orc, cam, g)
+    rng = np.random.default_rng(0)
+    pix = rng.choice(cam.width * cam.height, 4000, replace=False)
+    coef, fT, last, margin, margin_T = orc.composite_pixels(
+        cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64), g["conic"].astype(np.float64), scene.opacity,
+        scene.topk_idx, scene.topk_w, scene.L, pix, with_margin_T=True)
+    ok = _ok(margin, margin_T)
+    gc = g["coef"][0].reshape(-1, scene.L)[pix]
+    assert np.abs(gc - coef[:, 0])[ok].max() <= 2e-5
+    F = orc.decode(gc.astype(np.float64), scene.dictionary)
+    assert np.abs(g["feat"][0].reshape(-1, scene.D)[pix] - F).max() <= 1e-5

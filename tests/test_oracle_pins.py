@@ -199,8 +199,8 @@ def test_tile_lists_match_lexsort(orc):
     assert np.array_equal(keys, exp_keys)
     counts = np.bincount(tiles, minlength=cam.tiles_x * cam.tiles_y)
     assert np.array_equal(ranges[:, 1] - ranges[:, 0], counts)
-    nz = counts > 0
-    assert np.array_equal(ranges[nz, 0], np.concatenate([[0], np.cumsum(counts)[:-1]])[nz])
+    assert np.array_equal(ranges[:, 0], np.concatenate([[0], np.cumsum(counts)[:-1]]))
+    assert np.array_equal(ranges[:, 1], np.cumsum(counts))
 
 
 def test_tile_lists_capacity_error(orc):
