@@ -300,7 +300,11 @@ int orc_tile_lists(const double* cam_arr, int n, const float* mean2d, const int3
 /* contributing entry relative to the tile start (0 if none),          */
 /* *margin = smallest relative distance of an alpha decision (clamp,    */
 /* skip) to its threshold, *margin_T = the same for the stop decision   */
-/* (transmittance against 1e-4).                                        */
+/* (transmittance against 1e-4) divided by the transmittance's condition */
+/* number c = 1 + sum (alpha_j / (1 - alpha_j) + 0.02) over the Gaussians */
+/* blended so far and the current one: a relative perturbation e of     */
+/* every alpha moves T by about e (c - 1) relatively (the 0.02 per term */
+/* covers the rounding of each product).                                */
 /* ------------------------------------------------------------------ */
 static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, const uint32_t* ids,
                       const double* mean2d, const double* conic, const double* opacity,
@@ -310,6 +314,7 @@ static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, cons
     int cnt = 0;
     int32_t last = 0;
     double mg = INFINITY, mgT = INFINITY;
+    double cond = 1.0;
     for (uint32_t pos = start; pos < end; ++pos) {
         uint32_t i = ids[pos];
         double dx = mean2d[2 * i] - pxc;
@@ -325,9 +330,10 @@ static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, cons
         if (m2 < mg) mg = m2;
         if (alpha < ALPHA_MIN) continue;
         double testT = T * (1.0 - alpha);
-        double m3 = fabs(testT - T_MIN) / T_MIN;
+        double m3 = fabs(testT - T_MIN) / T_MIN / (cond + alpha / (1.0 - alpha) + 0.02);
         if (m3 < mgT) mgT = m3;
         if (testT < T_MIN) break;
+        cond += alpha / (1.0 - alpha) + 0.02;
         if (pos_out) pos_out[cnt] = (int32_t)(pos - start);
         if (e_out) e_out[cnt] = alpha * T;
         if (T_before_out) T_before_out[cnt] = T;

@@ -2,18 +2,26 @@
 // (float32 depth, id) inside each tile -- the "ordered Gaussian points within
 // a tile" that Eq. 3 composites.
 //
-// Pipeline (all on `stream`):
-//   1. k_count   : per Gaussian, +1/-1 at the four corners of its tile
-//                  rectangle in a (ty+1) x (tx+1) difference grid (4 atomics
-//                  per Gaussian instead of one per touched tile).
-//   2. k_scan    : one workgroup: 2D prefix sums turn the difference grid into
-//                  per-tile counts, then an exclusive scan gives tile ranges
-//                  and per-tile cursors, and the pair total P.
-//   3. k_emit    : per Gaussian, claim a slot in each touched tile's bucket and
-//                  store the 64-bit sort key (depth bits << 32 | id).
-//   4. k_sort_*  : one workgroup per tile sorts its bucket in LDS (bitonic
-//                  network over unique 64-bit keys, so the order is exact and
-//                  independent of the emit order) and writes ids / keys.
+// The P (tile, Gaussian) pairs (about 33 per Gaussian at 1440x1080) are never
+// sorted or counted with atomics one by one.  The expensive part works on
+// superblocks of S x S tiles (S = 4: 64 x 64 pixels), which a Gaussian touches
+// only 1-4 of:
+//   1. k_sb_count : per Gaussian, its tile rectangle (stored as 4 x u16) and
+//                   +1 for every superblock it touches, aggregated per
+//                   workgroup in an LDS histogram (one global atomic per
+//                   workgroup and superblock); also the exact pair count P;
+//   2. k_sb_scan  : one workgroup: superblock bucket offsets;
+//   3. k_sb_emit  : per Gaussian, the 64-bit key (depth bits << 32 | id) into
+//                   each touched superblock's bucket (LDS histogram again, one
+//                   reserving atomic per workgroup and superblock, LDS cursors);
+//   4. k_sb_sort  : one workgroup per superblock sorts its bucket in LDS and
+//                   counts, for each of its S x S tiles, the entries whose
+//                   rectangle covers the tile;
+//   5. k_tile_scan: one workgroup: tile ranges (row-major) and P;
+//   6. k_tile_fill: each tile's list is the ordered subsequence of its
+//                   superblock's sorted bucket whose rectangles cover the tile:
+//                   an order-preserving ballot compaction, one wave per tile,
+//                   so every tile list comes out already in (depth, id) order.
 #include "ls2_internal.h"
 
 namespace ls2 {
@@ -21,140 +29,200 @@ namespace ls2 {
 namespace {
 
 struct Meta {
-    long long P;          // total pairs
-    long long overflow;   // 1 if P > max_pairs
+    long long P;            // total (tile, Gaussian) pairs
+    long long overflow;     // 1 if P > max_pairs
+    long long sb_total;     // total (superblock, Gaussian) entries
+    long long sb_overflow;  // 1 if sb_total > max_pairs
+    unsigned long long P_rect;  // sum of tile-rectangle areas (= P), from pass 1
+    long long pad[3];
 };
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxSB = 4096;  // superblocks held in an LDS histogram
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
-struct Layout {
-    size_t meta, grid, cursor, bucket, total;
+struct Geo {
+    int S, sbx, sby, nsb;
 };
 
-inline Layout layout(const CamK& k, int64_t max_pairs) {
+// Superblock edge (in tiles): the smallest power of two >= 4 that keeps the
+// superblock count within the LDS histogram.
+inline Geo geo(const CamK& k) {
+    Geo g;
+    g.S = 4;
+    while (((k.tx + g.S - 1) / g.S) * ((k.ty + g.S - 1) / g.S) > kMaxSB) g.S *= 2;
+    g.sbx = (k.tx + g.S - 1) / g.S;
+    g.sby = (k.ty + g.S - 1) / g.S;
+    g.nsb = g.sbx * g.sby;
+    return g;
+}
+
+struct Layout {
+    size_t meta, sb_count, tile_count, sb_start, sb_cursor, rect, pool, total;
+};
+
+// meta, sb_count and tile_count come first: they are zeroed every call.
+inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
+    const Geo g = geo(k);
     Layout l;
     size_t off = 0;
     l.meta = off; off = align_up(off + sizeof(Meta));
-    l.grid = off; off = align_up(off + sizeof(int) * (size_t)(k.tx + 1) * (k.ty + 1));
-    l.cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)k.tx * k.ty);
-    l.bucket = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
+    l.sb_count = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.tile_count = off; off = align_up(off + sizeof(unsigned) * (size_t)k.tx * k.ty);
+    l.sb_start = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.sb_cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.rect = off; off = align_up(off + sizeof(ushort4) * (size_t)(n > 0 ? n : 1));
+    l.pool = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
     l.total = off;
     return l;
 }
 
 }  // namespace
 
-__global__ void k_fill_zero(int* __restrict__ p, long long n) {
+struct BinArgs {
+    CamK cam;
+    int n, S, sbx, nsb;
+    long long max_pairs;
+    const float* mean2d;
+    const int* radius;
+    const float* depth;
+    Meta* meta;
+    unsigned* sb_count;
+    unsigned* sb_start;
+    unsigned* sb_cursor;
+    unsigned* tile_count;
+    ushort4* rect;
+    unsigned long long* pool;
+    unsigned* ranges;
+    unsigned* ids;
+    unsigned long long* keys;
+};
+
+__global__ void k_bin_zero(unsigned* __restrict__ p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = 0u;
 }
 
-__global__ __launch_bounds__(256) void k_count(CamK cam, int n, const float* __restrict__ mean2d,
-                                               const int* __restrict__ radius, int* __restrict__ grid) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int r = radius[i];
-    if (r <= 0) return;
-    const float2 m = reinterpret_cast<const float2*>(mean2d)[i];
-    int x0, y0, x1, y1;
-    if (!tile_rect(m.x, m.y, r, cam.tx, cam.ty, x0, y0, x1, y1)) return;
-    const int w = cam.tx + 1;
-    atomicAdd(&grid[y0 * w + x0], 1);
-    atomicAdd(&grid[y0 * w + x1 + 1], -1);
-    atomicAdd(&grid[(y1 + 1) * w + x0], -1);
-    atomicAdd(&grid[(y1 + 1) * w + x1 + 1], 1);
+// Superblock rectangle of Gaussian i; optionally stores its tile rectangle
+// (x0, y0, x1, y1), or an empty one (0xffff, 0xffff, 0, 0) if culled.
+__device__ __forceinline__ bool sb_rect_of(const BinArgs& a, int i, int& sx0, int& sy0, int& sx1, int& sy1,
+                                           int& area, bool store) {
+    bool vis = false;
+    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+    const int r = a.radius[i];
+    if (r > 0) {
+        const float2 m = reinterpret_cast<const float2*>(a.mean2d)[i];
+        vis = tile_rect(m.x, m.y, r, a.cam.tx, a.cam.ty, x0, y0, x1, y1);
+    }
+    if (store)
+        a.rect[i] = vis ? make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1)
+                        : make_ushort4(0xffff, 0xffff, 0, 0);
+    if (!vis) return false;
+    area = (x1 - x0 + 1) * (y1 - y0 + 1);
+    const int sh = __builtin_ctz((unsigned)a.S);
+    sx0 = x0 >> sh; sy0 = y0 >> sh; sx1 = x1 >> sh; sy1 = y1 >> sh;
+    return true;
 }
 
-// Single workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(CamK cam, int* __restrict__ grid, unsigned* __restrict__ cursor,
-                                               unsigned* __restrict__ ranges, Meta* __restrict__ meta,
-                                               long long max_pairs) {
-    const int tid = threadIdx.x;
-    const int w = cam.tx + 1;
-    // row prefix sums
-    for (int y = tid; y < cam.ty; y += blockDim.x) {
-        int s = 0;
-        for (int x = 0; x < cam.tx; ++x) {
-            s += grid[y * w + x];
-            grid[y * w + x] = s;
+constexpr int kBinThreads = 1024;
+constexpr int kBinPerThread = 4;  // Gaussians per thread in the histogram passes
+
+__global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
+    __shared__ unsigned hist[kMaxSB];
+    __shared__ unsigned long long area_sum;
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
+    if (threadIdx.x == 0) area_sum = 0ull;
+    __syncthreads();
+    const int base = blockIdx.x * kBinThreads * kBinPerThread;
+    unsigned my_area = 0;
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int i = base + q * kBinThreads + threadIdx.x;
+        int sx0, sy0, sx1, sy1, area;
+        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, area, true)) {
+            my_area += (unsigned)area;
+            for (int sy = sy0; sy <= sy1; ++sy)
+                for (int sx = sx0; sx <= sx1; ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
         }
     }
+    if (my_area) atomicAdd(&area_sum, (unsigned long long)my_area);
     __syncthreads();
-    // column prefix sums -> per-tile counts
-    for (int x = tid; x < cam.tx; x += blockDim.x) {
-        int s = 0;
-        for (int y = 0; y < cam.ty; ++y) {
-            s += grid[y * w + x];
-            grid[y * w + x] = s;
-        }
-    }
-    __syncthreads();
-    // exclusive scan over tiles (row-major), 1024 at a time
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads)
+        if (hist[s]) atomicAdd(&a.sb_count[s], hist[s]);
+    if (threadIdx.x == 0 && area_sum) atomicAdd(&a.meta->P_rect, area_sum);
+}
+
+// Exclusive scan over `n` counts by one workgroup of 1024 threads, 1024 at a
+// time with a running carry.  Writes start (and, if `end` is non-null, end)
+// offsets; returns the total.
+__device__ long long block_scan(const unsigned* in, unsigned* start, int sstride, unsigned* end, int n) {
     __shared__ long long part[1024];
-    __shared__ long long carry_s;
-    if (tid == 0) carry_s = 0;
+    __shared__ long long carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
     __syncthreads();
-    const int ntiles = cam.tx * cam.ty;
-    for (int base = 0; base < ntiles; base += 1024) {
+    for (int base = 0; base < n; base += 1024) {
         const int t = base + tid;
-        long long c = 0;
-        if (t < ntiles) c = grid[(t / cam.tx) * w + (t % cam.tx)];
+        const long long c = t < n ? (long long)in[t] : 0;
         part[tid] = c;
         __syncthreads();
         for (int off = 1; off < 1024; off <<= 1) {
-            long long v = tid >= off ? part[tid - off] : 0;
+            const long long v = tid >= off ? part[tid - off] : 0;
             __syncthreads();
             part[tid] += v;
             __syncthreads();
         }
-        const long long incl = part[tid] + carry_s;
-        if (t < ntiles) {
-            // provisional: start in ranges[2t], count in ranges[2t+1]
-            ranges[2 * t] = (unsigned)(incl - c);
-            ranges[2 * t + 1] = (unsigned)c;
+        const long long incl = part[tid] + carry;
+        if (t < n) {
+            start[(size_t)t * sstride] = (unsigned)(incl - c);
+            if (end) end[(size_t)t * sstride] = (unsigned)incl;
         }
         __syncthreads();
-        if (tid == 1023) carry_s = incl;
+        if (tid == 1023) carry = incl;
         __syncthreads();
     }
-    const long long P = carry_s;
-    const bool overflow = P > max_pairs;
-    for (int t = tid; t < ntiles; t += blockDim.x) {
-        const unsigned start = ranges[2 * t], cnt = ranges[2 * t + 1];
-        if (overflow) {
-            ranges[2 * t] = 0;
-            ranges[2 * t + 1] = 0;
-        } else {
-            ranges[2 * t + 1] = start + cnt;
-            cursor[t] = start;
-        }
-    }
-    if (tid == 0) {
-        meta->P = P;
-        meta->overflow = overflow ? 1 : 0;
+    return carry;
+}
+
+__global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
+    const long long total = block_scan(a.sb_count, a.sb_start, 1, nullptr, a.nsb);
+    const bool over = total > a.max_pairs;
+    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) a.sb_cursor[s] = a.sb_start[s];
+    if (threadIdx.x == 0) {
+        a.meta->sb_total = total;
+        a.meta->sb_overflow = over ? 1 : 0;
     }
 }
 
-__global__ __launch_bounds__(256) void k_emit(CamK cam, int n, const float* __restrict__ mean2d,
-                                              const int* __restrict__ radius, const float* __restrict__ depth,
-                                              unsigned* __restrict__ cursor,
-                                              unsigned long long* __restrict__ bucket,
-                                              const Meta* __restrict__ meta) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (meta->overflow) return;
-    const int r = radius[i];
-    if (r <= 0) return;
-    const float2 m = reinterpret_cast<const float2*>(mean2d)[i];
-    int x0, y0, x1, y1;
-    if (!tile_rect(m.x, m.y, r, cam.tx, cam.ty, x0, y0, x1, y1)) return;
-    const unsigned long long key = ((unsigned long long)__float_as_uint(depth[i]) << 32) | (unsigned)i;
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) {
-            const unsigned pos = atomicAdd(&cursor[ty * cam.tx + tx], 1u);
-            bucket[pos] = key;
+__global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
+    __shared__ unsigned hist[kMaxSB];
+    if (a.meta->sb_overflow) return;
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
+    __syncthreads();
+    const int base = blockIdx.x * kBinThreads * kBinPerThread;
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int i = base + q * kBinThreads + threadIdx.x;
+        int sx0, sy0, sx1, sy1, area;
+        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, area, false))
+            for (int sy = sy0; sy <= sy1; ++sy)
+                for (int sx = sx0; sx <= sx1; ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
+    }
+    __syncthreads();
+    // reserve this workgroup's range in every touched bucket; hist becomes the cursor
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads)
+        if (hist[s]) hist[s] = atomicAdd(&a.sb_cursor[s], hist[s]);
+    __syncthreads();
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int i = base + q * kBinThreads + threadIdx.x;
+        int sx0, sy0, sx1, sy1, area;
+        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, area, false)) {
+            const unsigned long long key = ((unsigned long long)__float_as_uint(a.depth[i]) << 32) | (unsigned)i;
+            for (int sy = sy0; sy <= sy1; ++sy)
+                for (int sx = sx0; sx <= sx1; ++sx) {
+                    const unsigned pos = atomicAdd(&hist[sy * a.sbx + sx], 1u);
+                    a.pool[pos] = key;
+                }
         }
+    }
 }
 
 // Sorting network: bitonic sort in its all-ascending ("flip") form.  Stage k
@@ -164,59 +232,8 @@ __global__ __launch_bounds__(256) void k_emit(CamK cam, int n, const float* __re
 // input to a power of two with +infinity keys is equivalent to skipping every
 // comparator whose partner lies at or beyond `cnt`: such a comparator would
 // never move anything.  No padding is stored.
-
-// One tile's keys in LDS.  Handles tiles with lo < count <= CAP.
-template <int CAP, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_sort_lds(int ntiles, const unsigned* __restrict__ ranges,
-                                                      const unsigned long long* __restrict__ bucket,
-                                                      unsigned* __restrict__ ids,
-                                                      unsigned long long* __restrict__ keys, int lo) {
-    __shared__ unsigned long long s[CAP];
-    const int t = blockIdx.x;
-    if (t >= ntiles) return;
-    const unsigned start = ranges[2 * t], end = ranges[2 * t + 1];
-    const int cnt = (int)(end - start);
-    if (cnt <= lo || cnt > CAP) return;
-    int m = 1;
-    while (m < cnt) m <<= 1;
-    for (int i = threadIdx.x; i < cnt; i += THREADS) s[i] = bucket[start + i];
-    __syncthreads();
-    for (int k = 2; k <= m; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const int mask = (j == (k >> 1)) ? (k - 1) : j;  // flip first, then half-cleaners
-            for (int i = threadIdx.x; i < m; i += THREADS) {
-                const int p = i ^ mask;
-                if (p > i && p < cnt) {
-                    const unsigned long long a = s[i], b = s[p];
-                    if (a > b) {
-                        s[i] = b;
-                        s[p] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    const unsigned long long tk = (unsigned long long)t << 32;
-    for (int i = threadIdx.x; i < cnt; i += THREADS) {
-        const unsigned long long v = s[i];
-        ids[start + i] = (unsigned)(v & 0xffffffffull);
-        if (keys) keys[start + i] = tk | (v >> 32);
-    }
-}
-
-// Tiles longer than the LDS capacity: the same network in global memory, in
-// place in the bucket.
-__global__ __launch_bounds__(1024) void k_sort_global(int ntiles, const unsigned* __restrict__ ranges,
-                                                      unsigned long long* __restrict__ bucket,
-                                                      unsigned* __restrict__ ids,
-                                                      unsigned long long* __restrict__ keys, int lo) {
-    const int t = blockIdx.x;
-    if (t >= ntiles) return;
-    const unsigned start = ranges[2 * t], end = ranges[2 * t + 1];
-    const int cnt = (int)(end - start);
-    if (cnt <= lo) return;
-    unsigned long long* s = bucket + start;
+template <typename Ptr>
+__device__ void flip_bitonic(Ptr s, int cnt) {
     int m = 1;
     while (m < cnt) m <<= 1;
     for (int k = 2; k <= m; k <<= 1) {
@@ -225,10 +242,10 @@ __global__ __launch_bounds__(1024) void k_sort_global(int ntiles, const unsigned
             for (int i = threadIdx.x; i < m; i += blockDim.x) {
                 const int p = i ^ mask;
                 if (p > i && p < cnt) {
-                    const unsigned long long a = s[i], b = s[p];
-                    if (a > b) {
-                        s[i] = b;
-                        s[p] = a;
+                    const unsigned long long x = s[i], y = s[p];
+                    if (x > y) {
+                        s[i] = y;
+                        s[p] = x;
                     }
                 }
             }
@@ -236,11 +253,116 @@ __global__ __launch_bounds__(1024) void k_sort_global(int ntiles, const unsigned
             __syncthreads();
         }
     }
+}
+
+// Per-tile counts of one superblock's entries (tcnt: S*S LDS counters).
+__device__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long long* s, int cnt, unsigned* tcnt) {
+    const int S = a.S;
+    const int sx = sb % a.sbx, sy = sb / a.sbx;
+    const int tx0 = sx * S, ty0 = sy * S;
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) tcnt[t] = 0u;
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const unsigned id = (unsigned)(s[e] & 0xffffffffull);
+        const ushort4 r = a.rect[id];
+        const int x0 = max((int)r.x, tx0), x1 = min((int)r.z, tx0 + S - 1);
+        const int y0 = max((int)r.y, ty0), y1 = min((int)r.w, ty0 + S - 1);
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) atomicAdd(&tcnt[(y - ty0) * S + (x - tx0)], 1u);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+        const int x = tx0 + t % S, y = ty0 + t / S;
+        if (x < a.cam.tx && y < a.cam.ty) a.tile_count[y * a.cam.tx + x] = tcnt[t];
+    }
+}
+
+constexpr int kMaxS2 = 32 * 32;  // tile counters per superblock (S <= 32)
+
+// Superblocks with lo < count <= CAP: sort in LDS, write back, count tiles.
+template <int CAP, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_sb_sort_lds(BinArgs a, int lo) {
+    __shared__ unsigned long long s[CAP];
+    __shared__ unsigned tcnt[kMaxS2];
+    const int sb = blockIdx.x;
+    if (sb >= a.nsb || a.meta->sb_overflow) return;
+    const int cnt = (int)a.sb_count[sb];
+    if (cnt <= lo || cnt > CAP) return;
+    unsigned long long* g = a.pool + a.sb_start[sb];
+    for (int i = threadIdx.x; i < cnt; i += THREADS) s[i] = g[i];
+    __syncthreads();
+    flip_bitonic(s, cnt);
+    for (int i = threadIdx.x; i < cnt; i += THREADS) g[i] = s[i];
+    count_sb_tiles(a, sb, s, cnt, tcnt);
+}
+
+// Superblocks larger than the LDS capacity: same network in global memory.
+__global__ __launch_bounds__(1024) void k_sb_sort_global(BinArgs a, int lo) {
+    __shared__ unsigned tcnt[kMaxS2];
+    const int sb = blockIdx.x;
+    if (sb >= a.nsb || a.meta->sb_overflow) return;
+    const int cnt = (int)a.sb_count[sb];
+    if (cnt <= lo) return;
+    unsigned long long* g = a.pool + a.sb_start[sb];
+    flip_bitonic(g, cnt);
+    count_sb_tiles(a, sb, g, cnt, tcnt);
+}
+
+__global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
+    const int ntiles = a.cam.tx * a.cam.ty;
+    if (a.meta->sb_overflow) {
+        // the superblock buckets overflowed, hence P > max_pairs too: clear
+        // every range; P itself is known from the rectangle areas
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) a.ranges[2 * t] = a.ranges[2 * t + 1] = 0u;
+        if (threadIdx.x == 0) {
+            a.meta->P = (long long)a.meta->P_rect;
+            a.meta->overflow = 1;
+        }
+        return;
+    }
+    const long long total = block_scan(a.tile_count, a.ranges, 2, a.ranges + 1, ntiles);
+    const bool over = total > a.max_pairs;
+    __syncthreads();
+    if (over)
+        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) a.ranges[2 * t] = a.ranges[2 * t + 1] = 0u;
+    if (threadIdx.x == 0) {
+        a.meta->P = total;
+        a.meta->overflow = over ? 1 : 0;
+    }
+}
+
+// One wave per tile: ordered compaction of the superblock's sorted bucket.
+__global__ __launch_bounds__(64) void k_tile_fill(BinArgs a) {
+    const int ntiles = a.cam.tx * a.cam.ty;
+    int t, slot;
+    xcd_remap(blockIdx.x, gridDim.x, 1, t, slot);
+    if (t >= ntiles || a.meta->overflow) return;
+    const int tx = t % a.cam.tx, ty = t / a.cam.tx;
+    const int sh = __builtin_ctz((unsigned)a.S);
+    const int sb = (ty >> sh) * a.sbx + (tx >> sh);
+    const unsigned long long* list = a.pool + a.sb_start[sb];
+    const int cnt = (int)a.sb_count[sb];
+    unsigned out = a.ranges[2 * t];
+    const unsigned end = a.ranges[2 * t + 1];
+    const int lane = threadIdx.x;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const unsigned long long tk = (unsigned long long)t << 32;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const unsigned long long v = s[i];
-        ids[start + i] = (unsigned)(v & 0xffffffffull);
-        if (keys) keys[start + i] = tk | (v >> 32);
+    for (int b = 0; b < cnt; b += 64) {
+        const int e = b + lane;
+        bool hit = false;
+        unsigned long long key = 0;
+        if (e < cnt) {
+            key = list[e];
+            const ushort4 r = a.rect[(unsigned)(key & 0xffffffffull)];
+            hit = tx >= (int)r.x && tx <= (int)r.z && ty >= (int)r.y && ty <= (int)r.w;
+        }
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+        const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
+        if (hit && pos < end) {  // the counts of k_sb_sort use the same test, so pos < end always
+            a.ids[pos] = (unsigned)(key & 0xffffffffull);
+            if (a.keys) a.keys[pos] = tk | (key >> 32);
+        }
+        out += (unsigned)__builtin_popcountll(mask);
     }
 }
 
@@ -251,7 +373,7 @@ using namespace ls2;
 extern "C" int ls2_bin_sort_workspace(const ls2_camera* cam, int32_t n, int64_t max_pairs, size_t* bytes) {
     if (!cam_valid(cam) || n < 0 || max_pairs < 0 || !bytes) return LS2_ERR_ARG;
     if (max_pairs > 0xffffffffll) return LS2_ERR_UNSUPPORTED;  // 32-bit list positions
-    *bytes = layout(cam_k(*cam), max_pairs).total;
+    *bytes = layout(cam_k(*cam), n, max_pairs).total;
     return LS2_OK;
 }
 
@@ -265,48 +387,67 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     if (max_pairs > 0xffffffffll) return LS2_ERR_UNSUPPORTED;
     if (((uintptr_t)workspace & (kAlign - 1)) != 0) return LS2_ERR_ARG;
     const CamK k = cam_k(*cam);
-    const Layout lay = layout(k, max_pairs);
+    const Layout lay = layout(k, n, max_pairs);
     if (workspace_bytes < lay.total) return LS2_ERR_ARG;
+    const Geo g = geo(k);
     char* ws = static_cast<char*>(workspace);
-    Meta* meta = reinterpret_cast<Meta*>(ws + lay.meta);
-    int* grid = reinterpret_cast<int*>(ws + lay.grid);
-    unsigned* cursor = reinterpret_cast<unsigned*>(ws + lay.cursor);
-    unsigned long long* bucket = reinterpret_cast<unsigned long long*>(ws + lay.bucket);
+    BinArgs a;
+    a.cam = k;
+    a.n = n;
+    a.S = g.S;
+    a.sbx = g.sbx;
+    a.nsb = g.nsb;
+    a.max_pairs = max_pairs;
+    a.mean2d = mean2d;
+    a.radius = radius;
+    a.depth = depth;
+    a.meta = reinterpret_cast<Meta*>(ws + lay.meta);
+    a.sb_count = reinterpret_cast<unsigned*>(ws + lay.sb_count);
+    a.sb_start = reinterpret_cast<unsigned*>(ws + lay.sb_start);
+    a.sb_cursor = reinterpret_cast<unsigned*>(ws + lay.sb_cursor);
+    a.tile_count = reinterpret_cast<unsigned*>(ws + lay.tile_count);
+    a.rect = reinterpret_cast<ushort4*>(ws + lay.rect);
+    a.pool = reinterpret_cast<unsigned long long*>(ws + lay.pool);
+    a.ranges = tile_ranges;
+    a.ids = ids;
+    a.keys = reinterpret_cast<unsigned long long*>(keys);
     const int ntiles = k.tx * k.ty;
 
-    // zero the meta record and the difference grid (contiguous)
-    const long long zero_words = (long long)((lay.cursor - lay.meta) / sizeof(int));
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((zero_words + 255) / 256 < 1024 ? (zero_words + 255) / 256 : 1024)),
-                       dim3(256), 0, stream, reinterpret_cast<int*>(ws + lay.meta), zero_words);
+    // zero meta, superblock counts and tile counts (contiguous; tile counts of
+    // superblocks with no entries are never written by the sort kernels)
+    const long long zw = (long long)((lay.sb_start - lay.meta) / sizeof(unsigned));
+    const long long zb = (zw + 255) / 256;
+    hipLaunchKernelGGL(k_bin_zero, dim3((unsigned)(zb < 1024 ? zb : 1024)), dim3(256), 0, stream,
+                       reinterpret_cast<unsigned*>(ws + lay.meta), zw);
     LS2_LAUNCH_CHECK();
+    const int per_block = kBinThreads * kBinPerThread;
+    const int gblocks = (n + per_block - 1) / per_block;
     if (n > 0) {
-        hipLaunchKernelGGL(k_count, dim3((n + 255) / 256), dim3(256), 0, stream, k, n, mean2d, radius, grid);
+        hipLaunchKernelGGL(k_sb_count, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, k, grid, cursor, tile_ranges, meta,
-                       (long long)max_pairs);
+    hipLaunchKernelGGL(k_sb_scan, dim3(1), dim3(1024), 0, stream, a);
     LS2_LAUNCH_CHECK();
     if (n > 0 && max_pairs > 0) {
-        hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, stream, k, n, mean2d, radius, depth, cursor,
-                           bucket, meta);
+        hipLaunchKernelGGL(k_sb_emit, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
-        unsigned long long* keys64 = reinterpret_cast<unsigned long long*>(keys);
-        hipLaunchKernelGGL((k_sort_lds<512, 256>), dim3(ntiles), dim3(256), 0, stream, ntiles, tile_ranges, bucket,
-                           ids, keys64, 0);
+        hipLaunchKernelGGL((k_sb_sort_lds<2048, 256>), dim3(g.nsb), dim3(256), 0, stream, a, 0);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sort_lds<2048, 512>), dim3(ntiles), dim3(512), 0, stream, ntiles, tile_ranges, bucket,
-                           ids, keys64, 512);
+        hipLaunchKernelGGL((k_sb_sort_lds<16384, 1024>), dim3(g.nsb), dim3(1024), 0, stream, a, 2048);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sort_lds<16384, 1024>), dim3(ntiles), dim3(1024), 0, stream, ntiles, tile_ranges,
-                           bucket, ids, keys64, 2048);
+        hipLaunchKernelGGL(k_sb_sort_global, dim3(g.nsb), dim3(1024), 0, stream, a, 16384);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sort_global, dim3(ntiles), dim3(1024), 0, stream, ntiles, tile_ranges, bucket, ids,
-                           keys64, 16384);
+    }
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
+    LS2_LAUNCH_CHECK();
+    if (n > 0 && max_pairs > 0) {
+        hipLaunchKernelGGL(k_tile_fill, dim3(round_up8(ntiles)), dim3(64), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
     if (num_pairs) {
         Meta h;
-        if (hipMemcpyAsync(&h, meta, sizeof(Meta), hipMemcpyDeviceToHost, stream) != hipSuccess) return LS2_ERR_DEVICE;
+        if (hipMemcpyAsync(&h, a.meta, sizeof(Meta), hipMemcpyDeviceToHost, stream) != hipSuccess)
+            return LS2_ERR_DEVICE;
         if (hipStreamSynchronize(stream) != hipSuccess) return LS2_ERR_DEVICE;
         *num_pairs = h.P;
         if (h.overflow) return LS2_ERR_CAPACITY;
