@@ -135,82 +135,100 @@ static int rect_f32(float u, float v, int r, int tx, int ty, int* x0, int* y0, i
 /* the image-edge pixel of the 60-degree field of view and a numerical */
 /* Jacobian of the perspective map.                                    */
 /* ------------------------------------------------------------------ */
+static void project_one(const cam_t* cam, const double mu[3], const double s3[3], const double q[4], int i,
+                        double* mean2d, double* cov2d, double* conic, double* depth, double* extent,
+                        int32_t* radius, int32_t* rect, int32_t* touched) {
+    mean2d[2 * i] = mean2d[2 * i + 1] = 0;
+    cov2d[3 * i] = cov2d[3 * i + 1] = cov2d[3 * i + 2] = 0;
+    conic[3 * i] = conic[3 * i + 1] = conic[3 * i + 2] = 0;
+    depth[i] = 0; extent[i] = 0; radius[i] = 0; touched[i] = 0;
+    rect[4 * i] = rect[4 * i + 1] = rect[4 * i + 2] = rect[4 * i + 3] = 0;
+
+    double p[3];
+    for (int r = 0; r < 3; ++r)
+        p[r] = cam->R[3 * r] * mu[0] + cam->R[3 * r + 1] * mu[1] + cam->R[3 * r + 2] * mu[2] + cam->t[r];
+    double x = p[0], y = p[1], z = p[2];
+    if (!(z > cam->znear) || !isfinite(x) || !isfinite(y)) return;
+
+    /* Eq. 2: Sigma = R S S^T R^T */
+    double Rq[9];
+    quat_to_rot(q, Rq);
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * s3[c];
+    double Mt[9], Sig[9];
+    transpose3(M, Mt);
+    matmul3(M, Mt, Sig);
+
+    /* world -> camera covariance */
+    double Rt[9], tmp[9], Sc[9];
+    transpose3(cam->R, Rt);
+    matmul3(cam->R, Sig, tmp);
+    matmul3(tmp, Rt, Sc);
+
+    /* EWA: local affine approximation of the perspective map at the mean */
+    double J[6] = {cam->fx / z, 0.0, -cam->fx * x / (z * z),
+                   0.0, cam->fy / z, -cam->fy * y / (z * z)};
+    double JS[6];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += J[3 * r + k] * Sc[3 * k + c];
+            JS[3 * r + c] = acc;
+        }
+    double cv[4];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += JS[3 * r + k] * J[3 * c + k];
+            cv[2 * r + c] = acc;
+        }
+    double a = cv[0] + DILATION, b = cv[1], c = cv[3] + DILATION;
+    double det = a * c - b * b;
+    if (!(det > 0) || !isfinite(det)) return;
+
+    double mid = 0.5 * (a + c);
+    double disc = mid * mid - det;
+    double lam = mid + sqrt(disc > 0 ? disc : 0);
+    double ext = 3.0 * sqrt(lam);
+    if (!isfinite(ext) || ext > 1e7) return;
+    int r = (int)ceil(ext);
+
+    double u = cam->fx * x / z + cam->cx;
+    double v = cam->fy * y / z + cam->cy;
+    int x0, y0, x1, y1;
+    if (!rect_f32((float)u, (float)v, r, cam->tx, cam->ty, &x0, &y0, &x1, &y1)) return;
+
+    mean2d[2 * i] = u; mean2d[2 * i + 1] = v;
+    cov2d[3 * i] = a; cov2d[3 * i + 1] = b; cov2d[3 * i + 2] = c;
+    conic[3 * i] = c / det; conic[3 * i + 1] = -b / det; conic[3 * i + 2] = a / det;
+    depth[i] = z; extent[i] = ext; radius[i] = r;
+    rect[4 * i] = x0; rect[4 * i + 1] = y0; rect[4 * i + 2] = x1; rect[4 * i + 3] = y1;
+    touched[i] = (x1 - x0 + 1) * (y1 - y0 + 1);
+}
+
 void orc_project(const double* cam_arr, int n, const float* means, const float* scales,
                  const float* quats, double* mean2d, double* cov2d, double* conic,
                  double* depth, double* extent, int32_t* radius, int32_t* rect, int32_t* touched) {
     cam_t cam = cam_from(cam_arr);
     #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
-        mean2d[2 * i] = mean2d[2 * i + 1] = 0;
-        cov2d[3 * i] = cov2d[3 * i + 1] = cov2d[3 * i + 2] = 0;
-        conic[3 * i] = conic[3 * i + 1] = conic[3 * i + 2] = 0;
-        depth[i] = 0; extent[i] = 0; radius[i] = 0; touched[i] = 0;
-        rect[4 * i] = rect[4 * i + 1] = rect[4 * i + 2] = rect[4 * i + 3] = 0;
-
         double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
-        double p[3];
-        for (int r = 0; r < 3; ++r)
-            p[r] = cam.R[3 * r] * mu[0] + cam.R[3 * r + 1] * mu[1] + cam.R[3 * r + 2] * mu[2] + cam.t[r];
-        double x = p[0], y = p[1], z = p[2];
-        if (!(z > cam.znear) || !isfinite(x) || !isfinite(y)) continue;
-
-        /* Eq. 2: Sigma = R S S^T R^T */
+        double s3[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
         double q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
-        double Rq[9];
-        quat_to_rot(q, Rq);
-        double M[9];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * (double)scales[3 * i + c];
-        double Mt[9], Sig[9];
-        transpose3(M, Mt);
-        matmul3(M, Mt, Sig);
-
-        /* world -> camera covariance */
-        double Rt[9], tmp[9], Sc[9];
-        transpose3(cam.R, Rt);
-        matmul3(cam.R, Sig, tmp);
-        matmul3(tmp, Rt, Sc);
-
-        /* EWA: local affine approximation of the perspective map at the mean */
-        double J[6] = {cam.fx / z, 0.0, -cam.fx * x / (z * z),
-                       0.0, cam.fy / z, -cam.fy * y / (z * z)};
-        double JS[6];
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 3; ++c) {
-                double s = 0;
-                for (int k = 0; k < 3; ++k) s += J[3 * r + k] * Sc[3 * k + c];
-                JS[3 * r + c] = s;
-            }
-        double cv[4];
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c) {
-                double s = 0;
-                for (int k = 0; k < 3; ++k) s += JS[3 * r + k] * J[3 * c + k];
-                cv[2 * r + c] = s;
-            }
-        double a = cv[0] + DILATION, b = cv[1], c = cv[3] + DILATION;
-        double det = a * c - b * b;
-        if (!(det > 0) || !isfinite(det)) continue;
-
-        double mid = 0.5 * (a + c);
-        double disc = mid * mid - det;
-        double lam = mid + sqrt(disc > 0 ? disc : 0);
-        double ext = 3.0 * sqrt(lam);
-        if (!isfinite(ext) || ext > 1e7) continue;
-        int r = (int)ceil(ext);
-
-        double u = cam.fx * x / z + cam.cx;
-        double v = cam.fy * y / z + cam.cy;
-        int x0, y0, x1, y1;
-        if (!rect_f32((float)u, (float)v, r, cam.tx, cam.ty, &x0, &y0, &x1, &y1)) continue;
-
-        mean2d[2 * i] = u; mean2d[2 * i + 1] = v;
-        cov2d[3 * i] = a; cov2d[3 * i + 1] = b; cov2d[3 * i + 2] = c;
-        conic[3 * i] = c / det; conic[3 * i + 1] = -b / det; conic[3 * i + 2] = a / det;
-        depth[i] = z; extent[i] = ext; radius[i] = r;
-        rect[4 * i] = x0; rect[4 * i + 1] = y0; rect[4 * i + 2] = x1; rect[4 * i + 3] = y1;
-        touched[i] = (x1 - x0 + 1) * (y1 - y0 + 1);
+        project_one(&cam, mu, s3, q, i, mean2d, cov2d, conic, depth, extent, radius, rect, touched);
     }
+}
+
+/* Same projection on float64 inputs (finite-difference checks). */
+void orc_project_f64(const double* cam_arr, int n, const double* means, const double* scales,
+                     const double* quats, double* mean2d, double* cov2d, double* conic,
+                     double* depth, double* extent, int32_t* radius, int32_t* rect, int32_t* touched) {
+    cam_t cam = cam_from(cam_arr);
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+        project_one(&cam, means + 3 * i, scales + 3 * i, quats + 4 * i, i, mean2d, cov2d, conic, depth, extent,
+                    radius, rect, touched);
 }
 
 /* ------------------------------------------------------------------ */
@@ -655,3 +673,355 @@ void orc_query(int64_t M, int D, const double* feat, const float* pos, int n_neg
         out[m] = r;
     }
 }
+
+/* ================================================================== */
+/* Backward pass.  The paper learns the sparse coefficients and the    */
+/* codebook jointly (Section 3.3) but prints no backward formulas; the */
+/* functions below are the chain rule of the forward definitions above, */
+/* derived by hand in float64.  Every one is pinned by central finite  */
+/* differences of the corresponding forward function.  Discrete        */
+/* decisions (culling, tile rectangles, depth order, the alpha clamp,  */
+/* the 1/255 skip and the transmittance stop) are held fixed: they     */
+/* have zero derivative almost everywhere.                             */
+/* ================================================================== */
+
+/* Training loss on a feature map F against a target Y (M rows of D):
+ *   loss = mean_{m,d} |F - Y| + mean_m (1 - cos(F_m, Y_m)),
+ * cos(a, b) = a.b / (max(|a|, 1e-12) max(|b|, 1e-12)), sign(0) = 0.
+ * Writes the loss and dloss/dF. */
+void orc_loss_l1cos(int64_t M, int D, const double* F, const double* Y, double* loss, double* dF) {
+    double l1 = 0.0, lc = 0.0;
+    const double inv_md = 1.0 / ((double)M * D), inv_m = 1.0 / (double)M;
+    #pragma omp parallel for schedule(static) reduction(+ : l1, lc)
+    for (int64_t m = 0; m < M; ++m) {
+        const double* f = F + m * D;
+        const double* y = Y + m * D;
+        double* g = dF + m * D;
+        double fy = 0, ff = 0, yy = 0;
+        for (int d = 0; d < D; ++d) {
+            double e = f[d] - y[d];
+            l1 += fabs(e);
+            g[d] = (e > 0 ? 1.0 : (e < 0 ? -1.0 : 0.0)) * inv_md;
+            fy += f[d] * y[d];
+            ff += f[d] * f[d];
+            yy += y[d] * y[d];
+        }
+        double nf = sqrt(ff), ny = sqrt(yy);
+        double gf = nf > 1e-12 ? nf : 1e-12, gy = ny > 1e-12 ? ny : 1e-12;
+        double c = fy / (gf * gy);
+        lc += 1.0 - c;
+        /* d(-c)/df = -(y / (gf gy) - [nf > eps] fy f / (nf^3 gy)) */
+        for (int d = 0; d < D; ++d) {
+            double dc = y[d] / (gf * gy);
+            if (nf > 1e-12) dc -= fy * f[d] / (nf * nf * nf * gy);
+            g[d] -= dc * inv_m;
+        }
+    }
+    *loss = l1 * inv_md + lc * inv_m;
+}
+
+/* Relevancy backward: r = min_j sigmoid(tau (s_q - s_j)) = sigmoid(tau (s_q -
+ * s_j*)) with j* the first negative of largest similarity.  Writes
+ * dF = d_rel * dr/dF.  ``margin`` (per row, may be NULL) is the gap between
+ * the two largest negative similarities (the subgradient choice flips there). */
+static void cos_grad(const double* f, const float* e, int D, double* out_scale_e, double* out_scale_f,
+                     double* s_out) {
+    /* s = f.e / (gf ge); ds/df = e / (gf ge) - [nf > eps] (f.e) f / (nf^3 ge) */
+    double fe = 0, ff = 0, ee = 0;
+    for (int d = 0; d < D; ++d) {
+        fe += f[d] * (double)e[d];
+        ff += f[d] * f[d];
+        ee += (double)e[d] * (double)e[d];
+    }
+    double nf = sqrt(ff), ne = sqrt(ee);
+    double gf = nf > 1e-12 ? nf : 1e-12, ge = ne > 1e-12 ? ne : 1e-12;
+    *s_out = fe / (gf * ge);
+    *out_scale_e = 1.0 / (gf * ge);
+    *out_scale_f = nf > 1e-12 ? -fe / (nf * nf * nf * ge) : 0.0;
+}
+
+void orc_query_backward(int64_t M, int D, const double* feat, const float* pos, int n_neg, const float* neg,
+                        double tau, const double* d_rel, double* d_feat, double* margin) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < M; ++m) {
+        const double* f = feat + m * D;
+        double* g = d_feat + m * D;
+        double aq, bq, sq;
+        cos_grad(f, pos, D, &aq, &bq, &sq);
+        int jstar = 0;
+        double smax = -INFINITY, s2 = -INFINITY;
+        double aj = 0, bj = 0;
+        for (int j = 0; j < n_neg; ++j) {
+            double a_, b_, s_;
+            cos_grad(f, neg + (size_t)j * D, D, &a_, &b_, &s_);
+            if (s_ > smax) {
+                s2 = smax;
+                smax = s_;
+                jstar = j;
+                aj = a_;
+                bj = b_;
+            } else if (s_ > s2) {
+                s2 = s_;
+            }
+        }
+        if (margin) margin[m] = n_neg > 1 ? smax - s2 : INFINITY;
+        double r = 1.0 / (1.0 + exp(-tau * (sq - smax)));
+        double dr = d_rel[m] * tau * r * (1.0 - r); /* dr/d(s_q - s_j*) */
+        const float* ej = neg + (size_t)jstar * D;
+        for (int d = 0; d < D; ++d)
+            g[d] = dr * ((aq * pos[d] + bq * f[d]) - (aj * ej[d] + bj * f[d]));
+    }
+}
+
+/* Decode backward (Eq. 7 is linear): d_coef = d_feat S^T, d_dict = coef^T d_feat. */
+void orc_decode_backward(int64_t M, int L, int D, const double* coef, const double* dict, const double* d_feat,
+                         double* d_coef, double* d_dict) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t m = 0; m < M; ++m)
+        for (int l = 0; l < L; ++l) {
+            double s = 0;
+            for (int d = 0; d < D; ++d) s += d_feat[m * D + d] * dict[(size_t)l * D + d];
+            d_coef[m * L + l] = s;
+        }
+    #pragma omp parallel for schedule(static)
+    for (int l = 0; l < L; ++l) {
+        for (int d = 0; d < D; ++d) d_dict[(size_t)l * D + d] = 0.0;
+        for (int64_t m = 0; m < M; ++m) {
+            double c = coef[m * L + l];
+            if (c == 0.0) continue;
+            for (int d = 0; d < D; ++d) d_dict[(size_t)l * D + d] += c * d_feat[m * D + d];
+        }
+    }
+}
+
+/* Compositing backward.  For one pixel with contributors i = 1..n (front to
+ * back), blend weights e_i = alpha_i T_i, T_i = prod_{j<i} (1 - alpha_j):
+ *   W_l[j] = sum_i e_i w_{i,l,j}.
+ * With g_l = dL/dW_l and c_i = sum_l sum_k g_l[idx_ilk] w_ilk:
+ *   dL/dw_ilk  += g_l[idx_ilk] e_i
+ *   dL/dalpha_i = T_i c_i - (1 / (1 - alpha_i)) sum_{m > i} c_m e_m
+ * (e_m for m > i contains the factor 1 - alpha_i once).  Then
+ *   alpha_i = o_i exp(power_i) (unclamped; 0 gradient where clamped at 0.99),
+ *   dalpha/do = exp(power), dalpha/dpower = alpha,
+ *   power = -0.5 (A dx^2 + C dy^2) - B dx dy with (dx, dy) = mean2d - pixel:
+ *   dpower/du = -(A dx + B dy), dpower/dv = -(C dy + B dx),
+ *   dpower/dA = -dx^2 / 2, dpower/dB = -dx dy, dpower/dC = -dy^2 / 2.
+ * The forward walk is re-run here and its contributors stored; the suffix
+ * sums are formed directly.  Gradient outputs are overwritten. */
+void orc_composite_backward(const double* cam_arr, int n, int levels, int K, int L, const uint32_t* ranges,
+                            const uint32_t* ids, const double* mean2d, const double* conic, const double* opacity,
+                            const int32_t* topk_idx, const double* topk_w, const double* d_coef,
+                            double* d_mean2d, double* d_conic, double* d_opacity, double* d_w) {
+    cam_t cam = cam_from(cam_arr);
+    int ntiles = cam.tx * cam.ty;
+    size_t HW = (size_t)cam.W * cam.H;
+    memset(d_mean2d, 0, sizeof(double) * 2 * (size_t)n);
+    memset(d_conic, 0, sizeof(double) * 3 * (size_t)n);
+    memset(d_opacity, 0, sizeof(double) * (size_t)n);
+    memset(d_w, 0, sizeof(double) * (size_t)n * levels * K);
+    uint32_t maxlen = max_range(ranges, ntiles);
+    /* sequential over pixels: gradient accumulation into shared per-Gaussian
+     * slots stays deterministic and obviously race-free */
+    int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (maxlen + 1));
+    double* e = (double*)malloc(sizeof(double) * (maxlen + 1));
+    double* Tb = (double*)malloc(sizeof(double) * (maxlen + 1));
+    double* al = (double*)malloc(sizeof(double) * (maxlen + 1));
+    double* cc = (double*)malloc(sizeof(double) * (maxlen + 1));
+    for (int t = 0; t < ntiles; ++t) {
+        int tx = t % cam.tx, ty = t / cam.tx;
+        for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < cam.H; ++py)
+            for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < cam.W; ++px) {
+                size_t pix = (size_t)py * cam.W + px;
+                double T, mg;
+                int32_t lst;
+                int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids, mean2d, conic,
+                                     opacity, pos, e, Tb, al, &T, &lst, &mg, NULL);
+                for (int c = 0; c < cnt; ++c) {
+                    uint32_t i = ids[ranges[2 * t] + pos[c]];
+                    double s = 0;
+                    for (int lv = 0; lv < levels; ++lv) {
+                        const double* g = d_coef + ((size_t)lv * HW + pix) * L;
+                        for (int k = 0; k < K; ++k) {
+                            size_t o = ((size_t)i * levels + lv) * K + k;
+                            s += g[topk_idx[o]] * topk_w[o];
+                            d_w[o] += g[topk_idx[o]] * e[c];
+                        }
+                    }
+                    cc[c] = s;
+                }
+                double suffix = 0.0; /* sum_{m > i} c_m e_m */
+                for (int c = cnt - 1; c >= 0; --c) {
+                    uint32_t i = ids[ranges[2 * t] + pos[c]];
+                    double dalpha = Tb[c] * cc[c] - suffix / (1.0 - al[c]);
+                    suffix += cc[c] * e[c];
+                    double dx = mean2d[2 * i] - (px + 0.5), dy = mean2d[2 * i + 1] - (py + 0.5);
+                    double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
+                    double power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
+                    double G = exp(power);
+                    if (opacity[i] * G >= ALPHA_MAX) continue; /* clamped: no gradient */
+                    double dpow = dalpha * opacity[i] * G;
+                    d_opacity[i] += dalpha * G;
+                    d_mean2d[2 * i] += dpow * (-(A * dx + B * dy));
+                    d_mean2d[2 * i + 1] += dpow * (-(C * dy + B * dx));
+                    d_conic[3 * i] += dpow * (-0.5 * dx * dx);
+                    d_conic[3 * i + 1] += dpow * (-dx * dy);
+                    d_conic[3 * i + 2] += dpow * (-0.5 * dy * dy);
+                }
+            }
+    }
+    free(pos);
+    free(e);
+    free(Tb);
+    free(al);
+    free(cc);
+}
+
+/* Projection backward: from dL/d(mean2d) and dL/d(conic) to dL/d(means),
+ * dL/d(scales), dL/d(quats) through
+ *   p = R_wc mu + t,  (u, v) = (fx x/z + cx, fy y/z + cy),
+ *   Sigma = M M^T, M = R(q / |q|) diag(s),  Sigma_c = R_wc Sigma R_wc^T,
+ *   Sigma2D = J Sigma_c J^T + 0.3 I, J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]],
+ *   conic = Sigma2D^-1 as (A, B, C) = (c, -b, a) / (ac - b^2).
+ * Culled Gaussians (radius 0) get zero gradients.  Outputs overwritten. */
+static void quat_rot_grad(const double q_in[4], const double dR[9], double dq[4]) {
+    /* dL/dq for R(q/|q|): first dL/dqhat from the rotation formula, then the
+     * projection through the normalisation. */
+    double n = sqrt(q_in[0] * q_in[0] + q_in[1] * q_in[1] + q_in[2] * q_in[2] + q_in[3] * q_in[3]);
+    double w = q_in[0] / n, x = q_in[1] / n, y = q_in[2] / n, z = q_in[3] / n;
+    double g[4];
+    /* R00 = 1 - 2(y^2 + z^2)  R01 = 2(xy - wz)  R02 = 2(xz + wy)
+     * R10 = 2(xy + wz)  R11 = 1 - 2(x^2 + z^2)  R12 = 2(yz - wx)
+     * R20 = 2(xz - wy)  R21 = 2(yz + wx)  R22 = 1 - 2(x^2 + y^2) */
+    g[0] = 2 * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    g[1] = 2 * (y * dR[1] + z * dR[2] + y * dR[3] - 2 * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                2 * x * dR[8]);
+    g[2] = 2 * (-2 * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                2 * y * dR[8]);
+    g[3] = 2 * (-2 * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2 * z * dR[4] + y * dR[5] + x * dR[6] +
+                y * dR[7]);
+    double qh[4] = {w, x, y, z};
+    double dot = g[0] * qh[0] + g[1] * qh[1] + g[2] * qh[2] + g[3] * qh[3];
+    for (int k = 0; k < 4; ++k) dq[k] = (g[k] - dot * qh[k]) / n;
+}
+
+static void project_backward_one(const cam_t* cam, const double mu[3], const double s[3], const double q[4],
+                                 const double* d_mean2d, const double* d_conic, int i, double* d_means,
+                                 double* d_scales, double* d_quats) {
+    double p[3];
+    for (int r = 0; r < 3; ++r)
+        p[r] = cam->R[3 * r] * mu[0] + cam->R[3 * r + 1] * mu[1] + cam->R[3 * r + 2] * mu[2] + cam->t[r];
+    double x = p[0], y = p[1], z = p[2];
+    double Rq[9], M[9], Mt[9], Sig[9], Rt[9], tmp[9], Sc[9];
+    quat_to_rot(q, Rq);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * s[c];
+    transpose3(M, Mt);
+    matmul3(M, Mt, Sig);
+    transpose3(cam->R, Rt);
+    matmul3(cam->R, Sig, tmp);
+    matmul3(tmp, Rt, Sc);
+    double J[6] = {cam->fx / z, 0.0, -cam->fx * x / (z * z), 0.0, cam->fy / z, -cam->fy * y / (z * z)};
+    /* Sigma2D entries */
+    double cv[4];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) acc += J[3 * r + k] * Sc[3 * k + l] * J[3 * c + l];
+            cv[2 * r + c] = acc;
+        }
+    double a = cv[0] + DILATION, b = cv[1], c = cv[3] + DILATION;
+    double det = a * c - b * b;
+    /* conic (A, B, C) = (c, -b, a) / det: derivatives w.r.t. (a, b, c) */
+    double gA = d_conic[3 * i], gB = d_conic[3 * i + 1], gC = d_conic[3 * i + 2];
+    double d2 = det * det;
+    double ga = gA * (-c * c / d2) + gB * (b * c / d2) + gC * (1.0 / det - a * c / d2);
+    double gb = gA * (2.0 * b * c / d2) + gB * (-1.0 / det - 2.0 * b * b / d2) + gC * (2.0 * a * b / d2);
+    double gc = gA * (1.0 / det - a * c / d2) + gB * (a * b / d2) + gC * (-a * a / d2);
+    /* symmetric gradient matrix of Sigma2D: dL = ga da + gb db + gc dc with
+     * b appearing twice in the matrix */
+    double G2[4] = {ga, 0.5 * gb, 0.5 * gb, gc};
+    /* dL/dSigma_c = J^T G2 J; dL/dJ = 2 G2 J Sigma_c */
+    double GS[9];
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) {
+            double acc = 0;
+            for (int r = 0; r < 2; ++r)
+                for (int cc2 = 0; cc2 < 2; ++cc2) acc += J[3 * r + k] * G2[2 * r + cc2] * J[3 * cc2 + l];
+            GS[3 * k + l] = acc;
+        }
+    double GJ[6];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0;
+            for (int cc2 = 0; cc2 < 2; ++cc2)
+                for (int l = 0; l < 3; ++l) acc += G2[2 * r + cc2] * J[3 * cc2 + l] * Sc[3 * l + k];
+            GJ[3 * r + k] = 2.0 * acc;
+        }
+    /* J depends on p: J00 = fx/z, J02 = -fx x/z^2, J11 = fy/z, J12 = -fy y/z^2 */
+    double dp[3] = {0, 0, 0};
+    dp[0] += GJ[2] * (-cam->fx / (z * z));
+    dp[1] += GJ[5] * (-cam->fy / (z * z));
+    dp[2] += GJ[0] * (-cam->fx / (z * z)) + GJ[2] * (2.0 * cam->fx * x / (z * z * z)) +
+             GJ[4] * (-cam->fy / (z * z)) + GJ[5] * (2.0 * cam->fy * y / (z * z * z));
+    /* mean2d */
+    double gu = d_mean2d[2 * i], gv = d_mean2d[2 * i + 1];
+    dp[0] += gu * cam->fx / z;
+    dp[1] += gv * cam->fy / z;
+    dp[2] += gu * (-cam->fx * x / (z * z)) + gv * (-cam->fy * y / (z * z));
+    /* p = R_wc mu + t */
+    for (int k = 0; k < 3; ++k)
+        d_means[3 * i + k] = cam->R[k] * dp[0] + cam->R[3 + k] * dp[1] + cam->R[6 + k] * dp[2];
+    /* Sigma_c = R_wc Sigma R_wc^T -> dL/dSigma = R_wc^T GS R_wc */
+    double t1[9], GSig[9];
+    matmul3(Rt, GS, t1);
+    matmul3(t1, cam->R, GSig);
+    /* Sigma = M M^T -> dL/dM = (GSig + GSig^T) M */
+    double GSs[9], dM[9];
+    for (int k = 0; k < 9; ++k) GSs[k] = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int cc2 = 0; cc2 < 3; ++cc2) GSs[3 * r + cc2] = GSig[3 * r + cc2] + GSig[3 * cc2 + r];
+    matmul3(GSs, M, dM);
+    /* M = Rq diag(s) */
+    double dR[9];
+    for (int r = 0; r < 3; ++r)
+        for (int cc2 = 0; cc2 < 3; ++cc2) dR[3 * r + cc2] = dM[3 * r + cc2] * s[cc2];
+    for (int cc2 = 0; cc2 < 3; ++cc2) {
+        double acc = 0;
+        for (int r = 0; r < 3; ++r) acc += dM[3 * r + cc2] * Rq[3 * r + cc2];
+        d_scales[3 * i + cc2] = acc;
+    }
+    quat_rot_grad(q, dR, d_quats + 4 * i);
+}
+
+void orc_project_backward(const double* cam_arr, int n, const float* means, const float* scales, const float* quats,
+                          const int32_t* radius, const double* d_mean2d, const double* d_conic, double* d_means,
+                          double* d_scales, double* d_quats) {
+    cam_t cam = cam_from(cam_arr);
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < 3; ++k) d_means[3 * i + k] = d_scales[3 * i + k] = 0.0;
+        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = 0.0;
+        if (radius[i] <= 0) continue;
+        double mu[3] = {means[3 * i], means[3 * i + 1], means[3 * i + 2]};
+        double s3[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+        double q[4] = {quats[4 * i], quats[4 * i + 1], quats[4 * i + 2], quats[4 * i + 3]};
+        project_backward_one(&cam, mu, s3, q, d_mean2d, d_conic, i, d_means, d_scales, d_quats);
+    }
+}
+
+/* Same on float64 inputs (finite-difference checks). */
+void orc_project_backward_f64(const double* cam_arr, int n, const double* means, const double* scales,
+                              const double* quats, const int32_t* radius, const double* d_mean2d,
+                              const double* d_conic, double* d_means, double* d_scales, double* d_quats) {
+    cam_t cam = cam_from(cam_arr);
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i) {
+        for (int k = 0; k < 3; ++k) d_means[3 * i + k] = d_scales[3 * i + k] = 0.0;
+        for (int k = 0; k < 4; ++k) d_quats[4 * i + k] = 0.0;
+        if (radius[i] <= 0) continue;
+        project_backward_one(&cam, means + 3 * i, scales + 3 * i, quats + 4 * i, d_mean2d, d_conic, i, d_means,
+                             d_scales, d_quats);
+    }
+}
+

@@ -49,6 +49,8 @@ def _declare(L):
     L.orc_num_threads.restype = ctypes.c_int
     L.orc_project.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_project.restype = None
+    L.orc_project_f64.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+    L.orc_project_f64.restype = None
     L.orc_tile_lists.argtypes = [_P, ctypes.c_int, _P, _P, _P, i64, _P, _P, _P, _P]
     L.orc_tile_lists.restype = ctypes.c_int
     L.orc_composite.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P,
@@ -77,7 +79,16 @@ def _declare(L):
     del i32
 
 
-_BACKWARD_DECLS: dict = {}
+_P_ = ctypes.c_void_p
+_BACKWARD_DECLS: dict = {
+    "orc_loss_l1cos": [ctypes.c_int64, ctypes.c_int, _P_, _P_, _P_, _P_],
+    "orc_query_backward": [ctypes.c_int64, ctypes.c_int, _P_, _P_, ctypes.c_int, _P_, ctypes.c_double, _P_, _P_, _P_],
+    "orc_decode_backward": [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _P_, _P_, _P_, _P_, _P_],
+    "orc_composite_backward": [_P_, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P_, _P_, _P_, _P_, _P_,
+                               _P_, _P_, _P_, _P_, _P_, _P_, _P_],
+    "orc_project_backward": [_P_, ctypes.c_int, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_],
+    "orc_project_backward_f64": [_P_, ctypes.c_int, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_],
+}
 
 
 def _c(a, dtype):
@@ -98,17 +109,20 @@ def cam_array(cam) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-def project(cam, means, scales, quats):
+def project(cam, means, scales, quats, f64=False):
     """Projection of every Gaussian (Eqs. 1-2, EWA reading).  Returns a dict
     of float64/int32 arrays: mean2d (N,2), cov2d (N,3), conic (N,3), depth,
-    extent, radius, rect (N,4), touched."""
-    means, scales, quats = _c(means, np.float32), _c(scales, np.float32), _c(quats, np.float32)
+    extent, radius, rect (N,4), touched.  Inputs are taken as float32 (the
+    kernels' input type) unless f64 is set."""
+    dt = np.float64 if f64 else np.float32
+    means, scales, quats = _c(means, dt), _c(scales, dt), _c(quats, dt)
     n = means.shape[0]
     out = dict(mean2d=np.zeros((n, 2)), cov2d=np.zeros((n, 3)), conic=np.zeros((n, 3)),
                depth=np.zeros(n), extent=np.zeros(n), radius=np.zeros(n, np.int32),
                rect=np.zeros((n, 4), np.int32), touched=np.zeros(n, np.int32))
     ca = cam_array(cam)
-    lib().orc_project(_p(ca), n, _p(means), _p(scales), _p(quats), _p(out["mean2d"]), _p(out["cov2d"]),
+    fn = lib().orc_project_f64 if f64 else lib().orc_project
+    fn(_p(ca), n, _p(means), _p(scales), _p(quats), _p(out["mean2d"]), _p(out["cov2d"]),
                       _p(out["conic"]), _p(out["depth"]), _p(out["extent"]), _p(out["radius"]),
                       _p(out["rect"]), _p(out["touched"]))
     return out
@@ -243,3 +257,74 @@ def query(feat, pos, neg, tau=1.0):
     out = np.zeros(f.shape[0])
     lib().orc_query(f.shape[0], D, _p(f), _p(pos), neg.shape[0], _p(neg), float(tau), _p(out))
     return out.reshape(feat.shape[:-1])
+
+
+# -------------------------------------------------------------------------- backward
+def loss_l1cos(F, Y):
+    """loss = mean|F - Y| + mean_rows (1 - cos(F_row, Y_row)); returns (loss, dF)."""
+    D = F.shape[-1]
+    f = _c(F, np.float64).reshape(-1, D)
+    y = _c(Y, np.float64).reshape(-1, D)
+    dF = np.zeros_like(f)
+    loss = ctypes.c_double(0.0)
+    lib().orc_loss_l1cos(f.shape[0], D, _p(f), _p(y), ctypes.byref(loss), _p(dF))
+    return loss.value, dF.reshape(F.shape)
+
+
+def query_backward(feat, pos, neg, d_rel, tau=1.0):
+    """dL/dF of the relevancy given dL/dr.  Returns (d_feat, margin) where
+    margin is the gap between the two most similar negatives per row."""
+    D = feat.shape[-1]
+    f = _c(feat, np.float64).reshape(-1, D)
+    pos = _c(pos, np.float32)
+    neg = _c(neg, np.float32).reshape(-1, D)
+    dr = _c(d_rel, np.float64).reshape(-1)
+    out = np.zeros_like(f)
+    margin = np.zeros(f.shape[0])
+    lib().orc_query_backward(f.shape[0], D, _p(f), _p(pos), neg.shape[0], _p(neg), float(tau), _p(dr), _p(out),
+                             _p(margin))
+    return out.reshape(feat.shape), margin.reshape(feat.shape[:-1])
+
+
+def decode_backward(coef, dictionary, d_feat):
+    """(d_coef, d_dict) of F = W S."""
+    L, D = dictionary.shape
+    c = _c(coef, np.float64).reshape(-1, L)
+    s = _c(dictionary, np.float64)
+    g = _c(d_feat, np.float64).reshape(-1, D)
+    dc = np.zeros_like(c)
+    ds = np.zeros_like(s)
+    lib().orc_decode_backward(c.shape[0], L, D, _p(c), _p(s), _p(g), _p(dc), _p(ds))
+    return dc.reshape(coef.shape), ds
+
+
+def composite_backward(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, d_coef):
+    """Gradients of the sparse splat w.r.t. mean2d (N,2), conic (N,3),
+    opacity (N,), topk_w (N, levels, K) given d_coef (levels, H, W, L)."""
+    n, levels, K = topk_idx.shape
+    L = d_coef.shape[-1]
+    dm = np.zeros((n, 2))
+    dcn = np.zeros((n, 3))
+    do = np.zeros(n)
+    dw = np.zeros((n, levels, K))
+    ids = _c(ids, np.uint32)
+    args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
+            _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64),
+            _c(d_coef, np.float64)]
+    lib().orc_composite_backward(_p(cam_array(cam)), n, levels, K, L, *[_p(a) for a in args], _p(dm), _p(dcn),
+                                 _p(do), _p(dw))
+    return dm, dcn, do, dw
+
+
+def project_backward(cam, means, scales, quats, radius, d_mean2d, d_conic, f64=False):
+    """(d_means, d_scales, d_quats) of the projection."""
+    dt = np.float64 if f64 else np.float32
+    means, scales, quats = _c(means, dt), _c(scales, dt), _c(quats, dt)
+    n = means.shape[0]
+    dmu = np.zeros((n, 3))
+    ds = np.zeros((n, 3))
+    dq = np.zeros((n, 4))
+    fn = lib().orc_project_backward_f64 if f64 else lib().orc_project_backward
+    fn(_p(cam_array(cam)), n, _p(means), _p(scales), _p(quats), _p(_c(radius, np.int32)),
+                               _p(_c(d_mean2d, np.float64)), _p(_c(d_conic, np.float64)), _p(dmu), _p(ds), _p(dq))
+    return dmu, ds, dq
