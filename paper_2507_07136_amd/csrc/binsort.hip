@@ -98,6 +98,13 @@ struct BinArgs {
     unsigned long long* keys;
 };
 
+// Orders this wave's earlier shared/global writes before its later reads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void k_bin_zero(unsigned* __restrict__ p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         p[i] = 0u;
@@ -232,13 +239,23 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
 // input to a power of two with +infinity keys is equivalent to skipping every
 // comparator whose partner lies at or beyond `cnt`: such a comparator would
 // never move anything.  No padding is stored.
-template <typename Ptr>
+template <bool WAVE_LOCAL, typename Ptr>
 __device__ void flip_bitonic(Ptr s, int cnt) {
     int m = 1;
     while (m < cnt) m <<= 1;
     for (int k = 2; k <= m; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             const int mask = (j == (k >> 1)) ? (k - 1) : j;
+            // a comparator spanning less than 64 positions pairs two indices
+            // handled by the same wave (each wave owns 64-aligned index blocks),
+            // so in LDS only that wave's earlier writes must be visible; the
+            // global-memory variant always uses workgroup barriers
+            if (mask >= 64 || !WAVE_LOCAL) {
+                __threadfence_block();
+                __syncthreads();
+            } else {
+                wave_sync();
+            }
             for (int i = threadIdx.x; i < m; i += blockDim.x) {
                 const int p = i ^ mask;
                 if (p > i && p < cnt) {
@@ -249,26 +266,64 @@ __device__ void flip_bitonic(Ptr s, int cnt) {
                     }
                 }
             }
-            __threadfence_block();
-            __syncthreads();
         }
     }
+    __threadfence_block();
+    __syncthreads();
 }
 
 // Per-tile counts of one superblock's entries (tcnt: S*S LDS counters).
+// For 4x4-tile superblocks every entry contributes a 16-bit coverage mask and
+// each wave counts with 16 ballots per 64 entries; larger superblocks (only
+// for very large images) use LDS atomics.
 __device__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long long* s, int cnt, unsigned* tcnt) {
     const int S = a.S;
     const int sx = sb % a.sbx, sy = sb / a.sbx;
     const int tx0 = sx * S, ty0 = sy * S;
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) tcnt[t] = 0u;
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-        const unsigned id = (unsigned)(s[e] & 0xffffffffull);
-        const ushort4 r = a.rect[id];
-        const int x0 = max((int)r.x, tx0), x1 = min((int)r.z, tx0 + S - 1);
-        const int y0 = max((int)r.y, ty0), y1 = min((int)r.w, ty0 + S - 1);
-        for (int y = y0; y <= y1; ++y)
-            for (int x = x0; x <= x1; ++x) atomicAdd(&tcnt[(y - ty0) * S + (x - tx0)], 1u);
+    if (S == 4) {
+        unsigned wcnt[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) wcnt[b] = 0u;
+        const int cnt64 = (cnt + 63) & ~63;
+        constexpr int G = 4;  // rectangle gathers in flight per thread
+        for (int e0 = threadIdx.x; e0 < cnt64; e0 += G * blockDim.x) {
+            ushort4 rr[G];
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const int e = e0 + q * blockDim.x;
+                rr[q] = e < cnt ? a.rect[(unsigned)(s[e] & 0xffffffffull)] : make_ushort4(0xffff, 0xffff, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (e0 + q * blockDim.x >= cnt64) break;  // wave-uniform
+                const ushort4 r = rr[q];
+                unsigned cover = 0u;
+                const int x0 = max((int)r.x - tx0, 0), x1 = min((int)r.z - tx0, 3);
+                const int y0 = max((int)r.y - ty0, 0), y1 = min((int)r.w - ty0, 3);
+                if (x0 <= x1 && y0 <= y1) {
+                    const unsigned rowbits = ((1u << (x1 + 1)) - 1u) & ~((1u << x0) - 1u);
+                    for (int y = y0; y <= y1; ++y) cover |= rowbits << (4 * y);
+                }
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    wcnt[b] += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cover >> b) & 1u));
+            }
+        }
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (wcnt[b]) atomicAdd(&tcnt[b], wcnt[b]);
+    } else {
+        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const unsigned id = (unsigned)(s[e] & 0xffffffffull);
+            const ushort4 r = a.rect[id];
+            const int x0 = max((int)r.x, tx0), x1 = min((int)r.z, tx0 + S - 1);
+            const int y0 = max((int)r.y, ty0), y1 = min((int)r.w, ty0 + S - 1);
+            for (int y = y0; y <= y1; ++y)
+                for (int x = x0; x <= x1; ++x) atomicAdd(&tcnt[(y - ty0) * S + (x - tx0)], 1u);
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
@@ -289,9 +344,22 @@ __global__ __launch_bounds__(THREADS) void k_sb_sort_lds(BinArgs a, int lo) {
     const int cnt = (int)a.sb_count[sb];
     if (cnt <= lo || cnt > CAP) return;
     unsigned long long* g = a.pool + a.sb_start[sb];
-    for (int i = threadIdx.x; i < cnt; i += THREADS) s[i] = g[i];
-    __syncthreads();
-    flip_bitonic(s, cnt);
+    {
+        // issue all of this thread's loads before the first LDS write
+        constexpr int PER = CAP / THREADS;
+        unsigned long long v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + q * THREADS;
+            v[q] = i < cnt ? g[i] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = threadIdx.x + q * THREADS;
+            if (i < cnt) s[i] = v[q];
+        }
+    }
+    flip_bitonic<true>(s, cnt);  // starts and ends with a workgroup barrier
     for (int i = threadIdx.x; i < cnt; i += THREADS) g[i] = s[i];
     count_sb_tiles(a, sb, s, cnt, tcnt);
 }
@@ -304,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_sb_sort_global(BinArgs a, int lo) {
     const int cnt = (int)a.sb_count[sb];
     if (cnt <= lo) return;
     unsigned long long* g = a.pool + a.sb_start[sb];
-    flip_bitonic(g, cnt);
+    flip_bitonic<false>(g, cnt);
     count_sb_tiles(a, sb, g, cnt, tcnt);
 }
 
@@ -331,38 +399,65 @@ __global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
     }
 }
 
-// One wave per tile: ordered compaction of the superblock's sorted bucket.
-__global__ __launch_bounds__(64) void k_tile_fill(BinArgs a) {
-    const int ntiles = a.cam.tx * a.cam.ty;
-    int t, slot;
-    xcd_remap(blockIdx.x, gridDim.x, 1, t, slot);
-    if (t >= ntiles || a.meta->overflow) return;
-    const int tx = t % a.cam.tx, ty = t / a.cam.tx;
-    const int sh = __builtin_ctz((unsigned)a.S);
-    const int sb = (ty >> sh) * a.sbx + (tx >> sh);
+// One workgroup per superblock, one wave per tile (S = 4: 16 waves; larger
+// superblocks: each wave handles several tiles).  The sorted bucket is staged
+// through LDS in chunks of 1024 entries (key and tile rectangle), then every
+// wave compacts, in order, the entries whose rectangle covers its tile: an
+// order-preserving ballot compaction, so each tile's list comes out in
+// (depth, id) order.
+constexpr int kFillChunk = 1024;
+
+__global__ __launch_bounds__(1024) void k_tile_fill(BinArgs a) {
+    __shared__ unsigned long long skey[kFillChunk];
+    __shared__ ushort4 srect[kFillChunk];
+    __shared__ unsigned toff[kMaxS2];
+    int sb, slot;
+    xcd_remap(blockIdx.x, gridDim.x, 1, sb, slot);
+    if (sb >= a.nsb || a.meta->overflow) return;
+    const int S = a.S;
+    const int tx0 = (sb % a.sbx) * S, ty0 = (sb / a.sbx) * S;
     const unsigned long long* list = a.pool + a.sb_start[sb];
     const int cnt = (int)a.sb_count[sb];
-    unsigned out = a.ranges[2 * t];
-    const unsigned end = a.ranges[2 * t + 1];
-    const int lane = threadIdx.x;
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+        const int x = tx0 + t % S, y = ty0 + t / S;
+        toff[t] = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x)] : 0u;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const unsigned long long tk = (unsigned long long)t << 32;
-    for (int b = 0; b < cnt; b += 64) {
-        const int e = b + lane;
-        bool hit = false;
-        unsigned long long key = 0;
-        if (e < cnt) {
-            key = list[e];
-            const ushort4 r = a.rect[(unsigned)(key & 0xffffffffull)];
-            hit = tx >= (int)r.x && tx <= (int)r.z && ty >= (int)r.y && ty <= (int)r.w;
+    for (int base = 0; base < cnt; base += kFillChunk) {
+        const int n = min(kFillChunk, cnt - base);
+        __syncthreads();  // previous chunk consumed (and toff initialised)
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const unsigned long long key = list[base + e];
+            skey[e] = key;
+            srect[e] = a.rect[(unsigned)(key & 0xffffffffull)];
         }
-        const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
-        const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
-        if (hit && pos < end) {  // the counts of k_sb_sort use the same test, so pos < end always
-            a.ids[pos] = (unsigned)(key & 0xffffffffull);
-            if (a.keys) a.keys[pos] = tk | (key >> 32);
+        __syncthreads();
+        for (int t = wave; t < S * S; t += nwaves) {
+            const int tx = tx0 + t % S, ty = ty0 + t / S;
+            if (tx >= a.cam.tx || ty >= a.cam.ty) continue;
+            const unsigned long long tk = (unsigned long long)(ty * a.cam.tx + tx) << 32;
+            const unsigned end = a.ranges[2 * (ty * a.cam.tx + tx) + 1];
+            unsigned out = toff[t];
+            for (int b = 0; b < n; b += 64) {
+                const int e = b + lane;
+                bool hit = false;
+                unsigned long long key = 0;
+                if (e < n) {
+                    key = skey[e];
+                    const ushort4 r = srect[e];
+                    hit = tx >= (int)r.x && tx <= (int)r.z && ty >= (int)r.y && ty <= (int)r.w;
+                }
+                const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+                const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
+                if (hit && pos < end) {  // the sort kernel's counts use the same test: pos < end always
+                    a.ids[pos] = (unsigned)(key & 0xffffffffull);
+                    if (a.keys) a.keys[pos] = tk | (key >> 32);
+                }
+                out += (unsigned)__builtin_popcountll(mask);
+            }
+            if (lane == 0) toff[t] = out;  // only this wave touches tile t
         }
-        out += (unsigned)__builtin_popcountll(mask);
     }
 }
 
@@ -411,8 +506,6 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.ranges = tile_ranges;
     a.ids = ids;
     a.keys = reinterpret_cast<unsigned long long*>(keys);
-    const int ntiles = k.tx * k.ty;
-
     // zero meta, superblock counts and tile counts (contiguous; tile counts of
     // superblocks with no entries are never written by the sort kernels)
     const long long zw = (long long)((lay.sb_start - lay.meta) / sizeof(unsigned));
@@ -433,7 +526,9 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
         LS2_LAUNCH_CHECK();
         hipLaunchKernelGGL((k_sb_sort_lds<2048, 256>), dim3(g.nsb), dim3(256), 0, stream, a, 0);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sb_sort_lds<16384, 1024>), dim3(g.nsb), dim3(1024), 0, stream, a, 2048);
+        hipLaunchKernelGGL((k_sb_sort_lds<8192, 512>), dim3(g.nsb), dim3(512), 0, stream, a, 2048);
+        LS2_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_sb_sort_lds<16384, 1024>), dim3(g.nsb), dim3(1024), 0, stream, a, 8192);
         LS2_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sb_sort_global, dim3(g.nsb), dim3(1024), 0, stream, a, 16384);
         LS2_LAUNCH_CHECK();
@@ -441,7 +536,8 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
     LS2_LAUNCH_CHECK();
     if (n > 0 && max_pairs > 0) {
-        hipLaunchKernelGGL(k_tile_fill, dim3(round_up8(ntiles)), dim3(64), 0, stream, a);
+        const int fill_threads = g.S * g.S >= 16 ? 1024 : 64 * g.S * g.S;
+        hipLaunchKernelGGL(k_tile_fill, dim3(round_up8(g.nsb)), dim3(fill_threads), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
     if (num_pairs) {

@@ -37,6 +37,36 @@ __device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
     return (unsigned)__builtin_bit_cast(unsigned short, x) | ((unsigned)__builtin_bit_cast(unsigned short, y) << 16);
 }
 
+// Coefficient loads of one 32-pixel block (zeros past the end), issued ahead
+// of use so they overlap the previous block's work.
+template <int L>
+__device__ __forceinline__ void load_coef_bf16path(const DecodeArgs& a, long long bk, int col, int half,
+                                                   float4 (&raw)[L / 16][2]) {
+    const long long p = bk * 32 + col;
+    const bool ok = bk < a.nblocks && p < a.m;
+#pragma unroll
+    for (int ks = 0; ks < L / 16; ++ks) {
+        if (ok) {
+            const float4* src = reinterpret_cast<const float4*>(a.coef + p * L + ks * 16 + half * 8);
+            raw[ks][0] = src[0];
+            raw[ks][1] = src[1];
+        } else {
+            raw[ks][0] = raw[ks][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void load_coef_f32path(const DecodeArgs& a, long long bk, int col, int half,
+                                                  float4 (&raw)[L / 8]) {
+    const long long p = bk * 32 + col;
+    const bool ok = bk < a.nblocks && p < a.m;
+#pragma unroll
+    for (int q = 0; q < L / 8; ++q)
+        raw[q] = ok ? reinterpret_cast<const float4*>(a.coef + p * L + half * (L / 2))[q]
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // ---------------------------------------------------------------------------
 // bf16 compute.  MFMA 32x32x16: A (32 x 16) lane l holds row l%32, k =
 // (l/32)*8 + [0,8); B (16 x 32) lane l holds column l%32, same k; C (32 x 32)
@@ -44,7 +74,7 @@ __device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
 // A = S^T slice (features x k), B = W^T (k x pixels), C = F^T tile.
 // Each wave owns FW = 128 features (4 row tiles of 32).
 template <int L, bool OUT_BF16>
-__global__ __launch_bounds__(256) void k_decode_bf16(DecodeArgs a) {
+__global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeArgs a) {
     constexpr int KS = L / 16;   // k-steps
     constexpr int MT = 4;        // 32-feature tiles per wave
     constexpr int OSZ = OUT_BF16 ? 2 : 4;
@@ -73,24 +103,25 @@ __global__ __launch_bounds__(256) void k_decode_bf16(DecodeArgs a) {
             sa[mt][ks] = v;
         }
 
-    for (long long blk = blockIdx.x / a.nchunks; blk < a.nblocks; blk += gridDim.x / a.nchunks) {
+    // software pipeline: the next block's coefficients are loaded while the
+    // current block is multiplied and written out
+    const long long bstep = gridDim.x / a.nchunks;
+    long long blk = blockIdx.x / a.nchunks;
+    float4 raw[KS][2];
+    load_coef_bf16path<L>(a, blk, col, half, raw);
+    for (; blk < a.nblocks; blk += bstep) {
         const long long p0 = blk * 32;
-        const long long p = p0 + col;
-        // W^T fragments: pixel p, k = ks*16 + half*8 + [0,8)
+        // W^T fragments: pixel p0 + col, k = ks*16 + half*8 + [0,8)
         bf16x8 wb[KS];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            float4 u0 = make_float4(0.f, 0.f, 0.f, 0.f), u1 = u0;
-            if (p < a.m) {
-                const float4* src = reinterpret_cast<const float4*>(a.coef + p * L + ks * 16 + half * 8);
-                u0 = src[0];
-                u1 = src[1];
-            }
+            const float4 u0 = raw[ks][0], u1 = raw[ks][1];
             bf16x8 v;
             v[0] = (__bf16)u0.x; v[1] = (__bf16)u0.y; v[2] = (__bf16)u0.z; v[3] = (__bf16)u0.w;
             v[4] = (__bf16)u1.x; v[5] = (__bf16)u1.y; v[6] = (__bf16)u1.z; v[7] = (__bf16)u1.w;
             wb[ks] = v;
         }
+        load_coef_bf16path<L>(a, blk + bstep, col, half, raw);
         f32x16 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -140,7 +171,7 @@ __global__ __launch_bounds__(256) void k_decode_bf16(DecodeArgs a) {
 // pixel's coefficients as contiguous float4s.  Each wave owns FW = 64
 // features (2 row tiles).
 template <int L, bool OUT_BF16>
-__global__ __launch_bounds__(512) void k_decode_f32(DecodeArgs a) {
+__global__ __launch_bounds__(512, 1) void k_decode_f32(DecodeArgs a) {
     constexpr int KS = L / 2;
     constexpr int MT = 2;
     constexpr int OSZ = OUT_BF16 ? 2 : 4;
@@ -162,16 +193,18 @@ __global__ __launch_bounds__(512) void k_decode_f32(DecodeArgs a) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) sa[mt][s] = a.dict[(size_t)(half * KS + s) * D + f_wave + mt * 32 + col];
 
-    for (long long blk = blockIdx.x / a.nchunks; blk < a.nblocks; blk += gridDim.x / a.nchunks) {
+    const long long bstep = gridDim.x / a.nchunks;
+    long long blk = blockIdx.x / a.nchunks;
+    float4 raw[KS / 4];
+    load_coef_f32path<L>(a, blk, col, half, raw);
+    for (; blk < a.nblocks; blk += bstep) {
         const long long p0 = blk * 32;
-        const long long p = p0 + col;
         float wv[KS];
 #pragma unroll
         for (int q = 0; q < KS / 4; ++q) {
-            float4 u = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (p < a.m) u = reinterpret_cast<const float4*>(a.coef + p * L + half * KS)[q];
-            wv[4 * q] = u.x; wv[4 * q + 1] = u.y; wv[4 * q + 2] = u.z; wv[4 * q + 3] = u.w;
+            wv[4 * q] = raw[q].x; wv[4 * q + 1] = raw[q].y; wv[4 * q + 2] = raw[q].z; wv[4 * q + 3] = raw[q].w;
         }
+        load_coef_f32path<L>(a, blk + bstep, col, half, raw);
         f32x16 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -230,7 +263,7 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
     a.nchunks = a.D / a.FC;
     const int osz = OB ? 2 : 4;
     const size_t lds = (size_t)32 * (a.FC * osz + 16);
-    const int per_cu = lds <= 40 * 1024 ? 4 : (lds <= 80 * 1024 ? 2 : 1);
+    const int per_cu = lds <= 40 * 1024 ? 3 : (lds <= 80 * 1024 ? 2 : 1);
     long long grid = (long long)num_cus() * per_cu;
     grid -= grid % a.nchunks;
     const long long need = a.nblocks * a.nchunks;

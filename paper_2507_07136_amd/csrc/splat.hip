@@ -6,15 +6,19 @@
 //     pixel per lane; the four quadrant waves of a tile walk the same list
 //     independently (no workgroup barriers), so each stops as soon as all of
 //     its own pixels are saturated (ballot over the lanes);
-//   - the wave stages 64 list entries at a time into its own LDS slice (one
-//     entry per lane: a gather of the Gaussian's 2D mean, conic, opacity and
-//     K (index, weight) pairs per level), then every lane reads each entry
-//     back as a broadcast;
-//   - the K indices of the current Gaussian are wave-uniform, so they live in
-//     scalar registers and select a register of the per-lane accumulator
-//     vectors through the VGPR index mode: the L-dim coefficient vector of
-//     each pixel stays in VGPRs (32 floats per vector; L/32 vectors per
-//     level) and each blend touches only the K selected registers.
+//   - the wave stages 64 list entries at a time (one per lane: a gather of
+//     the Gaussian's 2D mean, conic, opacity and K (index, weight) pairs per
+//     level).  The staging lane also tests whether the Gaussian's
+//     alpha >= 1/255 ellipse (inflated for rounding) reaches any pixel centre
+//     of the quadrant; entries that cannot are dropped by an order-preserving
+//     ballot compaction, since every lane would skip them anyway;
+//   - every lane then reads each surviving entry back as an LDS broadcast;
+//   - only the K stored coefficients are blended.  For levels*L <= 128 the
+//     per-pixel L-vectors live in LDS as columns acc[c * 65 + lane] (a blend
+//     is one address add, a read, an FMA and a write; the padded stride keeps
+//     both this access and the coalesced write-out free of bank conflicts).
+//     For larger levels*L they live in VGPRs (32-float vectors selected with
+//     the wave-uniform index through the VGPR index mode).
 #include "ls2_internal.h"
 
 namespace ls2 {
@@ -38,28 +42,57 @@ struct SplatArgs {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
-// Record layout in LDS (dwords): u, v, A2, B2, C2, o, idx words, weights.
-// A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e), so that the
-// Gaussian exponent in base 2 is A2 dx^2 + B2 dx dy + C2 dy^2.
+// Staged record (dwords): u, v, A2, B2, C2, o, list position, idx words,
+// weights.  A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e): the
+// Gaussian's exponent in base 2 is A2 dx^2 + B2 dx dy + C2 dy^2.
 template <int KMAX, int LVMAX>
 struct Rec {
-    static constexpr int KW = (KMAX + 3) / 4;          // packed u8 index words per level
-    static constexpr int IDX = 6;
+    static constexpr int KW = (KMAX + 3) / 4;  // packed u8 index words per level
+    static constexpr int POS = 6;
+    static constexpr int IDX = 7;
     static constexpr int W = IDX + LVMAX * KW;
     static constexpr int RAW = W + LVMAX * KMAX;
-    static constexpr int STRIDE = (RAW + 3) & ~3;      // 16-byte aligned records
+    static constexpr int STRIDE = (RAW + 3) & ~3;  // 16-byte aligned records
 };
 
-// exponent (base 2) of the Gaussian at offset (dx, dy); shared by forward and
-// backward so both take the same decisions bit for bit.
+// Exponent (base 2) of the Gaussian at offset (dx, dy).  The backward pass
+// evaluates the same expression so both take identical decisions.
 __device__ __forceinline__ float gauss_power2(float A2, float B2, float C2, float dx, float dy) {
     return fmaf(dx, fmaf(A2, dx, B2 * dy), C2 * dy * dy);
 }
 
-template <int NV, int KMAX, int LVMAX>
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Can a Gaussian with mean (u, v), conic (A, B, C) and opacity o reach
+// alpha >= 1/255 at any pixel centre of the box [x0, x1] x [y0, y1]?
+// alpha >= 1/255 <=> d^T Q d <= 2 ln(255 o), an ellipse whose bounding box
+// has half-widths sqrt(2 ln(255 o) Sigma_xx) and sqrt(2 ln(255 o) Sigma_yy)
+// with Sigma = Q^-1.  The box is inflated by 1e-3 relative + 0.01 px, far
+// beyond the float32 error of the kernel's own alpha, so a dropped entry is
+// one that every pixel of the box skips.  Degenerate values are kept.
+__device__ __forceinline__ bool may_touch(float u, float v, float A, float B, float C, float o, float x0, float x1,
+                                          float y0, float y1) {
+    if (!(o >= 1.0f / 255.0f)) return o != o;  // o < 1/255 never blends (NaN kept)
+    const float det = A * C - B * B;
+    const float t2 = 2.0f * logf(255.0f * o);
+    if (!(det > 0.0f) || !(t2 >= 0.0f)) return true;
+    const float ex = sqrtf(t2 * C / det) * 1.001f + 0.01f;
+    const float ey = sqrtf(t2 * A / det) * 1.001f + 0.01f;
+    if (!(ex == ex) || !(ey == ey)) return true;
+    return u + ex >= x0 && u - ex <= x1 && v + ey >= y0 && v - ey <= y1;
+}
+
+// EXACT: K == KMAX and levels == LVMAX are known at compile time.
+template <int NV, int KMAX, int LVMAX, bool LDS_ACC, bool EXACT>
 __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
     using R = Rec<KMAX, LVMAX>;
+    constexpr int kStride = 65;  // LDS accumulator column stride
+    constexpr int kRows = LVMAX * NV * 32;
+    constexpr int kAccFloats = LDS_ACC ? (kRows + 1) * kStride : 1;  // + dump row for merged duplicates
+    constexpr int RV = LDS_ACC ? 1 : LVMAX;                          // register accumulators
+    constexpr int RN = LDS_ACC ? 1 : NV;
     __shared__ float4 stage4[64 * R::STRIDE / 4];
+    __shared__ float accs[kAccFloats];
     float* stage = reinterpret_cast<float*>(stage4);
 
     const CamK& cam = a.cam;
@@ -74,54 +107,130 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
     const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
     const bool inside = px < cam.W && py < cam.H;
     const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+    // pixel-centre box of the quadrant's pixels inside the image
+    const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
+    const float bx1 = (float)min(qx0 + 7, cam.W - 1) + 0.5f, by1 = (float)min(qy0 + 7, cam.H - 1) + 0.5f;
 
     const unsigned start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const int levels = a.levels, K = a.K;
-    const int lmask = a.L - 1;
+    const int levels = EXACT ? LVMAX : a.levels, K = EXACT ? KMAX : a.K, L = a.L;
+    const int lmask = L - 1;
+    const unsigned long long lt = (1ull << lane) - 1ull;
 
-    v32f acc[LVMAX][NV];
+    v32f acc[RV][RN];
 #pragma unroll
-    for (int lv = 0; lv < LVMAX; ++lv)
+    for (int lv = 0; lv < RV; ++lv)
 #pragma unroll
-        for (int h = 0; h < NV; ++h) acc[lv][h] = (v32f){};
+        for (int h = 0; h < RN; ++h) acc[lv][h] = (v32f){};
+    if (LDS_ACC)
+        for (int i = lane; i < kAccFloats; i += 64) accs[i] = 0.0f;
 
     float T = 1.0f;
     int last = 0;
     bool active = inside;
 
+    // Software pipeline over 64-entry batches: while batch b is processed,
+    // the records of batch b + 64 and the ids of batch b + 128 are in flight.
+    constexpr bool PREFETCH_CODES = LVMAX * KMAX <= 8;  // also prefetch the (index, weight) pairs
+    constexpr int PK = PREFETCH_CODES ? LVMAX * KMAX : 1;
+    const unsigned kBad = 0xffffffffu;
+    auto fetch_id = [&](unsigned pos) -> unsigned { return pos < end ? a.ids[pos] : kBad; };
+    unsigned nid = fetch_id(start + lane);           // ids of the batch staged next
+    unsigned nid2 = fetch_id(start + 64 + lane);     // ids of the batch after
+    float n_mu = 0.f, n_mv = 0.f, n_cA = 0.f, n_cB = 0.f, n_cC = 0.f, n_op = 0.f;
+    int n_ix[PK];
+    float n_w[PK];
+    auto fetch_rec = [&](unsigned id) {
+        if (id < (unsigned)a.n) {  // an id outside [0, n) can only come from a corrupted list
+            const float2 m = reinterpret_cast<const float2*>(a.mean2d)[id];
+            n_mu = m.x;
+            n_mv = m.y;
+            n_cA = a.conic[3 * id];
+            n_cB = a.conic[3 * id + 1];
+            n_cC = a.conic[3 * id + 2];
+            n_op = a.opacity[id];
+            if (PREFETCH_CODES) {
+#pragma unroll
+                for (int q = 0; q < PK; ++q) {
+                    const int lv = q / KMAX, k = q % KMAX;
+                    const bool ok = lv < levels && k < K;
+                    const size_t o = ((size_t)id * levels + lv) * K + k;
+                    n_ix[q] = ok ? a.topk_idx[o] : 0;
+                    n_w[q] = ok ? a.topk_w[o] : 0.0f;
+                }
+            }
+        } else {
+            n_op = 0.0f;
+        }
+    };
+    fetch_rec(nid);
+
     for (unsigned b = start; b < end; b += 64) {
         if (__builtin_amdgcn_ballot_w64(active) == 0) break;
         const int nb = (int)min(64u, end - b);
-        // ---- stage: lane j gathers entry b + j
-        if (lane < nb) {
-            unsigned id = a.ids[b + lane];
-            float* r = stage + lane * R::STRIDE;
-            // an id outside [0, n) can only come from a corrupted list; read
-            // Gaussian 0 instead and make the entry transparent
-            const bool bad = id >= (unsigned)a.n;
-            if (bad) id = 0;
-            const float2 m = reinterpret_cast<const float2*>(a.mean2d)[id];
-            const float cA = a.conic[3 * id], cB = a.conic[3 * id + 1], cC = a.conic[3 * id + 2];
-            r[0] = m.x;
-            r[1] = m.y;
+        // ---- stage: lane j holds entry b + j (fetched one batch ago)
+        const unsigned id = nid;
+        const float mu = n_mu, mv = n_mv, cA = n_cA, cB = n_cB, cC = n_cC, op = n_op;
+        int c_ix[PK];
+        float c_w[PK];
+#pragma unroll
+        for (int q = 0; q < PK; ++q) {
+            c_ix[q] = n_ix[q];
+            c_w[q] = n_w[q];
+        }
+        const bool keep = lane < nb && id < (unsigned)a.n && may_touch(mu, mv, cA, cB, cC, op, bx0, bx1, by0, by1);
+        // prefetch: records of batch b + 64, ids of batch b + 128
+        nid = nid2;
+        fetch_rec(nid);
+        nid2 = fetch_id(b + 128 + lane);
+        const unsigned long long kmask = __builtin_amdgcn_ballot_w64(keep);
+        const int nkeep = __builtin_popcountll(kmask);
+        __syncthreads();  // single-wave workgroup: the previous batch's stage reads are done
+        if (keep) {
+            float* r = stage + __builtin_popcountll(kmask & lt) * R::STRIDE;
+            r[0] = mu;
+            r[1] = mv;
             r[2] = -0.5f * kLog2e * cA;
             r[3] = -kLog2e * cB;
             r[4] = -0.5f * kLog2e * cC;
-            r[5] = bad ? 0.0f : a.opacity[id];
+            r[5] = op;
+            reinterpret_cast<unsigned*>(r)[R::POS] = b - start + lane;
 #pragma unroll
             for (int lv = 0; lv < LVMAX; ++lv) {
                 if (lv < levels) {
                     const size_t base = ((size_t)id * levels + lv) * K;
-                    unsigned wd[R::KW];
-#pragma unroll
-                    for (int q = 0; q < R::KW; ++q) wd[q] = 0;
+                    unsigned ix[KMAX];
+                    float wv[KMAX];
 #pragma unroll
                     for (int k = 0; k < KMAX; ++k) {
-                        if (k < K) {
-                            const unsigned ix = (unsigned)(a.topk_idx[base + k] & lmask);
-                            wd[k >> 2] |= ix << (8 * (k & 3));
-                            r[R::W + lv * KMAX + k] = a.topk_w[base + k];
+                        if (PREFETCH_CODES) {
+                            ix[k] = k < K ? (unsigned)(c_ix[lv * KMAX + k] & lmask) : 0u;
+                            wv[k] = k < K ? c_w[lv * KMAX + k] : 0.0f;
+                        } else {
+                            ix[k] = k < K ? (unsigned)(a.topk_idx[base + k] & lmask) : 0u;
+                            wv[k] = k < K ? a.topk_w[base + k] : 0.0f;
                         }
+                    }
+                    if (LDS_ACC) {
+                        // merge repeated indices so the K read-modify-writes of one
+                        // Gaussian touch distinct accumulators (they are issued
+                        // together); freed slots point at the dump row (0xff)
+#pragma unroll
+                        for (int k = 1; k < KMAX; ++k)
+#pragma unroll
+                            for (int k2 = 0; k2 < k; ++k2)
+                                if (k < K && ix[k2] == ix[k] && ix[k] != 0xffu) {
+                                    wv[k2] += wv[k];
+                                    wv[k] = 0.0f;
+                                    ix[k] = 0xffu;
+                                }
+                    }
+                    unsigned wd[R::KW];
+#pragma unroll
+                    for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k) {
+                        wd[k >> 2] |= ix[k] << (8 * (k & 3));
+                        r[R::W + lv * KMAX + k] = wv[k];
                     }
 #pragma unroll
                     for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + lv * R::KW + q] = wd[q];
@@ -130,74 +239,116 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
         }
         __syncthreads();  // single-wave workgroup: orders the LDS writes before the reads
 
-        for (int j = 0; j < nb; ++j) {
+        for (int j = 0; j < nkeep; ++j) {
             const float* r = stage + j * R::STRIDE;
             const float4 h0 = *reinterpret_cast<const float4*>(r);
-            const float2 h1 = *reinterpret_cast<const float2*>(r + 4);
+            const float4 h1 = *reinterpret_cast<const float4*>(r + 4);
             const float dx = h0.x - pxc, dy = h0.y - pyc;
             const float p2 = gauss_power2(h0.z, h0.w, h1.x, dx, dy);
-            const float g = h1.y * exp2f(p2);
+            const float g = h1.y * fast_exp2(p2);
             const float alpha = fminf(0.99f, g);
-            const float testT = T * (1.0f - alpha);
+            const float c = alpha * T;       // blend weight e_i = alpha_i T_i (Eq. 7)
+            const float testT = T - c;       // T (1 - alpha)
             const bool hit = active && p2 <= 0.0f && alpha >= (1.0f / 255.0f);
             const bool stop = hit && testT < 1e-4f;
             const bool contrib = hit && !stop;
             active = active && !stop;
-            const float c = contrib ? alpha * T : 0.0f;
-            if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
+            if (contrib) {  // divergent: only contributing lanes blend (exec mask)
 #pragma unroll
                 for (int lv = 0; lv < LVMAX; ++lv) {
                     if (lv < levels) {
+                        unsigned words[R::KW];
 #pragma unroll
-                        for (int k = 0; k < KMAX; ++k) {
-                            if (k < K) {
-                                const unsigned word = __builtin_amdgcn_readfirstlane(
-                                    reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + (k >> 2)]);
-                                const unsigned ix = (word >> (8 * (k & 3))) & 0xffu;
-                                const float w = __uint_as_float(__builtin_amdgcn_readfirstlane(
-                                    __float_as_uint(r[R::W + lv * KMAX + k])));
-                                const float x = w * c;
-                                const unsigned jl = ix & 31u, jh = ix >> 5;
+                        for (int q = 0; q < R::KW; ++q)
+                            words[q] = __builtin_amdgcn_readfirstlane(
+                                reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
+                        if (LDS_ACC) {
+                            float* col = accs + lane;
+                            float v[KMAX];
+                            int off[KMAX];
 #pragma unroll
-                                for (int h = 0; h < NV; ++h) acc[lv][h][jl] += (jh == (unsigned)h) ? x : 0.0f;
+                            for (int k = 0; k < KMAX; ++k) {
+                                if (k < K) {
+                                    const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                                    const int row = ix == 0xffu ? kRows : lv * L + (int)ix;
+                                    off[k] = row * kStride;
+                                    v[k] = col[off[k]];
+                                }
+                            }
+#pragma unroll
+                            for (int k = 0; k < KMAX; ++k)
+                                if (k < K) col[off[k]] = fmaf(r[R::W + lv * KMAX + k], c, v[k]);
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < KMAX; ++k) {
+                                if (k < K) {
+                                    const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                                    const float x = r[R::W + lv * KMAX + k] * c;
+                                    const unsigned jl = ix & 31u, jh = ix >> 5;
+#pragma unroll
+                                    for (int hh = 0; hh < RN; ++hh)
+                                        acc[lv < RV ? lv : 0][hh][jl] += (jh == (unsigned)hh) ? x : 0.0f;
+                                }
                             }
                         }
                     }
                 }
-                if (contrib) {
-                    T = testT;
-                    last = (int)(b - start) + j + 1;
-                }
+                T = testT;
+                last = __float_as_int(h1.z) + 1;  // record dword POS: list position
             }
-            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+            if ((j & 7) == 7 && __builtin_amdgcn_ballot_w64(active) == 0) break;
         }
-        __syncthreads();  // the next batch overwrites the stage
     }
 
-    if (!inside) return;
     const size_t HW = (size_t)cam.W * cam.H;
+    if (LDS_ACC) {
+        __syncthreads();
+        // coalesced write-out: each store instruction covers 64 x 16 bytes of
+        // one quadrant row (the row's 8 pixels x L floats are contiguous)
+        const int f4_per_px = L / 4;
+        const int f4_per_row = 8 * f4_per_px;
+        for (int lv = 0; lv < levels; ++lv) {
+            for (int ry = 0; ry < 8; ++ry) {
+                const int gy = qy0 + ry;
+                if (gy >= cam.H) break;
+                float4* rowbase = reinterpret_cast<float4*>(a.coef + ((size_t)lv * HW + (size_t)gy * cam.W + qx0) * L);
+                for (int f = lane; f < f4_per_row; f += 64) {
+                    const int pxl = f / f4_per_px, c4 = f - pxl * f4_per_px;
+                    if (qx0 + pxl >= cam.W) continue;
+                    const float* src = accs + (lv * L + 4 * c4) * kStride + ry * 8 + pxl;
+                    rowbase[f] = make_float4(src[0], src[kStride], src[2 * kStride], src[3 * kStride]);
+                }
+            }
+        }
+    }
+    if (!inside) return;
     const size_t pix = (size_t)py * cam.W + px;
+    if (!LDS_ACC) {
 #pragma unroll
-    for (int lv = 0; lv < LVMAX; ++lv) {
-        if (lv < levels) {
-            float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv * HW + pix) * (size_t)(NV * 32));
+        for (int lv = 0; lv < RV; ++lv) {
+            if (lv < levels) {
+                float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv * HW + pix) * (size_t)(RN * 32));
 #pragma unroll
-            for (int h = 0; h < NV; ++h)
+                for (int h = 0; h < RN; ++h)
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    dst[h * 8 + q] = make_float4(acc[lv][h][4 * q], acc[lv][h][4 * q + 1], acc[lv][h][4 * q + 2],
-                                                 acc[lv][h][4 * q + 3]);
+                    for (int q = 0; q < 8; ++q)
+                        dst[h * 8 + q] = make_float4(acc[lv][h][4 * q], acc[lv][h][4 * q + 1], acc[lv][h][4 * q + 2],
+                                                     acc[lv][h][4 * q + 3]);
+            }
         }
     }
     if (a.final_T) a.final_T[pix] = T;
     if (a.last) a.last[pix] = last;
 }
 
-template <int NV, int KMAX, int LVMAX>
+template <int NV, int KMAX, int LVMAX, bool LDS_ACC>
 static int launch_splat(const SplatArgs& a, hipStream_t stream) {
     const int ntiles = a.cam.tx * a.cam.ty;
     const int grid = round_up8(ntiles * 4);
-    hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, LVMAX>), dim3(grid), dim3(64), 0, stream, a);
+    if (a.K == KMAX && a.levels == LVMAX)
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, LVMAX, LDS_ACC, true>), dim3(grid), dim3(64), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, LVMAX, LDS_ACC, false>), dim3(grid), dim3(64), 0, stream, a);
     LS2_LAUNCH_CHECK();
     return LS2_OK;
 }
@@ -232,14 +383,18 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
     a.final_T = final_T;
     a.last = last;
     const bool k8 = K > 4;
-    const bool l3 = levels > 1;
-    if (L == 32) {
-        if (l3) return k8 ? launch_splat<1, 8, 3>(a, stream) : launch_splat<1, 4, 3>(a, stream);
-        return k8 ? launch_splat<1, 8, 1>(a, stream) : launch_splat<1, 4, 1>(a, stream);
+    // LDS accumulators while levels * L <= 128 (at most 33.5 KB per wave): the
+    // row of level lv, coefficient c is lv * L + c, so NV * 32 * LVMAX >= levels * L
+    if (levels == 1) {
+        if (L == 32) return k8 ? launch_splat<1, 8, 1, true>(a, stream) : launch_splat<1, 4, 1, true>(a, stream);
+        if (L == 64) return k8 ? launch_splat<2, 8, 1, true>(a, stream) : launch_splat<2, 4, 1, true>(a, stream);
+        return k8 ? launch_splat<4, 8, 1, true>(a, stream) : launch_splat<4, 4, 1, true>(a, stream);
     }
-    if (L == 64) {
-        if (l3) return k8 ? launch_splat<2, 8, 3>(a, stream) : launch_splat<2, 4, 3>(a, stream);
-        return k8 ? launch_splat<2, 8, 1>(a, stream) : launch_splat<2, 4, 1>(a, stream);
+    if (levels == 2) {
+        if (L == 32) return k8 ? launch_splat<1, 8, 2, true>(a, stream) : launch_splat<1, 4, 2, true>(a, stream);
+        return k8 ? launch_splat<2, 8, 2, true>(a, stream) : launch_splat<2, 4, 2, true>(a, stream);  // L = 64
     }
-    return k8 ? launch_splat<4, 8, 1>(a, stream) : launch_splat<4, 4, 1>(a, stream);
+    if (L == 32) return k8 ? launch_splat<1, 8, 3, true>(a, stream) : launch_splat<1, 4, 3, true>(a, stream);
+    // three levels of 64 coefficients: 192 accumulators per pixel in VGPRs
+    return k8 ? launch_splat<2, 8, 3, false>(a, stream) : launch_splat<2, 4, 3, false>(a, stream);
 }
