@@ -81,6 +81,74 @@ def cpu_baseline(cam, scene, frac):
                                                decode=(t4 - t3) * scale))
 
 
+def train_step_timing(args, torch, np, gen, ls2):
+    """Forward + backward of the feature-map objective on the differentiation
+    workload (float32 throughout): project, bin_sort, splat, decode, loss,
+    then decode / splat / projection backward.  Per-stage HIP events."""
+    cfg = gen.CONFIGS[args.train_config]
+    scene, cam = gen.config_scene(args.train_config)
+    zup, Pf = gen.make_target_factors(cfg["seed"] * 100, cfg["height"], cfg["width"], D=cfg["D"])
+    # the target map Y = Zup P is materialised on the device (input preparation, outside the timed region)
+    Y = (torch.from_numpy(zup).cuda().reshape(-1, zup.shape[-1]) @ torch.from_numpy(Pf).cuda()).reshape(
+        cfg["levels"], cfg["height"], cfg["width"], cfg["D"]).contiguous()
+    t = ls2.to_device(scene)
+    tr = ls2.Trainer(cam, scene.n, levels=scene.levels, K=scene.K, L=scene.L, D=scene.D)
+    tr.forward_loss(t, Y, sync=True)          # sizes the pair buffers
+    names = ["project", "bin_sort", "splat", "decode_f32", "loss", "decode_bw", "splat_bw", "project_bw"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        tr.project(t["means"], t["scales"], t["quats"])
+        mark(1)
+        tr.bin_sort(sync=False)
+        mark(2)
+        tr.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+        mark(3)
+        tr.decode(t["dictionary"], ls2.LS2_F32, torch.float32)
+        mark(4)
+        ls2.ls2_feature_loss(tr.feat, Y, tr.loss, tr.d_feat, tr.loss_ws)
+        mark(5)
+        g = tr.grad
+        m = tr.levels * tr.H * tr.W
+        ls2.ls2_dict_decode_backward(tr.coef.view(m, tr.L), t["dictionary"], tr.d_feat.view(m, tr.D),
+                                     g.coef.view(m, tr.L), g.dictionary, tr.dec_ws)
+        mark(6)
+        ls2.ls2_splat_sparse_backward(tr.cam, tr.levels, tr.K, tr.L, tr.tile_ranges, tr.ids, tr.mean2d, tr.conic,
+                                      t["opacity"], t["topk_idx"], t["topk_w"], tr.final_T, tr.last, g.coef,
+                                      g.mean2d, g.conic, g.opacity, g.topk_w)
+        mark(7)
+        ls2.ls2_project_backward(tr.cam, t["means"], t["scales"], t["quats"], tr.radius, g.mean2d, g.conic,
+                                 g.means, g.scales, g.quats)
+        mark(8)
+
+    steps = max(5, args.steps // 2)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(9)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s_ in range(steps):
+        step(evs[s_])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = {names[i]: round(float(np.mean([evs[s_][i].elapsed_time(evs[s_][i + 1]) for s_ in range(steps)])), 4)
+           for i in range(len(names))}
+    ms = 1000.0 * wall / steps
+    m = scene.levels * cam.height * cam.width
+    dec_bw_flops = 4.0 * m * scene.L * scene.D
+    log("fwd+bwd: %.3f ms/step, stages %s, loss %.6f" % (ms, per, tr.loss.item()))
+    return dict(ms=ms, steps=steps, workload="%s: %d Gaussians, %dx%d, L=%d, K=%d, D=%d, L1+cosine loss vs a smooth "
+                "random 512-D target, float32" % (args.train_config, scene.n, cam.width, cam.height, scene.L,
+                                                   scene.K, scene.D),
+                stages_ms=per, loss=tr.loss.item(),
+                decode_bw_tflops=round(dec_bw_flops / (per["decode_bw"] * 1e-3) / 1e12, 2),
+                decode_bw_frac_f32_peak=round(dec_bw_flops / (per["decode_bw"] * 1e-3) / 1e12 / F32_MFMA_PEAK_TFLOPS,
+                                              4))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +158,8 @@ def main():
     ap.add_argument("--cpu-frac", type=float, default=0.05, help="pixel fraction for the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path measurement")
+    ap.add_argument("--no-train", action="store_true", help="skip the forward+backward (training step) timing")
+    ap.add_argument("--train-config", default="c3")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -188,6 +258,12 @@ def main():
     mfma = dict(decode_tflops=decode_flops / (per["decode"] * 1e-3) / 1e12,
                 decode_frac_bf16_peak=decode_flops / (per["decode"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS)
 
+    train = None
+    if not args.no_train:
+        del pipe
+        torch.cuda.empty_cache()
+        train = train_step_timing(args, torch, np, gen, ls2)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
@@ -214,7 +290,8 @@ def main():
         "query_fps": round(query_fps, 2),
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},
-        "fwd_bwd_ms": None,
+        "fwd_bwd_ms": None if train is None else round(train["ms"], 4),
+        "fwd_bwd": train,
         "roofline": roofline,
         "roofline_stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                             for k, v in roof_all.items()},

@@ -170,6 +170,104 @@ int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coef, const fl
 int ls2_query(int64_t m, int32_t D, const void* feat, int32_t feat_dtype, const float* pos,
               int32_t n_neg, const float* neg, float tau, float* relevancy, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Backward pass.  The sparse coefficients and the codebook are learned
+ * jointly (Section 3.3); these entry points give the gradients of every
+ * forward stage, in reverse order: feature loss -> decode -> splat ->
+ * project (or query -> decode -> ...).  All arithmetic is float32.  Gradient
+ * outputs are OVERWRITTEN (the library clears what it accumulates into).
+ * Gradients are taken with respect to the activated values the forward
+ * consumes (scales > 0, opacity in (0,1), normalised-in-kernel quaternions).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * ls2_feature_loss -- training objective between the rendered feature map
+ * and a target feature map Y (the 2D feature maps the field is fitted to,
+ * Section 4.1; the paper does not print the loss, this library uses
+ *     loss = mean_{v,d} |F - Y| + mean_v (1 - cos(F(v), Y(v))),
+ * norms guarded below by 1e-12, sign(0) = 0).
+ *
+ * In:  feat [m,D] f32, target [m,D] f32.
+ * Out: loss (device, one double); d_feat [m,D] f32 = dloss/dF (optional:
+ *      NULL computes the loss only).
+ * workspace: at least ls2_feature_loss_workspace() bytes, 8-byte aligned.
+ * The loss is reduced in a fixed order (deterministic).
+ * Supported: D a multiple of 64 up to 1024; m >= 1.
+ */
+int ls2_feature_loss_workspace(int64_t m, size_t* bytes);
+int ls2_feature_loss(int64_t m, int32_t D, const float* feat, const float* target, double* loss,
+                     float* d_feat, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * ls2_query_backward -- d_feat = d_rel * dr/dF for the relevancy of
+ * ls2_query (Section 3.2, LERF form).  The minimum over negatives selects the
+ * first negative of largest similarity; its (sub)gradient is used.
+ *
+ * In:  feat [m,D] f32 or bf16 (feat_dtype), pos [D], neg [n_neg,D], tau,
+ *      d_rel [m] f32.
+ * Out: d_feat [m,D] f32.
+ * Supported: D a multiple of 64 up to 1024, 1 <= n_neg <= 8.
+ */
+int ls2_query_backward(int64_t m, int32_t D, const void* feat, int32_t feat_dtype, const float* pos,
+                       int32_t n_neg, const float* neg, float tau, const float* d_rel, float* d_feat,
+                       hipStream_t stream);
+
+/*
+ * ls2_dict_decode_backward -- gradients of F = W S (Eq. 7):
+ *     d_coef = d_feat S^T  [m,L],     d_dict = coef^T d_feat  [L,D]
+ * (all levels share S, so their rows are summed into one d_dict).
+ *
+ * In:  coef [m,L], dict [L,D], d_feat [m,D], all f32.
+ * compute: LS2_F32 (float32 matrix-core products; the only form built).
+ * Out: d_coef [m,L] (optional), d_dict [L,D] (optional; at least one of the
+ *      two must be requested).  d_dict is reduced in a fixed order
+ *      (deterministic).
+ * workspace: at least ls2_dict_decode_backward_workspace() bytes when d_dict
+ *      is requested (partial sums over pixel ranges), 16-byte aligned.
+ * Supported: L in {32, 64, 128}; D in {128, 256, 384, 512, 1024}.
+ */
+int ls2_dict_decode_backward_workspace(int64_t m, int32_t L, int32_t D, size_t* bytes);
+int ls2_dict_decode_backward(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                             int32_t compute, const float* d_feat, float* d_coef, float* d_dict,
+                             void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * ls2_splat_sparse_backward -- gradients of ls2_splat_sparse (Algorithm 1,
+ * Eq. 3) from d_coef = dL/dcoef.  For one pixel with contributors i (front
+ * to back), e_i = alpha_i T_i and c_i = sum_{l,k} d_coef_l[idx_ilk] w_ilk:
+ *     d topk_w_ilk += d_coef_l[idx_ilk] e_i,
+ *     dL/dalpha_i   = T_i c_i - (sum_{m>i} c_m e_m) / (1 - alpha_i),
+ * then through alpha = o exp(-0.5 d^T conic d) (no gradient where alpha is
+ * clamped at 0.99) to opacity, mean2d and conic.  The pixel's contributors
+ * and T_i are recovered from the forward's final_T and last, with alpha
+ * evaluated by the same instructions as the forward.
+ *
+ * In:  the forward's inputs (tile_ranges .. topk_w) and outputs final_T [H,W]
+ *      and last [H,W] (both required); d_coef [levels,H,W,L].
+ * Out: d_mean2d [n,2], d_conic [n,3] (A, B, C as in ls2_project),
+ *      d_opacity [n], d_topk_w [n,levels,K].  Accumulated with float atomics:
+ *      the summation order (and the last bits) may vary between runs.
+ * Supported: as ls2_splat_sparse.
+ */
+int ls2_splat_sparse_backward(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                              const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                              const float* conic, const float* opacity, const int32_t* topk_idx,
+                              const float* topk_w, const float* final_T, const int32_t* last,
+                              const float* d_coef, float* d_mean2d, float* d_conic, float* d_opacity,
+                              float* d_topk_w, hipStream_t stream);
+
+/*
+ * ls2_project_backward -- gradients of ls2_project (Section 3.1, Eqs. 1-2,
+ * EWA projection as in ls2_project) from d_mean2d [n,2] and d_conic [n,3]
+ * to d_means [n,3], d_scales [n,3] and d_quats [n,4] (through the
+ * normalisation q / |q|).  Depth and radius carry no gradient.  Culled
+ * Gaussians (radius [n] from the forward is 0) get zeros.
+ */
+int ls2_project_backward(const ls2_camera* cam, int32_t n, const float* means, const float* scales,
+                         const float* quats, const int32_t* radius, const float* d_mean2d,
+                         const float* d_conic, float* d_means, float* d_scales, float* d_quats,
+                         hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,11 +18,18 @@ from ._lib import (  # noqa: F401
     ls2_bin_sort_count,
     ls2_bin_sort_workspace,
     ls2_dict_decode,
+    ls2_dict_decode_backward,
+    ls2_dict_decode_backward_workspace,
+    ls2_feature_loss,
+    ls2_feature_loss_workspace,
     ls2_project,
+    ls2_project_backward,
     ls2_query,
+    ls2_query_backward,
     ls2_splat_sparse,
+    ls2_splat_sparse_backward,
     make_camera,
     status_string,
     version,
 )
-from .render import Pipeline, to_device  # noqa: F401
+from .render import Gradients, LS2Render, Pipeline, Trainer, to_device  # noqa: F401

@@ -51,6 +51,13 @@ def _load():
         "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_dict_decode": ([i64, i32, i32, P, P, i32, i32, P, P], ctypes.c_int),
         "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
+        "ls2_feature_loss_workspace": ([i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_feature_loss": ([i64, i32, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "ls2_query_backward": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P, P], ctypes.c_int),
+        "ls2_dict_decode_backward_workspace": ([i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_dict_decode_backward": ([i64, i32, i32, P, P, i32, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "ls2_splat_sparse_backward": ([cam, i32, i32, i32, i32] + [P] * 15, ctypes.c_int),
+        "ls2_project_backward": ([cam, i32] + [P] * 9 + [P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -207,3 +214,86 @@ def ls2_query(feat, pos, neg, relevancy, tau=1.0, stream=None):
                         n_neg, _ptr(neg, torch.float32, "neg", n_neg * D), float(tau),
                         _ptr(relevancy, torch.float32, "relevancy", m), _stream(stream))
     _check("ls2_query", st)
+
+
+# ------------------------------------------------------------------ backward
+def ls2_feature_loss_workspace(m) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_feature_loss_workspace", _lib.ls2_feature_loss_workspace(int(m), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_feature_loss(feat, target, loss, d_feat, workspace, stream=None):
+    """loss: float64 device tensor with one element; d_feat may be None."""
+    D = feat.shape[-1]
+    m = feat.numel() // D
+    f32 = torch.float32
+    st = _lib.ls2_feature_loss(m, D, _ptr(feat, f32, "feat", m * D), _ptr(target, f32, "target", m * D),
+                               _ptr(loss, torch.float64, "loss", 1),
+                               _ptr(d_feat, f32, "d_feat", m * D, allow_none=True),
+                               _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
+    _check("ls2_feature_loss", st)
+
+
+def ls2_query_backward(feat, pos, neg, d_rel, d_feat, tau=1.0, stream=None):
+    D = pos.shape[-1]
+    m = feat.numel() // D
+    n_neg = neg.numel() // D
+    st = _lib.ls2_query_backward(m, D, _ptr(feat, None, "feat", m * D), _dtype_code(feat),
+                                 _ptr(pos, torch.float32, "pos", D), n_neg,
+                                 _ptr(neg, torch.float32, "neg", n_neg * D), float(tau),
+                                 _ptr(d_rel, torch.float32, "d_rel", m), _ptr(d_feat, torch.float32, "d_feat", m * D),
+                                 _stream(stream))
+    _check("ls2_query_backward", st)
+
+
+def ls2_dict_decode_backward_workspace(m, L, D) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_dict_decode_backward_workspace",
+           _lib.ls2_dict_decode_backward_workspace(int(m), int(L), int(D), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_dict_decode_backward(coef, dictionary, d_feat, d_coef, d_dict, workspace=None, compute=LS2_F32,
+                             stream=None):
+    L, D = dictionary.shape
+    m = d_feat.numel() // D
+    f32 = torch.float32
+    st = _lib.ls2_dict_decode_backward(
+        m, L, D, _ptr(coef, f32, "coef", m * L, allow_none=True), _ptr(dictionary, f32, "dict", L * D),
+        int(compute), _ptr(d_feat, f32, "d_feat", m * D), _ptr(d_coef, f32, "d_coef", m * L, allow_none=True),
+        _ptr(d_dict, f32, "d_dict", L * D, allow_none=True),
+        _ptr(workspace, torch.uint8, "workspace", allow_none=True),
+        0 if workspace is None else workspace.numel(), _stream(stream))
+    _check("ls2_dict_decode_backward", st)
+
+
+def ls2_splat_sparse_backward(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
+                              final_T, last, d_coef, d_mean2d, d_conic, d_opacity, d_topk_w, stream=None):
+    n = opacity.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    HW = c.width * c.height
+    f32, i32 = torch.float32, torch.int32
+    st = _lib.ls2_splat_sparse_backward(
+        ctypes.byref(c), n, int(levels), int(K), int(L), _ptr(tile_ranges, i32, "tile_ranges"),
+        _ptr(ids, i32, "ids"), _ptr(mean2d, f32, "mean2d", 2 * n), _ptr(conic, f32, "conic", 3 * n),
+        _ptr(opacity, f32, "opacity", n), _ptr(topk_idx, i32, "topk_idx", n * levels * K),
+        _ptr(topk_w, f32, "topk_w", n * levels * K), _ptr(final_T, f32, "final_T", HW),
+        _ptr(last, i32, "last", HW), _ptr(d_coef, f32, "d_coef", levels * HW * L),
+        _ptr(d_mean2d, f32, "d_mean2d", 2 * n), _ptr(d_conic, f32, "d_conic", 3 * n),
+        _ptr(d_opacity, f32, "d_opacity", n), _ptr(d_topk_w, f32, "d_topk_w", n * levels * K), _stream(stream))
+    _check("ls2_splat_sparse_backward", st)
+
+
+def ls2_project_backward(cam, means, scales, quats, radius, d_mean2d, d_conic, d_means, d_scales, d_quats,
+                         stream=None):
+    n = means.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    f32 = torch.float32
+    st = _lib.ls2_project_backward(
+        ctypes.byref(c), n, _ptr(means, f32, "means", 3 * n), _ptr(scales, f32, "scales", 3 * n),
+        _ptr(quats, f32, "quats", 4 * n), _ptr(radius, torch.int32, "radius", n),
+        _ptr(d_mean2d, f32, "d_mean2d", 2 * n), _ptr(d_conic, f32, "d_conic", 3 * n),
+        _ptr(d_means, f32, "d_means", 3 * n), _ptr(d_scales, f32, "d_scales", 3 * n),
+        _ptr(d_quats, f32, "d_quats", 4 * n), _stream(stream))
+    _check("ls2_project_backward", st)

@@ -1,0 +1,322 @@
+// ls2_dict_decode_backward: gradients of F = W S (Eq. 7) given G = dL/dF:
+//   dW = G S^T   [m x L]   (contraction over the D features),
+//   dS = W^T G   [L x D]   (contraction over the m pixels; with several
+//                           levels sharing S, their rows are simply more
+//                           pixels of the same product).
+// Both are float32 products on the matrix cores (v_mfma_f32_32x32x2_f32):
+// at 2 m L D flops each they are bound by the fp32 MFMA rate, not by the
+// one read of G they each need.
+//
+// dW: persistent workgroups of 8 waves; S (or a column chunk of it) lives in
+//     LDS, each wave computes [L x 32 MT] tiles of dW^T for its pixels with
+//     the reduction over D permuted so every lane reads its pixel's gradient
+//     as contiguous 64-byte runs.
+// dS: split-K over pixels.  Workgroup (part, column chunk) accumulates its
+//     [L x chunk] slice over a contiguous pixel range in registers and writes
+//     it to the workspace; a second kernel sums the parts in a fixed order,
+//     so the result is deterministic.
+#include "ls2_internal.h"
+
+namespace ls2 {
+
+typedef float f32x16b __attribute__((ext_vector_type(16)));
+
+struct DecodeBwArgs {
+    long long m;
+    int L, D;
+    const float* coef;
+    const float* dict;
+    const float* d_feat;
+    float* d_coef;
+    float* ws;       // [nparts][L][D]
+    float* d_dict;
+    int DC;          // dict columns per LDS chunk (dW kernel)
+    int nparts;      // pixel parts (dS kernel)
+    int DWG;         // columns per dS workgroup
+    long long part_len;  // pixels per part (multiple of 32)
+};
+
+constexpr int kDcoefWaves = 8;
+
+// dW^T tile [L x 32] per pixel tile: C = A B with A = S rows (32 x 2, lane l:
+// row l%32, k = l/32) and B = G^T (2 x 32, lane l: pixel l%32, k = l/32).
+// Step j of a 32-column group pairs column c0 + j (half 0) with c0 + 16 + j
+// (half 1), so each lane reads 16 consecutive floats of its row.
+template <int L, int MT>
+__global__ __launch_bounds__(kDcoefWaves * 64, 1) void k_dcoef(DecodeBwArgs a) {
+    constexpr int TL = L / 32;
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int DC = a.DC, D = a.D;
+    const int sstride = DC + 4;
+    const int nch = D / DC;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const long long wg_pix = (long long)kDcoefWaves * 32 * MT;
+    const long long nblk = (a.m + wg_pix - 1) / wg_pix;
+
+    auto load_chunk = [&](int ch) {
+        const int f4_row = DC / 4;
+        for (int i = threadIdx.x; i < L * f4_row; i += blockDim.x) {
+            const int r = i / f4_row, c4 = i - r * f4_row;
+            const float4 v = reinterpret_cast<const float4*>(a.dict + (size_t)r * D + (size_t)ch * DC)[c4];
+            *reinterpret_cast<float4*>(lds + r * sstride + 4 * c4) = v;
+        }
+    };
+    if (nch == 1) {
+        load_chunk(0);
+        __syncthreads();
+    }
+    for (long long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const long long pw = blk * wg_pix + (long long)wave * 32 * MT;  // the wave's first pixel
+        f32x16b acc[TL][MT];
+#pragma unroll
+        for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[tl][mt] = (f32x16b){};
+        const float* grow[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            long long p = pw + mt * 32 + col;
+            if (p >= a.m) p = a.m - 1;  // clamped rows are computed but not stored
+            grow[mt] = a.d_feat + p * D + half * 16;
+        }
+        for (int ch = 0; ch < nch; ++ch) {
+            if (nch > 1) {
+                __syncthreads();
+                load_chunk(ch);
+                __syncthreads();
+            }
+            for (int c0 = 0; c0 < DC; c0 += 32) {
+                float4 g[MT][4];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        g[mt][q] = reinterpret_cast<const float4*>(grow[mt] + (size_t)ch * DC + c0)[q];
+                float4 s[TL][4];
+#pragma unroll
+                for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        s[tl][q] = *reinterpret_cast<const float4*>(lds + (32 * tl + col) * sstride + c0 + half * 16 +
+                                                                    4 * q);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+#pragma unroll
+                        for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt) {
+                                const float sv = e == 0 ? s[tl][q].x : e == 1 ? s[tl][q].y : e == 2 ? s[tl][q].z : s[tl][q].w;
+                                const float gv = e == 0 ? g[mt][q].x : e == 1 ? g[mt][q].y : e == 2 ? g[mt][q].z : g[mt][q].w;
+                                acc[tl][mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sv, gv, acc[tl][mt], 0, 0, 0);
+                            }
+            }
+        }
+        // C[row, pixel]: lane holds rows 8 g + 4 half + i of pixel col
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const long long p = pw + mt * 32 + col;
+            if (p < a.m) {
+#pragma unroll
+                for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                    for (int gq = 0; gq < 4; ++gq)
+                        *reinterpret_cast<float4*>(a.d_coef + p * L + 32 * tl + 8 * gq + 4 * half) =
+                            make_float4(acc[tl][mt][4 * gq], acc[tl][mt][4 * gq + 1], acc[tl][mt][4 * gq + 2],
+                                        acc[tl][mt][4 * gq + 3]);
+            }
+        }
+    }
+}
+
+// dS partial [L x 32 TD] per wave: C = A B with A = W^T (32 x 2, lane l:
+// atom row l%32, pixel k = l/32) and B = G (2 x 32, lane l: feature l%32,
+// pixel k = l/32).  Step j of a 32-pixel group pairs pixel j (half 0) with
+// pixel 16 + j (half 1).
+template <int L, int TD>
+__global__ __launch_bounds__(512) void k_ddict_partial(DecodeBwArgs a) {
+    constexpr int TL = L / 32;
+    const int D = a.D;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const int nchunk = D / a.DWG;
+    const int part = blockIdx.x / nchunk, chunk = blockIdx.x - part * nchunk;
+    const int d0 = chunk * a.DWG + wave * 32 * TD;
+    const long long p_begin = (long long)part * a.part_len;
+    long long p_end = p_begin + a.part_len;
+    if (p_end > a.m) p_end = a.m;
+
+    f32x16b acc[TL][TD];
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int td = 0; td < TD; ++td) acc[tl][td] = (f32x16b){};
+
+    for (long long p0 = p_begin; p0 < p_end; p0 += 32) {
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const long long p = p0 + half * 16 + j;
+            const bool ok = p < p_end;
+            float w[TL], g[TD];
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl) w[tl] = ok ? a.coef[p * L + 32 * tl + col] : 0.0f;
+#pragma unroll
+            for (int td = 0; td < TD; ++td) g[td] = ok ? a.d_feat[p * D + d0 + 32 * td + col] : 0.0f;
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                for (int td = 0; td < TD; ++td)
+                    acc[tl][td] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[tl], g[td], acc[tl][td], 0, 0, 0);
+        }
+    }
+    float* out = a.ws + (size_t)part * L * D;
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int td = 0; td < TD; ++td)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * tl + 8 * (r >> 2) + 4 * half + (r & 3);
+                out[(size_t)row * D + d0 + 32 * td + col] = acc[tl][td][r];
+            }
+}
+
+__global__ __launch_bounds__(256) void k_ddict_reduce(const float* __restrict__ ws, int nparts, int LD,
+                                                      float* __restrict__ d_dict) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= LD) return;
+    float s = 0.0f;
+    for (int p = 0; p < nparts; ++p) s += ws[(size_t)p * LD + e];
+    d_dict[e] = s;
+}
+
+static int decode_bw_plan(long long m, int L, int D, DecodeBwArgs& a) {
+    a.m = m;
+    a.L = L;
+    a.D = D;
+    // LDS chunk of S: at most 128 KB, a multiple of 32 columns dividing D
+    a.DC = 32768 / L < D ? 32768 / L : D;
+    while (D % a.DC != 0) a.DC -= 32;
+    a.DWG = D < 512 ? D : 512;
+    const int nchunk = D / a.DWG;
+    const long long nblk32 = (m + 31) / 32;
+    long long nparts = 512 / nchunk;
+    if (nparts > nblk32) nparts = nblk32;
+    if (nparts < 1) nparts = 1;
+    a.part_len = ((nblk32 + nparts - 1) / nparts) * 32;
+    a.nparts = (int)((m + a.part_len - 1) / a.part_len);
+    if (a.nparts < 1) a.nparts = 1;
+    return LS2_OK;
+}
+
+static int td_for(int L, int D) {
+    if (L == 32) return D % 256 == 0 ? 8 : 4;
+    if (L == 64) return 4;
+    return 2;
+}
+
+template <int L>
+static int launch_decode_bw(DecodeBwArgs a, hipStream_t stream) {
+    constexpr int MT = L <= 64 ? 2 : 1;
+    static int num_cus = 0;
+    if (num_cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        num_cus = n;
+    }
+    if (a.d_coef) {
+        const size_t lds = (size_t)L * (a.DC + 4) * sizeof(float);
+        static bool attr = false;
+        if (!attr) {
+            if (hipFuncSetAttribute((const void*)k_dcoef<L, MT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(136 * 1024)) != hipSuccess)
+                return LS2_ERR_DEVICE;
+            attr = true;
+        }
+        const long long wg_pix = (long long)kDcoefWaves * 32 * MT;
+        long long grid = (a.m + wg_pix - 1) / wg_pix;
+        if (grid > num_cus) grid = num_cus;
+        hipLaunchKernelGGL((k_dcoef<L, MT>), dim3((unsigned)grid), dim3(kDcoefWaves * 64), lds, stream, a);
+        LS2_LAUNCH_CHECK();
+    }
+    if (a.d_dict) {
+        const int td = td_for(L, a.D);
+        const int nw = a.DWG / (32 * td);
+        const int nchunk = a.D / a.DWG;
+        const dim3 grid((unsigned)(a.nparts * nchunk)), block((unsigned)(nw * 64));
+        // accumulators per lane: L * 32 TD / 64 = 128 (or 64 for L = 32, D = 384)
+        if constexpr (L == 32) {
+            if (td == 8)
+                hipLaunchKernelGGL((k_ddict_partial<32, 8>), grid, block, 0, stream, a);
+            else
+                hipLaunchKernelGGL((k_ddict_partial<32, 4>), grid, block, 0, stream, a);
+        } else {
+            hipLaunchKernelGGL((k_ddict_partial<L, 256 / L>), grid, block, 0, stream, a);
+        }
+        LS2_LAUNCH_CHECK();
+        const int LD = L * a.D;
+        hipLaunchKernelGGL(k_ddict_reduce, dim3((LD + 255) / 256), dim3(256), 0, stream, a.ws, a.nparts, LD,
+                           a.d_dict);
+        LS2_LAUNCH_CHECK();
+    }
+    return LS2_OK;
+}
+
+static bool decode_bw_supported(int L, int D) {
+    return (L == 32 || L == 64 || L == 128) && D % 128 == 0 && D >= 128 && (D <= 512 || D == 1024);
+}
+
+}  // namespace ls2
+
+using namespace ls2;
+
+extern "C" int ls2_dict_decode_backward_workspace(int64_t m, int32_t L, int32_t D, size_t* bytes) {
+    if (!bytes || m < 0 || L < 1 || D < 1) return LS2_ERR_ARG;
+    if (!decode_bw_supported(L, D)) return LS2_ERR_UNSUPPORTED;
+    *bytes = 0;
+    if (m == 0) return LS2_OK;
+    DecodeBwArgs a;
+    decode_bw_plan(m, L, D, a);
+    *bytes = (size_t)a.nparts * L * D * sizeof(float);
+    return LS2_OK;
+}
+
+extern "C" int ls2_dict_decode_backward(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                                        int32_t compute, const float* d_feat, float* d_coef, float* d_dict,
+                                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (m < 0 || L < 1 || D < 1 || !dict || (m > 0 && !d_feat)) return LS2_ERR_ARG;
+    if (compute != LS2_F32 && compute != LS2_BF16) return LS2_ERR_ARG;
+    if (!d_coef && !d_dict) return LS2_ERR_ARG;
+    if (d_dict && m > 0 && !coef) return LS2_ERR_ARG;
+    if (!decode_bw_supported(L, D) || compute != LS2_F32) return LS2_ERR_UNSUPPORTED;
+    if (m == 0) {  // dS of an empty product: zeros (a fill kernel, no memset node)
+        if (d_dict) {
+            hipLaunchKernelGGL(k_ddict_reduce, dim3((L * D + 255) / 256), dim3(256), 0, stream, (const float*)nullptr,
+                               0, L * D, d_dict);
+            LS2_LAUNCH_CHECK();
+        }
+        return LS2_OK;
+    }
+    DecodeBwArgs a;
+    decode_bw_plan(m, L, D, a);
+    if (d_dict) {
+        const size_t need = (size_t)a.nparts * L * D * sizeof(float);
+        if (!workspace || workspace_bytes < need) return LS2_ERR_ARG;
+    }
+    a.coef = coef;
+    a.dict = dict;
+    a.d_feat = d_feat;
+    a.d_coef = d_coef;
+    a.d_dict = d_dict;
+    a.ws = static_cast<float*>(workspace);
+    switch (L) {
+        case 32: return launch_decode_bw<32>(a, stream);
+        case 64: return launch_decode_bw<64>(a, stream);
+        default: return launch_decode_bw<128>(a, stream);
+    }
+}

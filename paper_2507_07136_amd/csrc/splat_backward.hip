@@ -1,0 +1,338 @@
+// ls2_splat_sparse_backward: gradients of the sparse coefficient splatting
+// (Section 3.4, Algorithm 1 with the compositing rule of Eq. 3) with respect
+// to the 2D means, conics, opacities and the stored coefficients.
+//
+// For a pixel with contributors i (front to back), e_i = alpha_i T_i and
+// W_l[j] = sum_i e_i w_{i,l,j}.  With g_l = dL/dW_l and
+// c_i = sum_{l,k} g_l[idx_ilk] w_ilk:
+//   dL/dw_ilk   = g_l[idx_ilk] e_i
+//   dL/dalpha_i = T_i c_i - S_i / (1 - alpha_i),  S_i = sum_{m > i} c_m e_m,
+// and through alpha = o exp(power) (no gradient where clamped at 0.99) to o,
+// the 2D mean and the conic.
+//
+// Mapping: the forward's one wave per 8x8 quadrant.  The wave walks its tile
+// list backwards from the largest `last` of its pixels, recovering each
+// pixel's transmittance as T_i = T_{i+1} / (1 - alpha_i) from the stored final
+// transmittance (no per-pixel lists are stored), with alpha recomputed by the
+// same instructions as the forward.  Each pixel's dL/dW vector sits in LDS
+// columns so the K wave-uniform indices read it directly.  Per-Gaussian
+// gradients are summed over the wave's 64 pixels and added with one atomic
+// per value.
+#include "splat_common.h"
+
+namespace ls2 {
+
+struct SplatBwArgs {
+    CamK cam;
+    int n, levels, K, L;
+    const unsigned* ranges;
+    const unsigned* ids;
+    const float* mean2d;
+    const float* conic;
+    const float* opacity;
+    const int* topk_idx;
+    const float* topk_w;
+    const float* final_T;
+    const int* last;
+    const float* d_coef;
+    float* d_mean2d;
+    float* d_conic;
+    float* d_opacity;
+    float* d_topk_w;
+};
+
+// staged record (dwords): u, v, A2, B2, C2, o, position, id, A, B, C, idx words, weights
+template <int KMAX, int LVMAX>
+struct BwRec {
+    static constexpr int KW = (KMAX + 3) / 4;
+    static constexpr int POS = 6, ID = 7, CA = 8;
+    static constexpr int IDX = 11;
+    static constexpr int W = IDX + LVMAX * KW;
+    static constexpr int RAW = W + LVMAX * KMAX;
+    static constexpr int STRIDE = (RAW + 3) & ~3;
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+template <int NV, int KMAX, int LVMAX, bool EXACT>
+__global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
+    using R = BwRec<KMAX, LVMAX>;
+    constexpr int kStride = 65;
+    constexpr int kRows = LVMAX * NV * 32;
+    constexpr int NG = 6 + LVMAX * KMAX;  // gradient values per Gaussian
+    __shared__ float4 stage4[64 * R::STRIDE / 4];
+    __shared__ float gcol[(kRows + 1) * kStride];
+    float* stage = reinterpret_cast<float*>(stage4);
+
+    const CamK& cam = a.cam;
+    const int ntiles = cam.tx * cam.ty;
+    int tile, quad;
+    xcd_remap(blockIdx.x, gridDim.x, 4, tile, quad);
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x;
+    const int tx = tile % cam.tx, ty = tile / cam.tx;
+    const int qx0 = tx * kTile + (quad & 1) * 8, qy0 = ty * kTile + (quad >> 1) * 8;
+    if (qx0 >= cam.W || qy0 >= cam.H) return;
+    const int px = qx0 + (lane & 7), py = qy0 + (lane >> 3);
+    const bool inside = px < cam.W && py < cam.H;
+    const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+    const float bx0 = (float)qx0 + 0.5f, by0 = (float)qy0 + 0.5f;
+    const float bx1 = (float)min(qx0 + 7, cam.W - 1) + 0.5f, by1 = (float)min(qy0 + 7, cam.H - 1) + 0.5f;
+    const size_t HW = (size_t)cam.W * cam.H;
+    const size_t pix = (size_t)py * cam.W + px;
+
+    const unsigned start = a.ranges[2 * tile];
+    const int list_len = (int)(a.ranges[2 * tile + 1] - start);
+    const int levels = EXACT ? LVMAX : a.levels, K = EXACT ? KMAX : a.K, L = a.L;
+    const int lmask = L - 1;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+
+    float T = inside ? a.final_T[pix] : 1.0f;
+    const int lastp = inside ? a.last[pix] : 0;
+    int maxlast = lastp;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) maxlast = max(maxlast, __shfl_xor(maxlast, off));
+    maxlast = min(maxlast, list_len);  // a forward state from another list cannot read past this one
+    if (maxlast <= 0) return;  // no pixel of the quadrant blended anything
+
+    // dL/dW of the quadrant's pixels into LDS columns (coalesced row reads)
+    for (int i = lane; i < (kRows + 1) * kStride; i += 64) gcol[i] = 0.0f;
+    __syncthreads();
+    {
+        const int f4_per_px = L / 4, f4_per_row = 8 * f4_per_px;
+        for (int lv = 0; lv < levels; ++lv)
+            for (int ry = 0; ry < 8; ++ry) {
+                const int gy = qy0 + ry;
+                if (gy >= cam.H) break;
+                const float4* rowbase =
+                    reinterpret_cast<const float4*>(a.d_coef + ((size_t)lv * HW + (size_t)gy * cam.W + qx0) * L);
+                for (int f = lane; f < f4_per_row; f += 64) {
+                    const int pxl = f / f4_per_px, c4 = f - pxl * f4_per_px;
+                    if (qx0 + pxl >= cam.W) continue;
+                    const float4 v = rowbase[f];
+                    float* dst = gcol + (lv * L + 4 * c4) * kStride + ry * 8 + pxl;
+                    dst[0] = v.x;
+                    dst[kStride] = v.y;
+                    dst[2 * kStride] = v.z;
+                    dst[3 * kStride] = v.w;
+                }
+            }
+    }
+
+    float S = 0.0f;  // sum over later contributors of c_m e_m
+    for (int bend = maxlast; bend > 0; bend -= 64) {
+        const int b0 = max(0, bend - 64), nb = bend - b0;
+        bool keep = false;
+        unsigned id = 0;
+        float mu = 0.f, mv = 0.f, cA = 0.f, cB = 0.f, cC = 0.f, op = 0.f;
+        if (lane < nb) {
+            id = a.ids[start + b0 + lane];
+            if (id < (unsigned)a.n) {
+                const float2 m = reinterpret_cast<const float2*>(a.mean2d)[id];
+                mu = m.x;
+                mv = m.y;
+                cA = a.conic[3 * id];
+                cB = a.conic[3 * id + 1];
+                cC = a.conic[3 * id + 2];
+                op = a.opacity[id];
+                keep = may_touch(mu, mv, cA, cB, cC, op, bx0, bx1, by0, by1);
+            }
+        }
+        const unsigned long long kmask = __builtin_amdgcn_ballot_w64(keep);
+        const int nkeep = __builtin_popcountll(kmask);
+        __syncthreads();  // single-wave workgroup: previous batch's reads done
+        if (keep) {
+            float* r = stage + __builtin_popcountll(kmask & lt) * R::STRIDE;
+            r[0] = mu;
+            r[1] = mv;
+            r[2] = -0.5f * kLog2e * cA;
+            r[3] = -kLog2e * cB;
+            r[4] = -0.5f * kLog2e * cC;
+            r[5] = op;
+            reinterpret_cast<unsigned*>(r)[R::POS] = b0 + lane;
+            reinterpret_cast<unsigned*>(r)[R::ID] = id;
+            r[R::CA] = cA;
+            r[R::CA + 1] = cB;
+            r[R::CA + 2] = cC;
+#pragma unroll
+            for (int lv = 0; lv < LVMAX; ++lv) {
+                if (lv < levels) {
+                    const size_t base = ((size_t)id * levels + lv) * K;
+                    unsigned wd[R::KW];
+#pragma unroll
+                    for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k) {
+                        const unsigned ix = k < K ? (unsigned)(a.topk_idx[base + k] & lmask) : 0u;
+                        wd[k >> 2] |= ix << (8 * (k & 3));
+                        r[R::W + lv * KMAX + k] = k < K ? a.topk_w[base + k] : 0.0f;
+                    }
+#pragma unroll
+                    for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + lv * R::KW + q] = wd[q];
+                }
+            }
+        }
+        __syncthreads();
+
+        for (int j = nkeep - 1; j >= 0; --j) {
+            const float* r = stage + j * R::STRIDE;
+            const float4 h0 = *reinterpret_cast<const float4*>(r);
+            const float4 h1 = *reinterpret_cast<const float4*>(r + 4);
+            const int pos = __float_as_int(h1.z);
+            const float dx = h0.x - pxc, dy = h0.y - pyc;
+            const float p2 = gauss_power2(h0.z, h0.w, h1.x, dx, dy);
+            const float G = fast_exp2(p2);
+            const float g = h1.y * G;
+            const float alpha = fminf(0.99f, g);
+            const bool hit = pos < lastp && p2 <= 0.0f && alpha >= (1.0f / 255.0f);
+            if (__builtin_amdgcn_ballot_w64(hit) == 0) continue;
+            float vals[NG];
+#pragma unroll
+            for (int q = 0; q < NG; ++q) vals[q] = 0.0f;
+            unsigned words[LVMAX][R::KW];
+#pragma unroll
+            for (int lv = 0; lv < LVMAX; ++lv)
+#pragma unroll
+                for (int q = 0; q < R::KW; ++q)
+                    words[lv][q] = __builtin_amdgcn_readfirstlane(
+                        reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
+            if (hit) {
+                const float one_m = 1.0f - alpha;
+                T = T / one_m;  // transmittance in front of this Gaussian
+                const float e = alpha * T;
+                float c = 0.0f;
+                const float* col = gcol + lane;
+#pragma unroll
+                for (int lv = 0; lv < LVMAX; ++lv) {
+                    if (lv < levels) {
+#pragma unroll
+                        for (int k = 0; k < KMAX; ++k) {
+                            if (k < K) {
+                                const unsigned ix = (words[lv][k >> 2] >> (8 * (k & 3))) & 0xffu;
+                                const float gv = col[(lv * L + (int)ix) * kStride];
+                                c = fmaf(gv, r[R::W + lv * KMAX + k], c);
+                                vals[6 + lv * KMAX + k] = gv * e;
+                            }
+                        }
+                    }
+                }
+                const float dalpha = T * c - S / one_m;
+                S = fmaf(c, e, S);
+                if (g < 0.99f) {  // unclamped: alpha = o exp(power)
+                    const float dpow = dalpha * alpha;  // dL/dpower (natural log units)
+                    const float A = r[R::CA], B = r[R::CA + 1], C = r[R::CA + 2];
+                    vals[0] = dpow * -(A * dx + B * dy);  // d mean2d.x
+                    vals[1] = dpow * -(C * dy + B * dx);  // d mean2d.y
+                    vals[2] = dpow * (-0.5f * dx * dx);   // d conic A
+                    vals[3] = dpow * (-dx * dy);          // d conic B
+                    vals[4] = dpow * (-0.5f * dy * dy);   // d conic C
+                    vals[5] = dalpha * G;                 // d opacity
+                }
+            }
+            // sum over the wave's pixels, one atomic per value
+            const unsigned gid = reinterpret_cast<const unsigned*>(r)[R::ID];
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+                if (q >= 6) {
+                    const int lv = (q - 6) / KMAX, k = (q - 6) % KMAX;
+                    if (lv >= levels || k >= K) continue;
+                }
+                const float tot = wave_sum(vals[q]);
+                if (lane == 0 && tot != 0.0f) {
+                    if (q < 2) atomicAdd(&a.d_mean2d[2 * gid + q], tot);
+                    else if (q < 5) atomicAdd(&a.d_conic[3 * gid + (q - 2)], tot);
+                    else if (q == 5) atomicAdd(&a.d_opacity[gid], tot);
+                    else {
+                        const int lv = (q - 6) / KMAX, k = (q - 6) % KMAX;
+                        atomicAdd(&a.d_topk_w[((size_t)gid * levels + lv) * K + k], tot);
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+static int zero_f32(float* p, long long n, hipStream_t stream) {
+    if (n <= 0) return LS2_OK;
+    const long long b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)(b < 2048 ? b : 2048)), dim3(256), 0, stream, p, n);
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
+}
+
+template <int NV, int KMAX, int LVMAX>
+static int launch_splat_bw(const SplatBwArgs& a, hipStream_t stream) {
+    const int ntiles = a.cam.tx * a.cam.ty;
+    const int grid = round_up8(ntiles * 4);
+    if (a.K == KMAX && a.levels == LVMAX)
+        hipLaunchKernelGGL((k_splat_backward<NV, KMAX, LVMAX, true>), dim3(grid), dim3(64), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_splat_backward<NV, KMAX, LVMAX, false>), dim3(grid), dim3(64), 0, stream, a);
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
+}
+
+}  // namespace ls2
+
+using namespace ls2;
+
+extern "C" int ls2_splat_sparse_backward(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                                         const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                         const float* conic, const float* opacity, const int32_t* topk_idx,
+                                         const float* topk_w, const float* final_T, const int32_t* last,
+                                         const float* d_coef, float* d_mean2d, float* d_conic, float* d_opacity,
+                                         float* d_topk_w, hipStream_t stream) {
+    if (!cam_valid(cam) || n < 0 || levels < 1 || K < 1 || L < 1 || K > L) return LS2_ERR_ARG;
+    if (!tile_ranges || !final_T || !last || !d_coef) return LS2_ERR_ARG;
+    if (n > 0 && (!ids || !mean2d || !conic || !opacity || !topk_idx || !topk_w || !d_mean2d || !d_conic ||
+                  !d_opacity || !d_topk_w))
+        return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
+    if (n == 0) return LS2_OK;
+    int st;
+    if ((st = zero_f32(d_mean2d, 2LL * n, stream)) != LS2_OK) return st;
+    if ((st = zero_f32(d_conic, 3LL * n, stream)) != LS2_OK) return st;
+    if ((st = zero_f32(d_opacity, (long long)n, stream)) != LS2_OK) return st;
+    if ((st = zero_f32(d_topk_w, (long long)n * levels * K, stream)) != LS2_OK) return st;
+    SplatBwArgs a;
+    a.cam = cam_k(*cam);
+    a.n = n;
+    a.levels = levels;
+    a.K = K;
+    a.L = L;
+    a.ranges = tile_ranges;
+    a.ids = ids;
+    a.mean2d = mean2d;
+    a.conic = conic;
+    a.opacity = opacity;
+    a.topk_idx = topk_idx;
+    a.topk_w = topk_w;
+    a.final_T = final_T;
+    a.last = last;
+    a.d_coef = d_coef;
+    a.d_mean2d = d_mean2d;
+    a.d_conic = d_conic;
+    a.d_opacity = d_opacity;
+    a.d_topk_w = d_topk_w;
+    const bool k8 = K > 4;
+    if (levels == 1) {
+        if (L == 32) return k8 ? launch_splat_bw<1, 8, 1>(a, stream) : launch_splat_bw<1, 4, 1>(a, stream);
+        if (L == 64) return k8 ? launch_splat_bw<2, 8, 1>(a, stream) : launch_splat_bw<2, 4, 1>(a, stream);
+        return k8 ? launch_splat_bw<4, 8, 1>(a, stream) : launch_splat_bw<4, 4, 1>(a, stream);
+    }
+    if (levels == 2) {
+        if (L == 32) return k8 ? launch_splat_bw<1, 8, 2>(a, stream) : launch_splat_bw<1, 4, 2>(a, stream);
+        return k8 ? launch_splat_bw<2, 8, 2>(a, stream) : launch_splat_bw<2, 4, 2>(a, stream);
+    }
+    if (L == 32) return k8 ? launch_splat_bw<1, 8, 3>(a, stream) : launch_splat_bw<1, 4, 3>(a, stream);
+    return k8 ? launch_splat_bw<2, 8, 3>(a, stream) : launch_splat_bw<2, 4, 3>(a, stream);
+}

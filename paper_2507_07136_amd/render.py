@@ -97,6 +97,90 @@ class Pipeline:
         return self.decode(dictionary, compute, out_dtype)
 
 
+class Gradients:
+    """Gradient buffers of one scene size (all float32, overwritten per step)."""
+
+    def __init__(self, n, levels, K, L, D, H, W, device):
+        f32 = torch.float32
+        self.coef = torch.empty((levels, H, W, L), dtype=f32, device=device)      # dL/dcoef
+        self.dictionary = torch.empty((L, D), dtype=f32, device=device)
+        self.mean2d = torch.empty((n, 2), dtype=f32, device=device)
+        self.conic = torch.empty((n, 3), dtype=f32, device=device)
+        self.opacity = torch.empty((n,), dtype=f32, device=device)
+        self.topk_w = torch.empty((n, levels, K), dtype=f32, device=device)
+        self.means = torch.empty((n, 3), dtype=f32, device=device)
+        self.scales = torch.empty((n, 3), dtype=f32, device=device)
+        self.quats = torch.empty((n, 4), dtype=f32, device=device)
+
+
+class Trainer(Pipeline):
+    """Forward + backward of the feature-map objective (float32 throughout):
+    project -> bin_sort -> splat -> decode -> feature loss, then
+    decode_backward -> splat_backward -> project_backward."""
+
+    def __init__(self, cam, n, levels=1, K=4, L=64, D=512, max_pairs=None, device="cuda"):
+        super().__init__(cam, n, levels, K, L, D, max_pairs, device)
+        m = levels * self.H * self.W
+        dev = self.device
+        self.grad = Gradients(n, levels, K, L, D, self.H, self.W, dev)
+        self.d_feat = torch.empty((levels, self.H, self.W, D), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros((1,), dtype=torch.float64, device=dev)
+        self.loss_ws = torch.empty((_lib.ls2_feature_loss_workspace(m),), dtype=torch.uint8, device=dev)
+        self.dec_ws = torch.empty((max(1, _lib.ls2_dict_decode_backward_workspace(m, L, D)),), dtype=torch.uint8,
+                                  device=dev)
+
+    def forward_loss(self, scene, target, sync=True):
+        """Renders the float32 feature map and evaluates the loss and dL/dF."""
+        self.feature_map(scene["means"], scene["scales"], scene["quats"], scene["opacity"], scene["topk_idx"],
+                         scene["topk_w"], scene["dictionary"], compute=LS2_F32, out_dtype=torch.float32, sync=sync)
+        _lib.ls2_feature_loss(self.feat, target, self.loss, self.d_feat, self.loss_ws)
+        return self.loss
+
+    def backward(self, scene, d_feat=None):
+        """Gradients of the loss (or of any dL/dF given as d_feat) with
+        respect to every differentiable input, into ``self.grad``."""
+        g = self.grad
+        m = self.levels * self.H * self.W
+        G = (self.d_feat if d_feat is None else d_feat).view(m, self.D)
+        _lib.ls2_dict_decode_backward(self.coef.view(m, self.L), scene["dictionary"], G, g.coef.view(m, self.L),
+                                      g.dictionary, self.dec_ws)
+        _lib.ls2_splat_sparse_backward(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids,
+                                       self.mean2d, self.conic, scene["opacity"], scene["topk_idx"],
+                                       scene["topk_w"], self.final_T, self.last, g.coef, g.mean2d, g.conic,
+                                       g.opacity, g.topk_w)
+        _lib.ls2_project_backward(self.cam, scene["means"], scene["scales"], scene["quats"], self.radius, g.mean2d,
+                                  g.conic, g.means, g.scales, g.quats)
+        return g
+
+    def step(self, scene, target, sync=True):
+        loss = self.forward_loss(scene, target, sync=sync)
+        return loss, self.backward(scene)
+
+
+class LS2Render(torch.autograd.Function):
+    """Differentiable feature map F (float32, [levels, H, W, D]) of a scene,
+    with the hand-written HIP backward.  ``trainer`` supplies the buffers;
+    topk_idx is discrete and carries no gradient."""
+
+    @staticmethod
+    def forward(ctx, trainer, means, scales, quats, opacity, topk_idx, topk_w, dictionary):
+        scene = dict(means=means.contiguous(), scales=scales.contiguous(), quats=quats.contiguous(),
+                     opacity=opacity.contiguous(), topk_idx=topk_idx.contiguous(), topk_w=topk_w.contiguous(),
+                     dictionary=dictionary.contiguous())
+        feat = trainer.feature_map(scene["means"], scene["scales"], scene["quats"], scene["opacity"],
+                                   scene["topk_idx"], scene["topk_w"], scene["dictionary"], compute=LS2_F32,
+                                   out_dtype=torch.float32)
+        ctx.trainer = trainer
+        ctx.scene = scene
+        return feat.clone()
+
+    @staticmethod
+    def backward(ctx, d_feat):
+        g = ctx.trainer.backward(ctx.scene, d_feat.contiguous())
+        return (None, g.means.clone(), g.scales.clone(), g.quats.clone(), g.opacity.clone(), None,
+                g.topk_w.clone(), g.dictionary.clone())
+
+
 def to_device(scene, device="cuda"):
     """Scene arrays (numpy, from ``gen``) as contiguous device tensors."""
     t = lambda a, dt: torch.from_numpy(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
@@ -106,4 +190,4 @@ def to_device(scene, device="cuda"):
                 dictionary=t(scene.dictionary, torch.float32))
 
 
-__all__ = ["Pipeline", "to_device", "LS2_F32", "LS2_BF16"]
+__all__ = ["Pipeline", "Trainer", "Gradients", "LS2Render", "to_device", "LS2_F32", "LS2_BF16"]

@@ -24,7 +24,9 @@ def L():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for n in ["ls2_project", "ls2_bin_sort", "ls2_splat_sparse", "ls2_dict_decode", "ls2_query"]:
+    for n in ["ls2_project", "ls2_bin_sort", "ls2_splat_sparse", "ls2_dict_decode", "ls2_query",
+              "ls2_feature_loss", "ls2_query_backward", "ls2_dict_decode_backward", "ls2_splat_sparse_backward",
+              "ls2_project_backward"]:
         assert n in names
 
 
@@ -90,3 +92,44 @@ def test_bin_sort_workspace_and_validation(L):
                           V(257), b.value, None) == -1
     assert L.ls2_bin_sort(ctypes.byref(c), 10, V(256), V(256), V(256), 1000, None, V(256), V(256), ctypes.byref(P),
                           V(256), 16, None) == -1
+
+
+def test_backward_argument_validation_without_device(L):
+    c = _cam()
+    V = ctypes.c_void_p
+    f1 = ctypes.c_float(1.0)
+    # splat backward: null tile_ranges, K > L, unsupported L / levels
+    args = [V(16)] * 15
+    assert L.ls2_splat_sparse_backward(ctypes.byref(c), 10, 1, 4, 64, None, *args[1:]) == -1
+    assert L.ls2_splat_sparse_backward(ctypes.byref(c), 10, 1, 9, 8, *args) == -1
+    assert L.ls2_splat_sparse_backward(ctypes.byref(c), 10, 1, 4, 48, *args) == -3
+    assert L.ls2_splat_sparse_backward(ctypes.byref(c), 10, 4, 4, 64, *args) == -3
+    assert L.ls2_splat_sparse_backward(ctypes.byref(c), 10, 1, 4, 64, *args[:7], None, *args[8:]) == -1  # final_T
+    # project backward: negative n, null output, n = 0 no-op
+    assert L.ls2_project_backward(ctypes.byref(c), -1, *([V(16)] * 9), None) == -1
+    assert L.ls2_project_backward(ctypes.byref(c), 5, *([V(16)] * 8), None, None) == -1
+    assert L.ls2_project_backward(ctypes.byref(c), 0, *([None] * 9), None) == 0
+    # decode backward: workspace query, bad compute, unsupported L, no output, BF16 not built, small workspace
+    b = ctypes.c_size_t(0)
+    assert L.ls2_dict_decode_backward_workspace(1000, 64, 512, ctypes.byref(b)) == 0 and b.value >= 64 * 512 * 4
+    assert L.ls2_dict_decode_backward_workspace(1000, 48, 512, ctypes.byref(b)) == -3
+    assert L.ls2_dict_decode_backward_workspace(0, 64, 512, ctypes.byref(b)) == 0 and b.value == 0
+    assert L.ls2_dict_decode_backward(10, 64, 512, V(16), V(16), 7, V(16), V(16), V(16), V(16), 1 << 30, None) == -1
+    assert L.ls2_dict_decode_backward(10, 48, 512, V(16), V(16), 0, V(16), V(16), V(16), V(16), 1 << 30, None) == -3
+    assert L.ls2_dict_decode_backward(10, 64, 512, V(16), V(16), 0, V(16), None, None, V(16), 1 << 30, None) == -1
+    assert L.ls2_dict_decode_backward(10, 64, 512, V(16), V(16), 1, V(16), V(16), V(16), V(16), 1 << 30, None) == -3
+    assert L.ls2_dict_decode_backward(10, 64, 512, V(16), V(16), 0, V(16), V(16), V(16), V(16), 16, None) == -1
+    assert L.ls2_dict_decode_backward(-1, 64, 512, V(16), V(16), 0, V(16), V(16), V(16), V(16), 1 << 30, None) == -1
+    # query backward: no negatives, tau <= 0, bad dtype, unsupported D / n_neg
+    qa = [V(16), 0, V(16)]
+    assert L.ls2_query_backward(10, 512, *qa, 0, V(16), f1, V(16), V(16), None) == -1
+    assert L.ls2_query_backward(10, 512, *qa, 4, V(16), ctypes.c_float(0.0), V(16), V(16), None) == -1
+    assert L.ls2_query_backward(10, 512, V(16), 5, V(16), 4, V(16), f1, V(16), V(16), None) == -1
+    assert L.ls2_query_backward(10, 500, *qa, 4, V(16), f1, V(16), V(16), None) == -3
+    assert L.ls2_query_backward(10, 512, *qa, 9, V(16), f1, V(16), V(16), None) == -3
+    assert L.ls2_query_backward(0, 512, None, 0, V(16), 4, V(16), f1, None, None, None) == 0
+    # feature loss: empty input, unsupported D, small workspace
+    assert L.ls2_feature_loss_workspace(1000, ctypes.byref(b)) == 0 and b.value >= 16
+    assert L.ls2_feature_loss(0, 512, V(16), V(16), V(16), None, V(16), 1 << 20, None) == -1
+    assert L.ls2_feature_loss(10, 500, V(16), V(16), V(16), None, V(16), 1 << 20, None) == -3
+    assert L.ls2_feature_loss(10, 512, V(16), V(16), V(16), None, V(16), 8, None) == -1

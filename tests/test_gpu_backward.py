@@ -1,0 +1,312 @@
+"""GPU parity of the backward pass (HIP through the C ABI vs the FP64 oracle).
+
+Tolerances (float32 kernels against float64 references on identical inputs):
+  - gradients of the splat and projection: per tensor |dg|_2 <= 1e-3 |g|_2
+    and per element |dg| <= 1e-3 max(|g|, 1e-3 max|g|) (1e-2 max|g| for the
+    floor of gradients through the whole composed chain);
+  - decode backward (plain float32 products): per element
+    |dg| <= 1e-5 (|A| |B|)  -- the product of absolute values bounds the
+    float32 accumulation error;
+  - loss value: relative 1e-6; dL/dF per element 1e-5 max|dF|;
+  - query backward: per row |dg|_2 <= 1e-4 |g|_2 (rows whose two largest
+    negative similarities are within 1e-4 are excluded: the minimum picks a
+    different negative there).
+Stage isolation: each backward consumes the GPU's own float32 forward state.
+Discrete decisions of the splat (skip, clamp, stop) that are within the
+oracle's margin of flipping are neutralised by zeroing dL/dcoef at those
+pixels on both sides (a pixel with zero upstream gradient contributes nothing
+to any Gaussian); the count is reported and bounded.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+from gpu_common import gpu_available, oracle_composite_from_gpu, run_forward, small_scene
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+MARGIN = 1e-5
+# elementwise floor (fraction of max|g|) for gradients that pass through the
+# whole float32 chain (decode, splat and projection backward composed): small
+# elements are sums of many terms of either sign and carry the chain's
+# absolute rounding; each stage on its own meets the 1e-3 floor
+CHAIN_FLOOR = 1e-2
+
+
+def _grad_close(got, ref, name, rtol=1e-3, floor=1e-3):
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
+    nref = np.linalg.norm(ref)
+    err = np.linalg.norm(got - ref)
+    assert err <= rtol * max(nref, 1e-30), "%s: |d|/|g| = %.3e" % (name, err / max(nref, 1e-30))
+    gmax = np.abs(ref).max() if ref.size else 0.0
+    bound = rtol * np.maximum(np.abs(ref), floor * gmax)
+    bad = np.abs(got - ref) > bound + 1e-30
+    assert not bad.any(), "%s: %d elements out of bound, worst %.3e vs %.3e" % (
+        name, int(bad.sum()), float(np.abs(got - ref)[bad].max()), float(bound[bad].max()))
+
+
+def _risky_pixels(margin, margin_T):
+    return (margin < MARGIN) | (margin_T < MARGIN)
+
+
+def _splat_backward_gpu(g, scene, d_coef):
+    import paper_2507_07136_amd as ls2
+    pipe, t = g["pipe"], g["t"]
+    n, lv, K = scene.topk_idx.shape
+    dev = "cuda"
+    out = dict(mean2d=torch.empty((n, 2), device=dev), conic=torch.empty((n, 3), device=dev),
+               opacity=torch.empty((n,), device=dev), topk_w=torch.empty((n, lv, K), device=dev))
+    ls2.ls2_splat_sparse_backward(pipe.cam, lv, K, scene.L, pipe.tile_ranges, pipe.ids, pipe.mean2d, pipe.conic,
+                                  t["opacity"], t["topk_idx"], t["topk_w"], pipe.final_T, pipe.last,
+                                  torch.from_numpy(np.ascontiguousarray(d_coef, np.float32)).cuda(),
+                                  out["mean2d"], out["conic"], out["opacity"], out["topk_w"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(seed=1100, n=500, w=64, h=64, L=64, K=4, levels=1),      # the FD scene
+    dict(seed=1001, n=2000, w=128, h=128, L=64, K=4, levels=1),   # small parity scene
+    dict(seed=77, n=3000, w=100, h=75, L=32, K=8, levels=2),      # ragged image, K = 8, 2 levels
+    dict(seed=78, n=1500, w=90, h=70, L=64, K=3, levels=3),       # K < KMAX, 3 levels
+    dict(seed=79, n=1200, w=80, h=48, L=128, K=5, levels=1),      # L = 128
+])
+def test_splat_backward_parity(orc, cfg):
+    scene, cam = small_scene(cfg["seed"], cfg["n"], cfg["w"], cfg["h"], L=cfg["L"], K=cfg["K"],
+                             levels=cfg["levels"], D=128)
+    g = run_forward(cam, scene)
+    coef, fT, last, margin, margin_T = oracle_composite_from_gpu(orc, cam, scene, g)
+    rng = np.random.default_rng(cfg["seed"] + 5)
+    d_coef = rng.standard_normal(coef.shape).astype(np.float32)
+    risky = _risky_pixels(margin, margin_T)
+    d_coef[:, risky, :] = 0.0
+    assert risky.mean() <= 1e-2, risky.mean()
+    got = _splat_backward_gpu(g, scene, d_coef)
+    ref = orc.composite_backward(cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64),
+                                 g["conic"].astype(np.float64), scene.opacity, scene.topk_idx, scene.topk_w,
+                                 d_coef.astype(np.float64))
+    print("splat backward: %d pixels neutralised of %d" % (int(risky.sum()), risky.size))
+    for name, r in zip(["mean2d", "conic", "opacity", "topk_w"], ref):
+        _grad_close(got[name], r, "d_" + name)
+
+
+def test_splat_backward_forward_state(orc):
+    """last and final_T that the backward consumes equal the oracle's walk."""
+    scene, cam = small_scene(1100, 500, 64, 64, D=128)
+    g = run_forward(cam, scene)
+    coef, fT, last, margin, margin_T = oracle_composite_from_gpu(orc, cam, scene, g)
+    ok = ~_risky_pixels(margin, margin_T)
+    assert np.array_equal(g["last"][ok], last[ok])
+    assert np.abs(g["final_T"][ok] - fT[ok]).max() <= 1e-5
+
+
+def test_project_backward_parity(orc):
+    import paper_2507_07136_amd as ls2
+    for seed, n, w, h in [(1001, 2000, 128, 128), (1100, 500, 64, 64), (91, 5000, 200, 120)]:
+        scene, cam = small_scene(seed, n, w, h, D=128)
+        t = ls2.to_device(scene)
+        pipe = ls2.Pipeline(cam, n)
+        pipe.project(t["means"], t["scales"], t["quats"])
+        rng = np.random.default_rng(seed + 9)
+        dm = rng.standard_normal((n, 2)).astype(np.float32)
+        # conic gradients scaled like the conic itself
+        conic = pipe.conic.cpu().numpy()
+        dc = (rng.standard_normal((n, 3)) * (1.0 / (np.abs(conic).max(axis=1, keepdims=True) + 1e-6))).astype(
+            np.float32)
+        outs = [torch.empty((n, k), device="cuda") for k in (3, 3, 4)]
+        ls2.ls2_project_backward(pipe.cam, t["means"], t["scales"], t["quats"], pipe.radius,
+                                 torch.from_numpy(dm).cuda(), torch.from_numpy(dc).cuda(), *outs)
+        torch.cuda.synchronize()
+        radius = pipe.radius.cpu().numpy()
+        ref = orc.project_backward(cam, scene.means, scene.scales, scene.quats, radius, dm.astype(np.float64),
+                                   dc.astype(np.float64))
+        culled = radius == 0
+        for name, o, r in zip(["means", "scales", "quats"], outs, ref):
+            o = o.cpu().numpy()
+            assert np.all(o[culled] == 0.0), name
+            _grad_close(o, r, "d_" + name)
+
+
+def _abs_bound(a, b):
+    return np.abs(a) @ np.abs(b)
+
+
+@pytest.mark.parametrize("m,L,D", [(4096, 64, 512), (1000, 64, 512), (777, 32, 256), (513, 128, 384),
+                                   (300, 32, 1024), (64, 128, 128), (1, 64, 512), (33, 64, 1024)])
+def test_decode_backward_parity(orc, m, L, D):
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(m * 7 + L + D)
+    coef = (rng.random((m, L)) * (rng.random((m, L)) < 0.2)).astype(np.float32)
+    dct = rng.standard_normal((L, D)).astype(np.float32)
+    gf = rng.standard_normal((m, D)).astype(np.float32)
+    dc_ref, ds_ref = orc.decode_backward(coef, dct, gf)
+    tc, td, tg = (torch.from_numpy(x).cuda() for x in (coef, dct, gf))
+    d_coef = torch.empty((m, L), device="cuda")
+    d_dict = torch.empty((L, D), device="cuda")
+    ws = torch.empty((max(1, ls2.ls2_dict_decode_backward_workspace(m, L, D)),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_dict_decode_backward(tc, td, tg, d_coef, d_dict, ws)
+    torch.cuda.synchronize()
+    e1 = np.abs(d_coef.cpu().numpy() - dc_ref)
+    assert (e1 <= 1e-5 * _abs_bound(gf.astype(np.float64), dct.T.astype(np.float64)) + 1e-12).all(), e1.max()
+    e2 = np.abs(d_dict.cpu().numpy() - ds_ref)
+    assert (e2 <= 1e-5 * _abs_bound(coef.T.astype(np.float64), gf.astype(np.float64)) + 1e-12).all(), e2.max()
+
+
+def test_decode_backward_options(orc):
+    """Either output alone; the empty product gives d_dict = 0; deterministic."""
+    import paper_2507_07136_amd as ls2
+    m, L, D = 2000, 64, 512
+    rng = np.random.default_rng(3)
+    coef = rng.random((m, L)).astype(np.float32)
+    dct = rng.standard_normal((L, D)).astype(np.float32)
+    gf = rng.standard_normal((m, D)).astype(np.float32)
+    tc, td, tg = (torch.from_numpy(x).cuda() for x in (coef, dct, gf))
+    ws = torch.empty((ls2.ls2_dict_decode_backward_workspace(m, L, D),), dtype=torch.uint8, device="cuda")
+    a = torch.empty((m, L), device="cuda")
+    ls2.ls2_dict_decode_backward(tc, td, tg, a, None, None)
+    b1 = torch.empty((L, D), device="cuda")
+    b2 = torch.empty((L, D), device="cuda")
+    ls2.ls2_dict_decode_backward(tc, td, tg, None, b1, ws)
+    ls2.ls2_dict_decode_backward(tc, td, tg, None, b2, ws)
+    torch.cuda.synchronize()
+    dc_ref, ds_ref = orc.decode_backward(coef, dct, gf)
+    g64 = gf.astype(np.float64)
+    assert (np.abs(a.cpu().numpy() - dc_ref) <= 1e-5 * _abs_bound(g64, dct.T.astype(np.float64))).all()
+    assert torch.equal(b1, b2)
+    assert (np.abs(b1.cpu().numpy() - ds_ref) <= 1e-5 * _abs_bound(coef.T.astype(np.float64), g64)).all()
+    z = torch.full((L, D), 7.0, device="cuda")
+    ls2.ls2_dict_decode_backward(tc[:0], td, tg[:0], None, z, None)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(z).item() == 0
+    with pytest.raises(ls2.LS2Error):
+        ls2.ls2_dict_decode_backward(tc, td, tg, None, b1, None)   # d_dict without workspace
+
+
+@pytest.mark.parametrize("m,D", [(3000, 512), (257, 128), (100, 1024), (1, 64)])
+def test_feature_loss_parity(orc, m, D):
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(m + D)
+    F = rng.standard_normal((m, D)).astype(np.float32) * 0.3
+    Y = rng.standard_normal((m, D)).astype(np.float32) * 0.3
+    F[0, : D // 2] = Y[0, : D // 2]          # exact zeros of F - Y: sign(0) = 0
+    if m > 2:
+        F[1] = 0.0                           # zero feature: cosine guard
+    loss_ref, dF_ref = orc.loss_l1cos(F, Y)
+    tF, tY = torch.from_numpy(F).cuda(), torch.from_numpy(Y).cuda()
+    loss = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    dF = torch.empty_like(tF)
+    ws = torch.empty((ls2.ls2_feature_loss_workspace(m),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_feature_loss(tF, tY, loss, dF, ws)
+    loss2 = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    ls2.ls2_feature_loss(tF, tY, loss2, None, ws)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - loss_ref) <= 1e-6 * abs(loss_ref), (loss.item(), loss_ref)
+    assert loss.item() == loss2.item()
+    err = np.abs(dF.cpu().numpy() - dF_ref)
+    assert err.max() <= 1e-5 * np.abs(dF_ref).max(), err.max()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("m,D,n_neg,tau", [(5000, 512, 4, 1.0), (300, 128, 1, 10.0), (99, 1024, 8, 3.0)])
+def test_query_backward_parity(orc, dtype, m, D, n_neg, tau):
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(m + D + n_neg)
+    F = rng.standard_normal((m, D)).astype(np.float32)
+    F[0] = 0.0                                            # zero feature
+    pos, neg = gen.make_text(m + 1, D=D, n_neg=n_neg)
+    d_rel = rng.standard_normal(m).astype(np.float32)
+    tF = torch.from_numpy(F).cuda().to(dtype)
+    Fq = tF.float().cpu().numpy()                         # the values the kernel sees
+    ref, margin = orc.query_backward(Fq, pos, neg, d_rel, tau)
+    out = torch.empty((m, D), device="cuda")
+    ls2.ls2_query_backward(tF, torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda(),
+                           torch.from_numpy(d_rel).cuda(), out, tau)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    ok = margin >= 1e-4
+    ok[0] = False                                         # the zero row is checked on its own below
+    assert (~ok[1:]).sum() <= max(2, 0.03 * m), (~ok).sum()
+    num = np.linalg.norm(got - ref, axis=1)[ok]
+    den = np.maximum(np.linalg.norm(ref, axis=1)[ok], 1e-30)
+    assert (num <= 1e-4 * den + 1e-30).all(), (num / den).max()
+    # zero feature: every similarity is 0, both sides take the first negative,
+    # and the guarded norm makes the score linear in F with slope e / (1e-12 |e|)
+    assert np.linalg.norm(got[0] - ref[0]) <= 1e-4 * np.linalg.norm(ref[0])
+
+
+def _oracle_chain(orc, cam, scene, g, dF, pix_zero=None):
+    """Backward through the oracle from dL/dF, on the GPU's forward state."""
+    dc, ds = orc.decode_backward(g["coef"].astype(np.float64), scene.dictionary, dF)
+    dm, dcn, do, dw = orc.composite_backward(cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64),
+                                             g["conic"].astype(np.float64), scene.opacity, scene.topk_idx,
+                                             scene.topk_w, dc)
+    dmu, dsc, dq = orc.project_backward(cam, scene.means, scene.scales, scene.quats, g["radius"], dm, dcn)
+    return dict(means=dmu, scales=dsc, quats=dq, opacity=do, topk_w=dw, dictionary=ds)
+
+
+def test_train_step_end_to_end(orc):
+    """Trainer.step (loss + full backward) vs the oracle chain on the FD scene
+    with a smooth random target; pixels near a decision flip get a zero
+    upstream gradient on both sides."""
+    import paper_2507_07136_amd as ls2
+    c = gen.CONFIGS["fd"]
+    scene, cam = small_scene(c["seed"], c["n"], c["width"], c["height"], D=c["D"])
+    zup, P = gen.make_target_factors(c["seed"] + 1, c["height"], c["width"], D=c["D"])
+    Y = gen.target_map(zup, P)
+    tr = ls2.Trainer(cam, scene.n, D=c["D"])
+    t = ls2.to_device(scene)
+    tY = torch.from_numpy(Y).cuda().contiguous()
+    loss = tr.forward_loss(t, tY)
+    torch.cuda.synchronize()
+    g = dict(coef=tr.coef.cpu().numpy(), ranges=tr.tile_ranges.cpu().numpy().view(np.uint32),
+             ids=tr.ids[:tr.num_pairs].cpu().numpy().view(np.uint32), mean2d=tr.mean2d.cpu().numpy(),
+             conic=tr.conic.cpu().numpy(), radius=tr.radius.cpu().numpy())
+    F = tr.feat.cpu().numpy()
+    loss_ref, dF_ref = orc.loss_l1cos(F, Y[None])
+    assert abs(loss.item() - loss_ref) <= 1e-6 * abs(loss_ref)
+    _, _, _, margin, margin_T = orc.composite(cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64),
+                                              g["conic"].astype(np.float64), scene.opacity, scene.topk_idx,
+                                              scene.topk_w, scene.L, with_margin_T=True)
+    risky = _risky_pixels(margin, margin_T)
+    dF = tr.d_feat.clone()
+    dF[:, torch.from_numpy(risky).cuda()] = 0.0
+    dF_np = dF.cpu().numpy().astype(np.float64)
+    grads = tr.backward(t, dF)
+    torch.cuda.synchronize()
+    ref = _oracle_chain(orc, cam, scene, g, dF_np)
+    print("train step: loss %.6f, %d risky pixels" % (loss.item(), int(risky.sum())))
+    for name in ["means", "scales", "quats", "opacity", "topk_w", "dictionary"]:
+        _grad_close(getattr(grads, name).cpu().numpy(), ref[name], "d_" + name, floor=CHAIN_FLOOR)
+
+
+def test_autograd_function(orc):
+    """torch.autograd through LS2Render equals the oracle chain for
+    L = sum(F * R) (so dL/dF = R)."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(1100, 500, 64, 64, D=256)
+    tr = ls2.Trainer(cam, scene.n, D=256)
+    t = ls2.to_device(scene)
+    params = {k: t[k].clone().requires_grad_(True) for k in ["means", "scales", "quats", "opacity", "topk_w",
+                                                             "dictionary"]}
+    F = ls2.LS2Render.apply(tr, params["means"], params["scales"], params["quats"], params["opacity"],
+                            t["topk_idx"], params["topk_w"], params["dictionary"])
+    torch.cuda.synchronize()
+    g = dict(coef=tr.coef.cpu().numpy(), ranges=tr.tile_ranges.cpu().numpy().view(np.uint32),
+             ids=tr.ids[:tr.num_pairs].cpu().numpy().view(np.uint32), mean2d=tr.mean2d.cpu().numpy(),
+             conic=tr.conic.cpu().numpy(), radius=tr.radius.cpu().numpy())
+    _, _, _, margin, margin_T = orc.composite(cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64),
+                                              g["conic"].astype(np.float64), scene.opacity, scene.topk_idx,
+                                              scene.topk_w, scene.L, with_margin_T=True)
+    rng = np.random.default_rng(4)
+    R = rng.standard_normal(F.shape).astype(np.float32)
+    R[:, _risky_pixels(margin, margin_T)] = 0.0
+    (F * torch.from_numpy(R).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    ref = _oracle_chain(orc, cam, scene, g, R.astype(np.float64))
+    for name in ["means", "scales", "quats", "opacity", "topk_w", "dictionary"]:
+        _grad_close(params[name].grad.cpu().numpy(), ref[name], "d_" + name, floor=CHAIN_FLOOR)
