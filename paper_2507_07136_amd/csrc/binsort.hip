@@ -14,9 +14,12 @@
 //   3. k_sb_emit  : per Gaussian, the 64-bit key (depth bits << 32 | id) into
 //                   each touched superblock's bucket (LDS histogram again, one
 //                   reserving atomic per workgroup and superblock, LDS cursors);
-//   4. k_sb_sort  : one workgroup per superblock sorts its bucket in LDS and
+//   4. k_sb_sort_radix: one workgroup per superblock sorts its bucket with an
+//                   LSD radix sort in LDS (8-bit digits, stable ballot
+//                   ranking, only the digits that vary within the bucket) and
 //                   counts, for each of its S x S tiles, the entries whose
-//                   rectangle covers the tile;
+//                   rectangle covers the tile (buckets beyond the LDS
+//                   capacity use a bitonic network in global memory);
 //   5. k_tile_scan: one workgroup: tile ranges (row-major) and P;
 //   6. k_tile_fill: each tile's list is the ordered subsequence of its
 //                   superblock's sorted bucket whose rectangles cover the tile:
@@ -334,34 +337,147 @@ __device__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long lon
 
 constexpr int kMaxS2 = 32 * 32;  // tile counters per superblock (S <= 32)
 
-// Superblocks with lo < count <= CAP: sort in LDS, write back, count tiles.
-template <int CAP, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_sb_sort_lds(BinArgs a, int lo) {
-    __shared__ unsigned long long s[CAP];
+// Superblocks with count <= CAP: least-significant-digit radix sort in LDS,
+// then write back and count tiles.
+//
+// The 64-bit keys (float32 depth bits << 32 | id) stay in registers: wave w
+// owns the contiguous chunks [w cpw, (w+1) cpw) of 64 positions, lane l of
+// chunk c holds position 64 c + l (positions past the count hold ~0, which
+// sorts last).  Each pass on an 8-bit digit
+//   1. counts the digits of every wave in wave-private LDS counters,
+//   2. turns the counts into scatter offsets (digit-major, then wave order),
+//   3. scatters: within a chunk the lanes holding the same digit find each
+//      other with eight ballots, so a key's destination is its wave's
+//      running offset for the digit plus its rank among those lanes -- the
+//      order of equal digits is kept (stable), which makes the passes an LSD
+//      sort,
+//   4. reloads the keys in the new order.
+// Digits on which every key of the bucket agrees are skipped: in practice the
+// exponent of the depth and the high bits of the id are constant, leaving
+// about six passes.
+constexpr int kRadixCap = 16384;
+constexpr int kRadixWaves = 16;
+
+__global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
+    constexpr int NW = kRadixWaves;
+    constexpr int ITEMS = kRadixCap / (64 * NW);  // chunks per wave, at most
+    __shared__ unsigned long long xbuf[kRadixCap];
+    __shared__ unsigned ctr[NW][256];
     __shared__ unsigned tcnt[kMaxS2];
+    __shared__ unsigned wsum[4];
+    __shared__ unsigned bits[4];
     const int sb = blockIdx.x;
     if (sb >= a.nsb || a.meta->sb_overflow) return;
     const int cnt = (int)a.sb_count[sb];
-    if (cnt <= lo || cnt > CAP) return;
+    if (cnt > kRadixCap || cnt == 0) return;  // larger buckets: k_sb_sort_global; tile counts are pre-zeroed
     unsigned long long* g = a.pool + a.sb_start[sb];
-    {
-        // issue all of this thread's loads before the first LDS write
-        constexpr int PER = CAP / THREADS;
-        unsigned long long v[PER];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int nchunk = (cnt + 63) >> 6;
+    const int cpw = (nchunk + NW - 1) / NW;
+    const int c0 = w * cpw;
+    const int mine = max(0, min(cpw, nchunk - c0));  // this wave's chunks (wave-uniform)
+
+    unsigned long long key[ITEMS];
+    unsigned long long kor = 0ull, kand = ~0ull;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int i = threadIdx.x + q * THREADS;
-            v[q] = i < cnt ? g[i] : 0ull;
-        }
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int i = threadIdx.x + q * THREADS;
-            if (i < cnt) s[i] = v[q];
+    for (int c = 0; c < ITEMS; ++c) {
+        key[c] = ~0ull;
+        if (c < mine) {
+            const int p = (c0 + c) * 64 + lane;
+            if (p < cnt) {
+                key[c] = g[p];
+                kor |= key[c];
+                kand &= key[c];
+            }
+            xbuf[p] = key[c];
         }
     }
-    flip_bitonic<true>(s, cnt);  // starts and ends with a workgroup barrier
-    for (int i = threadIdx.x; i < cnt; i += THREADS) g[i] = s[i];
-    count_sb_tiles(a, sb, s, cnt, tcnt);
+    if (threadIdx.x < 4) bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
+    __syncthreads();
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        kor |= __shfl_xor(kor, off);
+        kand &= __shfl_xor(kand, off);
+    }
+    if (lane == 0 && mine > 0) {
+        atomicOr(&bits[0], (unsigned)kor);
+        atomicOr(&bits[1], (unsigned)(kor >> 32));
+        atomicAnd(&bits[2], (unsigned)kand);
+        atomicAnd(&bits[3], (unsigned)(kand >> 32));
+    }
+    __syncthreads();
+    const unsigned long long varying = (((unsigned long long)bits[1] << 32) | bits[0]) ^
+                                       (((unsigned long long)bits[3] << 32) | bits[2]);
+
+    for (int shift = 0; shift < 64; shift += 8) {
+        if (((varying >> shift) & 0xffull) == 0ull) continue;  // uniform across the workgroup
+        // 1. per-wave digit counts
+        for (int i = lane; i < 256; i += 64) ctr[w][i] = 0u;
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c)
+            if (c < mine) atomicAdd(&ctr[w][(unsigned)(key[c] >> shift) & 0xffu], 1u);
+        __syncthreads();
+        // 2. scatter offsets, digit-major then wave order (waves 0-3 own one digit per lane)
+        unsigned total = 0u, incl = 0u;
+        if (threadIdx.x < 256) {
+            const int d = threadIdx.x;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) {
+                const unsigned x = ctr[v][d];
+                ctr[v][d] = total;
+                total += x;
+            }
+            incl = total;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const unsigned y = __shfl_up(incl, off);
+                if (lane >= off) incl += y;
+            }
+            if (lane == 63) wsum[w] = incl;
+        }
+        __syncthreads();
+        if (threadIdx.x < 256) {
+            const int d = threadIdx.x;
+            unsigned base = incl - total;  // digits below d inside this wave
+            for (int v = 0; v < w; ++v) base += wsum[v];
+#pragma unroll
+            for (int v = 0; v < NW; ++v) ctr[v][d] += base;
+        }
+        __syncthreads();
+        // 3. stable scatter
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c) {
+            if (c < mine) {
+                const unsigned d = (unsigned)(key[c] >> shift) & 0xffu;
+                unsigned long long peers = ~0ull;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const bool bit = (d >> b) & 1u;
+                    const unsigned long long bal = __builtin_amdgcn_ballot_w64(bit);
+                    peers &= bit ? bal : ~bal;
+                }
+                const unsigned rank = (unsigned)__builtin_popcountll(peers & lt);
+                const unsigned base = ctr[w][d];
+                if ((peers & lt) == 0ull) ctr[w][d] = base + (unsigned)__builtin_popcountll(peers);
+                xbuf[base + rank] = key[c];
+            }
+        }
+        __syncthreads();
+        // 4. reload in the new order
+#pragma unroll
+        for (int c = 0; c < ITEMS; ++c)
+            if (c < mine) key[c] = xbuf[(c0 + c) * 64 + lane];
+    }
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        if (c < mine) {
+            const int p = (c0 + c) * 64 + lane;
+            if (p < cnt) g[p] = key[c];
+        }
+    }
+    count_sb_tiles(a, sb, xbuf, cnt, tcnt);  // starts with a workgroup barrier
 }
 
 // Superblocks larger than the LDS capacity: same network in global memory.
@@ -524,13 +640,9 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     if (n > 0 && max_pairs > 0) {
         hipLaunchKernelGGL(k_sb_emit, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sb_sort_lds<2048, 256>), dim3(g.nsb), dim3(256), 0, stream, a, 0);
+        hipLaunchKernelGGL(k_sb_sort_radix, dim3(g.nsb), dim3(kRadixWaves * 64), 0, stream, a);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sb_sort_lds<8192, 512>), dim3(g.nsb), dim3(512), 0, stream, a, 2048);
-        LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL((k_sb_sort_lds<16384, 1024>), dim3(g.nsb), dim3(1024), 0, stream, a, 8192);
-        LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sb_sort_global, dim3(g.nsb), dim3(1024), 0, stream, a, 16384);
+        hipLaunchKernelGGL(k_sb_sort_global, dim3(g.nsb), dim3(1024), 0, stream, a, kRadixCap);
         LS2_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
