@@ -94,7 +94,7 @@ def train_step_timing(args, torch, np, gen, ls2):
     t = ls2.to_device(scene)
     tr = ls2.Trainer(cam, scene.n, levels=scene.levels, K=scene.K, L=scene.L, D=scene.D)
     tr.forward_loss(t, Y, sync=True)          # sizes the pair buffers
-    names = ["project", "bin_sort", "splat", "decode_f32", "loss", "decode_bw", "splat_bw", "project_bw"]
+    names = ["project", "bin_sort", "splat", "decode_loss", "decode_bw", "splat_bw", "project_bw"]
 
     def step(ev=None):
         def mark(i):
@@ -107,28 +107,26 @@ def train_step_timing(args, torch, np, gen, ls2):
         mark(2)
         tr.splat(t["opacity"], t["topk_idx"], t["topk_w"])
         mark(3)
-        tr.decode(t["dictionary"], ls2.LS2_F32, torch.float32)
+        tr.decode_loss(t["dictionary"], Y)      # float32 decode fused with the loss (F stays on chip)
         mark(4)
-        ls2.ls2_feature_loss(tr.feat, Y, tr.loss, tr.d_feat, tr.loss_ws)
-        mark(5)
         g = tr.grad
         m = tr.levels * tr.H * tr.W
         ls2.ls2_dict_decode_backward(tr.coef.view(m, tr.L), t["dictionary"], tr.d_feat.view(m, tr.D),
                                      g.coef.view(m, tr.L), g.dictionary, tr.dec_ws)
-        mark(6)
+        mark(5)
         ls2.ls2_splat_sparse_backward(tr.cam, tr.levels, tr.K, tr.L, tr.tile_ranges, tr.ids, tr.mean2d, tr.conic,
                                       t["opacity"], t["topk_idx"], t["topk_w"], tr.final_T, tr.last, g.coef,
                                       g.mean2d, g.conic, g.opacity, g.topk_w)
-        mark(7)
+        mark(6)
         ls2.ls2_project_backward(tr.cam, t["means"], t["scales"], t["quats"], tr.radius, g.mean2d, g.conic,
                                  g.means, g.scales, g.quats)
-        mark(8)
+        mark(7)
 
     steps = max(5, args.steps // 2)
     for _ in range(3):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(9)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
     t0 = time.perf_counter()
     for s_ in range(steps):
         step(evs[s_])
@@ -160,6 +158,8 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path measurement")
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward (training step) timing")
     ap.add_argument("--train-config", default="c3")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -169,6 +169,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 5}), flush=True)
+        return
 
     import gen
     import paper_2507_07136_amd as ls2
@@ -235,6 +244,28 @@ def main():
     qwall, qper = run(ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
     query_fps = max(5, args.steps // 2) / qwall
 
+    # relevancy straight from the coefficient map (Eq. 7): project, bin, splat, query_coef
+    def coef_query_frame():
+        pipe.project(t["means"], t["scales"], t["quats"])
+        pipe.bin_sort(sync=False)
+        pipe.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+        pipe.query_coef(t["dictionary"], post, negt)
+    nq = max(5, args.steps // 2)
+    for _ in range(3):
+        coef_query_frame()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    for _ in range(nq):
+        coef_query_frame()
+    e0.record()
+    pipe.query_coef(t["dictionary"], post, negt)
+    e1.record()
+    torch.cuda.synchronize()
+    cq_wall = time.perf_counter() - t0
+    query_coef = dict(fps=round(nq / cq_wall, 2), query_coef_ms=round(e0.elapsed_time(e1), 4))
+    log("coefficient-space query: %s" % query_coef)
+
     f32 = None
     if not args.no_f32:
         fwall, fper = run(ls2.LS2_F32, torch.float32, max(5, args.steps // 2), 3)
@@ -288,6 +319,7 @@ def main():
                    "pairs": P},
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
         "query_fps": round(query_fps, 2),
+        "query_from_coefficients": query_coef,
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},
         "fwd_bwd_ms": None if train is None else round(train["ms"], 4),

@@ -170,6 +170,25 @@ int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coef, const fl
 int ls2_query(int64_t m, int32_t D, const void* feat, int32_t feat_dtype, const float* pos,
               int32_t n_neg, const float* neg, float tau, float* relevancy, hipStream_t stream);
 
+/*
+ * ls2_query_coef -- the relevancy of ls2_query computed from the coefficient
+ * map, without forming the feature map.  Eq. 7 gives F = W S, so
+ * F . e = W . (S e) and |F|^2 = W^T (S S^T) W; the cosine similarities and
+ * r = sigmoid(tau (s_q - max_j s_j)) follow exactly (up to float32 rounding)
+ * from the L coefficients of each pixel.
+ *
+ * In:  coef [m,L] f32 (m = levels*H*W rows of ls2_splat_sparse's output),
+ *      dict [L,D], pos [D], neg [n_neg,D] f32.
+ * Out: relevancy [m] f32.
+ * workspace: at least ls2_query_coef_workspace() bytes (projected embeddings
+ *      and the L x L Gram matrix, rebuilt by every call), 16-byte aligned.
+ * Supported: L in {32, 64, 128}, 1 <= n_neg <= 8, any D >= 1.
+ */
+int ls2_query_coef_workspace(int32_t L, int32_t n_neg, size_t* bytes);
+int ls2_query_coef(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict, const float* pos,
+                   int32_t n_neg, const float* neg, float tau, float* relevancy, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Backward pass.  The sparse coefficients and the codebook are learned
  * jointly (Section 3.3); these entry points give the gradients of every
@@ -197,6 +216,25 @@ int ls2_query(int64_t m, int32_t D, const void* feat, int32_t feat_dtype, const 
 int ls2_feature_loss_workspace(int64_t m, size_t* bytes);
 int ls2_feature_loss(int64_t m, int32_t D, const float* feat, const float* target, double* loss,
                      float* d_feat, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * ls2_decode_feature_loss -- ls2_dict_decode (LS2_F32 compute, float32
+ * output) fused with ls2_feature_loss: F = W S (Eq. 7) is formed tile by tile
+ * on the matrix cores and consumed in place, so the feature map itself need
+ * not travel through HBM.  F, d_feat and the loss equal those of decoding and
+ * then calling ls2_feature_loss up to float32 rounding (same formulas, same
+ * per-row reduction order; the loss is summed in a different fixed order).
+ *
+ * In:  coef [m,L], dict [L,D], target [m,D], all f32.
+ * Out: loss (device, one double); d_feat [m,D]; feat [m,D] f32 (optional).
+ * workspace: at least ls2_decode_feature_loss_workspace() bytes, 8-byte
+ *      aligned.
+ * Supported: L in {32, 64}; D in {128, 256, 384, 512}; m >= 1.
+ */
+int ls2_decode_feature_loss_workspace(int64_t m, int32_t D, size_t* bytes);
+int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                            const float* target, double* loss, float* d_feat, float* feat, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream);
 
 /*
  * ls2_query_backward -- d_feat = d_rel * dr/dF for the relevancy of

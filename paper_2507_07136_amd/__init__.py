@@ -17,6 +17,8 @@ from ._lib import (  # noqa: F401
     ls2_bin_sort,
     ls2_bin_sort_count,
     ls2_bin_sort_workspace,
+    ls2_decode_feature_loss,
+    ls2_decode_feature_loss_workspace,
     ls2_dict_decode,
     ls2_dict_decode_backward,
     ls2_dict_decode_backward_workspace,
@@ -25,6 +27,8 @@ from ._lib import (  # noqa: F401
     ls2_project,
     ls2_project_backward,
     ls2_query,
+    ls2_query_coef,
+    ls2_query_coef_workspace,
     ls2_query_backward,
     ls2_splat_sparse,
     ls2_splat_sparse_backward,

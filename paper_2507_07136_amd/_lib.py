@@ -35,7 +35,7 @@ class ls2_camera(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libls2.so not built at %s: run `python -m paper_2507_07136_amd.build` "
+        raise ImportError("libls2.so not built at %s: run `python paper_2507_07136_amd/build.py` "
                           "(or __graft_entry__.build())" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
@@ -51,9 +51,13 @@ def _load():
         "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_dict_decode": ([i64, i32, i32, P, P, i32, i32, P, P], ctypes.c_int),
         "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
+        "ls2_query_coef_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_query_coef": ([i64, i32, i32, P, P, P, i32, P, ctypes.c_float, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_feature_loss_workspace": ([i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_feature_loss": ([i64, i32, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_query_backward": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P, P], ctypes.c_int),
+        "ls2_decode_feature_loss_workspace": ([i64, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_decode_feature_loss": ([i64, i32, i32, P, P, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_dict_decode_backward_workspace": ([i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_dict_decode_backward": ([i64, i32, i32, P, P, i32, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_splat_sparse_backward": ([cam, i32, i32, i32, i32] + [P] * 15, ctypes.c_int),
@@ -216,6 +220,24 @@ def ls2_query(feat, pos, neg, relevancy, tau=1.0, stream=None):
     _check("ls2_query", st)
 
 
+def ls2_query_coef_workspace(L, n_neg) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_query_coef_workspace", _lib.ls2_query_coef_workspace(int(L), int(n_neg), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_query_coef(coef, dictionary, pos, neg, relevancy, workspace, tau=1.0, stream=None):
+    L, D = dictionary.shape
+    m = coef.numel() // L
+    n_neg = neg.numel() // D
+    f32 = torch.float32
+    st = _lib.ls2_query_coef(m, L, D, _ptr(coef, f32, "coef", m * L), _ptr(dictionary, f32, "dict", L * D),
+                             _ptr(pos, f32, "pos", D), n_neg, _ptr(neg, f32, "neg", n_neg * D), float(tau),
+                             _ptr(relevancy, f32, "relevancy", m), _ptr(workspace, torch.uint8, "workspace"),
+                             workspace.numel(), _stream(stream))
+    _check("ls2_query_coef", st)
+
+
 # ------------------------------------------------------------------ backward
 def ls2_feature_loss_workspace(m) -> int:
     b = ctypes.c_size_t(0)
@@ -233,6 +255,24 @@ def ls2_feature_loss(feat, target, loss, d_feat, workspace, stream=None):
                                _ptr(d_feat, f32, "d_feat", m * D, allow_none=True),
                                _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
     _check("ls2_feature_loss", st)
+
+
+def ls2_decode_feature_loss_workspace(m, D) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_decode_feature_loss_workspace", _lib.ls2_decode_feature_loss_workspace(int(m), int(D),
+                                                                                       ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_decode_feature_loss(coef, dictionary, target, loss, d_feat, workspace, feat=None, stream=None):
+    L, D = dictionary.shape
+    m = coef.numel() // L
+    f32 = torch.float32
+    st = _lib.ls2_decode_feature_loss(m, L, D, _ptr(coef, f32, "coef", m * L), _ptr(dictionary, f32, "dict", L * D),
+                                      _ptr(target, f32, "target", m * D), _ptr(loss, torch.float64, "loss", 1),
+                                      _ptr(d_feat, f32, "d_feat", m * D), _ptr(feat, f32, "feat", m * D, allow_none=True),
+                                      _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
+    _check("ls2_decode_feature_loss", st)
 
 
 def ls2_query_backward(feat, pos, neg, d_rel, d_feat, tau=1.0, stream=None):

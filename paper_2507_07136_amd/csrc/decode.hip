@@ -256,6 +256,178 @@ static int num_cus() {
     return g_num_cus;
 }
 
+// ---------------------------------------------------------------------------
+// Decode fused with the feature loss (float32 compute).  The MFMA part is the
+// f32 kernel above; instead of streaming the 32 x D tile of F out, each wave
+// takes four of its rows, reads the matching target rows (coalesced), forms
+// the row's L1 / cosine terms and writes dL/dF.  Lane layout and reduction
+// order of the row phase are those of ls2_feature_loss, so dL/dF matches
+// decoding and then calling the loss up to float32 rounding.  F is written
+// only if asked for.
+struct DecodeLossArgs {
+    DecodeArgs d;
+    const float* target;
+    float* d_feat;
+    float* feat;        // optional
+    double* partial;    // [gridDim.x][2]
+};
+
+__device__ __forceinline__ float sgn_dl(float e) { return e > 0.f ? 1.f : (e < 0.f ? -1.f : 0.f); }
+
+template <int L>
+__global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
+    constexpr int KS = L / 2;
+    constexpr int MT = 2;
+    constexpr int MAXV = 2;  // float4s per lane in a row: D <= 512
+    extern __shared__ float4 smem4[];
+    __shared__ double red[2][8];
+    char* smem = reinterpret_cast<char*>(smem4);
+    const DecodeArgs& a = la.d;
+    const int D = a.D;  // == FC: one chunk
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int srow = D * 4 + 16;
+    const int col = lane & 31, half = lane >> 5;
+    const int f_wave = wave * (MT * 32);
+    const int nv4 = D / 4;
+    const float inv_md = (float)(1.0 / ((double)a.m * D)), inv_m = (float)(1.0 / (double)a.m);
+    double l1_acc = 0.0, lc_acc = 0.0;
+
+    float sa[MT][KS];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) sa[mt][s] = a.dict[(size_t)(half * KS + s) * D + f_wave + mt * 32 + col];
+
+    long long blk = blockIdx.x;
+    const long long bstep = gridDim.x;
+    float4 raw[KS / 4];
+    load_coef_f32path<L>(a, blk, col, half, raw);
+    for (; blk < a.nblocks; blk += bstep) {
+        const long long p0 = blk * 32;
+        float wv[KS];
+#pragma unroll
+        for (int q = 0; q < KS / 4; ++q) {
+            wv[4 * q] = raw[q].x; wv[4 * q + 1] = raw[q].y; wv[4 * q + 2] = raw[q].z; wv[4 * q + 3] = raw[q].w;
+        }
+        load_coef_f32path<L>(a, blk + bstep, col, half, raw);
+        f32x16 acc[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            acc[mt] = (f32x16){};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[mt][s], wv[s], acc[mt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int f = f_wave + mt * 32 + g * 8 + half * 4;
+                *reinterpret_cast<float4*>(smem + col * srow + f * 4) =
+                    make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+            }
+        __syncthreads();
+        // row phase: wave w takes rows w, w + nwaves, ...
+        for (int r = wave; r < 32; r += nwaves) {
+            const long long row = p0 + r;
+            if (row >= a.m) break;
+            const float4* frow = reinterpret_cast<const float4*>(smem + r * srow);
+            float4 f[MAXV], y[MAXV];
+            float l1 = 0.f, fy = 0.f, ff = 0.f, yy = 0.f;
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) {
+                const int v = lane + 64 * q;
+                f[q] = y[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (v < nv4) {
+                    f[q] = frow[v];
+                    y[q] = reinterpret_cast<const float4*>(la.target + row * D)[v];
+                }
+                l1 += fabsf(f[q].x - y[q].x) + fabsf(f[q].y - y[q].y) + fabsf(f[q].z - y[q].z) + fabsf(f[q].w - y[q].w);
+                fy = fmaf(f[q].x, y[q].x, fmaf(f[q].y, y[q].y, fmaf(f[q].z, y[q].z, fmaf(f[q].w, y[q].w, fy))));
+                ff = fmaf(f[q].x, f[q].x, fmaf(f[q].y, f[q].y, fmaf(f[q].z, f[q].z, fmaf(f[q].w, f[q].w, ff))));
+                yy = fmaf(y[q].x, y[q].x, fmaf(y[q].y, y[q].y, fmaf(y[q].z, y[q].z, fmaf(y[q].w, y[q].w, yy))));
+            }
+            l1 = wave_allsum(l1);
+            fy = wave_allsum(fy);
+            ff = wave_allsum(ff);
+            yy = wave_allsum(yy);
+            const float nf = sqrtf(ff), ny = sqrtf(yy);
+            const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
+            const float cs = fy / (gf * gy);
+            l1_acc += (double)l1;
+            lc_acc += (double)(1.0f - cs);
+            const float ay = inv_m / (gf * gy);
+            const float bf = nf > 1e-12f ? inv_m * fy / (nf * nf * nf * gy) : 0.f;
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) {
+                const int v = lane + 64 * q;
+                if (v < nv4) {
+                    f32x4v o;
+                    o.x = sgn_dl(f[q].x - y[q].x) * inv_md - ay * y[q].x + bf * f[q].x;
+                    o.y = sgn_dl(f[q].y - y[q].y) * inv_md - ay * y[q].y + bf * f[q].y;
+                    o.z = sgn_dl(f[q].z - y[q].z) * inv_md - ay * y[q].z + bf * f[q].z;
+                    o.w = sgn_dl(f[q].w - y[q].w) * inv_md - ay * y[q].w + bf * f[q].w;
+                    __builtin_nontemporal_store(o, reinterpret_cast<f32x4v*>(la.d_feat + row * D) + v);
+                    if (la.feat) {
+                        const f32x4v fv = {f[q].x, f[q].y, f[q].z, f[q].w};
+                        __builtin_nontemporal_store(fv, reinterpret_cast<f32x4v*>(la.feat + row * D) + v);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        red[0][wave] = l1_acc;
+        red[1][wave] = lc_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int w = 0; w < nwaves; ++w) {
+            s0 += red[0][w];
+            s1 += red[1][w];
+        }
+        la.partial[2 * blockIdx.x] = s0;
+        la.partial[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_decode_loss_final(const double* __restrict__ partial, int nblocks,
+                                                          long long m, int D, double* __restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double l1 = 0.0, lc = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        l1 += partial[2 * b];
+        lc += partial[2 * b + 1];
+    }
+    *loss = l1 / ((double)m * D) + lc / (double)m;
+}
+
+constexpr int kDecodeLossMaxBlocks = 4096;
+
+template <int L>
+static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
+    DecodeArgs& a = la.d;
+    a.FC = a.D;
+    a.nchunks = 1;
+    const size_t lds = (size_t)32 * (a.D * 4 + 16);
+    const int per_cu = lds <= 40 * 1024 ? 3 : (lds <= 80 * 1024 ? 2 : 1);
+    long long grid = (long long)num_cus() * per_cu;
+    if (grid > a.nblocks) grid = a.nblocks;
+    if (grid > kDecodeLossMaxBlocks) grid = kDecodeLossMaxBlocks;
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute((const void*)k_decode_loss_f32<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                96 * 1024) != hipSuccess)
+            return LS2_ERR_DEVICE;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_decode_loss_f32<L>), dim3((unsigned)grid), dim3((a.D / 64) * 64), lds, stream, la);
+    LS2_LAUNCH_CHECK();
+    return (int)grid;
+}
+
 template <int L, bool OB>
 static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) {
     DecodeArgs a = a0;
@@ -317,4 +489,36 @@ extern "C" int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coe
         case 64: return ob ? launch_decode<64, true>(a, compute, stream) : launch_decode<64, false>(a, compute, stream);
         default: return ob ? launch_decode<128, true>(a, compute, stream) : launch_decode<128, false>(a, compute, stream);
     }
+}
+
+
+extern "C" int ls2_decode_feature_loss_workspace(int64_t m, int32_t D, size_t* bytes) {
+    if (!bytes || m < 0 || D < 1) return LS2_ERR_ARG;
+    *bytes = (size_t)kDecodeLossMaxBlocks * 2 * sizeof(double);
+    return LS2_OK;
+}
+
+extern "C" int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                                       const float* target, double* loss, float* d_feat, float* feat,
+                                       void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (m < 1 || L < 1 || D < 1 || !coef || !dict || !target || !loss || !d_feat || !workspace) return LS2_ERR_ARG;
+    if (workspace_bytes < (size_t)kDecodeLossMaxBlocks * 2 * sizeof(double)) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64) || D % 128 != 0 || D > 512) return LS2_ERR_UNSUPPORTED;
+    DecodeLossArgs la;
+    la.d.m = m;
+    la.d.D = D;
+    la.d.coef = coef;
+    la.d.dict = dict;
+    la.d.feat = nullptr;
+    la.d.nblocks = (m + 31) / 32;
+    la.target = target;
+    la.d_feat = d_feat;
+    la.feat = feat;
+    la.partial = static_cast<double*>(workspace);
+    int grid;
+    grid = L == 32 ? launch_decode_loss<32>(la, stream) : launch_decode_loss<64>(la, stream);
+    if (grid < 0) return grid;
+    hipLaunchKernelGGL(k_decode_loss_final, dim3(1), dim3(64), 0, stream, la.partial, grid, m, D, loss);
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
 }

@@ -18,12 +18,6 @@ namespace ls2 {
 constexpr int kLossBlocks = 2048;
 constexpr int kLossMaxV = 4;  // float4s per lane: D <= 1024
 
-__device__ __forceinline__ float wave_allsum_l(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 __device__ __forceinline__ float sgn(float e) { return e > 0.f ? 1.f : (e < 0.f ? -1.f : 0.f); }
 
 __global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, const float* __restrict__ F,
@@ -51,10 +45,10 @@ __global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, const 
             ff = fmaf(f[q].x, f[q].x, fmaf(f[q].y, f[q].y, fmaf(f[q].z, f[q].z, fmaf(f[q].w, f[q].w, ff))));
             yy = fmaf(y[q].x, y[q].x, fmaf(y[q].y, y[q].y, fmaf(y[q].z, y[q].z, fmaf(y[q].w, y[q].w, yy))));
         }
-        l1 = wave_allsum_l(l1);
-        fy = wave_allsum_l(fy);
-        ff = wave_allsum_l(ff);
-        yy = wave_allsum_l(yy);
+        l1 = wave_allsum(l1);
+        fy = wave_allsum(fy);
+        ff = wave_allsum(ff);
+        yy = wave_allsum(yy);
         const float nf = sqrtf(ff), ny = sqrtf(yy);
         const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
         const float c = fy / (gf * gy);

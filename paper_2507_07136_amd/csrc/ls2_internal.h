@@ -80,6 +80,31 @@ __device__ inline void xcd_remap(int b, int grid, int per, int& item, int& slot)
 
 inline int round_up8(int x) { return (x + 7) & ~7; }
 
+// Sum over the 64 lanes of a wave with DPP moves (no LDS round trip).  xor 1
+// and xor 2 inside quads, the half-row and row mirrors complete each 16-lane
+// row, row broadcasts 15 and 31 add rows 0-2 into row 3: the total is exact
+// in lane 63 only.  Every lane must be active.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false);
+    return v + __int_as_float(moved);
+}
+
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+    v = dpp_add<0xb1>(v);          // quad_perm [1,0,3,2]
+    v = dpp_add<0x4e>(v);          // quad_perm [2,3,0,1]
+    v = dpp_add<0x141>(v);         // row_half_mirror
+    v = dpp_add<0x140>(v);         // row_mirror
+    v = dpp_add<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// The wave sum, broadcast to every lane (as a wave-uniform value).
+__device__ __forceinline__ float wave_allsum(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(v)), 63));
+}
+
 #define LS2_LAUNCH_CHECK()                                              \
     do {                                                                \
         if (hipGetLastError() != hipSuccess) return LS2_ERR_DEVICE;     \

@@ -17,12 +17,6 @@ namespace ls2 {
 constexpr int kQbMaxNeg = 8;
 constexpr int kQbMaxV = 4;  // float4s per lane: D <= 1024
 
-__device__ __forceinline__ float wave_allsum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 template <bool BF16>
 __global__ __launch_bounds__(256) void k_query_backward(long long m, int D, const void* __restrict__ feat,
                                                         const float* __restrict__ pos, int n_neg,

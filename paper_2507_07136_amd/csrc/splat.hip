@@ -210,64 +210,83 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
         }
         __syncthreads();  // single-wave workgroup: orders the LDS writes before the reads
 
-        for (int j = 0; j < nkeep; ++j) {
-            const float* r = stage + j * R::STRIDE;
-            const float4 h0 = *reinterpret_cast<const float4*>(r);
-            const float4 h1 = *reinterpret_cast<const float4*>(r + 4);
-            const float dx = h0.x - pxc, dy = h0.y - pyc;
-            const float p2 = gauss_power2(h0.z, h0.w, h1.x, dx, dy);
-            const float g = h1.y * fast_exp2(p2);
-            const float alpha = fminf(0.99f, g);
-            const float c = alpha * T;       // blend weight e_i = alpha_i T_i (Eq. 7)
-            const float testT = T - c;       // T (1 - alpha)
-            const bool hit = active && p2 <= 0.0f && alpha >= (1.0f / 255.0f);
-            const bool stop = hit && testT < 1e-4f;
-            const bool contrib = hit && !stop;
-            active = active && !stop;
-            if (contrib) {  // divergent: only contributing lanes blend (exec mask)
+        // Evaluate UNR staged entries at a time: their alphas are independent,
+        // so the LDS reads and exponentials of the group overlap; the
+        // transmittance logic and the blends then run in list order.
+        constexpr int UNR = 4;
+        for (int j = 0; j < nkeep; j += UNR) {
+            float4 h0[UNR], h1[UNR];
+            float p2[UNR], g[UNR];
 #pragma unroll
-                for (int lv = 0; lv < LVMAX; ++lv) {
-                    if (lv < levels) {
-                        unsigned words[R::KW];
+            for (int u = 0; u < UNR; ++u) {
+                const float* r = stage + min(j + u, 63) * R::STRIDE;  // past nkeep: read, never used
+                h0[u] = *reinterpret_cast<const float4*>(r);
+                h1[u] = *reinterpret_cast<const float4*>(r + 4);
+            }
 #pragma unroll
-                        for (int q = 0; q < R::KW; ++q)
-                            words[q] = __builtin_amdgcn_readfirstlane(
-                                reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
-                        if (LDS_ACC) {
-                            float* col = accs + lane;
-                            float v[KMAX];
-                            int off[KMAX];
+            for (int u = 0; u < UNR; ++u) {
+                const float dx = h0[u].x - pxc, dy = h0[u].y - pyc;
+                p2[u] = gauss_power2(h0[u].z, h0[u].w, h1[u].x, dx, dy);
+                g[u] = h1[u].y * fast_exp2(p2[u]);
+            }
 #pragma unroll
-                            for (int k = 0; k < KMAX; ++k) {
-                                if (k < K) {
-                                    const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
-                                    const int row = ix == 0xffu ? kRows : lv * L + (int)ix;
-                                    off[k] = row * kStride;
-                                    v[k] = col[off[k]];
+            for (int u = 0; u < UNR; ++u) {
+                if (j + u >= nkeep) break;  // wave-uniform
+                const float* r = stage + (j + u) * R::STRIDE;
+                const float alpha = fminf(0.99f, g[u]);
+                const float c = alpha * T;       // blend weight e_i = alpha_i T_i (Eq. 7)
+                const float testT = T - c;       // T (1 - alpha)
+                const bool hit = active && p2[u] <= 0.0f && alpha >= (1.0f / 255.0f);
+                const bool stop = hit && testT < 1e-4f;
+                const bool contrib = hit && !stop;
+                active = active && !stop;
+                if (contrib) {  // divergent: only contributing lanes blend (exec mask)
+#pragma unroll
+                    for (int lv = 0; lv < LVMAX; ++lv) {
+                        if (lv < levels) {
+                            unsigned words[R::KW];
+#pragma unroll
+                            for (int q = 0; q < R::KW; ++q)
+                                words[q] = __builtin_amdgcn_readfirstlane(
+                                    reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
+                            if (LDS_ACC) {
+                                // K reads, then K FMAs and writes (repeated indices were
+                                // merged at staging, so the K addresses are distinct)
+                                float* col = accs + lane;
+                                float v[KMAX];
+                                int off[KMAX];
+#pragma unroll
+                                for (int k = 0; k < KMAX; ++k) {
+                                    if (k < K) {
+                                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                                        const int row = ix == 0xffu ? kRows : lv * L + (int)ix;
+                                        off[k] = row * kStride;
+                                        v[k] = col[off[k]];
+                                    }
                                 }
-                            }
 #pragma unroll
-                            for (int k = 0; k < KMAX; ++k)
-                                if (k < K) col[off[k]] = fmaf(r[R::W + lv * KMAX + k], c, v[k]);
-                        } else {
+                                for (int k = 0; k < KMAX; ++k)
+                                    if (k < K) col[off[k]] = fmaf(r[R::W + lv * KMAX + k], c, v[k]);
+                            } else {
 #pragma unroll
-                            for (int k = 0; k < KMAX; ++k) {
-                                if (k < K) {
-                                    const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
-                                    const float x = r[R::W + lv * KMAX + k] * c;
-                                    const unsigned jl = ix & 31u, jh = ix >> 5;
+                                for (int k = 0; k < KMAX; ++k) {
+                                    if (k < K) {
+                                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                                        const float x = r[R::W + lv * KMAX + k] * c;
+                                        const unsigned jl = ix & 31u, jh = ix >> 5;
 #pragma unroll
-                                    for (int hh = 0; hh < RN; ++hh)
-                                        acc[lv < RV ? lv : 0][hh][jl] += (jh == (unsigned)hh) ? x : 0.0f;
+                                        for (int hh = 0; hh < RN; ++hh)
+                                            acc[lv < RV ? lv : 0][hh][jl] += (jh == (unsigned)hh) ? x : 0.0f;
+                                    }
                                 }
                             }
                         }
                     }
+                    T = testT;
+                    last = __float_as_int(h1[u].z) + 1;  // record dword POS: list position
                 }
-                T = testT;
-                last = __float_as_int(h1.z) + 1;  // record dword POS: list position
             }
-            if ((j & 7) == 7 && __builtin_amdgcn_ballot_w64(active) == 0) break;
+            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
         }
     }
 

@@ -52,11 +52,6 @@ struct BwRec {
     static constexpr int STRIDE = (RAW + 3) & ~3;
 };
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
 
 template <int NV, int KMAX, int LVMAX, bool EXACT>
 __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
@@ -201,8 +196,8 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                     words[lv][q] = __builtin_amdgcn_readfirstlane(
                         reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
             if (hit) {
-                const float one_m = 1.0f - alpha;
-                T = T / one_m;  // transmittance in front of this Gaussian
+                const float inv_one_m = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; 1 - alpha >= 0.01
+                T = T * inv_one_m;  // transmittance in front of this Gaussian
                 const float e = alpha * T;
                 float c = 0.0f;
                 const float* col = gcol + lane;
@@ -220,7 +215,7 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                         }
                     }
                 }
-                const float dalpha = T * c - S / one_m;
+                const float dalpha = T * c - S * inv_one_m;
                 S = fmaf(c, e, S);
                 if (g < 0.99f) {  // unclamped: alpha = o exp(power)
                     const float dpow = dalpha * alpha;  // dL/dpower (natural log units)
@@ -241,8 +236,8 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                     const int lv = (q - 6) / KMAX, k = (q - 6) % KMAX;
                     if (lv >= levels || k >= K) continue;
                 }
-                const float tot = wave_sum(vals[q]);
-                if (lane == 0 && tot != 0.0f) {
+                const float tot = wave_sum_lane63(vals[q]);
+                if (lane == 63 && tot != 0.0f) {
                     if (q < 2) atomicAdd(&a.d_mean2d[2 * gid + q], tot);
                     else if (q < 5) atomicAdd(&a.d_conic[3 * gid + (q - 2)], tot);
                     else if (q == 5) atomicAdd(&a.d_opacity[gid], tot);

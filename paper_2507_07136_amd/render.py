@@ -88,6 +88,20 @@ class Pipeline:
         _lib.ls2_query(self.feat, pos, neg, self.relevancy, tau)
         return self.relevancy
 
+    def query_coef(self, dictionary, pos, neg, tau: float = 1.0):
+        """Relevancy straight from the coefficient map (Eq. 7), no feature map."""
+        if self.relevancy is None:
+            self.relevancy = torch.empty((self.levels, self.H, self.W), dtype=torch.float32, device=self.device)
+        n_neg = neg.numel() // self.D
+        key = (self.L, n_neg)
+        if getattr(self, "_qc_key", None) != key:
+            self._qc_ws = torch.empty((_lib.ls2_query_coef_workspace(self.L, n_neg),), dtype=torch.uint8,
+                                      device=self.device)
+            self._qc_key = key
+        m = self.levels * self.H * self.W
+        _lib.ls2_query_coef(self.coef.view(m, self.L), dictionary, pos, neg, self.relevancy.view(m), self._qc_ws, tau)
+        return self.relevancy
+
     def feature_map(self, means, scales, quats, opacity, topk_idx, topk_w, dictionary, compute=LS2_BF16,
                     out_dtype=torch.bfloat16, sync: bool = True):
         """One feature-map frame: project, bin and sort, splat, decode."""
@@ -128,13 +142,35 @@ class Trainer(Pipeline):
         self.loss_ws = torch.empty((_lib.ls2_feature_loss_workspace(m),), dtype=torch.uint8, device=dev)
         self.dec_ws = torch.empty((max(1, _lib.ls2_dict_decode_backward_workspace(m, L, D)),), dtype=torch.uint8,
                                   device=dev)
+        # decode fused with the loss where the kernel exists (L <= 64, D <= 512)
+        self.fused_loss = L in (32, 64) and D % 128 == 0 and D <= 512
+        if self.fused_loss:
+            self.fused_ws = torch.empty((_lib.ls2_decode_feature_loss_workspace(m, D),), dtype=torch.uint8,
+                                        device=dev)
 
-    def forward_loss(self, scene, target, sync=True):
-        """Renders the float32 feature map and evaluates the loss and dL/dF."""
-        self.feature_map(scene["means"], scene["scales"], scene["quats"], scene["opacity"], scene["topk_idx"],
-                         scene["topk_w"], scene["dictionary"], compute=LS2_F32, out_dtype=torch.float32, sync=sync)
-        _lib.ls2_feature_loss(self.feat, target, self.loss, self.d_feat, self.loss_ws)
+    def decode_loss(self, dictionary, target, keep_feat=False):
+        """Float32 decode + loss + dL/dF; the feature map is kept only if asked."""
+        m = self.levels * self.H * self.W
+        if self.fused_loss:
+            feat = None
+            if keep_feat:
+                if self.feat is None or self.feat.dtype != torch.float32:
+                    self.feat = torch.empty((self.levels, self.H, self.W, self.D), dtype=torch.float32,
+                                            device=self.device)
+                feat = self.feat.view(m, self.D)
+            _lib.ls2_decode_feature_loss(self.coef.view(m, self.L), dictionary, target.view(m, self.D), self.loss,
+                                         self.d_feat.view(m, self.D), self.fused_ws, feat)
+        else:
+            self.decode(dictionary, LS2_F32, torch.float32)
+            _lib.ls2_feature_loss(self.feat, target, self.loss, self.d_feat, self.loss_ws)
         return self.loss
+
+    def forward_loss(self, scene, target, sync=True, keep_feat=False):
+        """Renders the scene and evaluates the loss and dL/dF (float32)."""
+        self.project(scene["means"], scene["scales"], scene["quats"])
+        self.bin_sort(sync=sync)
+        self.splat(scene["opacity"], scene["topk_idx"], scene["topk_w"])
+        return self.decode_loss(scene["dictionary"], target, keep_feat=keep_feat)
 
     def backward(self, scene, d_feat=None):
         """Gradients of the loss (or of any dL/dF given as d_feat) with

@@ -128,6 +128,14 @@ def test_backward_argument_validation_without_device(L):
     assert L.ls2_query_backward(10, 500, *qa, 4, V(16), f1, V(16), V(16), None) == -3
     assert L.ls2_query_backward(10, 512, *qa, 9, V(16), f1, V(16), V(16), None) == -3
     assert L.ls2_query_backward(0, 512, None, 0, V(16), 4, V(16), f1, None, None, None) == 0
+    # fused decode + loss: unsupported L / D, null output, small workspace
+    assert L.ls2_decode_feature_loss_workspace(1000, 512, ctypes.byref(b)) == 0 and b.value >= 16
+    fa = [V(16)] * 5
+    assert L.ls2_decode_feature_loss(10, 128, 512, *fa, None, V(16), 1 << 20, None) == -3
+    assert L.ls2_decode_feature_loss(10, 64, 1024, *fa, None, V(16), 1 << 20, None) == -3
+    assert L.ls2_decode_feature_loss(10, 64, 512, V(16), V(16), V(16), V(16), None, None, V(16), 1 << 20,
+                                     None) == -1
+    assert L.ls2_decode_feature_loss(10, 64, 512, *fa, None, V(16), 8, None) == -1
     # feature loss: empty input, unsupported D, small workspace
     assert L.ls2_feature_loss_workspace(1000, ctypes.byref(b)) == 0 and b.value >= 16
     assert L.ls2_feature_loss(0, 512, V(16), V(16), V(16), None, V(16), 1 << 20, None) == -1

@@ -211,6 +211,43 @@ def test_feature_loss_parity(orc, m, D):
     assert err.max() <= 1e-5 * np.abs(dF_ref).max(), err.max()
 
 
+@pytest.mark.parametrize("m,L,D", [(3000, 64, 512), (1001, 32, 256), (33, 64, 128), (1, 32, 384)])
+def test_decode_feature_loss_fused(orc, m, L, D):
+    """The fused decode + loss equals decode then loss (float32 rounding) and
+    the oracle's loss of the oracle's decode."""
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(m + L + D)
+    coef = (rng.random((m, L)) * (rng.random((m, L)) < 0.3)).astype(np.float32)
+    dct = rng.standard_normal((L, D)).astype(np.float32)
+    dct /= np.linalg.norm(dct, axis=1, keepdims=True)
+    Y = (rng.standard_normal((m, D)) * 0.1).astype(np.float32)
+    tc, td, tY = (torch.from_numpy(x).cuda() for x in (coef, dct, Y))
+    loss_f = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    dF_f = torch.empty((m, D), device="cuda")
+    F_f = torch.empty((m, D), device="cuda")
+    ws = torch.empty((ls2.ls2_decode_feature_loss_workspace(m, D),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_decode_feature_loss(tc, td, tY, loss_f, dF_f, ws, feat=F_f)
+    loss_n = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    dF_u = torch.empty((m, D), device="cuda")
+    ls2.ls2_decode_feature_loss(tc, td, tY, loss_n, dF_u, ws)            # without the feature map
+    F_u = torch.empty((m, D), device="cuda")
+    ls2.ls2_dict_decode(tc, td, F_u, ls2.LS2_F32)
+    loss_u = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    dF_uu = torch.empty((m, D), device="cuda")
+    lws = torch.empty((ls2.ls2_feature_loss_workspace(m),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_feature_loss(F_u, tY, loss_u, dF_uu, lws)
+    torch.cuda.synchronize()
+    assert torch.equal(F_f, F_u)                                   # same matrix-core products
+    assert torch.equal(dF_f, dF_u)
+    gmax = dF_uu.abs().max().item()
+    assert (dF_f - dF_uu).abs().max().item() <= 1e-6 * gmax
+    assert abs(loss_f.item() - loss_u.item()) <= 1e-12 * abs(loss_u.item())
+    assert loss_f.item() == loss_n.item()
+    loss_ref, dF_ref = orc.loss_l1cos(orc.decode(coef, dct), Y)
+    assert abs(loss_f.item() - loss_ref) <= 1e-5 * abs(loss_ref)
+    assert np.abs(dF_f.cpu().numpy() - dF_ref).max() <= 1e-3 * np.abs(dF_ref).max()
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("m,D,n_neg,tau", [(5000, 512, 4, 1.0), (300, 128, 1, 10.0), (99, 1024, 8, 3.0)])
 def test_query_backward_parity(orc, dtype, m, D, n_neg, tau):
@@ -261,7 +298,7 @@ def test_train_step_end_to_end(orc):
     tr = ls2.Trainer(cam, scene.n, D=c["D"])
     t = ls2.to_device(scene)
     tY = torch.from_numpy(Y).cuda().contiguous()
-    loss = tr.forward_loss(t, tY)
+    loss = tr.forward_loss(t, tY, keep_feat=True)
     torch.cuda.synchronize()
     g = dict(coef=tr.coef.cpu().numpy(), ranges=tr.tile_ranges.cpu().numpy().view(np.uint32),
              ids=tr.ids[:tr.num_pairs].cpu().numpy().view(np.uint32), mean2d=tr.mean2d.cpu().numpy(),

@@ -293,3 +293,37 @@ def test_c2_full_size_sampled(orc):
     assert np.abs(gc - coef[:, 0])[ok].max() <= 2e-5
     F = orc.decode(gc.astype(np.float64), scene.dictionary)
     assert np.abs(g["feat"][0].reshape(-1, scene.D)[pix] - F).max() <= 1e-5
+
+
+@pytest.mark.parametrize("L,D,n_neg,tau", [(64, 512, 4, 1.0), (32, 256, 1, 10.0), (128, 384, 8, 3.0)])
+def test_query_coef_parity(orc, L, D, n_neg, tau):
+    """Relevancy from the coefficient map equals the oracle's relevancy of the
+    oracle-decoded feature map (Eq. 7), float32 tolerance."""
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(L + D + n_neg)
+    m = 3001
+    coef = (rng.random((m, L)) * (rng.random((m, L)) < 0.3)).astype(np.float32)
+    coef[0] = 0.0                                   # empty pixel: r = 0.5
+    dct = rng.standard_normal((L, D)).astype(np.float32)
+    dct /= np.linalg.norm(dct, axis=1, keepdims=True)
+    pos, neg = gen.make_text(L + D, D=D, n_neg=n_neg)
+    ref = orc.query(orc.decode(coef, dct), pos, neg, tau)
+    out = torch.empty((m,), device="cuda")
+    ws = torch.empty((ls2.ls2_query_coef_workspace(L, n_neg),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_query_coef(torch.from_numpy(coef).cuda(), torch.from_numpy(dct).cuda(), torch.from_numpy(pos).cuda(),
+                       torch.from_numpy(neg).cuda(), out, ws, tau)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert got[0] == 0.5
+    assert np.abs(got - ref).max() <= 1e-5 * max(1.0, tau / 4), np.abs(got - ref).max()
+
+
+def test_query_coef_end_to_end_c1(orc, c1):
+    """Score c1 from its rendered coefficients; equals the oracle's query of the
+    oracle decode of the same coefficients (stage-isolated)."""
+    scene, cam, g = c1
+    pos, neg = gen.make_text(11)
+    rel = g["pipe"].query_coef(g["t"]["dictionary"], torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda())
+    torch.cuda.synchronize()
+    ref = orc.query(orc.decode(g["coef"].astype(np.float64), scene.dictionary), pos, neg)
+    assert np.abs(rel.cpu().numpy() - ref).max() <= 1e-5
