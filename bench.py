@@ -51,6 +51,44 @@ def algorithmic_bytes(stage, n, P, H, W, L, D, K, levels, feat_bytes):
     return 0
 
 
+def _source_sha(hip):
+    """sha256 prefix of a kernel source and the library's headers."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2507_07136_amd", "csrc")
+    h = hashlib.sha256()
+    for f in [os.path.join(csrc, hip)] + sorted(os.path.join(csrc, x) for x in os.listdir(csrc) if x.endswith(".h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(stage, config):
+    """HBM bytes per launch of a stage from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters, scaled by the copy-kernel calibration; None when no
+    counters exist for this workload or the kernel changed since they were
+    taken."""
+    path = os.path.join(ROOT, "profiles", "%s_hbm_counters.txt" % config)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    entry = None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            fields = dict(t.split("=", 1) for t in line.split())
+            if "stage" in fields:
+                if fields["stage"] == stage:
+                    entry = fields
+            else:
+                kv.update(fields)
+    if entry is None or _source_sha(entry["source"]) != entry["source_sha"]:
+        return None
+    return (float(entry["fetch_kib"]) * 1024.0 * float(kv["copy_fetch_factor"]) +
+            float(entry["write_kib"]) * 1024.0 * float(kv["copy_write_factor"]))
+
+
 def cpu_baseline(cam, scene, frac):
     """The FP64 oracle, untuned, on a bounded sample of the same frame:
     projection and binning of the full scene, compositing + decode of a random
@@ -282,8 +320,10 @@ def main():
     dom = max(per, key=per.get)
     b = algorithmic_bytes(dom, n, P, H, W, L, D, K, levels, 2)
     ach = b / (per[dom] * 1e-3) / 1e9
+    traffic = counter_traffic(dom, args.config)
     roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
-                    traffic=None, kernel=dom, kernel_ms=round(per[dom], 4), algorithmic_bytes=int(b))
+                    traffic=None if traffic is None else int(traffic), kernel=dom, kernel_ms=round(per[dom], 4),
+                    algorithmic_bytes=int(b))
     M = levels * H * W
     decode_flops = 2.0 * M * L * D
     mfma = dict(decode_tflops=decode_flops / (per["decode"] * 1e-3) / 1e12,
