@@ -19,7 +19,8 @@
 //                   ranking, only the digits that vary within the bucket) and
 //                   counts, for each of its S x S tiles, the entries whose
 //                   rectangle covers the tile (buckets beyond the LDS
-//                   capacity use a bitonic network in global memory);
+//                   capacity use a bitonic network in global memory in
+//                   the same workgroup);
 //   5. k_tile_scan: one workgroup: tile ranges (row-major) and P;
 //   6. k_tile_fill: each tile's list is the ordered subsequence of its
 //                   superblock's sorted bucket whose rectangles cover the tile:
@@ -161,34 +162,49 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
     if (threadIdx.x == 0 && area_sum) atomicAdd(&a.meta->P_rect, area_sum);
 }
 
-// Exclusive scan over `n` counts by one workgroup of 1024 threads, 1024 at a
+// Exclusive scan over `n` counts by one workgroup of 1024 threads, 8192 at a
 // time with a running carry.  Writes start (and, if `end` is non-null, end)
 // offsets; returns the total.
 __device__ long long block_scan(const unsigned* in, unsigned* start, int sstride, unsigned* end, int n) {
-    __shared__ long long part[1024];
-    __shared__ long long carry;
-    const int tid = threadIdx.x;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
-        const int t = base + tid;
-        const long long c = t < n ? (long long)in[t] : 0;
-        part[tid] = c;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const long long v = tid >= off ? part[tid - off] : 0;
-            __syncthreads();
-            part[tid] += v;
-            __syncthreads();
+    // 1024 threads, 8 consecutive elements per thread per round: a serial scan
+    // inside the thread, a shuffle scan across the wave, one LDS step across
+    // the 16 waves
+    constexpr int PER = 8;
+    __shared__ long long wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    long long carry = 0;
+    for (int base = 0; base < n; base += 1024 * PER) {
+        const int t0 = base + tid * PER;
+        unsigned v[PER];
+        long long loc = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            v[k] = t0 + k < n ? in[t0 + k] : 0u;
+            loc += v[k];
         }
-        const long long incl = part[tid] + carry;
-        if (t < n) {
-            start[(size_t)t * sstride] = (unsigned)(incl - c);
-            if (end) end[(size_t)t * sstride] = (unsigned)incl;
+        long long x = loc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(x, off);
+            if (lane >= off) x += y;
         }
+        if (lane == 63) wsum[wave] = x;
         __syncthreads();
-        if (tid == 1023) carry = incl;
-        __syncthreads();
+        long long run = carry + x - loc, tot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) run += wsum[w];
+            tot += wsum[w];
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if (t0 + k < n) {
+                start[(size_t)(t0 + k) * sstride] = (unsigned)run;
+                run += v[k];
+                if (end) end[(size_t)(t0 + k) * sstride] = (unsigned)run;
+            }
+        }
+        carry += tot;
+        __syncthreads();  // wsum is rewritten by the next round
     }
     return carry;
 }
@@ -369,8 +385,13 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
     const int sb = blockIdx.x;
     if (sb >= a.nsb || a.meta->sb_overflow) return;
     const int cnt = (int)a.sb_count[sb];
-    if (cnt > kRadixCap || cnt == 0) return;  // larger buckets: k_sb_sort_global; tile counts are pre-zeroed
+    if (cnt == 0) return;  // tile counts are pre-zeroed
     unsigned long long* g = a.pool + a.sb_start[sb];
+    if (cnt > kRadixCap) {  // beyond the LDS capacity: bitonic network in global memory
+        flip_bitonic<false>(g, cnt);
+        count_sb_tiles(a, sb, g, cnt, tcnt);
+        return;
+    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nchunk = (cnt + 63) >> 6;
@@ -480,17 +501,6 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
     count_sb_tiles(a, sb, xbuf, cnt, tcnt);  // starts with a workgroup barrier
 }
 
-// Superblocks larger than the LDS capacity: same network in global memory.
-__global__ __launch_bounds__(1024) void k_sb_sort_global(BinArgs a, int lo) {
-    __shared__ unsigned tcnt[kMaxS2];
-    const int sb = blockIdx.x;
-    if (sb >= a.nsb || a.meta->sb_overflow) return;
-    const int cnt = (int)a.sb_count[sb];
-    if (cnt <= lo) return;
-    unsigned long long* g = a.pool + a.sb_start[sb];
-    flip_bitonic<false>(g, cnt);
-    count_sb_tiles(a, sb, g, cnt, tcnt);
-}
 
 __global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
     const int ntiles = a.cam.tx * a.cam.ty;
@@ -641,8 +651,6 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
         hipLaunchKernelGGL(k_sb_emit, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_sb_sort_radix, dim3(g.nsb), dim3(kRadixWaves * 64), 0, stream, a);
-        LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sb_sort_global, dim3(g.nsb), dim3(1024), 0, stream, a, kRadixCap);
         LS2_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);

@@ -108,11 +108,9 @@ __global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeAr
     const long long bstep = gridDim.x / a.nchunks;
     long long blk = blockIdx.x / a.nchunks;
     float4 raw[KS][2];
-    load_coef_bf16path<L>(a, blk, col, half, raw);
-    for (; blk < a.nblocks; blk += bstep) {
-        const long long p0 = blk * 32;
-        // W^T fragments: pixel p0 + col, k = ks*16 + half*8 + [0,8)
-        bf16x8 wb[KS];
+    // W^T fragments: pixel p0 + col, k = ks*16 + half*8 + [0,8)
+    bf16x8 wb[KS];
+    auto convert = [&]() {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const float4 u0 = raw[ks][0], u1 = raw[ks][1];
@@ -121,6 +119,14 @@ __global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeAr
             v[4] = (__bf16)u1.x; v[5] = (__bf16)u1.y; v[6] = (__bf16)u1.z; v[7] = (__bf16)u1.w;
             wb[ks] = v;
         }
+    };
+    load_coef_bf16path<L>(a, blk, col, half, raw);
+    convert();
+    for (; blk < a.nblocks; blk += bstep) {
+        const long long p0 = blk * 32;
+        // the next block's coefficients: loaded during this block's products,
+        // converted before this block's stores are issued (so waiting for
+        // them never waits for stores)
         load_coef_bf16path<L>(a, blk + bstep, col, half, raw);
         f32x16 acc[MT];
 #pragma unroll
@@ -147,19 +153,29 @@ __global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeAr
                         make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
                 }
             }
-        __syncthreads();
+        lds_barrier();
+        convert();
+        // materialise the next block's operands here (ordered before the
+        // stores), so that waiting for their loads never waits for stores
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(wb[ks]));
         // write the 32 x D tile as contiguous rows
         const int chunks_per_row = row_bytes / 16;
         const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
         const int nvec = (int)rows * chunks_per_row;
         const long long out_row = (long long)D * OSZ;
         char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
-        for (int c = threadIdx.x; c < nvec; c += nwaves * 64) {
-            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
-            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+        // 32 rows x FC*OSZ/16 vectors over FC/2 threads: exactly 4*OSZ per thread
+#pragma unroll
+        for (int it = 0; it < 4 * OSZ; ++it) {
+            const int c = threadIdx.x + it * nwaves * 64;
+            if (c < nvec) {
+                const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+                const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+            }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -196,15 +212,18 @@ __global__ __launch_bounds__(512, 1) void k_decode_f32(DecodeArgs a) {
     const long long bstep = gridDim.x / a.nchunks;
     long long blk = blockIdx.x / a.nchunks;
     float4 raw[KS / 4];
-    load_coef_f32path<L>(a, blk, col, half, raw);
-    for (; blk < a.nblocks; blk += bstep) {
-        const long long p0 = blk * 32;
-        float wv[KS];
+    float wv[KS];
+    auto convert = [&]() {
 #pragma unroll
         for (int q = 0; q < KS / 4; ++q) {
             wv[4 * q] = raw[q].x; wv[4 * q + 1] = raw[q].y; wv[4 * q + 2] = raw[q].z; wv[4 * q + 3] = raw[q].w;
         }
-        load_coef_f32path<L>(a, blk + bstep, col, half, raw);
+    };
+    load_coef_f32path<L>(a, blk, col, half, raw);
+    convert();
+    for (; blk < a.nblocks; blk += bstep) {
+        const long long p0 = blk * 32;
+        load_coef_f32path<L>(a, blk + bstep, col, half, raw);  // converted before this block's stores
         f32x16 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -228,19 +247,36 @@ __global__ __launch_bounds__(512, 1) void k_decode_f32(DecodeArgs a) {
                         make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
                 }
             }
-        __syncthreads();
+        lds_barrier();
+        convert();
+#pragma unroll
+        for (int k = 0; k < KS; ++k) asm volatile("" : "+v"(wv[k]));  // before the stores, as above
         const int chunks_per_row = row_bytes / 16;
         const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
         const int nvec = (int)rows * chunks_per_row;
         const long long out_row = (long long)D * OSZ;
         char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
-        for (int c = threadIdx.x; c < nvec; c += nwaves * 64) {
-            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
-            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+        // 32 rows x FC*OSZ/16 vectors over FC threads: exactly 2*OSZ per thread
+#pragma unroll
+        for (int it = 0; it < 2 * OSZ; ++it) {
+            const int c = threadIdx.x + it * nwaves * 64;
+            if (c < nvec) {
+                const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+                const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+            }
         }
-        __syncthreads();
+        lds_barrier();
     }
+}
+
+// Workgroups of `kernel` that fit on one CU at once (registers, LDS, waves):
+// persistent grids are sized to exactly fill the chip, so no workgroup waits
+// for a second round at reduced occupancy.
+static int resident_per_cu(const void* kernel, int threads, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess || nb < 1) nb = 1;
+    return nb;
 }
 
 static int g_num_cus = 0;
@@ -305,6 +341,21 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
     load_coef_f32path<L>(a, blk, col, half, raw);
     for (; blk < a.nblocks; blk += bstep) {
         const long long p0 = blk * 32;
+        // target rows of this wave's first PF rows: loaded now, used after the
+        // matrix-core phase (which hides their latency)
+        constexpr int PF = 4;
+        float4 ypf[PF][MAXV];
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const long long row = p0 + wave + k * nwaves;
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) {
+                const int v = lane + 64 * q;
+                ypf[k][q] = (wave + k * nwaves < 32 && row < a.m && v < nv4)
+                                ? reinterpret_cast<const float4*>(la.target + row * D)[v]
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
         float wv[KS];
 #pragma unroll
         for (int q = 0; q < KS / 4; ++q) {
@@ -326,9 +377,9 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
                 *reinterpret_cast<float4*>(smem + col * srow + f * 4) =
                     make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
             }
-        __syncthreads();
+        lds_barrier();
         // row phase: wave w takes rows w, w + nwaves, ...
-        for (int r = wave; r < 32; r += nwaves) {
+        for (int k = 0, r = wave; r < 32; ++k, r += nwaves) {
             const long long row = p0 + r;
             if (row >= a.m) break;
             const float4* frow = reinterpret_cast<const float4*>(smem + r * srow);
@@ -340,7 +391,13 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
                 f[q] = y[q] = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (v < nv4) {
                     f[q] = frow[v];
-                    y[q] = reinterpret_cast<const float4*>(la.target + row * D)[v];
+                    if (k < PF) {
+#pragma unroll
+                        for (int kk = 0; kk < PF; ++kk)
+                            if (kk == k) y[q] = ypf[kk][q];
+                    } else {
+                        y[q] = reinterpret_cast<const float4*>(la.target + row * D)[v];
+                    }
                 }
                 l1 += fabsf(f[q].x - y[q].x) + fabsf(f[q].y - y[q].y) + fabsf(f[q].z - y[q].z) + fabsf(f[q].w - y[q].w);
                 fy = fmaf(f[q].x, y[q].x, fmaf(f[q].y, y[q].y, fmaf(f[q].z, y[q].z, fmaf(f[q].w, y[q].w, fy))));
@@ -375,7 +432,7 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
     if (lane == 0) {
         red[0][wave] = l1_acc;
@@ -394,14 +451,28 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
 }
 
 __global__ __launch_bounds__(64) void k_decode_loss_final(const double* __restrict__ partial, int nblocks,
-                                                          long long m, int D, double* __restrict__ loss) {
-    if (threadIdx.x != 0) return;
+                                                  long long m, int D, double* __restrict__ loss) {
+    // lane t adds the partials t, t + 64, ... in order; lane 0 then adds the
+    // 64 lane sums in order: a fixed summation order, so the loss is
+    // reproducible
+    __shared__ double s[2][64];
+    const int t = threadIdx.x;
     double l1 = 0.0, lc = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = t; b < nblocks; b += 64) {
         l1 += partial[2 * b];
         lc += partial[2 * b + 1];
     }
-    *loss = l1 / ((double)m * D) + lc / (double)m;
+    s[0][t] = l1;
+    s[1][t] = lc;
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, c = 0.0;
+        for (int k = 0; k < 64; ++k) {
+            a += s[0][k];
+            c += s[1][k];
+        }
+        *loss = a / ((double)m * D) + c / (double)m;
+    }
 }
 
 constexpr int kDecodeLossMaxBlocks = 4096;
@@ -412,10 +483,6 @@ static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
     a.FC = a.D;
     a.nchunks = 1;
     const size_t lds = (size_t)32 * (a.D * 4 + 16);
-    const int per_cu = lds <= 40 * 1024 ? 3 : (lds <= 80 * 1024 ? 2 : 1);
-    long long grid = (long long)num_cus() * per_cu;
-    if (grid > a.nblocks) grid = a.nblocks;
-    if (grid > kDecodeLossMaxBlocks) grid = kDecodeLossMaxBlocks;
     static bool attr = false;
     if (!attr) {
         if (hipFuncSetAttribute((const void*)k_decode_loss_f32<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -423,7 +490,11 @@ static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
             return LS2_ERR_DEVICE;
         attr = true;
     }
-    hipLaunchKernelGGL((k_decode_loss_f32<L>), dim3((unsigned)grid), dim3((a.D / 64) * 64), lds, stream, la);
+    const int threads = (a.D / 64) * 64;
+    long long grid = (long long)num_cus() * resident_per_cu((const void*)k_decode_loss_f32<L>, threads, lds);
+    if (grid > a.nblocks) grid = a.nblocks;
+    if (grid > kDecodeLossMaxBlocks) grid = kDecodeLossMaxBlocks;
+    hipLaunchKernelGGL((k_decode_loss_f32<L>), dim3((unsigned)grid), dim3(threads), lds, stream, la);
     LS2_LAUNCH_CHECK();
     return (int)grid;
 }
@@ -435,11 +506,13 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
     a.nchunks = a.D / a.FC;
     const int osz = OB ? 2 : 4;
     const size_t lds = (size_t)32 * (a.FC * osz + 16);
-    const int per_cu = lds <= 40 * 1024 ? 3 : (lds <= 80 * 1024 ? 2 : 1);
-    long long grid = (long long)num_cus() * per_cu;
-    grid -= grid % a.nchunks;
     const long long need = a.nblocks * a.nchunks;
-    if (grid > need) grid = need;
+    auto grid_for = [&](const void* kernel, int threads) {
+        long long grid = (long long)num_cus() * resident_per_cu(kernel, threads, lds);
+        grid -= grid % a.nchunks;
+        if (grid < a.nchunks) grid = a.nchunks;
+        return grid > need ? need : grid;
+    };
     if (compute == LS2_BF16) {
         const int threads = (a.FC / 128) * 64;
         static bool attr = false;
@@ -449,6 +522,7 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
                 return LS2_ERR_DEVICE;
             attr = true;
         }
+        const long long grid = grid_for((const void*)k_decode_bf16<L, OB>, threads);
         hipLaunchKernelGGL((k_decode_bf16<L, OB>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
     } else {
         const int threads = (a.FC / 64) * 64;
@@ -459,6 +533,7 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
                 return LS2_ERR_DEVICE;
             attr = true;
         }
+        const long long grid = grid_for((const void*)k_decode_f32<L, OB>, threads);
         hipLaunchKernelGGL((k_decode_f32<L, OB>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
     }
     LS2_LAUNCH_CHECK();

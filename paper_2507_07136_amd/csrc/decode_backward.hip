@@ -81,39 +81,50 @@ __global__ __launch_bounds__(kDcoefWaves * 64, 1) void k_dcoef(DecodeBwArgs a) {
             if (p >= a.m) p = a.m - 1;  // clamped rows are computed but not stored
             grow[mt] = a.d_feat + p * D + half * 16;
         }
-        for (int ch = 0; ch < nch; ++ch) {
-            if (nch > 1) {
-                __syncthreads();
-                load_chunk(ch);
-                __syncthreads();
+        // column groups of 32 over the whole row; the next group's gradient
+        // loads are issued before the current group's matrix-core work
+        const int ngroups = D / 32;
+        float4 g[MT][4], gn[MT][4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g[mt][q] = reinterpret_cast<const float4*>(grow[mt])[q];
+        for (int cg = 0; cg < ngroups; ++cg) {
+            const int col0 = cg * 32;
+            const int c0 = col0 % DC;
+            if (nch > 1 && c0 == 0) {
+                lds_barrier();
+                load_chunk(col0 / DC);
+                lds_barrier();
             }
-            for (int c0 = 0; c0 < DC; c0 += 32) {
-                float4 g[MT][4];
+            if (cg + 1 < ngroups) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        g[mt][q] = reinterpret_cast<const float4*>(grow[mt] + (size_t)ch * DC + c0)[q];
-                float4 s[TL][4];
+                    for (int q = 0; q < 4; ++q) gn[mt][q] = reinterpret_cast<const float4*>(grow[mt] + col0 + 32)[q];
+            }
+            float4 s[TL][4];
 #pragma unroll
-                for (int tl = 0; tl < TL; ++tl)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        s[tl][q] = *reinterpret_cast<const float4*>(lds + (32 * tl + col) * sstride + c0 + half * 16 +
-                                                                    4 * q);
+            for (int tl = 0; tl < TL; ++tl)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
+                    s[tl][q] = *reinterpret_cast<const float4*>(lds + (32 * tl + col) * sstride + c0 + half * 16 + 4 * q);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-                        for (int tl = 0; tl < TL; ++tl)
+                for (int e = 0; e < 4; ++e)
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt) {
-                                const float sv = e == 0 ? s[tl][q].x : e == 1 ? s[tl][q].y : e == 2 ? s[tl][q].z : s[tl][q].w;
-                                const float gv = e == 0 ? g[mt][q].x : e == 1 ? g[mt][q].y : e == 2 ? g[mt][q].z : g[mt][q].w;
-                                acc[tl][mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sv, gv, acc[tl][mt], 0, 0, 0);
-                            }
-            }
+                    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            const float sv = e == 0 ? s[tl][q].x : e == 1 ? s[tl][q].y : e == 2 ? s[tl][q].z : s[tl][q].w;
+                            const float gv = e == 0 ? g[mt][q].x : e == 1 ? g[mt][q].y : e == 2 ? g[mt][q].z : g[mt][q].w;
+                            acc[tl][mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sv, gv, acc[tl][mt], 0, 0, 0);
+                        }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) g[mt][q] = gn[mt][q];
         }
         // C[row, pixel]: lane holds rows 8 g + 4 half + i of pixel col
 #pragma unroll
@@ -156,7 +167,9 @@ __global__ __launch_bounds__(512) void k_ddict_partial(DecodeBwArgs a) {
         for (int td = 0; td < TD; ++td) acc[tl][td] = (f32x16b){};
 
     for (long long p0 = p_begin; p0 < p_end; p0 += 32) {
-#pragma unroll 4
+        // fully unrolled: the group's operand loads are all issued ahead of
+        // its matrix-core work
+#pragma unroll
         for (int j = 0; j < 16; ++j) {
             const long long p = p0 + half * 16 + j;
             const bool ok = p < p_end;
@@ -184,13 +197,37 @@ __global__ __launch_bounds__(512) void k_ddict_partial(DecodeBwArgs a) {
             }
 }
 
-__global__ __launch_bounds__(256) void k_ddict_reduce(const float* __restrict__ ws, int nparts, int LD,
-                                                      float* __restrict__ d_dict) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= LD) return;
-    float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += ws[(size_t)p * LD + e];
-    d_dict[e] = s;
+// d_dict[e] = sum over parts of ws[part][e].  A workgroup takes 64
+// consecutive elements; its 16 waves each add a contiguous slice of the parts
+// (eight loads in flight per lane), then wave 0 adds the 16 slice sums in
+// order: a fixed order, so the result is reproducible.
+__global__ __launch_bounds__(1024) void k_ddict_reduce(const float* __restrict__ ws, int nparts, int LD,
+                                                       float* __restrict__ d_dict) {
+    __shared__ float part_sum[16][64];
+    const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const int per = (nparts + 15) / 16;
+    const int p0 = slice * per, p1 = min(nparts, p0 + per);
+    float acc = 0.0f;
+    if (e < LD) {
+        int p = p0;
+        for (; p + 8 <= p1; p += 8) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = ws[(size_t)(p + k) * LD + e];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += v[k];
+        }
+        for (; p < p1; ++p) acc += ws[(size_t)p * LD + e];
+    }
+    part_sum[slice][lane] = acc;
+    __syncthreads();
+    if (slice == 0 && e < LD) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += part_sum[k][lane];
+        d_dict[e] = s;
+    }
 }
 
 static int decode_bw_plan(long long m, int L, int D, DecodeBwArgs& a) {
@@ -260,7 +297,7 @@ static int launch_decode_bw(DecodeBwArgs a, hipStream_t stream) {
         }
         LS2_LAUNCH_CHECK();
         const int LD = L * a.D;
-        hipLaunchKernelGGL(k_ddict_reduce, dim3((LD + 255) / 256), dim3(256), 0, stream, a.ws, a.nparts, LD,
+        hipLaunchKernelGGL(k_ddict_reduce, dim3((LD + 63) / 64), dim3(1024), 0, stream, a.ws, a.nparts, LD,
                            a.d_dict);
         LS2_LAUNCH_CHECK();
     }
@@ -296,7 +333,7 @@ extern "C" int ls2_dict_decode_backward(int64_t m, int32_t L, int32_t D, const f
     if (!decode_bw_supported(L, D) || compute != LS2_F32) return LS2_ERR_UNSUPPORTED;
     if (m == 0) {  // dS of an empty product: zeros (a fill kernel, no memset node)
         if (d_dict) {
-            hipLaunchKernelGGL(k_ddict_reduce, dim3((L * D + 255) / 256), dim3(256), 0, stream, (const float*)nullptr,
+            hipLaunchKernelGGL(k_ddict_reduce, dim3((L * D + 63) / 64), dim3(1024), 0, stream, (const float*)nullptr,
                                0, L * D, d_dict);
             LS2_LAUNCH_CHECK();
         }

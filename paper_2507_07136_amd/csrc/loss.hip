@@ -83,14 +83,28 @@ __global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, const 
 }
 
 __global__ __launch_bounds__(64) void k_feature_loss_final(const double* __restrict__ partial, int nblocks,
-                                                           long long m, int D, double* __restrict__ loss) {
-    if (threadIdx.x != 0) return;
+                                                  long long m, int D, double* __restrict__ loss) {
+    // lane t adds the partials t, t + 64, ... in order; lane 0 then adds the
+    // 64 lane sums in order: a fixed summation order, so the loss is
+    // reproducible
+    __shared__ double s[2][64];
+    const int t = threadIdx.x;
     double l1 = 0.0, lc = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = t; b < nblocks; b += 64) {
         l1 += partial[2 * b];
         lc += partial[2 * b + 1];
     }
-    *loss = l1 / ((double)m * D) + lc / (double)m;
+    s[0][t] = l1;
+    s[1][t] = lc;
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0, c = 0.0;
+        for (int k = 0; k < 64; ++k) {
+            a += s[0][k];
+            c += s[1][k];
+        }
+        *loss = a / ((double)m * D) + c / (double)m;
+    }
 }
 
 static int loss_blocks(long long m) {

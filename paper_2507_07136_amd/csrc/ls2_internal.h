@@ -105,6 +105,22 @@ __device__ __forceinline__ float wave_allsum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(v)), 63));
 }
 
+// Workgroup barrier that orders LDS only: waits for this wave's outstanding
+// LDS operations, then meets the other waves.  Unlike __syncthreads() it does
+// not wait for global loads and stores in flight, so streaming stores of one
+// tile overlap the work on the next.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// For single-wave workgroups: LDS operations of one wave complete in order,
+// so only the compiler must not move LDS accesses across this point.
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 #define LS2_LAUNCH_CHECK()                                              \
     do {                                                                \
         if (hipGetLastError() != hipSuccess) return LS2_ERR_DEVICE;     \

@@ -36,29 +36,35 @@ __host__ __device__ inline QcLayout qc_layout(int L, int nt) {
     return q;
 }
 
-__global__ __launch_bounds__(64) void k_qc_prep(int L, int D, const float* __restrict__ dict,
-                                                const float* __restrict__ pos, int n_neg,
-                                                const float* __restrict__ neg, float* __restrict__ ws) {
+// One workgroup per codebook row i, four waves: each wave forms some of the
+// dot products of row i (with every row j, and with every embedding) from
+// coalesced loads and a wave reduction.
+__global__ __launch_bounds__(256) void k_qc_prep(int L, int D, const float* __restrict__ dict,
+                                                 const float* __restrict__ pos, int n_neg,
+                                                 const float* __restrict__ neg, float* __restrict__ ws) {
     const QcLayout q = qc_layout(L, 1 + n_neg);
-    const int i = blockIdx.x, lane = threadIdx.x;
+    const int i = blockIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* si = dict + (size_t)i * D;
-    // Gram row i: lane j (and j + 64) dots rows i and j
-    for (int j = lane; j < L; j += 64) {
-        const float* sj = dict + (size_t)j * D;
-        float acc = 0.0f;
-        for (int d = 0; d < D; ++d) acc = fmaf(si[d], sj[d], acc);
-        ws[q.gram + (size_t)i * L + j] = acc;
-    }
-    // projections of the embeddings on row i, and (block 0) their norms
-    if (lane < q.nt) {
-        const float* e = lane == 0 ? pos : neg + (size_t)(lane - 1) * D;
+    // rows j = 0 .. L-1, then embeddings t = 0 .. nt-1, spread over the waves
+    for (int job = wave; job < L + q.nt; job += 4) {
+        const float* v = job < L ? dict + (size_t)job * D
+                                 : (job == L ? pos : neg + (size_t)(job - L - 1) * D);
         float acc = 0.0f, ee = 0.0f;
-        for (int d = 0; d < D; ++d) {
-            acc = fmaf(si[d], e[d], acc);
-            ee = fmaf(e[d], e[d], ee);
+        for (int d = lane; d < D; d += 64) {
+            acc = fmaf(si[d], v[d], acc);
+            ee = fmaf(v[d], v[d], ee);
         }
-        ws[q.proj + (size_t)lane * L + i] = acc;
-        if (i == 0) ws[q.norms + lane] = fmaxf(sqrtf(ee), 1e-12f);
+        acc = wave_allsum(acc);
+        if (job < L) {
+            if (lane == 0) ws[q.gram + (size_t)i * L + job] = acc;
+        } else {
+            const int t = job - L;
+            if (lane == 0) ws[q.proj + (size_t)t * L + i] = acc;
+            if (i == 0) {
+                ee = wave_allsum(ee);
+                if (lane == 0) ws[q.norms + t] = fmaxf(sqrtf(ee), 1e-12f);
+            }
+        }
     }
 }
 
@@ -214,7 +220,7 @@ extern "C" int ls2_query_coef(int64_t m, int32_t L, int32_t D, const float* coef
     const QcLayout q = qc_layout(L, 1 + n_neg);
     if (workspace_bytes < q.total * sizeof(float)) return LS2_ERR_ARG;
     float* ws = static_cast<float*>(workspace);
-    hipLaunchKernelGGL(k_qc_prep, dim3(L), dim3(64), 0, stream, L, D, dict, pos, n_neg, neg, ws);
+    hipLaunchKernelGGL(k_qc_prep, dim3(L), dim3(256), 0, stream, L, D, dict, pos, n_neg, neg, ws);
     LS2_LAUNCH_CHECK();
     if (m == 0) return LS2_OK;
     if (L <= 64) {

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
         nid2 = fetch_id(b + 128 + lane);
         const unsigned long long kmask = __builtin_amdgcn_ballot_w64(keep);
         const int nkeep = __builtin_popcountll(kmask);
-        __syncthreads();  // single-wave workgroup: the previous batch's stage reads are done
+        wave_lds_order();  // single-wave workgroup: the previous batch's stage reads are done
         if (keep) {
             float* r = stage + __builtin_popcountll(kmask & lt) * R::STRIDE;
             r[0] = mu;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
                 }
             }
         }
-        __syncthreads();  // single-wave workgroup: orders the LDS writes before the reads
+        wave_lds_order();  // single-wave workgroup: orders the LDS writes before the reads
 
         // Evaluate UNR staged entries at a time: their alphas are independent,
         // so the LDS reads and exponentials of the group overlap; the

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
         }
         const unsigned long long kmask = __builtin_amdgcn_ballot_w64(keep);
         const int nkeep = __builtin_popcountll(kmask);
-        __syncthreads();  // single-wave workgroup: previous batch's reads done
+        wave_lds_order();  // single-wave workgroup: previous batch's reads done
         if (keep) {
             float* r = stage + __builtin_popcountll(kmask & lt) * R::STRIDE;
             r[0] = mu;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                 }
             }
         }
-        __syncthreads();
+        wave_lds_order();
 
         for (int j = nkeep - 1; j >= 0; --j) {
             const float* r = stage + j * R::STRIDE;
