@@ -39,6 +39,22 @@ __device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
 
 // Coefficient loads of one 32-pixel block (zeros past the end), issued ahead
 // of use so they overlap the previous block's work.
+// Unconditional variant: out-of-range blocks and rows read a valid row
+// instead (their results are never stored), so every wave issues the same
+// number of loads and the waits can be counted exactly.
+template <int L>
+__device__ __forceinline__ void load_coef_bf16path_clamped(const DecodeArgs& a, long long bk, int col, int half,
+                                                           float4 (&raw)[L / 16][2]) {
+    long long p = (bk < a.nblocks ? bk : 0) * 32 + col;
+    if (p >= a.m) p = a.m - 1;
+#pragma unroll
+    for (int ks = 0; ks < L / 16; ++ks) {
+        const float4* src = reinterpret_cast<const float4*>(a.coef + p * L + ks * 16 + half * 8);
+        raw[ks][0] = src[0];
+        raw[ks][1] = src[1];
+    }
+}
+
 template <int L>
 __device__ __forceinline__ void load_coef_bf16path(const DecodeArgs& a, long long bk, int col, int half,
                                                    float4 (&raw)[L / 16][2]) {
@@ -72,25 +88,36 @@ __device__ __forceinline__ void load_coef_f32path(const DecodeArgs& a, long long
 // (l/32)*8 + [0,8); B (16 x 32) lane l holds column l%32, same k; C (32 x 32)
 // lane l holds column l%32, rows (r/4)*8 + (l/32)*4 + r%4 for register r.
 // A = S^T slice (features x k), B = W^T (k x pixels), C = F^T tile.
-// Each wave owns FW = 128 features (4 row tiles of 32).
+// Each wave owns 64 features (2 row tiles of 32); a workgroup has FC/64
+// waves.  The 32-pixel coefficient tile is loaded once per workgroup, rounded
+// to bf16 into a double-buffered LDS tile, and read back as B operands; the
+// next tile's loads (at most two float4 per thread) are in flight during the
+// current tile's work.  Few registers per wave let 16 waves share a CU, which
+// keeps the HBM write stream busy while single waves wait on their memory
+// counters.
+constexpr int kTileRowBytes(int L) { return L * 2 + 16; }  // padded bf16 coefficient row
+
 template <int L, bool OUT_BF16>
-__global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeArgs a) {
+__global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
     constexpr int KS = L / 16;   // k-steps
-    constexpr int MT = 4;        // 32-feature tiles per wave
+    constexpr int MT = 2;        // 32-feature tiles per wave
     constexpr int OSZ = OUT_BF16 ? 2 : 4;
+    constexpr int TROW = kTileRowBytes(L);
+    constexpr int TILE = 32 * TROW;  // bytes of one coefficient tile
+    constexpr int F4 = 32 * L / 4;   // float4s in a tile
     extern __shared__ float4 smem4[];
-    char* smem = reinterpret_cast<char*>(smem4);
+    char* tiles = reinterpret_cast<char*>(smem4);  // two coefficient tiles
+    char* smem = tiles + 2 * TILE;                 // output staging
 
     const int D = a.D;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
-    const int chunk = blockIdx.x % a.nchunks;          // this workgroup's feature chunk
-    const int row_bytes = a.FC * OSZ;                  // bytes of one row inside the chunk
-    const int srow = row_bytes + 16;                   // padded LDS row (bytes)
+    const int nthreads = blockDim.x;
+    const int chunk = blockIdx.x % a.nchunks;
+    const int row_bytes = a.FC * OSZ;
+    const int srow = row_bytes + 16;
     const int col = lane & 31, half = lane >> 5;
     const int f_wave = chunk * a.FC + wave * (MT * 32);
 
-    // S^T fragments for this wave: features f_wave + mt*32 + col, k = ks*16 + half*8 + [0,8)
     bf16x8 sa[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -103,31 +130,49 @@ __global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeAr
             sa[mt][ks] = v;
         }
 
-    // software pipeline: the next block's coefficients are loaded while the
-    // current block is multiplied and written out
     const long long bstep = gridDim.x / a.nchunks;
     long long blk = blockIdx.x / a.nchunks;
-    float4 raw[KS][2];
-    // W^T fragments: pixel p0 + col, k = ks*16 + half*8 + [0,8)
-    bf16x8 wb[KS];
-    auto convert = [&]() {
+    // cooperative tile loads: float4 number i = threadIdx.x + j * nthreads of
+    // the tile (row i / (L/4), columns 4 (i % (L/4)) ..); rows past the end
+    // read the last row (never stored)
+    constexpr int PER = (F4 + 127) / 128;  // float4 per thread, at most (workgroups have >= 128 threads)
+    float4 pre[PER];
+    auto load_tile = [&](long long bk) {
+        const long long b = bk < a.nblocks ? bk : 0;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const float4 u0 = raw[ks][0], u1 = raw[ks][1];
-            bf16x8 v;
-            v[0] = (__bf16)u0.x; v[1] = (__bf16)u0.y; v[2] = (__bf16)u0.z; v[3] = (__bf16)u0.w;
-            v[4] = (__bf16)u1.x; v[5] = (__bf16)u1.y; v[6] = (__bf16)u1.z; v[7] = (__bf16)u1.w;
-            wb[ks] = v;
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * nthreads;
+            if (i < F4) {
+                long long p = b * 32 + i / (L / 4);
+                if (p >= a.m) p = a.m - 1;
+                pre[j] = reinterpret_cast<const float4*>(a.coef + p * L)[i % (L / 4)];
+            }
         }
     };
-    load_coef_bf16path<L>(a, blk, col, half, raw);
-    convert();
+    auto store_tile = [&](char* t) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = threadIdx.x + j * nthreads;
+            if (i < F4) {
+                uint2 v;
+                v.x = pack_bf16x2(pre[j].x, pre[j].y);
+                v.y = pack_bf16x2(pre[j].z, pre[j].w);
+                *reinterpret_cast<uint2*>(t + (i / (L / 4)) * TROW + (i % (L / 4)) * 8) = v;
+            }
+        }
+    };
+    load_tile(blk);
+    store_tile(tiles);
+    load_tile(blk + bstep);
+    lds_barrier();
+    int cur = 0;
     for (; blk < a.nblocks; blk += bstep) {
         const long long p0 = blk * 32;
-        // the next block's coefficients: loaded during this block's products,
-        // converted before this block's stores are issued (so waiting for
-        // them never waits for stores)
-        load_coef_bf16path<L>(a, blk + bstep, col, half, raw);
+        const char* t = tiles + cur * TILE;
+        // B operands from the tile: pixel col, k = ks*16 + half*8 + [0,8)
+        bf16x8 wb[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) wb[ks] = *reinterpret_cast<const bf16x8*>(t + col * TROW + (ks * 16 + half * 8) * 2);
         f32x16 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -153,29 +198,28 @@ __global__ __launch_bounds__(256, (L <= 64 ? 2 : 1)) void k_decode_bf16(DecodeAr
                         make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
                 }
             }
+        // the next tile goes to the other buffer (its last readers finished
+        // before the previous barrier)
+        store_tile(tiles + (cur ^ 1) * TILE);
         lds_barrier();
-        convert();
-        // materialise the next block's operands here (ordered before the
-        // stores), so that waiting for their loads never waits for stores
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) asm volatile("" : "+v"(wb[ks]));
-        // write the 32 x D tile as contiguous rows
+        load_tile(blk + 2 * bstep);
+        // write the 32 x FC tile as contiguous rows: 32 rows x FC*OSZ/16
+        // vectors over FC threads, exactly 2*OSZ per thread (unconditional: a
+        // partial last block re-stores its final vector)
         const int chunks_per_row = row_bytes / 16;
         const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
         const int nvec = (int)rows * chunks_per_row;
         const long long out_row = (long long)D * OSZ;
         char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
-        // 32 rows x FC*OSZ/16 vectors over FC/2 threads: exactly 4*OSZ per thread
 #pragma unroll
-        for (int it = 0; it < 4 * OSZ; ++it) {
-            const int c = threadIdx.x + it * nwaves * 64;
-            if (c < nvec) {
-                const int r = c / chunks_per_row, q = c - r * chunks_per_row;
-                const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
-            }
+        for (int it = 0; it < 2 * OSZ; ++it) {
+            const int c = min((int)threadIdx.x + it * nthreads, nvec - 1);
+            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
         }
         lds_barrier();
+        cur ^= 1;
     }
 }
 
@@ -259,12 +303,13 @@ __global__ __launch_bounds__(512, 1) void k_decode_f32(DecodeArgs a) {
         // 32 rows x FC*OSZ/16 vectors over FC threads: exactly 2*OSZ per thread
 #pragma unroll
         for (int it = 0; it < 2 * OSZ; ++it) {
-            const int c = threadIdx.x + it * nwaves * 64;
-            if (c < nvec) {
-                const int r = c / chunks_per_row, q = c - r * chunks_per_row;
-                const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
-            }
+            // unconditional: in a partial last block the surplus lanes store the
+            // block's final vector again (same data, same address), which keeps
+            // the store count fixed so the waits above stay exact
+            const int c = min(threadIdx.x + it * nwaves * 64, nvec - 1);
+            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
         }
         lds_barrier();
     }
@@ -514,7 +559,8 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
         return grid > need ? need : grid;
     };
     if (compute == LS2_BF16) {
-        const int threads = (a.FC / 128) * 64;
+        const int threads = (a.FC / 64) * 64;
+        const size_t lds_b = lds + 2 * (size_t)32 * kTileRowBytes(L);
         static bool attr = false;
         if (!attr) {
             if (hipFuncSetAttribute((const void*)k_decode_bf16<L, OB>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -522,8 +568,11 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
                 return LS2_ERR_DEVICE;
             attr = true;
         }
-        const long long grid = grid_for((const void*)k_decode_bf16<L, OB>, threads);
-        hipLaunchKernelGGL((k_decode_bf16<L, OB>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+        long long grid = (long long)num_cus() * resident_per_cu((const void*)k_decode_bf16<L, OB>, threads, lds_b);
+        grid -= grid % a.nchunks;
+        if (grid < a.nchunks) grid = a.nchunks;
+        if (grid > need) grid = need;
+        hipLaunchKernelGGL((k_decode_bf16<L, OB>), dim3((unsigned)grid), dim3(threads), lds_b, stream, a);
     } else {
         const int threads = (a.FC / 64) * 64;
         static bool attr = false;
