@@ -257,16 +257,21 @@ def main():
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
     def run(compute, out_dtype, steps, warmup, query=False):
+        """Wall-clock rate over `steps` uninstrumented frames, then the same
+        number of frames with HIP events between the stages (per-stage
+        times; these frames are not part of the rate)."""
         for _ in range(warmup):
             frame(compute, out_dtype, query=query)
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for _ in range(steps):
+            frame(compute, out_dtype, query=query)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         for s in range(steps):
             frame(compute, out_dtype, evs[s], query=query)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         nst = 5 if query else 4
         per = {stages[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                for i in range(nst)}

@@ -20,21 +20,27 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 
 // Can a Gaussian with mean (u, v), conic (A, B, C) and opacity o reach
 // alpha >= 1/255 at any pixel centre of the box [x0, x1] x [y0, y1]?
-// alpha >= 1/255 <=> d^T Q d <= 2 ln(255 o), an ellipse whose bounding box
-// has half-widths sqrt(2 ln(255 o) Sigma_xx) and sqrt(2 ln(255 o) Sigma_yy)
-// with Sigma = Q^-1.  The box is inflated by 1e-3 relative + 0.01 px, far
-// beyond the float32 error of the kernel's own alpha, so a dropped entry is
-// one that every pixel of the box skips.  Degenerate values are kept.
+// alpha >= 1/255 <=> q(d) = d^T Q d <= t2 = 2 ln(255 o), Q = [[A, B], [B, C]].
+// q is convex, so its minimum over the box is 0 if the mean lies inside and
+// otherwise lies on an edge; on an edge with fixed dx the minimum over dy is
+// at dy = -B dx / C clamped to the edge (symmetrically for fixed dy).  The
+// test compares that exact minimum against t2 inflated by 2e-3 relative plus
+// 0.02, far beyond the float32 error of the kernel's own alpha, so a dropped
+// entry is one that every pixel of the box skips.  Degenerate values are kept.
 __device__ __forceinline__ bool may_touch(float u, float v, float A, float B, float C, float o, float x0, float x1,
                                           float y0, float y1) {
     if (!(o >= 1.0f / 255.0f)) return o != o;  // o < 1/255 never blends (NaN kept)
-    const float det = A * C - B * B;
     const float t2 = 2.0f * logf(255.0f * o);
-    if (!(det > 0.0f) || !(t2 >= 0.0f)) return true;
-    const float ex = sqrtf(t2 * C / det) * 1.001f + 0.01f;
-    const float ey = sqrtf(t2 * A / det) * 1.001f + 0.01f;
-    if (!(ex == ex) || !(ey == ey)) return true;
-    return u + ex >= x0 && u - ex <= x1 && v + ey >= y0 && v - ey <= y1;
+    if (!(A > 0.0f) || !(C > 0.0f) || !(A * C - B * B > 0.0f) || !(t2 >= 0.0f)) return true;
+    const float dx0 = x0 - u, dx1 = x1 - u, dy0 = y0 - v, dy1 = y1 - v;
+    if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;  // mean inside the box
+    const float bc = B / C, ba = B / A;
+    auto q = [&](float dx, float dy) { return fmaf(A * dx, dx, fmaf(2.0f * B * dx, dy, C * dy * dy)); };
+    auto on_x = [&](float dx) { return q(dx, fminf(fmaxf(-bc * dx, dy0), dy1)); };  // edge dx fixed
+    auto on_y = [&](float dy) { return q(fminf(fmaxf(-ba * dy, dx0), dx1), dy); };  // edge dy fixed
+    const float m = fminf(fminf(on_x(dx0), on_x(dx1)), fminf(on_y(dy0), on_y(dy1)));
+    if (!(m == m)) return true;
+    return m <= fmaf(t2, 1.002f, 0.02f);
 }
 
 }  // namespace ls2
