@@ -189,6 +189,38 @@ int ls2_query_coef(int64_t m, int32_t L, int32_t D, const float* coef, const flo
                    int32_t n_neg, const float* neg, float tau, float* relevancy, void* workspace,
                    size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * ls2_postprocess -- relevancy post-processing (Section 3.2: a mean filter on
+ * each level's relevancy map, then one semantic level is selected; the
+ * evaluation appendix: the localization point is the argmax of the smoothed
+ * map, the mask is the normalised smoothed map above a threshold, the blend
+ * 0.5 (M + Avg(M)) and selection by the mean relevancy inside the mask are
+ * the variant used for some datasets).
+ *
+ * In:  relevancy [levels,H,W] f32; kernel: odd box size (the mean runs over
+ *      the kernel x kernel window clipped to the image); smooth_mode
+ *      LS2_SMOOTH_AVG (Avg(M)) or LS2_SMOOTH_HALF (0.5 (M + Avg(M)));
+ *      select_mode LS2_SELECT_MAX (level with the largest smoothed maximum)
+ *      or LS2_SELECT_MASK_MEAN (level with the largest mean smoothed value
+ *      inside its own mask; an empty mask counts as -inf); threshold on the
+ *      normalised map (s - min) / (max - min) (0 when max == min), mask =
+ *      normalised > threshold.  Ties go to the lowest level / first pixel in
+ *      row-major order.
+ * Out: smoothed [levels,H,W] f32; mask [H,W] u8 (0/1) of the selected level;
+ *      result [4] int32 = selected level, x, y, y * W + x of the argmax;
+ *      level_stats [levels,4] f32 (optional) = max, min, mask mean, mask count.
+ * workspace: at least ls2_postprocess_workspace() bytes, 256-byte aligned.
+ * Every reduction runs in a fixed order (deterministic).
+ * Supported: levels <= 8, H * W < 2^31.
+ */
+enum { LS2_SMOOTH_AVG = 0, LS2_SMOOTH_HALF = 1 };
+enum { LS2_SELECT_MAX = 0, LS2_SELECT_MASK_MEAN = 1 };
+int ls2_postprocess_workspace(int32_t levels, int32_t H, int32_t W, size_t* bytes);
+int ls2_postprocess(int32_t levels, int32_t H, int32_t W, const float* relevancy, int32_t kernel,
+                    int32_t smooth_mode, int32_t select_mode, float threshold, float* smoothed,
+                    uint8_t* mask, int32_t* result, float* level_stats, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Backward pass.  The sparse coefficients and the codebook are learned
  * jointly (Section 3.3); these entry points give the gradients of every

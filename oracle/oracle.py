@@ -328,3 +328,51 @@ def project_backward(cam, means, scales, quats, radius, d_mean2d, d_conic, f64=F
     fn(_p(cam_array(cam)), n, _p(means), _p(scales), _p(quats), _p(_c(radius, np.int32)),
                                _p(_c(d_mean2d, np.float64)), _p(_c(d_conic, np.float64)), _p(dmu), _p(ds), _p(dq))
     return dmu, ds, dq
+
+
+# -------------------------------------------------------------------------- post-processing
+def postprocess(relevancy, kernel, smooth_mode=0, select_mode=0, threshold=0.5):
+    """Relevancy post-processing (Section 3.2: a mean filter over each level's
+    relevancy map, then one level is selected; the evaluation appendix gives
+    the localization point as the argmax of the smoothed map, the mask as the
+    normalised smoothed map above a threshold, and two selection rules).
+
+    relevancy: [levels, H, W].  kernel: odd box size.  smooth_mode 0: Avg(M),
+    1: 0.5 (M + Avg(M)).  select_mode 0: the level with the largest smoothed
+    maximum; 1: the level with the largest mean of the smoothed map inside its
+    own mask.  Readings: the box mean runs over the window clipped to the
+    image; ties (argmax, level) go to the smallest index; normalisation is
+    (s - min) / (max - min) per level (zero when max == min); the mask is
+    normalised > threshold; a level with an empty mask has mean -inf.
+
+    Plain float64 loops over the definitions.  Returns (smoothed, mask,
+    result=[level, x, y, flat index], stats [levels, 4] = max, min,
+    mask mean, mask count)."""
+    M = np.asarray(relevancy, np.float64)
+    lv, H, W = M.shape
+    r = kernel // 2
+    S = np.zeros_like(M)
+    for l in range(lv):
+        for y in range(H):
+            y0, y1 = max(0, y - r), min(H - 1, y + r)
+            for x in range(W):
+                x0, x1 = max(0, x - r), min(W - 1, x + r)
+                S[l, y, x] = M[l, y0:y1 + 1, x0:x1 + 1].sum() / ((y1 - y0 + 1) * (x1 - x0 + 1))
+    if smooth_mode == 1:
+        S = 0.5 * (M + S)
+    stats = np.zeros((lv, 4))
+    masks = np.zeros((lv, H, W), bool)
+    argmax = np.zeros(lv, np.int64)
+    for l in range(lv):
+        flat = S[l].reshape(-1)
+        argmax[l] = int(np.argmax(flat))       # first maximum in row-major order
+        mx, mn = flat.max(), flat.min()
+        norm = (S[l] - mn) / (mx - mn) if mx > mn else np.zeros_like(S[l])
+        masks[l] = norm > threshold
+        cnt = masks[l].sum()
+        stats[l] = (mx, mn, S[l][masks[l]].mean() if cnt else -np.inf, cnt)
+    key = stats[:, 0] if select_mode == 0 else stats[:, 2]
+    sel = int(np.argmax(key))                  # first level on ties
+    idx = int(argmax[sel])
+    result = np.array([sel, idx % W, idx // W, idx], np.int64)
+    return S, masks[sel].astype(np.uint8), result, stats

@@ -12,6 +12,10 @@ from ._lib import (  # noqa: F401
     LS2_ERR_UNSUPPORTED,
     LS2_F32,
     LS2_OK,
+    LS2_SELECT_MASK_MEAN,
+    LS2_SELECT_MAX,
+    LS2_SMOOTH_AVG,
+    LS2_SMOOTH_HALF,
     LS2Error,
     LIB_PATH,
     ls2_bin_sort,
@@ -24,6 +28,8 @@ from ._lib import (  # noqa: F401
     ls2_dict_decode_backward_workspace,
     ls2_feature_loss,
     ls2_feature_loss_workspace,
+    ls2_postprocess,
+    ls2_postprocess_workspace,
     ls2_project,
     ls2_project_backward,
     ls2_query,

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libls2.so")
 
 LS2_OK, LS2_ERR_ARG, LS2_ERR_CAPACITY, LS2_ERR_UNSUPPORTED, LS2_ERR_DEVICE = 0, -1, -2, -3, -4
 LS2_F32, LS2_BF16 = 0, 1
+LS2_SMOOTH_AVG, LS2_SMOOTH_HALF = 0, 1
+LS2_SELECT_MAX, LS2_SELECT_MASK_MEAN = 0, 1
 TILE = 16
 
 
@@ -53,6 +55,9 @@ def _load():
         "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_query_coef_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_query_coef": ([i64, i32, i32, P, P, P, i32, P, ctypes.c_float, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "ls2_postprocess_workspace": ([i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_postprocess": ([i32, i32, i32, P, i32, i32, i32, ctypes.c_float, P, P, P, P, P, ctypes.c_size_t, P],
+                            ctypes.c_int),
         "ls2_feature_loss_workspace": ([i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_feature_loss": ([i64, i32, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_query_backward": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P, P], ctypes.c_int),
@@ -236,6 +241,27 @@ def ls2_query_coef(coef, dictionary, pos, neg, relevancy, workspace, tau=1.0, st
                              _ptr(relevancy, f32, "relevancy", m), _ptr(workspace, torch.uint8, "workspace"),
                              workspace.numel(), _stream(stream))
     _check("ls2_query_coef", st)
+
+
+def ls2_postprocess_workspace(levels, H, W) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_postprocess_workspace", _lib.ls2_postprocess_workspace(int(levels), int(H), int(W), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_postprocess(relevancy, kernel, smoothed, mask, result, workspace, smooth_mode=LS2_SMOOTH_AVG,
+                    select_mode=LS2_SELECT_MAX, threshold=0.5, level_stats=None, stream=None):
+    """relevancy [levels, H, W] f32 -> smoothed (same shape), mask [H, W] uint8,
+    result [4] int32 (level, x, y, flat index), level_stats [levels, 4] (optional)."""
+    levels, H, W = relevancy.shape
+    n = levels * H * W
+    st = _lib.ls2_postprocess(int(levels), int(H), int(W), _ptr(relevancy, torch.float32, "relevancy", n), int(kernel),
+                              int(smooth_mode), int(select_mode), float(threshold),
+                              _ptr(smoothed, torch.float32, "smoothed", n), _ptr(mask, torch.uint8, "mask", H * W),
+                              _ptr(result, torch.int32, "result", 4),
+                              _ptr(level_stats, torch.float32, "level_stats", 4 * levels, allow_none=True),
+                              _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
+    _check("ls2_postprocess", st)
 
 
 # ------------------------------------------------------------------ backward
