@@ -185,6 +185,42 @@ def train_step_timing(args, torch, np, gen, ls2):
                                               4))
 
 
+def dense_ablation(args, torch, np, gen, ls2):
+    """Sparse (K of L blended) against dense (all L blended) splatting on the
+    1440x1080 scene with one level (L = 64) and three levels (3 x 64 = 192,
+    the rendering dimension Table 9 times); same lists, HIP events around the
+    splat kernel only."""
+    out = {}
+    for levels in (1, 3):
+        scene, cam = gen.config_scene(args.config, levels=levels)
+        t = ls2.to_device(scene)
+        pipe = ls2.Pipeline(cam, scene.n, levels=levels, K=scene.K, L=scene.L, D=scene.D)
+        pipe.project(t["means"], t["scales"], t["quats"])
+        pipe.bin_sort(sync=True)
+        n, L = scene.n, scene.L
+        Wd = torch.zeros((n, levels, L), dtype=torch.float32, device="cuda")
+        Wd.scatter_add_(2, t["topk_idx"].long(), t["topk_w"])    # input preparation
+        times = {}
+        for name, fn in (("sparse", lambda: pipe.splat(t["opacity"], t["topk_idx"], t["topk_w"])),
+                         ("dense", lambda: pipe.splat_dense(t["opacity"], Wd))):
+            for _ in range(2):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times[name + "_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+        times["dense_over_sparse"] = round(times["dense_ms"] / times["sparse_ms"], 2)
+        out["%dx%d" % (levels, L)] = times
+        del pipe, t, Wd
+        torch.cuda.empty_cache()
+    log("sparse vs dense splat: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +232,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path measurement")
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward (training step) timing")
     ap.add_argument("--train-config", default="c3")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the sparse-vs-dense splat timing")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
@@ -340,6 +377,8 @@ def main():
         torch.cuda.empty_cache()
         train = train_step_timing(args, torch, np, gen, ls2)
 
+    ablation = None if args.no_ablation else dense_ablation(args, torch, np, gen, ls2)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
@@ -367,6 +406,7 @@ def main():
         "query_from_coefficients": query_coef,
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},
+        "sparse_vs_dense_splat": ablation,
         "fwd_bwd_ms": None if train is None else round(train["ms"], 4),
         "fwd_bwd": train,
         "roofline": roofline,

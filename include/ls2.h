@@ -139,6 +139,20 @@ int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K
                      hipStream_t stream);
 
 /*
+ * ls2_splat_dense -- the dense form of the coefficient splatting: every
+ * Gaussian blends all L coefficients of each level (the rendering that
+ * Section 3.4 avoids by blending only the K non-zero ones; Table 9 times both).
+ * Same lists, alpha rule, culling and outputs as ls2_splat_sparse; weights are
+ * dense [n,levels,L].  With weights that are zero outside the stored indices
+ * the result equals ls2_splat_sparse (LDS-accumulator forms, levels * L <= 128)
+ * bit for bit.  Kept as the ablation baseline and as a cross-check.
+ * Supported: L in {32, 64}, levels in {1, 2, 3}, levels * L <= 192.
+ */
+int ls2_splat_dense(const ls2_camera* cam, int32_t n, int32_t levels, int32_t L, const uint32_t* tile_ranges,
+                    const uint32_t* ids, const float* mean2d, const float* conic, const float* opacity,
+                    const float* weights, float* coef, float* final_T, int32_t* last, hipStream_t stream);
+
+/*
  * ls2_dict_decode -- feature map F = W S (Eq. 7: rendering the sparse
  * coefficients and multiplying by the global codebook S equals rendering
  * the D-dimensional features).  One product shared by all levels.

@@ -36,6 +36,7 @@ from ._lib import (  # noqa: F401
     ls2_query_coef,
     ls2_query_coef_workspace,
     ls2_query_backward,
+    ls2_splat_dense,
     ls2_splat_sparse,
     ls2_splat_sparse_backward,
     make_camera,

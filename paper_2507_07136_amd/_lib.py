@@ -52,6 +52,7 @@ def _load():
         "ls2_bin_sort_count": ([P, ctypes.POINTER(ctypes.c_int64), P], ctypes.c_int),
         "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_dict_decode": ([i64, i32, i32, P, P, i32, i32, P, P], ctypes.c_int),
+        "ls2_splat_dense": ([cam, i32, i32, i32, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_query_coef_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_query_coef": ([i64, i32, i32, P, P, P, i32, P, ctypes.c_float, P, P, ctypes.c_size_t, P], ctypes.c_int),
@@ -196,6 +197,21 @@ def ls2_splat_sparse(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity
                                _ptr(final_T, f32, "final_T", HW, allow_none=True),
                                _ptr(last, i32, "last", HW, allow_none=True), _stream(stream))
     _check("ls2_splat_sparse", st)
+
+
+def ls2_splat_dense(cam, levels, L, tile_ranges, ids, mean2d, conic, opacity, weights, coef, final_T=None, last=None,
+                    stream=None):
+    n = opacity.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    HW = c.width * c.height
+    f32, i32 = torch.float32, torch.int32
+    st = _lib.ls2_splat_dense(ctypes.byref(c), n, int(levels), int(L), _ptr(tile_ranges, i32, "tile_ranges"),
+                              _ptr(ids, i32, "ids"), _ptr(mean2d, f32, "mean2d", 2 * n),
+                              _ptr(conic, f32, "conic", 3 * n), _ptr(opacity, f32, "opacity", n),
+                              _ptr(weights, f32, "weights", n * levels * L), _ptr(coef, f32, "coef", levels * HW * L),
+                              _ptr(final_T, f32, "final_T", HW, allow_none=True),
+                              _ptr(last, i32, "last", HW, allow_none=True), _stream(stream))
+    _check("ls2_splat_dense", st)
 
 
 def _dtype_code(t):

@@ -75,6 +75,11 @@ class Pipeline:
         _lib.ls2_splat_sparse(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids, self.mean2d,
                               self.conic, opacity, topk_idx, topk_w, self.coef, self.final_T, self.last)
 
+    def splat_dense(self, opacity, weights):
+        """Dense form (all L coefficients per Gaussian) into the same buffers."""
+        _lib.ls2_splat_dense(self.cam, self.levels, self.L, self.tile_ranges, self.ids, self.mean2d, self.conic,
+                             opacity, weights, self.coef, self.final_T, self.last)
+
     def decode(self, dictionary, compute=LS2_BF16, out_dtype=torch.bfloat16):
         m = self.levels * self.H * self.W
         if self.feat is None or self.feat.dtype != out_dtype:

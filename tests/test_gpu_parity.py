@@ -327,3 +327,32 @@ def test_query_coef_end_to_end_c1(orc, c1):
     torch.cuda.synchronize()
     ref = orc.query(orc.decode(g["coef"].astype(np.float64), scene.dictionary), pos, neg)
     assert np.abs(rel.cpu().numpy() - ref).max() <= 1e-5
+
+
+def _dense_weights(scene):
+    n, lv, K = scene.topk_idx.shape
+    W = np.zeros((n, lv, scene.L), np.float32)
+    for k in range(K):   # in k order, as the sparse kernel merges repeated indices
+        np.add.at(W, (np.arange(n)[:, None], np.arange(lv)[None, :], scene.topk_idx[:, :, k]), scene.topk_w[:, :, k])
+    return W
+
+
+@pytest.mark.parametrize("L,K,levels", [(64, 4, 1), (32, 8, 2), (64, 8, 2), (32, 4, 3), (64, 4, 3)])
+def test_dense_splat_equals_sparse(L, K, levels):
+    """Dense-L splat of the scattered codes equals the sparse splat: bit for bit
+    where the sparse kernel accumulates in LDS with the same fused multiply-add
+    (levels * L <= 128), to float32 rounding where it uses register vectors."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(303 + L + K + levels, 3000, 120, 90, L=L, K=K, levels=levels, D=128)
+    g = run_forward(cam, scene)
+    pipe, t = g["pipe"], g["t"]
+    Wd = torch.from_numpy(_dense_weights(scene)).cuda()
+    pipe.splat_dense(t["opacity"], Wd)
+    torch.cuda.synchronize()
+    coef_d = pipe.coef.cpu().numpy()
+    assert np.array_equal(pipe.last.cpu().numpy(), g["last"])
+    if levels * L <= 128:
+        assert np.array_equal(coef_d, g["coef"])
+        assert np.array_equal(pipe.final_T.cpu().numpy(), g["final_T"])
+    else:
+        assert np.abs(coef_d - g["coef"]).max() <= 1e-6
