@@ -185,6 +185,78 @@ def train_step_timing(args, torch, np, gen, ls2):
                                               4))
 
 
+def full_form(args, torch, np, gen, ls2, steps=2):
+    """The full form: 1M Gaussians at 1920x1080, three semantic levels (each
+    with its own K=4 codes over one shared 64x512 codebook), a batch of 8
+    views on a radius-3 circle.  One step = for every view: project, bin,
+    splat, float32 decode fused with the L1 + cosine loss against that view's
+    per-level targets, decode / splat / projection backward, and the
+    accumulation of the per-Gaussian and codebook gradients over the views."""
+    cfg = gen.CONFIGS["c5"]
+    scene, _ = gen.config_scene("c5")
+    H, W, D, levels = cfg["height"], cfg["width"], cfg["D"], cfg["levels"]
+    cams = [gen.orbit_camera(W, H, j, 8) for j in range(8)]
+    t = ls2.to_device(scene)
+    # per (view, level) targets, materialised on the device (input preparation)
+    targets = []
+    for j in range(8):
+        Y = torch.empty((levels, H, W, D), dtype=torch.float32, device="cuda")
+        for lv in range(levels):
+            zup, Pf = gen.make_target_factors(1005 * 100 + 8 * lv + j, H, W, D=D)
+            Y[lv] = (torch.from_numpy(zup).cuda().reshape(-1, zup.shape[-1]) @ torch.from_numpy(Pf).cuda()).reshape(
+                H, W, D)
+        targets.append(Y)
+    tr = ls2.Trainer(cams[0], scene.n, levels=levels, K=scene.K, L=scene.L, D=D)
+    total = ls2.Gradients(scene.n, levels, scene.K, scene.L, D, H, W, "cuda")
+    pairs = []
+    for j in range(8):                                  # size the pair buffers for every view
+        tr.set_camera(cams[j])
+        tr.project(t["means"], t["scales"], t["quats"])
+        pairs.append(tr.bin_sort(sync=True))
+    torch.cuda.synchronize()
+
+    def step():
+        for name in ("dictionary", "means", "scales", "quats", "opacity", "topk_w"):
+            getattr(total, name).zero_()
+        for j in range(8):
+            tr.set_camera(cams[j])
+            tr.forward_loss(t, targets[j], sync=False)
+            tr.backward(t)
+            tr.accumulate_into(total)
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    # algorithmic HBM bytes of one step (per view: projection, lists, splat,
+    # fused decode + loss, decode / splat / projection backward)
+    n, L, K, M = scene.n, scene.L, scene.K, levels * H * W
+    per_view = []
+    for P in pairs:
+        b = algorithmic_bytes("project", n, P, H, W, L, D, K, levels, 4)
+        b += algorithmic_bytes("bin_sort", n, P, H, W, L, D, K, levels, 4)
+        b += algorithmic_bytes("splat", n, P, H, W, L, D, K, levels, 4)
+        b += M * L * 4 + 2 * M * D * 4                      # decode + loss: W in, Y in, dL/dF out
+        b += 2 * M * D * 4 + 2 * M * L * 4                  # decode backward: G twice, W in, dW out
+        b += M * L * 4 + H * W * 8 + P * 4 + n * (8 + 12 + 4 + levels * K * 8) + n * levels * K * 4 + n * 24
+        b += n * (40 + 20 + 40)                             # projection backward
+        per_view.append(b)
+    gb = sum(per_view) / 1e9
+    out = dict(workload="c5: %d Gaussians, %dx%d, %d levels (L=%d, K=%d each, shared %dx%d codebook), 8 orbit views; "
+                        "float32 forward + loss + backward per view, gradients accumulated over the views"
+                        % (n, W, H, levels, L, K, L, D),
+               ms_per_step=round(ms, 3), ms_per_view=round(ms / 8, 3), pairs_per_view=[int(P) for P in pairs],
+               algorithmic_GB_per_step=round(gb, 2), hbm_GBs=round(gb / (ms * 1e-3), 1),
+               hbm_frac=round(gb / (ms * 1e-3) / HBM_PEAK_GBS, 4), loss_last_view=tr.loss.item())
+    log("full form: %s" % out)
+    del targets, tr, total, t
+    torch.cuda.empty_cache()
+    return out
+
+
 def dense_ablation(args, torch, np, gen, ls2):
     """Sparse (K of L blended) against dense (all L blended) splatting on the
     1440x1080 scene with one level (L = 64) and three levels (3 x 64 = 192,
@@ -233,6 +305,8 @@ def main():
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward (training step) timing")
     ap.add_argument("--train-config", default="c3")
     ap.add_argument("--no-ablation", action="store_true", help="skip the sparse-vs-dense splat timing")
+    ap.add_argument("--no-full-form", action="store_true",
+                    help="skip the 1M-Gaussian, 3-level, 8-view training step")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
@@ -378,6 +452,7 @@ def main():
         train = train_step_timing(args, torch, np, gen, ls2)
 
     ablation = None if args.no_ablation else dense_ablation(args, torch, np, gen, ls2)
+    full = None if args.no_full_form else full_form(args, torch, np, gen, ls2)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -407,6 +482,7 @@ def main():
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},
         "sparse_vs_dense_splat": ablation,
+        "full_form": full,
         "fwd_bwd_ms": None if train is None else round(train["ms"], 4),
         "fwd_bwd": train,
         "roofline": roofline,

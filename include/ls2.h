@@ -341,6 +341,25 @@ int ls2_splat_sparse_backward(const ls2_camera* cam, int32_t n, int32_t levels, 
                               float* d_topk_w, hipStream_t stream);
 
 /*
+ * ls2_sparse_codes -- the sparse coefficient parametrisation (Section 3.3): a
+ * Gaussian's L-dimensional parameter z is normalised by a softmax, its K
+ * largest values are kept and renormalised to sum 1, which equals the softmax
+ * of the K kept logits.  Indices come in descending order of the logit, ties
+ * to the smaller index.  ls2_sparse_codes_backward gives dL/dz from dL/dw with
+ * the selection held fixed: dz_j = w_j (dw_j - sum_k w_k dw_k) for kept j, 0
+ * otherwise (d_logits is overwritten).
+ *
+ * In:  logits [rows,L] f32 (rows = n * levels).
+ * Out: topk_idx [rows,K] int32, topk_w [rows,K] f32 (the layout
+ *      ls2_splat_sparse consumes).
+ * Supported: L a multiple of 4 up to 1024, 1 <= K <= 8.
+ */
+int ls2_sparse_codes(int64_t rows, int32_t L, int32_t K, const float* logits, int32_t* topk_idx, float* topk_w,
+                     hipStream_t stream);
+int ls2_sparse_codes_backward(int64_t rows, int32_t L, int32_t K, const int32_t* topk_idx, const float* topk_w,
+                              const float* d_topk_w, float* d_logits, hipStream_t stream);
+
+/*
  * ls2_project_backward -- gradients of ls2_project (Section 3.1, Eqs. 1-2,
  * EWA projection as in ls2_project) from d_mean2d [n,2] and d_conic [n,3]
  * to d_means [n,3], d_scales [n,3] and d_quats [n,4] (through the
@@ -351,6 +370,13 @@ int ls2_project_backward(const ls2_camera* cam, int32_t n, const float* means, c
                          const float* quats, const int32_t* radius, const float* d_mean2d,
                          const float* d_conic, float* d_means, float* d_scales, float* d_quats,
                          hipStream_t stream);
+
+/*
+ * ls2_accumulate -- dst[i] += src[i] for i < n (f32): sums the gradients of
+ * the views of one training step (the batch of camera views is one step).
+ * Both pointers 16-byte aligned.
+ */
+int ls2_accumulate(int64_t n, const float* src, float* dst, hipStream_t stream);
 
 #ifdef __cplusplus
 }

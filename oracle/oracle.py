@@ -376,3 +376,38 @@ def postprocess(relevancy, kernel, smooth_mode=0, select_mode=0, threshold=0.5):
     idx = int(argmax[sel])
     result = np.array([sel, idx % W, idx // W, idx], np.int64)
     return S, masks[sel].astype(np.uint8), result, stats
+
+
+# -------------------------------------------------------------------------- sparse code parametrisation
+def sparse_codes(logits, K):
+    """Section 3.3: the L-dimensional parameter of a Gaussian is normalised by a
+    softmax, the top-K values are kept and renormalised to sum 1.  Returns
+    (idx [rows, K] int32, w [rows, K]) with indices in descending order of the
+    logit (ties: smaller index first).  Since every softmax value shares the
+    same denominator, the renormalised weights are the softmax of the K kept
+    logits; computed here from the definition (softmax, select, divide)."""
+    z = np.asarray(logits, np.float64)
+    rows, L = z.shape
+    idx = np.zeros((rows, K), np.int32)
+    w = np.zeros((rows, K))
+    for r in range(rows):
+        p = np.exp(z[r] - z[r].max())
+        p /= p.sum()
+        order = sorted(range(L), key=lambda j: (-z[r, j], j))[:K]
+        idx[r] = order
+        kept = p[order]
+        w[r] = kept / kept.sum()
+    return idx, w
+
+
+def sparse_codes_backward(logits, K, d_w):
+    """d logits of sparse_codes given dL/dw (the selection is piecewise
+    constant): for kept j, dz_j = w_j (dw_j - sum_k w_k dw_k); 0 elsewhere."""
+    idx, w = sparse_codes(logits, K)
+    d_w = np.asarray(d_w, np.float64)
+    dz = np.zeros(np.asarray(logits).shape)
+    for r in range(dz.shape[0]):
+        s = float((w[r] * d_w[r]).sum())
+        for k in range(K):
+            dz[r, idx[r, k]] = w[r, k] * (d_w[r, k] - s)
+    return dz

@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     LS2_SMOOTH_HALF,
     LS2Error,
     LIB_PATH,
+    ls2_accumulate,
     ls2_bin_sort,
     ls2_bin_sort_count,
     ls2_bin_sort_workspace,
@@ -36,6 +37,8 @@ from ._lib import (  # noqa: F401
     ls2_query_coef,
     ls2_query_coef_workspace,
     ls2_query_backward,
+    ls2_sparse_codes,
+    ls2_sparse_codes_backward,
     ls2_splat_dense,
     ls2_splat_sparse,
     ls2_splat_sparse_backward,

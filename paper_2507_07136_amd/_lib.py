@@ -68,6 +68,9 @@ def _load():
         "ls2_dict_decode_backward": ([i64, i32, i32, P, P, i32, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_splat_sparse_backward": ([cam, i32, i32, i32, i32] + [P] * 15, ctypes.c_int),
         "ls2_project_backward": ([cam, i32] + [P] * 9 + [P], ctypes.c_int),
+        "ls2_sparse_codes": ([i64, i32, i32, P, P, P, P], ctypes.c_int),
+        "ls2_accumulate": ([i64, P, P, P], ctypes.c_int),
+        "ls2_sparse_codes_backward": ([i64, i32, i32, P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -379,3 +382,31 @@ def ls2_project_backward(cam, means, scales, quats, radius, d_mean2d, d_conic, d
         _ptr(d_means, f32, "d_means", 3 * n), _ptr(d_scales, f32, "d_scales", 3 * n),
         _ptr(d_quats, f32, "d_quats", 4 * n), _stream(stream))
     _check("ls2_project_backward", st)
+
+
+def ls2_sparse_codes(logits, K, topk_idx, topk_w, stream=None):
+    """logits [..., L] -> topk_idx [..., K] int32, topk_w [..., K] f32."""
+    L = logits.shape[-1]
+    rows = logits.numel() // L
+    st = _lib.ls2_sparse_codes(rows, L, int(K), _ptr(logits, torch.float32, "logits", rows * L),
+                               _ptr(topk_idx, torch.int32, "topk_idx", rows * K),
+                               _ptr(topk_w, torch.float32, "topk_w", rows * K), _stream(stream))
+    _check("ls2_sparse_codes", st)
+
+
+def ls2_sparse_codes_backward(topk_idx, topk_w, d_topk_w, d_logits, stream=None):
+    L = d_logits.shape[-1]
+    rows = d_logits.numel() // L
+    K = topk_idx.shape[-1]
+    st = _lib.ls2_sparse_codes_backward(rows, L, int(K), _ptr(topk_idx, torch.int32, "topk_idx", rows * K),
+                                        _ptr(topk_w, torch.float32, "topk_w", rows * K),
+                                        _ptr(d_topk_w, torch.float32, "d_topk_w", rows * K),
+                                        _ptr(d_logits, torch.float32, "d_logits", rows * L), _stream(stream))
+    _check("ls2_sparse_codes_backward", st)
+
+
+def ls2_accumulate(src, dst, stream=None):
+    """dst += src (float32, same number of elements)."""
+    n = src.numel()
+    _check("ls2_accumulate", _lib.ls2_accumulate(n, _ptr(src, torch.float32, "src", n),
+                                                 _ptr(dst, torch.float32, "dst", n), _stream(stream)))

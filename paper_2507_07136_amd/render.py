@@ -193,6 +193,19 @@ class Trainer(Pipeline):
                                   g.conic, g.means, g.scales, g.quats)
         return g
 
+    def set_camera(self, cam):
+        """Switch to another view of the same image size (buffers are reused)."""
+        c = _lib.make_camera(cam)
+        if (c.width, c.height) != (self.W, self.H):
+            raise ValueError("set_camera: image size differs from the trainer's buffers")
+        self.cam = c
+
+    def accumulate_into(self, total):
+        """total.<name> += self.grad.<name> for every gradient buffer (a
+        ``Gradients`` of the same shapes), e.g. over the views of a step."""
+        for name in ("dictionary", "means", "scales", "quats", "opacity", "topk_w"):
+            _lib.ls2_accumulate(getattr(self.grad, name), getattr(total, name))
+
     def step(self, scene, target, sync=True):
         loss = self.forward_loss(scene, target, sync=sync)
         return loss, self.backward(scene)

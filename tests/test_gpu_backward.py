@@ -347,3 +347,28 @@ def test_autograd_function(orc):
     ref = _oracle_chain(orc, cam, scene, g, R.astype(np.float64))
     for name in ["means", "scales", "quats", "opacity", "topk_w", "dictionary"]:
         _grad_close(params[name].grad.cpu().numpy(), ref[name], "d_" + name, floor=CHAIN_FLOOR)
+
+
+@pytest.mark.parametrize("rows,L,K", [(5000, 64, 4), (777, 128, 8), (33, 32, 1), (1, 64, 8)])
+def test_sparse_codes_parity(orc, rows, L, K):
+    """Softmax / top-K / renormalise and its backward against the oracle:
+    indices bit-exact (logits are distinct except one planted tie),
+    weights and gradients within float32 rounding."""
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(rows + L + K)
+    z = (rng.normal(size=(rows, L)) * 2).astype(np.float32)
+    z[0, 5] = z[0, 9] = z[0].max() + 1.0           # tie for the top: index 5 first
+    dw = rng.normal(size=(rows, K)).astype(np.float32)
+    tz = torch.from_numpy(z).cuda()
+    idx = torch.empty((rows, K), dtype=torch.int32, device="cuda")
+    w = torch.empty((rows, K), dtype=torch.float32, device="cuda")
+    ls2.ls2_sparse_codes(tz, K, idx, w)
+    dz = torch.empty((rows, L), dtype=torch.float32, device="cuda")
+    ls2.ls2_sparse_codes_backward(idx, w, torch.from_numpy(dw).cuda(), dz)
+    torch.cuda.synchronize()
+    ridx, rw = orc.sparse_codes(z, K)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert idx[0, 0].item() == 5 and (K == 1 or idx[0, 1].item() == 9)
+    assert np.abs(w.cpu().numpy() - rw).max() <= 1e-6
+    rdz = orc.sparse_codes_backward(z, K, dw)
+    assert np.abs(dz.cpu().numpy() - rdz).max() <= 1e-5 * max(1.0, np.abs(rdz).max())
