@@ -307,6 +307,8 @@ def main():
     ap.add_argument("--no-ablation", action="store_true", help="skip the sparse-vs-dense splat timing")
     ap.add_argument("--no-full-form", action="store_true",
                     help="skip the 1M-Gaussian, 3-level, 8-view training step")
+    ap.add_argument("--full-form-only", action="store_true",
+                    help="only run the full-form training step and print its JSON (for profiling it alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes five times (counter calibration)")
     args = ap.parse_args()
@@ -334,6 +336,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.full_form_only:
+        print(json.dumps({"full_form": full_form(args, torch, np, gen, ls2, steps=max(1, args.steps))}), flush=True)
+        return
     cfg = gen.CONFIGS[args.config]
     log("generating scene", args.config, cfg)
     scene, cam = gen.config_scene(args.config)

@@ -308,6 +308,9 @@ int ls2_query_backward(int64_t m, int32_t D, const void* feat, int32_t feat_dtyp
  *      (deterministic).
  * workspace: at least ls2_dict_decode_backward_workspace() bytes when d_dict
  *      is requested (partial sums over pixel ranges), 16-byte aligned.
+ * coef, dict, d_feat and d_coef must be 16-byte aligned (LS2_ERR_ARG
+ *      otherwise).  With L <= 64, D <= 512 and both outputs requested, one
+ *      kernel forms both products from a single read of d_feat.
  * Supported: L in {32, 64, 128}; D in {128, 256, 384, 512, 1024}.
  */
 int ls2_dict_decode_backward_workspace(int64_t m, int32_t L, int32_t D, size_t* bytes);

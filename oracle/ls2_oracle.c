@@ -808,6 +808,60 @@ void orc_decode_backward(int64_t M, int L, int D, const double* coef, const doub
  *   dpower/dA = -dx^2 / 2, dpower/dB = -dx dy, dpower/dC = -dy^2 / 2.
  * The forward walk is re-run here and its contributors stored; the suffix
  * sums are formed directly.  Gradient outputs are overwritten. */
+/* One pixel's share of the splat gradients: g0 points at the pixel's     */
+/* dL/dcoef of level 0 and level lv sits lv_stride doubles further.  The   */
+/* scratch arrays hold maxlen + 1 entries.                                */
+static void backward_pixel(const cam_t* cam, int px, int py, int levels, int K, const uint32_t* ranges,
+                           const uint32_t* ids, const double* mean2d, const double* conic, const double* opacity,
+                           const int32_t* topk_idx, const double* topk_w, const double* g0, size_t lv_stride,
+                           int32_t* pos, double* e, double* Tb, double* al, double* cc, double* d_mean2d,
+                           double* d_conic, double* d_opacity, double* d_w) {
+    int t = (py / ORC_TILE) * cam->tx + px / ORC_TILE;
+    double T, mg;
+    int32_t lst;
+    int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids, mean2d, conic, opacity, pos,
+                         e, Tb, al, &T, &lst, &mg, NULL);
+    for (int c = 0; c < cnt; ++c) {
+        uint32_t i = ids[ranges[2 * t] + pos[c]];
+        double s = 0;
+        for (int lv = 0; lv < levels; ++lv) {
+            const double* g = g0 + (size_t)lv * lv_stride;
+            for (int k = 0; k < K; ++k) {
+                size_t o = ((size_t)i * levels + lv) * K + k;
+                s += g[topk_idx[o]] * topk_w[o];
+                d_w[o] += g[topk_idx[o]] * e[c];
+            }
+        }
+        cc[c] = s;
+    }
+    double suffix = 0.0; /* sum_{m > i} c_m e_m */
+    for (int c = cnt - 1; c >= 0; --c) {
+        uint32_t i = ids[ranges[2 * t] + pos[c]];
+        double dalpha = Tb[c] * cc[c] - suffix / (1.0 - al[c]);
+        suffix += cc[c] * e[c];
+        double dx = mean2d[2 * i] - (px + 0.5), dy = mean2d[2 * i + 1] - (py + 0.5);
+        double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
+        double power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
+        double G = exp(power);
+        if (opacity[i] * G >= ALPHA_MAX) continue; /* clamped: no gradient */
+        double dpow = dalpha * opacity[i] * G;
+        d_opacity[i] += dalpha * G;
+        d_mean2d[2 * i] += dpow * (-(A * dx + B * dy));
+        d_mean2d[2 * i + 1] += dpow * (-(C * dy + B * dx));
+        d_conic[3 * i] += dpow * (-0.5 * dx * dx);
+        d_conic[3 * i + 1] += dpow * (-dx * dy);
+        d_conic[3 * i + 2] += dpow * (-0.5 * dy * dy);
+    }
+}
+
+static void zero_splat_grads(int n, int levels, int K, double* d_mean2d, double* d_conic, double* d_opacity,
+                             double* d_w) {
+    memset(d_mean2d, 0, sizeof(double) * 2 * (size_t)n);
+    memset(d_conic, 0, sizeof(double) * 3 * (size_t)n);
+    memset(d_opacity, 0, sizeof(double) * (size_t)n);
+    memset(d_w, 0, sizeof(double) * (size_t)n * levels * K);
+}
+
 void orc_composite_backward(const double* cam_arr, int n, int levels, int K, int L, const uint32_t* ranges,
                             const uint32_t* ids, const double* mean2d, const double* conic, const double* opacity,
                             const int32_t* topk_idx, const double* topk_w, const double* d_coef,
@@ -815,10 +869,7 @@ void orc_composite_backward(const double* cam_arr, int n, int levels, int K, int
     cam_t cam = cam_from(cam_arr);
     int ntiles = cam.tx * cam.ty;
     size_t HW = (size_t)cam.W * cam.H;
-    memset(d_mean2d, 0, sizeof(double) * 2 * (size_t)n);
-    memset(d_conic, 0, sizeof(double) * 3 * (size_t)n);
-    memset(d_opacity, 0, sizeof(double) * (size_t)n);
-    memset(d_w, 0, sizeof(double) * (size_t)n * levels * K);
+    zero_splat_grads(n, levels, K, d_mean2d, d_conic, d_opacity, d_w);
     uint32_t maxlen = max_range(ranges, ntiles);
     /* sequential over pixels: gradient accumulation into shared per-Gaussian
      * slots stays deterministic and obviously race-free */
@@ -830,45 +881,39 @@ void orc_composite_backward(const double* cam_arr, int n, int levels, int K, int
     for (int t = 0; t < ntiles; ++t) {
         int tx = t % cam.tx, ty = t / cam.tx;
         for (int py = ty * ORC_TILE; py < (ty + 1) * ORC_TILE && py < cam.H; ++py)
-            for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < cam.W; ++px) {
-                size_t pix = (size_t)py * cam.W + px;
-                double T, mg;
-                int32_t lst;
-                int cnt = walk_pixel(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids, mean2d, conic,
-                                     opacity, pos, e, Tb, al, &T, &lst, &mg, NULL);
-                for (int c = 0; c < cnt; ++c) {
-                    uint32_t i = ids[ranges[2 * t] + pos[c]];
-                    double s = 0;
-                    for (int lv = 0; lv < levels; ++lv) {
-                        const double* g = d_coef + ((size_t)lv * HW + pix) * L;
-                        for (int k = 0; k < K; ++k) {
-                            size_t o = ((size_t)i * levels + lv) * K + k;
-                            s += g[topk_idx[o]] * topk_w[o];
-                            d_w[o] += g[topk_idx[o]] * e[c];
-                        }
-                    }
-                    cc[c] = s;
-                }
-                double suffix = 0.0; /* sum_{m > i} c_m e_m */
-                for (int c = cnt - 1; c >= 0; --c) {
-                    uint32_t i = ids[ranges[2 * t] + pos[c]];
-                    double dalpha = Tb[c] * cc[c] - suffix / (1.0 - al[c]);
-                    suffix += cc[c] * e[c];
-                    double dx = mean2d[2 * i] - (px + 0.5), dy = mean2d[2 * i + 1] - (py + 0.5);
-                    double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
-                    double power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
-                    double G = exp(power);
-                    if (opacity[i] * G >= ALPHA_MAX) continue; /* clamped: no gradient */
-                    double dpow = dalpha * opacity[i] * G;
-                    d_opacity[i] += dalpha * G;
-                    d_mean2d[2 * i] += dpow * (-(A * dx + B * dy));
-                    d_mean2d[2 * i + 1] += dpow * (-(C * dy + B * dx));
-                    d_conic[3 * i] += dpow * (-0.5 * dx * dx);
-                    d_conic[3 * i + 1] += dpow * (-dx * dy);
-                    d_conic[3 * i + 2] += dpow * (-0.5 * dy * dy);
-                }
-            }
+            for (int px = tx * ORC_TILE; px < (tx + 1) * ORC_TILE && px < cam.W; ++px)
+                backward_pixel(&cam, px, py, levels, K, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
+                               d_coef + ((size_t)py * cam.W + px) * L, HW * L, pos, e, Tb, al, cc, d_mean2d,
+                               d_conic, d_opacity, d_w);
     }
+    free(pos);
+    free(e);
+    free(Tb);
+    free(al);
+    free(cc);
+}
+
+/* The same gradients when dL/dcoef is zero outside the listed pixels (flat */
+/* indices py * W + px, each listed once): a pixel with zero upstream       */
+/* gradient adds nothing to any Gaussian, so only the listed pixels are     */
+/* walked.  d_coef: [npix, levels, L], row q for pixel pix[q].             */
+void orc_composite_backward_pixels(const double* cam_arr, int n, int levels, int K, int L,
+                                   const uint32_t* ranges, const uint32_t* ids, const double* mean2d,
+                                   const double* conic, const double* opacity, const int32_t* topk_idx,
+                                   const double* topk_w, int64_t npix, const int64_t* pix, const double* d_coef,
+                                   double* d_mean2d, double* d_conic, double* d_opacity, double* d_w) {
+    cam_t cam = cam_from(cam_arr);
+    zero_splat_grads(n, levels, K, d_mean2d, d_conic, d_opacity, d_w);
+    uint32_t maxlen = max_range(ranges, cam.tx * cam.ty);
+    int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (maxlen + 1));
+    double* e = (double*)malloc(sizeof(double) * (maxlen + 1));
+    double* Tb = (double*)malloc(sizeof(double) * (maxlen + 1));
+    double* al = (double*)malloc(sizeof(double) * (maxlen + 1));
+    double* cc = (double*)malloc(sizeof(double) * (maxlen + 1));
+    for (int64_t q = 0; q < npix; ++q)
+        backward_pixel(&cam, (int)(pix[q] % cam.W), (int)(pix[q] / cam.W), levels, K, ranges, ids, mean2d, conic,
+                       opacity, topk_idx, topk_w, d_coef + (size_t)q * levels * L, L, pos, e, Tb, al, cc, d_mean2d,
+                       d_conic, d_opacity, d_w);
     free(pos);
     free(e);
     free(Tb);

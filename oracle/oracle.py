@@ -86,6 +86,8 @@ _BACKWARD_DECLS: dict = {
     "orc_decode_backward": [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _P_, _P_, _P_, _P_, _P_],
     "orc_composite_backward": [_P_, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P_, _P_, _P_, _P_, _P_,
                                _P_, _P_, _P_, _P_, _P_, _P_, _P_],
+    "orc_composite_backward_pixels": [_P_, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P_, _P_, _P_,
+                                      _P_, _P_, _P_, _P_, ctypes.c_int64, _P_, _P_, _P_, _P_, _P_, _P_],
     "orc_project_backward": [_P_, ctypes.c_int, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_],
     "orc_project_backward_f64": [_P_, ctypes.c_int, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_, _P_],
 }
@@ -313,6 +315,27 @@ def composite_backward(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_
             _c(d_coef, np.float64)]
     lib().orc_composite_backward(_p(cam_array(cam)), n, levels, K, L, *[_p(a) for a in args], _p(dm), _p(dcn),
                                  _p(do), _p(dw))
+    return dm, dcn, do, dw
+
+
+def composite_backward_pixels(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, pix, d_coef_pix):
+    """``composite_backward`` for an upstream gradient that is zero outside the
+    flat pixel indices ``pix`` (each listed once); d_coef_pix (npix, levels, L)
+    holds the gradient of those pixels.  Same outputs."""
+    n, levels, K = topk_idx.shape
+    pix = _c(pix, np.int64)
+    g = _c(d_coef_pix, np.float64)
+    assert g.shape[:2] == (pix.shape[0], levels) and len(np.unique(pix)) == pix.shape[0]
+    L = g.shape[-1]
+    dm = np.zeros((n, 2))
+    dcn = np.zeros((n, 3))
+    do = np.zeros(n)
+    dw = np.zeros((n, levels, K))
+    ids = _c(ids, np.uint32)
+    args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
+            _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64)]
+    lib().orc_composite_backward_pixels(_p(cam_array(cam)), n, levels, K, L, *[_p(a) for a in args], pix.shape[0],
+                                        _p(pix), _p(g), _p(dm), _p(dcn), _p(do), _p(dw))
     return dm, dcn, do, dw
 
 

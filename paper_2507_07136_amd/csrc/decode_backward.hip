@@ -230,6 +230,156 @@ __global__ __launch_bounds__(1024) void k_ddict_reduce(const float* __restrict__
     }
 }
 
+// Both products in one pass over G (L <= 64, D a multiple of 64, D <= 512):
+// a workgroup of D / 64 waves walks 32-pixel tiles; wave w owns features
+// [64 w, 64 w + 64).  Per tile:
+//   1. each wave copies its 32 x 64 slice of G, and the workgroup the tile's
+//      32 x L coefficients W, into LDS (both loaded coalesced during the
+//      previous tile), then issues the loads of the next tile;
+//   2. each wave forms its dW^T partial [L x 32] = S[:, its features]
+//      G[tile, its features]^T (S in registers) and writes it to LDS;
+//   3. after a barrier each wave accumulates dS[:, its features] += W^T G in
+//      registers and then takes its share of summing the D / 64 partials (in
+//      wave order) into the tile's dW rows, so the sums overlap the other
+//      waves' matrix-core work.
+// At the end each workgroup writes its dS partial; k_ddict_reduce sums the
+// partials in a fixed order.  G is read from HBM once instead of twice.
+constexpr int kFusedRow = 68;  // G staging / partial row stride (floats)
+
+template <int L, int WPT>
+__global__ __launch_bounds__(512, 1) void k_decode_bw_fused(DecodeBwArgs a) {
+    constexpr int TL = L / 32;
+    constexpr int PROW = L + 4;
+    constexpr int WROW = L + 4;
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int D = a.D;
+    const int nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const int f_wave = wave * 64;
+    float* stage = lds + wave * (32 * kFusedRow);                  // [32 px][68], this wave's G slice
+    float* part = lds + nwaves * (32 * kFusedRow);                 // [nwaves][32 px][L + 4]
+    float* wt = part + nwaves * (32 * PROW);                       // [32 px][L + 4], the tile's W
+    const long long nblk = (a.m + 31) / 32;
+
+    // S in the dW layout: sb[tl][j] = S[32 tl + col][f_wave + 32 half + j]
+    float sb[TL][32];
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int j = 0; j < 32; ++j) sb[tl][j] = a.dict[(size_t)(32 * tl + col) * D + f_wave + 32 * half + j];
+
+    f32x16b accd[TL][2];
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) accd[tl][mt] = (f32x16b){};
+
+    // coalesced G slice loads: instruction i covers rows 4 i .. 4 i + 3, lane
+    // l row 4 i + l / 16, float4 column l % 16.  W: float4 number
+    // threadIdx.x + k blockDim.x of the tile (row-major), k < WPT
+    const int lrow = lane >> 4, lc4 = lane & 15;
+    constexpr int W4 = 32 * L / 4;   // float4s in a W tile; WPT >= W4 / blockDim.x
+    float4 gr[8], wreg[WPT];
+    auto load_tile = [&](long long blk) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const long long p = blk * 32 + 4 * i + lrow;
+            gr[i] = (blk < nblk && p < a.m) ? reinterpret_cast<const float4*>(a.d_feat + p * D + f_wave)[lc4]
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int idx = threadIdx.x + k * blockDim.x;
+            const int wr = idx / (L / 4), wc4 = idx - wr * (L / 4);
+            const long long p = blk * 32 + wr;
+            wreg[k] = (idx < W4 && blk < nblk && p < a.m) ? reinterpret_cast<const float4*>(a.coef + p * L)[wc4]
+                                                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    long long blk = blockIdx.x;
+    load_tile(blk);
+    for (; blk < nblk; blk += gridDim.x) {
+        const long long p0 = blk * 32;
+        // 1. LDS copies (every read of the previous tile's copies ended before
+        //    the barrier that closed it)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) *reinterpret_cast<float4*>(stage + (4 * i + lrow) * kFusedRow + 4 * lc4) = gr[i];
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int idx = threadIdx.x + k * blockDim.x;
+            const int wr = idx / (L / 4), wc4 = idx - wr * (L / 4);
+            if (idx < W4) *reinterpret_cast<float4*>(wt + wr * WROW + 4 * wc4) = wreg[k];
+        }
+        wave_lds_order();
+        load_tile(blk + gridDim.x);
+        // 2. dW^T partial over this wave's 64 features
+        f32x16b accc[TL];
+#pragma unroll
+        for (int tl = 0; tl < TL; ++tl) accc[tl] = (f32x16b){};
+#pragma unroll
+        for (int j4 = 0; j4 < 8; ++j4) {
+            const float4 g4 = *reinterpret_cast<const float4*>(stage + col * kFusedRow + 32 * half + 4 * j4);
+            const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int tl = 0; tl < TL; ++tl)
+                    accc[tl] = __builtin_amdgcn_mfma_f32_32x32x2f32(sb[tl][4 * j4 + e], gv[e], accc[tl], 0, 0, 0);
+        }
+        // lane holds atoms 32 tl + 8 g + 4 half + i of pixel col
+        float* pw = part + wave * (32 * PROW) + col * PROW;
+#pragma unroll
+        for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                *reinterpret_cast<float4*>(pw + 32 * tl + 8 * g + 4 * half) =
+                    make_float4(accc[tl][4 * g], accc[tl][4 * g + 1], accc[tl][4 * g + 2], accc[tl][4 * g + 3]);
+        lds_barrier();
+        // 3a. dS += W^T G: step s pairs pixel q(s) (half 0) with q(s) + 8 (half 1)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int q = (s >> 3) * 16 + (s & 7) + 8 * half;
+            float w[TL], g[2];
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl) w[tl] = wt[q * WROW + 32 * tl + col];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) g[mt] = stage[q * kFusedRow + 32 * mt + col];
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+                    accd[tl][mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[tl], g[mt], accd[tl][mt], 0, 0, 0);
+        }
+        // 3b. this thread's share of the tile's dW rows
+        for (int t = threadIdx.x; t < W4; t += blockDim.x) {
+            const int px = t / (L / 4), a4 = t - px * (L / 4);
+            float4 s4 = *reinterpret_cast<const float4*>(part + px * PROW + 4 * a4);
+            for (int w = 1; w < nwaves; ++w) {
+                const float4 v = *reinterpret_cast<const float4*>(part + w * (32 * PROW) + px * PROW + 4 * a4);
+                s4.x += v.x;
+                s4.y += v.y;
+                s4.z += v.z;
+                s4.w += v.w;
+            }
+            const long long p = p0 + px;
+            if (p < a.m) *reinterpret_cast<float4*>(a.d_coef + p * L + 4 * a4) = s4;
+        }
+        lds_barrier();
+    }
+    float* out = a.ws + (size_t)blockIdx.x * L * D;
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * tl + 8 * (r >> 2) + 4 * half + (r & 3);
+                out[(size_t)row * D + f_wave + 32 * mt + col] = accd[tl][mt][r];
+            }
+}
+
 static int decode_bw_plan(long long m, int L, int D, DecodeBwArgs& a) {
     a.m = m;
     a.L = L;
@@ -255,6 +405,13 @@ static int td_for(int L, int D) {
     return 2;
 }
 
+static bool fused_bw_ok(int L, int D) { return (L == 32 || L == 64) && D % 64 == 0 && D <= 512; }
+
+static size_t fused_bw_lds(int L, int D) {
+    const int nw = D / 64;
+    return ((size_t)nw * 32 * kFusedRow + (size_t)nw * 32 * (L + 4) + (size_t)32 * (L + 4)) * sizeof(float);
+}
+
 template <int L>
 static int launch_decode_bw(DecodeBwArgs a, hipStream_t stream) {
     constexpr int MT = L <= 64 ? 2 : 1;
@@ -265,6 +422,42 @@ static int launch_decode_bw(DecodeBwArgs a, hipStream_t stream) {
             hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
             n = 256;
         num_cus = n;
+    }
+    if constexpr (L <= 64) {
+        if (a.d_coef && a.d_dict && fused_bw_ok(L, a.D)) {
+            const size_t lds = fused_bw_lds(L, a.D);
+            const int threads = (a.D / 64) * 64;
+            const int wpt_need = (32 * L / 4 + threads - 1) / threads;
+            const void* kern = wpt_need <= 1   ? (const void*)k_decode_bw_fused<L, 1>
+                               : wpt_need <= 2 ? (const void*)k_decode_bw_fused<L, 2>
+                                               : (const void*)k_decode_bw_fused<L, 4>;
+            static bool attr[3] = {false, false, false};
+            const int ai = wpt_need <= 1 ? 0 : (wpt_need <= 2 ? 1 : 2);
+            if (!attr[ai]) {
+                if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(160 * 1024)) !=
+                    hipSuccess)
+                    return LS2_ERR_DEVICE;
+                attr[ai] = true;
+            }
+            // one workgroup per CU (the partial products fill the LDS), at most
+            // one dS partial per workspace slot
+            const long long nblk = (a.m + 31) / 32;
+            long long grid = num_cus;
+            if (grid > a.nparts) grid = a.nparts;
+            if (grid > nblk) grid = nblk;
+            if (ai == 0)
+                hipLaunchKernelGGL((k_decode_bw_fused<L, 1>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+            else if (ai == 1)
+                hipLaunchKernelGGL((k_decode_bw_fused<L, 2>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+            else
+                hipLaunchKernelGGL((k_decode_bw_fused<L, 4>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+            LS2_LAUNCH_CHECK();
+            const int LD = L * a.D;
+            hipLaunchKernelGGL(k_ddict_reduce, dim3((LD + 63) / 64), dim3(1024), 0, stream, a.ws, (int)grid, LD,
+                               a.d_dict);
+            LS2_LAUNCH_CHECK();
+            return LS2_OK;
+        }
     }
     if (a.d_coef) {
         const size_t lds = (size_t)L * (a.DC + 4) * sizeof(float);
@@ -331,6 +524,7 @@ extern "C" int ls2_dict_decode_backward(int64_t m, int32_t L, int32_t D, const f
     if (!d_coef && !d_dict) return LS2_ERR_ARG;
     if (d_dict && m > 0 && !coef) return LS2_ERR_ARG;
     if (!decode_bw_supported(L, D) || compute != LS2_F32) return LS2_ERR_UNSUPPORTED;
+    if (!aligned16(coef) || !aligned16(dict) || !aligned16(d_feat) || !aligned16(d_coef)) return LS2_ERR_ARG;
     if (m == 0) {  // dS of an empty product: zeros (a fill kernel, no memset node)
         if (d_dict) {
             hipLaunchKernelGGL(k_ddict_reduce, dim3((L * D + 63) / 64), dim3(1024), 0, stream, (const float*)nullptr,

@@ -100,6 +100,10 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
+// Host-side check of the 16-byte alignment that float4 accesses need (a null
+// pointer passes; null arguments are checked separately).
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 // The wave sum, broadcast to every lane (as a wave-uniform value).
 __device__ __forceinline__ float wave_allsum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(v)), 63));

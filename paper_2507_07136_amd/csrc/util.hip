@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_accumulate(long long n, const float* __
 
 extern "C" int ls2_accumulate(int64_t n, const float* src, float* dst, hipStream_t stream) {
     if (n < 0 || (n > 0 && (!src || !dst))) return LS2_ERR_ARG;
-    if (((uintptr_t)src & 15) != 0 || ((uintptr_t)dst & 15) != 0) return LS2_ERR_ARG;
+    if (!ls2::aligned16(src) || !ls2::aligned16(dst)) return LS2_ERR_ARG;
     if (n == 0) return LS2_OK;
     long long blocks = (n / 4 + 255) / 256;
     if (blocks < 1) blocks = 1;

@@ -55,3 +55,19 @@ def small_scene(seed, n, w, h, L=64, K=4, levels=1, D=512):
     scene = gen.make_scene(seed, n, L=L, K=K, D=D, levels=levels)
     cam = gen.make_camera(w, h)
     return scene, cam
+
+
+def grad_close(got, ref, name, rtol=1e-3, floor=1e-3):
+    """Per tensor |got - ref|_2 <= rtol |ref|_2 and per element
+    |got - ref| <= rtol max(|ref|, floor max|ref|)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert got.shape == ref.shape, (name, got.shape, ref.shape)
+    nref = np.linalg.norm(ref)
+    err = np.linalg.norm(got - ref)
+    assert err <= rtol * max(nref, 1e-30), "%s: |d|/|g| = %.3e" % (name, err / max(nref, 1e-30))
+    gmax = np.abs(ref).max() if ref.size else 0.0
+    bound = rtol * np.maximum(np.abs(ref), floor * gmax)
+    bad = np.abs(got - ref) > bound + 1e-30
+    assert not bad.any(), "%s: %d elements out of bound, worst %.3e vs %.3e" % (
+        name, int(bad.sum()), float(np.abs(got - ref)[bad].max()), float(bound[bad].max()))

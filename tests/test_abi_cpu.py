@@ -141,3 +141,22 @@ def test_backward_argument_validation_without_device(L):
     assert L.ls2_feature_loss(0, 512, V(16), V(16), V(16), None, V(16), 1 << 20, None) == -1
     assert L.ls2_feature_loss(10, 500, V(16), V(16), V(16), None, V(16), 1 << 20, None) == -3
     assert L.ls2_feature_loss(10, 512, V(16), V(16), V(16), None, V(16), 8, None) == -1
+
+
+def test_codes_and_accumulate_validation_without_device(L):
+    V = ctypes.c_void_p
+    # sparse codes: K > L, K = 0, null output, unsupported K / L, rows = 0 no-op
+    assert L.ls2_sparse_codes(10, 4, 8, V(16), V(16), V(16), None) == -1
+    assert L.ls2_sparse_codes(10, 64, 0, V(16), V(16), V(16), None) == -1
+    assert L.ls2_sparse_codes(10, 64, 4, V(16), None, V(16), None) == -1
+    assert L.ls2_sparse_codes(10, 64, 9, V(16), V(16), V(16), None) == -3
+    assert L.ls2_sparse_codes(10, 30, 4, V(16), V(16), V(16), None) == -3
+    assert L.ls2_sparse_codes(0, 64, 4, None, None, None, None) == 0
+    assert L.ls2_sparse_codes_backward(10, 64, 4, V(16), V(16), V(16), None, None) == -1
+    assert L.ls2_sparse_codes_backward(-1, 64, 4, V(16), V(16), V(16), V(16), None) == -1
+    assert L.ls2_sparse_codes_backward(0, 64, 4, None, None, None, None, None) == 0
+    # accumulate: negative n, null or misaligned pointers, n = 0 no-op
+    assert L.ls2_accumulate(-1, V(16), V(16), None) == -1
+    assert L.ls2_accumulate(8, None, V(16), None) == -1
+    assert L.ls2_accumulate(8, V(16), V(20), None) == -1
+    assert L.ls2_accumulate(0, None, None, None) == 0

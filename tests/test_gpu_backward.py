@@ -24,6 +24,7 @@ import pytest
 import torch
 
 import gen
+from gpu_common import grad_close as _grad_close
 from gpu_common import gpu_available, oracle_composite_from_gpu, run_forward, small_scene
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -34,20 +35,6 @@ MARGIN = 1e-5
 # elements are sums of many terms of either sign and carry the chain's
 # absolute rounding; each stage on its own meets the 1e-3 floor
 CHAIN_FLOOR = 1e-2
-
-
-def _grad_close(got, ref, name, rtol=1e-3, floor=1e-3):
-    got = np.asarray(got, np.float64)
-    ref = np.asarray(ref, np.float64)
-    assert got.shape == ref.shape, (name, got.shape, ref.shape)
-    nref = np.linalg.norm(ref)
-    err = np.linalg.norm(got - ref)
-    assert err <= rtol * max(nref, 1e-30), "%s: |d|/|g| = %.3e" % (name, err / max(nref, 1e-30))
-    gmax = np.abs(ref).max() if ref.size else 0.0
-    bound = rtol * np.maximum(np.abs(ref), floor * gmax)
-    bad = np.abs(got - ref) > bound + 1e-30
-    assert not bad.any(), "%s: %d elements out of bound, worst %.3e vs %.3e" % (
-        name, int(bad.sum()), float(np.abs(got - ref)[bad].max()), float(bound[bad].max()))
 
 
 def _risky_pixels(margin, margin_T):
@@ -137,7 +124,9 @@ def _abs_bound(a, b):
 
 
 @pytest.mark.parametrize("m,L,D", [(4096, 64, 512), (1000, 64, 512), (777, 32, 256), (513, 128, 384),
-                                   (300, 32, 1024), (64, 128, 128), (1, 64, 512), (33, 64, 1024)])
+                                   (300, 32, 1024), (64, 128, 128), (1, 64, 512), (33, 64, 1024),
+                                   # many 32-pixel tiles per workgroup, ragged tails, 6 and 2 waves
+                                   (100003, 64, 512), (40009, 64, 384), (9001, 32, 128)])
 def test_decode_backward_parity(orc, m, L, D):
     import paper_2507_07136_amd as ls2
     rng = np.random.default_rng(m * 7 + L + D)
@@ -372,3 +361,19 @@ def test_sparse_codes_parity(orc, rows, L, K):
     assert np.abs(w.cpu().numpy() - rw).max() <= 1e-6
     rdz = orc.sparse_codes_backward(z, K, dw)
     assert np.abs(dz.cpu().numpy() - rdz).max() <= 1e-5 * max(1.0, np.abs(rdz).max())
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 4099, 1 << 22])
+def test_accumulate_exact(n):
+    """dst += src equals the float32 sum elementwise, bit for bit (one
+    rounding per element), ragged tails included; two calls in a row."""
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal(n).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    c = rng.standard_normal(n).astype(np.float32)
+    dst = torch.from_numpy(a).cuda()
+    ls2.ls2_accumulate(torch.from_numpy(b).cuda(), dst)
+    ls2.ls2_accumulate(torch.from_numpy(c).cuda(), dst)
+    torch.cuda.synchronize()
+    assert np.array_equal(dst.cpu().numpy(), (a + b) + c)

@@ -114,6 +114,34 @@ def test_composite_grad(orc):
     assert checked >= 140 and skipped <= 10
 
 
+def test_composite_backward_pixels_matches_masked(orc):
+    """The pixel-list backward equals the full backward with dL/dcoef zeroed
+    outside the listed pixels (an upstream-zero pixel adds nothing), in any
+    list order (only the summation order differs)."""
+    scene, cam = _small_splat_scene()
+    pr = orc.project(cam, scene.means, scene.scales, scene.quats)
+    keys, ids, ranges = orc.tile_lists(cam, pr["mean2d"].astype(np.float32), pr["radius"],
+                                       pr["depth"].astype(np.float32))
+    rng = np.random.default_rng(8)
+    npx = cam.width * cam.height
+    pix = rng.choice(npx, 300, replace=False)
+    G = np.zeros((scene.levels, npx, scene.L))
+    G[:, pix] = rng.normal(size=(scene.levels, len(pix), scene.L))
+    args = (cam, ranges, ids, pr["mean2d"], pr["conic"], scene.opacity, scene.topk_idx, scene.topk_w)
+    full = orc.composite_backward(*args, G.reshape(scene.levels, cam.height, cam.width, scene.L))
+    part = orc.composite_backward_pixels(*args, pix, G[:, pix].transpose(1, 0, 2))
+    for a, b in zip(full, part):
+        assert np.abs(a).max() > 0
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-15 * np.abs(a).max())
+    # every pixel listed: the full backward
+    allpix = rng.permutation(npx)
+    Gf = rng.normal(size=(scene.levels, npx, scene.L))
+    full = orc.composite_backward(*args, Gf.reshape(scene.levels, cam.height, cam.width, scene.L))
+    part = orc.composite_backward_pixels(*args, allpix, Gf[:, allpix].transpose(1, 0, 2))
+    for a, b in zip(full, part):
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-14 * np.abs(a).max())
+
+
 def test_composite_grad_weights_exact(orc):
     """For one Gaussian, dW/dw_k = alpha e_idx exactly (linear in w)."""
     scene, cam = _small_splat_scene(n=1, levels=1, K=4, L=16)
