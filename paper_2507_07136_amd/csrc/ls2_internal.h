@@ -104,6 +104,78 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // pointer passes; null arguments are checked separately).
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+// Reduce-scatter of V per-lane values over the 64 lanes of a wave.  Each step
+// pairs lane l with the lane that differs in one bit: lanes with the bit
+// clear keep the first ceil(n/2) of their n values, lanes with it set the
+// rest, each adding its partner's copy.  Bits 5 and 4 use v_permlane32_swap /
+// v_permlane16_swap (one swap exchanges a whole pair), bits 3..0 DPP moves
+// (row_ror 8, row_half_mirror, quad_perm xor 2, xor 1).  Once one value is
+// left the remaining bits are summed as a butterfly.  On return lane l holds
+// the wave total of value tr_slot(V, l).index (see below); every lane must be
+// active.
+template <int BIT>
+__device__ __forceinline__ float tr_exchange(float x, float y, int lane) {
+    if constexpr (BIT == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else if constexpr (BIT == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        constexpr int CTRL = BIT == 3 ? 0x128 : BIT == 2 ? 0x141 : BIT == 1 ? 0x4e : 0xb1;
+        const bool hi = (lane >> BIT) & 1;
+        const float send = hi ? x : y;
+        const float recv = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(send), CTRL, 0xf, 0xf, false));
+        return (hi ? y : x) + recv;
+    }
+}
+
+template <int BIT, int V>
+__device__ __forceinline__ float tr_reduce(const float (&v)[V], int lane) {
+    static_assert(V >= 1 && V <= 64, "tr_reduce: 1..64 values");
+    if constexpr (V == 1) {
+        if constexpr (BIT >= 0) {
+            const float nv[1] = {tr_exchange<BIT>(v[0], v[0], lane)};
+            return tr_reduce<BIT - 1, 1>(nv, lane);
+        } else {
+            return v[0];
+        }
+    } else {
+        static_assert(BIT >= 0, "tr_reduce: more values than lanes");
+        constexpr int H = (V + 1) / 2;
+        float nv[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) nv[i] = tr_exchange<BIT>(v[i], i + H < V ? v[i + H] : 0.0f, lane);
+        return tr_reduce<BIT - 1, H>(nv, lane);
+    }
+}
+
+// Which value lane l ends with after tr_reduce<5, V>: index, whether that
+// slot holds a value (not padding), and whether l is the one lane (lowest
+// of the butterfly group) that should use it.
+struct TrSlot {
+    int index;
+    bool valid;
+    bool leader;
+};
+__device__ __forceinline__ TrSlot tr_slot(int V, int lane) {
+    int base = 0, cnt = V, size = V, bit = 5;
+    for (; bit >= 0 && size > 1; --bit) {
+        const int h = (size + 1) / 2;
+        if ((lane >> bit) & 1) {
+            base += h;
+            cnt = cnt - h > 0 ? cnt - h : 0;
+        } else {
+            cnt = cnt < h ? cnt : h;
+        }
+        size = h;
+    }
+    // bits bit..0 were summed as a butterfly: every lane of the group holds
+    // the total; the group's lowest lane is the leader
+    const int rest = bit >= 0 ? ((1 << (bit + 1)) - 1) : 0;
+    return TrSlot{base, cnt > 0, (lane & rest) == 0};
+}
+
 // The wave sum, broadcast to every lane (as a wave-uniform value).
 __device__ __forceinline__ float wave_allsum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_lane63(v)), 63));

@@ -10,14 +10,18 @@
 // and through alpha = o exp(power) (no gradient where clamped at 0.99) to o,
 // the 2D mean and the conic.
 //
-// Mapping: the forward's one wave per 8x8 quadrant.  The wave walks its tile
-// list backwards from the largest `last` of its pixels, recovering each
-// pixel's transmittance as T_i = T_{i+1} / (1 - alpha_i) from the stored final
+// Mapping: one wave per (8x8 quadrant, level).  The wave walks its tile list
+// backwards from the largest `last` of its pixels, recovering each pixel's
+// transmittance as T_i = T_{i+1} / (1 - alpha_i) from the stored final
 // transmittance (no per-pixel lists are stored), with alpha recomputed by the
-// same instructions as the forward.  Each pixel's dL/dW vector sits in LDS
-// columns so the K wave-uniform indices read it directly.  Per-Gaussian
-// gradients are summed over the wave's 64 pixels and added with one atomic
-// per value.
+// same instructions as the forward.  Its level's dL/dW vectors sit in LDS
+// columns so the K wave-uniform indices read them directly.  dL/dalpha is a
+// sum over levels of T_i c_il - S_il / (1 - alpha_i) (S_il: the level's share
+// of S_i), so each level wave adds its own share of the mean / conic /
+// opacity gradients; with one level per wave the LDS footprint stays small
+// enough for several waves per SIMD.  Per Gaussian the wave's 6 + K values are
+// summed over its 64 pixels in one reduce-scatter and added with one atomic
+// instruction (one lane per value).
 #include "splat_common.h"
 
 namespace ls2 {
@@ -42,32 +46,33 @@ struct SplatBwArgs {
 };
 
 // staged record (dwords): u, v, A2, B2, C2, o, position, id, A, B, C, idx words, weights
-template <int KMAX, int LVMAX>
+template <int KMAX>
 struct BwRec {
     static constexpr int KW = (KMAX + 3) / 4;
     static constexpr int POS = 6, ID = 7, CA = 8;
     static constexpr int IDX = 11;
-    static constexpr int W = IDX + LVMAX * KW;
-    static constexpr int RAW = W + LVMAX * KMAX;
+    static constexpr int W = IDX + KW;
+    static constexpr int RAW = W + KMAX;
     static constexpr int STRIDE = (RAW + 3) & ~3;
 };
 
-
-template <int NV, int KMAX, int LVMAX, bool EXACT>
+template <int NV, int KMAX, bool EXACT>
 __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
-    using R = BwRec<KMAX, LVMAX>;
+    using R = BwRec<KMAX>;
     constexpr int kStride = 65;
-    constexpr int kRows = LVMAX * NV * 32;
-    constexpr int NG = 6 + LVMAX * KMAX;  // gradient values per Gaussian
+    constexpr int kRows = NV * 32;  // L
+    constexpr int NG = 6 + KMAX;    // gradient values per Gaussian
     __shared__ float4 stage4[64 * R::STRIDE / 4];
     __shared__ float gcol[(kRows + 1) * kStride];
     float* stage = reinterpret_cast<float*>(stage4);
 
     const CamK& cam = a.cam;
     const int ntiles = cam.tx * cam.ty;
-    int tile, quad;
-    xcd_remap(blockIdx.x, gridDim.x, 4, tile, quad);
+    const int levels = a.levels;
+    int tile, slot;
+    xcd_remap(blockIdx.x, gridDim.x, 4 * levels, tile, slot);
     if (tile >= ntiles) return;
+    const int lv = slot >> 2, quad = slot & 3;
     const int lane = threadIdx.x;
     const int tx = tile % cam.tx, ty = tile / cam.tx;
     const int qx0 = tx * kTile + (quad & 1) * 8, qy0 = ty * kTile + (quad >> 1) * 8;
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
 
     const unsigned start = a.ranges[2 * tile];
     const int list_len = (int)(a.ranges[2 * tile + 1] - start);
-    const int levels = EXACT ? LVMAX : a.levels, K = EXACT ? KMAX : a.K, L = a.L;
+    const int K = EXACT ? KMAX : a.K, L = a.L;
     const int lmask = L - 1;
     const unsigned long long lt = (1ull << lane) - 1ull;
 
@@ -94,31 +99,52 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
     maxlast = min(maxlast, list_len);  // a forward state from another list cannot read past this one
     if (maxlast <= 0) return;  // no pixel of the quadrant blended anything
 
-    // dL/dW of the quadrant's pixels into LDS columns (coalesced row reads)
+    // this lane's output after the reduce-scatter: value q of each Gaussian
+    // goes to base[q] + stride[q] * id
+    const TrSlot ts = tr_slot(NG, lane);
+    float* out_base = nullptr;
+    int out_stride = 0;
+    bool out_on = ts.valid && ts.leader;
+    if (ts.index < 2) {
+        out_base = a.d_mean2d + ts.index;
+        out_stride = 2;
+    } else if (ts.index < 5) {
+        out_base = a.d_conic + (ts.index - 2);
+        out_stride = 3;
+    } else if (ts.index == 5) {
+        out_base = a.d_opacity;
+        out_stride = 1;
+    } else {
+        const int k = ts.index - 6;
+        out_on = out_on && k < K;
+        out_base = a.d_topk_w + (size_t)lv * K + k;
+        out_stride = levels * K;
+    }
+
+    // dL/dW of the quadrant's pixels at this level into LDS columns
     for (int i = lane; i < (kRows + 1) * kStride; i += 64) gcol[i] = 0.0f;
     __syncthreads();
     {
         const int f4_per_px = L / 4, f4_per_row = 8 * f4_per_px;
-        for (int lv = 0; lv < levels; ++lv)
-            for (int ry = 0; ry < 8; ++ry) {
-                const int gy = qy0 + ry;
-                if (gy >= cam.H) break;
-                const float4* rowbase =
-                    reinterpret_cast<const float4*>(a.d_coef + ((size_t)lv * HW + (size_t)gy * cam.W + qx0) * L);
-                for (int f = lane; f < f4_per_row; f += 64) {
-                    const int pxl = f / f4_per_px, c4 = f - pxl * f4_per_px;
-                    if (qx0 + pxl >= cam.W) continue;
-                    const float4 v = rowbase[f];
-                    float* dst = gcol + (lv * L + 4 * c4) * kStride + ry * 8 + pxl;
-                    dst[0] = v.x;
-                    dst[kStride] = v.y;
-                    dst[2 * kStride] = v.z;
-                    dst[3 * kStride] = v.w;
-                }
+        for (int ry = 0; ry < 8; ++ry) {
+            const int gy = qy0 + ry;
+            if (gy >= cam.H) break;
+            const float4* rowbase =
+                reinterpret_cast<const float4*>(a.d_coef + ((size_t)lv * HW + (size_t)gy * cam.W + qx0) * L);
+            for (int f = lane; f < f4_per_row; f += 64) {
+                const int pxl = f / f4_per_px, c4 = f - pxl * f4_per_px;
+                if (qx0 + pxl >= cam.W) continue;
+                const float4 v = rowbase[f];
+                float* dst = gcol + (4 * c4) * kStride + ry * 8 + pxl;
+                dst[0] = v.x;
+                dst[kStride] = v.y;
+                dst[2 * kStride] = v.z;
+                dst[3 * kStride] = v.w;
             }
+        }
     }
 
-    float S = 0.0f;  // sum over later contributors of c_m e_m
+    float S = 0.0f;  // this level's sum over later contributors of c_m e_m
     for (int bend = maxlast; bend > 0; bend -= 64) {
         const int b0 = max(0, bend - 64), nb = bend - b0;
         bool keep = false;
@@ -153,23 +179,18 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
             r[R::CA] = cA;
             r[R::CA + 1] = cB;
             r[R::CA + 2] = cC;
+            const size_t base = ((size_t)id * levels + lv) * K;
+            unsigned wd[R::KW];
 #pragma unroll
-            for (int lv = 0; lv < LVMAX; ++lv) {
-                if (lv < levels) {
-                    const size_t base = ((size_t)id * levels + lv) * K;
-                    unsigned wd[R::KW];
+            for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
 #pragma unroll
-                    for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
-#pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        const unsigned ix = k < K ? (unsigned)(a.topk_idx[base + k] & lmask) : 0u;
-                        wd[k >> 2] |= ix << (8 * (k & 3));
-                        r[R::W + lv * KMAX + k] = k < K ? a.topk_w[base + k] : 0.0f;
-                    }
-#pragma unroll
-                    for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + lv * R::KW + q] = wd[q];
-                }
+            for (int k = 0; k < KMAX; ++k) {
+                const unsigned ix = k < K ? (unsigned)(a.topk_idx[base + k] & lmask) : 0u;
+                wd[k >> 2] |= ix << (8 * (k & 3));
+                r[R::W + k] = k < K ? a.topk_w[base + k] : 0.0f;
             }
+#pragma unroll
+            for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + q] = wd[q];
         }
         wave_lds_order();
 
@@ -188,13 +209,10 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
             float vals[NG];
 #pragma unroll
             for (int q = 0; q < NG; ++q) vals[q] = 0.0f;
-            unsigned words[LVMAX][R::KW];
+            unsigned words[R::KW];
 #pragma unroll
-            for (int lv = 0; lv < LVMAX; ++lv)
-#pragma unroll
-                for (int q = 0; q < R::KW; ++q)
-                    words[lv][q] = __builtin_amdgcn_readfirstlane(
-                        reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
+            for (int q = 0; q < R::KW; ++q)
+                words[q] = __builtin_amdgcn_readfirstlane(reinterpret_cast<const unsigned*>(r)[R::IDX + q]);
             if (hit) {
                 const float inv_one_m = __builtin_amdgcn_rcpf(1.0f - alpha);  // 1 ulp; 1 - alpha >= 0.01
                 T = T * inv_one_m;  // transmittance in front of this Gaussian
@@ -202,17 +220,12 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                 float c = 0.0f;
                 const float* col = gcol + lane;
 #pragma unroll
-                for (int lv = 0; lv < LVMAX; ++lv) {
-                    if (lv < levels) {
-#pragma unroll
-                        for (int k = 0; k < KMAX; ++k) {
-                            if (k < K) {
-                                const unsigned ix = (words[lv][k >> 2] >> (8 * (k & 3))) & 0xffu;
-                                const float gv = col[(lv * L + (int)ix) * kStride];
-                                c = fmaf(gv, r[R::W + lv * KMAX + k], c);
-                                vals[6 + lv * KMAX + k] = gv * e;
-                            }
-                        }
+                for (int k = 0; k < KMAX; ++k) {
+                    if (k < K) {
+                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                        const float gv = col[(int)ix * kStride];
+                        c = fmaf(gv, r[R::W + k], c);
+                        vals[6 + k] = gv * e;
                     }
                 }
                 const float dalpha = T * c - S * inv_one_m;
@@ -228,25 +241,10 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                     vals[5] = dalpha * G;                 // d opacity
                 }
             }
-            // sum over the wave's pixels, one atomic per value
+            // sums over the wave's pixels, one value per lane, one atomic instruction
+            const float tot = tr_reduce<5, NG>(vals, lane);
             const unsigned gid = reinterpret_cast<const unsigned*>(r)[R::ID];
-#pragma unroll
-            for (int q = 0; q < NG; ++q) {
-                if (q >= 6) {
-                    const int lv = (q - 6) / KMAX, k = (q - 6) % KMAX;
-                    if (lv >= levels || k >= K) continue;
-                }
-                const float tot = wave_sum_lane63(vals[q]);
-                if (lane == 63 && tot != 0.0f) {
-                    if (q < 2) atomicAdd(&a.d_mean2d[2 * gid + q], tot);
-                    else if (q < 5) atomicAdd(&a.d_conic[3 * gid + (q - 2)], tot);
-                    else if (q == 5) atomicAdd(&a.d_opacity[gid], tot);
-                    else {
-                        const int lv = (q - 6) / KMAX, k = (q - 6) % KMAX;
-                        atomicAdd(&a.d_topk_w[((size_t)gid * levels + lv) * K + k], tot);
-                    }
-                }
-            }
+            if (out_on && tot != 0.0f) atomicAdd(out_base + (size_t)out_stride * gid, tot);
         }
     }
 }
@@ -264,14 +262,14 @@ static int zero_f32(float* p, long long n, hipStream_t stream) {
     return LS2_OK;
 }
 
-template <int NV, int KMAX, int LVMAX>
+template <int NV, int KMAX>
 static int launch_splat_bw(const SplatBwArgs& a, hipStream_t stream) {
     const int ntiles = a.cam.tx * a.cam.ty;
-    const int grid = round_up8(ntiles * 4);
-    if (a.K == KMAX && a.levels == LVMAX)
-        hipLaunchKernelGGL((k_splat_backward<NV, KMAX, LVMAX, true>), dim3(grid), dim3(64), 0, stream, a);
+    const int grid = round_up8(ntiles * 4 * a.levels);
+    if (a.K == KMAX)
+        hipLaunchKernelGGL((k_splat_backward<NV, KMAX, true>), dim3(grid), dim3(64), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_splat_backward<NV, KMAX, LVMAX, false>), dim3(grid), dim3(64), 0, stream, a);
+        hipLaunchKernelGGL((k_splat_backward<NV, KMAX, false>), dim3(grid), dim3(64), 0, stream, a);
     LS2_LAUNCH_CHECK();
     return LS2_OK;
 }
@@ -319,15 +317,7 @@ extern "C" int ls2_splat_sparse_backward(const ls2_camera* cam, int32_t n, int32
     a.d_opacity = d_opacity;
     a.d_topk_w = d_topk_w;
     const bool k8 = K > 4;
-    if (levels == 1) {
-        if (L == 32) return k8 ? launch_splat_bw<1, 8, 1>(a, stream) : launch_splat_bw<1, 4, 1>(a, stream);
-        if (L == 64) return k8 ? launch_splat_bw<2, 8, 1>(a, stream) : launch_splat_bw<2, 4, 1>(a, stream);
-        return k8 ? launch_splat_bw<4, 8, 1>(a, stream) : launch_splat_bw<4, 4, 1>(a, stream);
-    }
-    if (levels == 2) {
-        if (L == 32) return k8 ? launch_splat_bw<1, 8, 2>(a, stream) : launch_splat_bw<1, 4, 2>(a, stream);
-        return k8 ? launch_splat_bw<2, 8, 2>(a, stream) : launch_splat_bw<2, 4, 2>(a, stream);
-    }
-    if (L == 32) return k8 ? launch_splat_bw<1, 8, 3>(a, stream) : launch_splat_bw<1, 4, 3>(a, stream);
-    return k8 ? launch_splat_bw<2, 8, 3>(a, stream) : launch_splat_bw<2, 4, 3>(a, stream);
+    if (L == 32) return k8 ? launch_splat_bw<1, 8>(a, stream) : launch_splat_bw<1, 4>(a, stream);
+    if (L == 64) return k8 ? launch_splat_bw<2, 8>(a, stream) : launch_splat_bw<2, 4>(a, stream);
+    return k8 ? launch_splat_bw<4, 8>(a, stream) : launch_splat_bw<4, 4>(a, stream);
 }
