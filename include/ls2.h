@@ -120,7 +120,8 @@ int ls2_bin_sort_count(const void* workspace, int64_t* num_pairs, hipStream_t st
  * otherwise for every level l and each of the K stored pairs (j, w_ilj):
  *     coef_l(v)[j] += w_ilj * alpha_i * T,   then T *= 1 - alpha_i.
  * Only the K non-zero coefficients are touched (O(K) per Gaussian, not O(L)).
- * Levels share alpha and T (one traversal renders every level).
+ * Levels share alpha and T (each level's pass takes the same decisions).
+ * Repeated indices within one Gaussian's K pairs add their weights.
  *
  * In:  tile_ranges, ids from ls2_bin_sort; mean2d [n,2], conic [n,3] from
  *      ls2_project; opacity [n] in (0,1); topk_idx [n,levels,K] int32 in
@@ -143,9 +144,10 @@ int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K
  * Gaussian blends all L coefficients of each level (the rendering that
  * Section 3.4 avoids by blending only the K non-zero ones; Table 9 times both).
  * Same lists, alpha rule, culling and outputs as ls2_splat_sparse; weights are
- * dense [n,levels,L].  With weights that are zero outside the stored indices
- * the result equals ls2_splat_sparse (LDS-accumulator forms, levels * L <= 128)
- * bit for bit.  Kept as the ablation baseline and as a cross-check.
+ * dense [n,levels,L].  With the stored pairs scattered into dense weights
+ * (repeated indices summed in slot order) the result equals ls2_splat_sparse
+ * bit for bit: both blend with one fused multiply-add per coefficient in list
+ * order.  Kept as the ablation baseline and as a cross-check.
  * Supported: L in {32, 64}, levels in {1, 2, 3}, levels * L <= 192.
  */
 int ls2_splat_dense(const ls2_camera* cam, int32_t n, int32_t levels, int32_t L, const uint32_t* tile_ranges,

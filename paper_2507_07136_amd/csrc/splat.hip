@@ -2,23 +2,25 @@
 // Appendix A Algorithm 1) with the front-to-back rule of Eq. 3.
 //
 // Mapping on CDNA4:
-//   - one wavefront (64 lanes) per 8x8 pixel quadrant of a 16x16 tile, one
-//     pixel per lane; the four quadrant waves of a tile walk the same list
+//   - one wavefront (64 lanes) per (8x8 pixel quadrant of a 16x16 tile,
+//     level), one pixel per lane; the waves of a tile walk the same list
 //     independently (no workgroup barriers), so each stops as soon as all of
-//     its own pixels are saturated (ballot over the lanes);
+//     its own pixels are saturated (ballot over the lanes).  The level waves
+//     of a quadrant recompute the same alphas and transmittance (identical
+//     instructions); only level 0's wave writes final_T and last;
 //   - the wave stages 64 list entries at a time (one per lane: a gather of
-//     the Gaussian's 2D mean, conic, opacity and K (index, weight) pairs per
-//     level).  The staging lane also tests whether the Gaussian's
-//     alpha >= 1/255 ellipse (inflated for rounding) reaches any pixel centre
-//     of the quadrant; entries that cannot are dropped by an order-preserving
-//     ballot compaction, since every lane would skip them anyway;
+//     the Gaussian's 2D mean, conic, opacity and its K (index, weight) pairs
+//     at the wave's level).  The staging lane also tests whether the
+//     Gaussian's alpha >= 1/255 ellipse (inflated for rounding) reaches any
+//     pixel centre of the quadrant; entries that cannot are dropped by an
+//     order-preserving ballot compaction, since every lane would skip them;
 //   - every lane then reads each surviving entry back as an LDS broadcast;
-//   - only the K stored coefficients are blended.  For levels*L <= 128 the
-//     per-pixel L-vectors live in LDS as columns acc[c * 65 + lane] (a blend
-//     is one address add, a read, an FMA and a write; the padded stride keeps
-//     both this access and the coalesced write-out free of bank conflicts).
-//     For larger levels*L they live in VGPRs (32-float vectors selected with
-//     the wave-uniform index through the VGPR index mode).
+//   - only the K stored coefficients are blended, into the pixel's L
+//     accumulators held in VGPRs as 32-float vectors addressed with the
+//     wave-uniform index through the VGPR index mode (one fused multiply-add
+//     per coefficient and vector; repeated indices of a Gaussian are merged
+//     at staging).  With one level per wave the L accumulators fit in
+//     registers at 4 waves per SIMD.
 #include "splat_common.h"
 
 namespace ls2 {
@@ -43,34 +45,29 @@ struct SplatArgs {
 // Staged record (dwords): u, v, A2, B2, C2, o, list position, idx words,
 // weights.  A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e): the
 // Gaussian's exponent in base 2 is A2 dx^2 + B2 dx dy + C2 dy^2.
-template <int KMAX, int LVMAX>
+template <int KMAX>
 struct Rec {
-    static constexpr int KW = (KMAX + 3) / 4;  // packed u8 index words per level
+    static constexpr int KW = (KMAX + 3) / 4;  // packed u8 index words
     static constexpr int POS = 6;
     static constexpr int IDX = 7;
-    static constexpr int W = IDX + LVMAX * KW;
-    static constexpr int RAW = W + LVMAX * KMAX;
+    static constexpr int W = IDX + KW;
+    static constexpr int RAW = W + KMAX;
     static constexpr int STRIDE = (RAW + 3) & ~3;  // 16-byte aligned records
 };
 
-// EXACT: K == KMAX and levels == LVMAX are known at compile time.
-template <int NV, int KMAX, int LVMAX, bool LDS_ACC, bool EXACT>
+// EXACT: K == KMAX is known at compile time.  NV = L / 32 accumulator vectors.
+template <int NV, int KMAX, bool EXACT>
 __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
-    using R = Rec<KMAX, LVMAX>;
-    constexpr int kStride = 65;  // LDS accumulator column stride
-    constexpr int kRows = LVMAX * NV * 32;
-    constexpr int kAccFloats = LDS_ACC ? (kRows + 1) * kStride : 1;  // + dump row for merged duplicates
-    constexpr int RV = LDS_ACC ? 1 : LVMAX;                          // register accumulators
-    constexpr int RN = LDS_ACC ? 1 : NV;
+    using R = Rec<KMAX>;
     __shared__ float4 stage4[64 * R::STRIDE / 4];
-    __shared__ float accs[kAccFloats];
     float* stage = reinterpret_cast<float*>(stage4);
 
     const CamK& cam = a.cam;
     const int ntiles = cam.tx * cam.ty;
-    int tile, quad;
-    xcd_remap(blockIdx.x, gridDim.x, 4, tile, quad);
+    int tile, slot;
+    xcd_remap(blockIdx.x, gridDim.x, 4 * a.levels, tile, slot);
     if (tile >= ntiles) return;
+    const int quad = slot & 3, lv0 = slot >> 2;
     const int lane = threadIdx.x;
     const int tx = tile % cam.tx, ty = tile / cam.tx;
     const int qx0 = tx * kTile + (quad & 1) * 8, qy0 = ty * kTile + (quad >> 1) * 8;
@@ -83,17 +80,14 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
     const float bx1 = (float)min(qx0 + 7, cam.W - 1) + 0.5f, by1 = (float)min(qy0 + 7, cam.H - 1) + 0.5f;
 
     const unsigned start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const int levels = EXACT ? LVMAX : a.levels, K = EXACT ? KMAX : a.K, L = a.L;
+    const int K = EXACT ? KMAX : a.K, L = a.L;
+    const int lstride = a.levels;  // levels per Gaussian in topk_idx / topk_w
     const int lmask = L - 1;
     const unsigned long long lt = (1ull << lane) - 1ull;
 
-    v32f acc[RV][RN];
+    v32f acc[NV];
 #pragma unroll
-    for (int lv = 0; lv < RV; ++lv)
-#pragma unroll
-        for (int h = 0; h < RN; ++h) acc[lv][h] = (v32f){};
-    if (LDS_ACC)
-        for (int i = lane; i < kAccFloats; i += 64) accs[i] = 0.0f;
+    for (int h = 0; h < NV; ++h) acc[h] = (v32f){};
 
     float T = 1.0f;
     int last = 0;
@@ -101,8 +95,7 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
 
     // Software pipeline over 64-entry batches: while batch b is processed,
     // the records of batch b + 64 and the ids of batch b + 128 are in flight.
-    constexpr bool PREFETCH_CODES = LVMAX * KMAX <= 8;  // also prefetch the (index, weight) pairs
-    constexpr int PK = PREFETCH_CODES ? LVMAX * KMAX : 1;
+    constexpr int PK = KMAX;  // the (index, weight) pairs are prefetched too
     const unsigned kBad = 0xffffffffu;
     auto fetch_id = [&](unsigned pos) -> unsigned { return pos < end ? a.ids[pos] : kBad; };
     unsigned nid = fetch_id(start + lane);           // ids of the batch staged next
@@ -119,15 +112,11 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
             n_cB = a.conic[3 * id + 1];
             n_cC = a.conic[3 * id + 2];
             n_op = a.opacity[id];
-            if (PREFETCH_CODES) {
 #pragma unroll
-                for (int q = 0; q < PK; ++q) {
-                    const int lv = q / KMAX, k = q % KMAX;
-                    const bool ok = lv < levels && k < K;
-                    const size_t o = ((size_t)id * levels + lv) * K + k;
-                    n_ix[q] = ok ? a.topk_idx[o] : 0;
-                    n_w[q] = ok ? a.topk_w[o] : 0.0f;
-                }
+            for (int k = 0; k < KMAX; ++k) {
+                const size_t o = ((size_t)id * lstride + lv0) * K + k;
+                n_ix[k] = k < K ? a.topk_idx[o] : 0;
+                n_w[k] = k < K ? a.topk_w[o] : 0.0f;
             }
         } else {
             n_op = 0.0f;
@@ -165,48 +154,35 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
             r[4] = -0.5f * kLog2e * cC;
             r[5] = op;
             reinterpret_cast<unsigned*>(r)[R::POS] = b - start + lane;
+            unsigned ix[KMAX];
+            float wv[KMAX];
 #pragma unroll
-            for (int lv = 0; lv < LVMAX; ++lv) {
-                if (lv < levels) {
-                    const size_t base = ((size_t)id * levels + lv) * K;
-                    unsigned ix[KMAX];
-                    float wv[KMAX];
-#pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        if (PREFETCH_CODES) {
-                            ix[k] = k < K ? (unsigned)(c_ix[lv * KMAX + k] & lmask) : 0u;
-                            wv[k] = k < K ? c_w[lv * KMAX + k] : 0.0f;
-                        } else {
-                            ix[k] = k < K ? (unsigned)(a.topk_idx[base + k] & lmask) : 0u;
-                            wv[k] = k < K ? a.topk_w[base + k] : 0.0f;
-                        }
-                    }
-                    if (LDS_ACC) {
-                        // merge repeated indices so the K read-modify-writes of one
-                        // Gaussian touch distinct accumulators (they are issued
-                        // together); freed slots point at the dump row (0xff)
-#pragma unroll
-                        for (int k = 1; k < KMAX; ++k)
-#pragma unroll
-                            for (int k2 = 0; k2 < k; ++k2)
-                                if (k < K && ix[k2] == ix[k] && ix[k] != 0xffu) {
-                                    wv[k2] += wv[k];
-                                    wv[k] = 0.0f;
-                                    ix[k] = 0xffu;
-                                }
-                    }
-                    unsigned wd[R::KW];
-#pragma unroll
-                    for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
-#pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        wd[k >> 2] |= ix[k] << (8 * (k & 3));
-                        r[R::W + lv * KMAX + k] = wv[k];
-                    }
-#pragma unroll
-                    for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + lv * R::KW + q] = wd[q];
-                }
+            for (int k = 0; k < KMAX; ++k) {
+                ix[k] = k < K ? (unsigned)(c_ix[k] & lmask) : 0xffu;
+                wv[k] = k < K ? c_w[k] : 0.0f;
             }
+            // merge repeated indices into their first slot (the sum of their
+            // weights, in slot order); freed slots get index 0xff, which no
+            // accumulator vector matches
+#pragma unroll
+            for (int k = 1; k < KMAX; ++k)
+#pragma unroll
+                for (int k2 = 0; k2 < k; ++k2)
+                    if (ix[k2] == ix[k] && ix[k] != 0xffu) {
+                        wv[k2] += wv[k];
+                        wv[k] = 0.0f;
+                        ix[k] = 0xffu;
+                    }
+            unsigned wd[R::KW];
+#pragma unroll
+            for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) {
+                wd[k >> 2] |= ix[k] << (8 * (k & 3));
+                r[R::W + k] = wv[k];
+            }
+#pragma unroll
+            for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + q] = wd[q];
         }
         wave_lds_order();  // single-wave workgroup: orders the LDS writes before the reads
 
@@ -241,45 +217,19 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
                 const bool contrib = hit && !stop;
                 active = active && !stop;
                 if (contrib) {  // divergent: only contributing lanes blend (exec mask)
+                    unsigned words[R::KW];
 #pragma unroll
-                    for (int lv = 0; lv < LVMAX; ++lv) {
-                        if (lv < levels) {
-                            unsigned words[R::KW];
+                    for (int q = 0; q < R::KW; ++q)
+                        words[q] = __builtin_amdgcn_readfirstlane(reinterpret_cast<const unsigned*>(r)[R::IDX + q]);
 #pragma unroll
-                            for (int q = 0; q < R::KW; ++q)
-                                words[q] = __builtin_amdgcn_readfirstlane(
-                                    reinterpret_cast<const unsigned*>(r)[R::IDX + lv * R::KW + q]);
-                            if (LDS_ACC) {
-                                // K reads, then K FMAs and writes (repeated indices were
-                                // merged at staging, so the K addresses are distinct)
-                                float* col = accs + lane;
-                                float v[KMAX];
-                                int off[KMAX];
+                    for (int k = 0; k < KMAX; ++k) {
+                        if (k < K) {
+                            const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                            const float w = r[R::W + k];
+                            const unsigned jl = ix & 31u, jh = ix >> 5;
 #pragma unroll
-                                for (int k = 0; k < KMAX; ++k) {
-                                    if (k < K) {
-                                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
-                                        const int row = ix == 0xffu ? kRows : lv * L + (int)ix;
-                                        off[k] = row * kStride;
-                                        v[k] = col[off[k]];
-                                    }
-                                }
-#pragma unroll
-                                for (int k = 0; k < KMAX; ++k)
-                                    if (k < K) col[off[k]] = fmaf(r[R::W + lv * KMAX + k], c, v[k]);
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < KMAX; ++k) {
-                                    if (k < K) {
-                                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
-                                        const float x = r[R::W + lv * KMAX + k] * c;
-                                        const unsigned jl = ix & 31u, jh = ix >> 5;
-#pragma unroll
-                                        for (int hh = 0; hh < RN; ++hh)
-                                            acc[lv < RV ? lv : 0][hh][jl] += (jh == (unsigned)hh) ? x : 0.0f;
-                                    }
-                                }
-                            }
+                            for (int hh = 0; hh < NV; ++hh)
+                                acc[hh][jl] = fmaf(jh == (unsigned)hh ? w : 0.0f, c, acc[hh][jl]);
                         }
                     }
                     T = testT;
@@ -290,55 +240,29 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
         }
     }
 
-    const size_t HW = (size_t)cam.W * cam.H;
-    if (LDS_ACC) {
-        __syncthreads();
-        // coalesced write-out: each store instruction covers 64 x 16 bytes of
-        // one quadrant row (the row's 8 pixels x L floats are contiguous)
-        const int f4_per_px = L / 4;
-        const int f4_per_row = 8 * f4_per_px;
-        for (int lv = 0; lv < levels; ++lv) {
-            for (int ry = 0; ry < 8; ++ry) {
-                const int gy = qy0 + ry;
-                if (gy >= cam.H) break;
-                float4* rowbase = reinterpret_cast<float4*>(a.coef + ((size_t)lv * HW + (size_t)gy * cam.W + qx0) * L);
-                for (int f = lane; f < f4_per_row; f += 64) {
-                    const int pxl = f / f4_per_px, c4 = f - pxl * f4_per_px;
-                    if (qx0 + pxl >= cam.W) continue;
-                    const float* src = accs + (lv * L + 4 * c4) * kStride + ry * 8 + pxl;
-                    rowbase[f] = make_float4(src[0], src[kStride], src[2 * kStride], src[3 * kStride]);
-                }
-            }
-        }
-    }
     if (!inside) return;
+    const size_t HW = (size_t)cam.W * cam.H;
     const size_t pix = (size_t)py * cam.W + px;
-    if (!LDS_ACC) {
+    float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv0 * HW + pix) * (size_t)(NV * 32));
 #pragma unroll
-        for (int lv = 0; lv < RV; ++lv) {
-            if (lv < levels) {
-                float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv * HW + pix) * (size_t)(RN * 32));
+    for (int h = 0; h < NV; ++h)
 #pragma unroll
-                for (int h = 0; h < RN; ++h)
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        dst[h * 8 + q] = make_float4(acc[lv][h][4 * q], acc[lv][h][4 * q + 1], acc[lv][h][4 * q + 2],
-                                                     acc[lv][h][4 * q + 3]);
-            }
-        }
+        for (int q = 0; q < 8; ++q)
+            dst[h * 8 + q] = make_float4(acc[h][4 * q], acc[h][4 * q + 1], acc[h][4 * q + 2], acc[h][4 * q + 3]);
+    if (lv0 == 0) {  // every level wave of the quadrant computes the same T and last
+        if (a.final_T) a.final_T[pix] = T;
+        if (a.last) a.last[pix] = last;
     }
-    if (a.final_T) a.final_T[pix] = T;
-    if (a.last) a.last[pix] = last;
 }
 
-template <int NV, int KMAX, int LVMAX, bool LDS_ACC>
+template <int NV, int KMAX>
 static int launch_splat(const SplatArgs& a, hipStream_t stream) {
     const int ntiles = a.cam.tx * a.cam.ty;
-    const int grid = round_up8(ntiles * 4);
-    if (a.K == KMAX && a.levels == LVMAX)
-        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, LVMAX, LDS_ACC, true>), dim3(grid), dim3(64), 0, stream, a);
+    const int grid = round_up8(ntiles * 4 * a.levels);
+    if (a.K == KMAX)
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, true>), dim3(grid), dim3(64), 0, stream, a);
     else
-        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, LVMAX, LDS_ACC, false>), dim3(grid), dim3(64), 0, stream, a);
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, false>), dim3(grid), dim3(64), 0, stream, a);
     LS2_LAUNCH_CHECK();
     return LS2_OK;
 }
@@ -373,18 +297,7 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
     a.final_T = final_T;
     a.last = last;
     const bool k8 = K > 4;
-    // LDS accumulators while levels * L <= 128 (at most 33.5 KB per wave): the
-    // row of level lv, coefficient c is lv * L + c, so NV * 32 * LVMAX >= levels * L
-    if (levels == 1) {
-        if (L == 32) return k8 ? launch_splat<1, 8, 1, true>(a, stream) : launch_splat<1, 4, 1, true>(a, stream);
-        if (L == 64) return k8 ? launch_splat<2, 8, 1, true>(a, stream) : launch_splat<2, 4, 1, true>(a, stream);
-        return k8 ? launch_splat<4, 8, 1, true>(a, stream) : launch_splat<4, 4, 1, true>(a, stream);
-    }
-    if (levels == 2) {
-        if (L == 32) return k8 ? launch_splat<1, 8, 2, true>(a, stream) : launch_splat<1, 4, 2, true>(a, stream);
-        return k8 ? launch_splat<2, 8, 2, true>(a, stream) : launch_splat<2, 4, 2, true>(a, stream);  // L = 64
-    }
-    if (L == 32) return k8 ? launch_splat<1, 8, 3, true>(a, stream) : launch_splat<1, 4, 3, true>(a, stream);
-    // three levels of 64 coefficients: 192 accumulators per pixel in VGPRs
-    return k8 ? launch_splat<2, 8, 3, false>(a, stream) : launch_splat<2, 4, 3, false>(a, stream);
+    if (L == 32) return k8 ? launch_splat<1, 8>(a, stream) : launch_splat<1, 4>(a, stream);
+    if (L == 64) return k8 ? launch_splat<2, 8>(a, stream) : launch_splat<2, 4>(a, stream);
+    return k8 ? launch_splat<4, 8>(a, stream) : launch_splat<4, 4>(a, stream);
 }

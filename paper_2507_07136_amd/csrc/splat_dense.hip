@@ -4,7 +4,7 @@
 // the two).  Same quadrant mapping, culling, staging and alpha arithmetic as
 // ls2_splat_sparse; the per-pixel accumulators live in VGPRs (the coefficient
 // index is static here), the Gaussian's weights are read with wave-uniform
-// loads.  With weights that are zero outside a Gaussian's K stored indices
+// loads.  As in the sparse splat, one wave renders one level of one quadrant.  With weights that are zero outside a Gaussian's K stored indices
 // the result equals ls2_splat_sparse bit for bit (an added exact zero leaves
 // every float unchanged).
 #include "splat_common.h"
@@ -25,16 +25,17 @@ struct SplatDenseArgs {
     int* last;
 };
 
-template <int L, int LV>
+template <int L>
 __global__ __launch_bounds__(64) void k_splat_dense(SplatDenseArgs a) {
     constexpr int STRIDE = 8;  // u, v, A2, B2, C2, o, position, id
     __shared__ float4 stage4[64 * STRIDE / 4];
     float* stage = reinterpret_cast<float*>(stage4);
     const CamK& cam = a.cam;
     const int ntiles = cam.tx * cam.ty;
-    int tile, quad;
-    xcd_remap(blockIdx.x, gridDim.x, 4, tile, quad);
+    int tile, slot;
+    xcd_remap(blockIdx.x, gridDim.x, 4 * a.levels, tile, slot);
     if (tile >= ntiles) return;
+    const int quad = slot & 3, lv0 = slot >> 2;
     const int lane = threadIdx.x;
     const int tx = tile % cam.tx, ty = tile / cam.tx;
     const int qx0 = tx * kTile + (quad & 1) * 8, qy0 = ty * kTile + (quad >> 1) * 8;
@@ -47,11 +48,9 @@ __global__ __launch_bounds__(64) void k_splat_dense(SplatDenseArgs a) {
     const unsigned start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const unsigned long long lt = (1ull << lane) - 1ull;
 
-    float acc[LV][L];
+    float acc[L];
 #pragma unroll
-    for (int lv = 0; lv < LV; ++lv)
-#pragma unroll
-        for (int c = 0; c < L; ++c) acc[lv][c] = 0.0f;
+    for (int c = 0; c < L; ++c) acc[c] = 0.0f;
     float T = 1.0f;
     int last = 0;
     bool active = inside;
@@ -106,13 +105,10 @@ __global__ __launch_bounds__(64) void k_splat_dense(SplatDenseArgs a) {
             if (__builtin_amdgcn_ballot_w64(contrib) != 0) {
                 // the Gaussian's dense weights: a wave-uniform address
                 const unsigned gid = __builtin_amdgcn_readfirstlane(__float_as_uint(h1.w));
-                const float* w = a.weights + (size_t)gid * a.levels * L;
+                const float* w = a.weights + ((size_t)gid * a.levels + lv0) * L;
                 const float cc = contrib ? c : 0.0f;
 #pragma unroll
-                for (int lv = 0; lv < LV; ++lv)
-#pragma unroll
-                    for (int q = 0; q < L; ++q)
-                        acc[lv][q] = contrib ? fmaf(w[lv * L + q], cc, acc[lv][q]) : acc[lv][q];
+                for (int q = 0; q < L; ++q) acc[q] = contrib ? fmaf(w[q], cc, acc[q]) : acc[q];
                 if (contrib) {
                     T = testT;
                     last = __float_as_int(h1.z) + 1;
@@ -124,21 +120,19 @@ __global__ __launch_bounds__(64) void k_splat_dense(SplatDenseArgs a) {
     if (!inside) return;
     const size_t HW = (size_t)cam.W * cam.H;
     const size_t pix = (size_t)py * cam.W + px;
+    float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv0 * HW + pix) * L);
 #pragma unroll
-    for (int lv = 0; lv < LV; ++lv) {
-        float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv * HW + pix) * L);
-#pragma unroll
-        for (int q = 0; q < L / 4; ++q)
-            dst[q] = make_float4(acc[lv][4 * q], acc[lv][4 * q + 1], acc[lv][4 * q + 2], acc[lv][4 * q + 3]);
+    for (int q = 0; q < L / 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+    if (lv0 == 0) {
+        if (a.final_T) a.final_T[pix] = T;
+        if (a.last) a.last[pix] = last;
     }
-    if (a.final_T) a.final_T[pix] = T;
-    if (a.last) a.last[pix] = last;
 }
 
-template <int L, int LV>
+template <int L>
 static int launch_dense(const SplatDenseArgs& a, hipStream_t stream) {
-    const int grid = round_up8(a.cam.tx * a.cam.ty * 4);
-    hipLaunchKernelGGL((k_splat_dense<L, LV>), dim3(grid), dim3(64), 0, stream, a);
+    const int grid = round_up8(a.cam.tx * a.cam.ty * 4 * a.levels);
+    hipLaunchKernelGGL((k_splat_dense<L>), dim3(grid), dim3(64), 0, stream, a);
     LS2_LAUNCH_CHECK();
     return LS2_OK;
 }
@@ -169,9 +163,5 @@ extern "C" int ls2_splat_dense(const ls2_camera* cam, int32_t n, int32_t levels,
     a.coef = coef;
     a.final_T = final_T;
     a.last = last;
-    if (L == 32)
-        return levels == 1 ? launch_dense<32, 1>(a, stream)
-                           : (levels == 2 ? launch_dense<32, 2>(a, stream) : launch_dense<32, 3>(a, stream));
-    return levels == 1 ? launch_dense<64, 1>(a, stream)
-                       : (levels == 2 ? launch_dense<64, 2>(a, stream) : launch_dense<64, 3>(a, stream));
+    return L == 32 ? launch_dense<32>(a, stream) : launch_dense<64>(a, stream);
 }
