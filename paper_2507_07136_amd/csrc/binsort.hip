@@ -62,7 +62,7 @@ inline Geo geo(const CamK& k) {
 }
 
 struct Layout {
-    size_t meta, sb_count, tile_count, sb_start, sb_cursor, rect, pool, total;
+    size_t meta, sb_count, tile_count, sb_start, sb_cursor, sb_order, rect, pool, total;
 };
 
 // meta, sb_count and tile_count come first: they are zeroed every call.
@@ -75,6 +75,7 @@ inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     l.tile_count = off; off = align_up(off + sizeof(unsigned) * (size_t)k.tx * k.ty);
     l.sb_start = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.sb_order = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.rect = off; off = align_up(off + sizeof(ushort4) * (size_t)(n > 0 ? n : 1));
     l.pool = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
     l.total = off;
@@ -94,6 +95,7 @@ struct BinArgs {
     unsigned* sb_count;
     unsigned* sb_start;
     unsigned* sb_cursor;
+    unsigned* sb_order;  // superblocks by decreasing bucket size (size classes)
     unsigned* tile_count;
     ushort4* rect;
     unsigned long long* pool;
@@ -209,7 +211,14 @@ __device__ long long block_scan(const unsigned* in, unsigned* start, int sstride
     return carry;
 }
 
+// Size class of a bucket for the processing order: 256-entry steps up to
+// 8192, then 1024-entry steps (class 63: 39936 and more).
+__device__ __forceinline__ int size_class(unsigned c) {
+    return c < 8192u ? (int)(c >> 8) : 32 + (int)min(31u, (c - 8192u) >> 10);
+}
+
 __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
+    __shared__ unsigned cls[64];
     const long long total = block_scan(a.sb_count, a.sb_start, 1, nullptr, a.nsb);
     const bool over = total > a.max_pairs;
     for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) a.sb_cursor[s] = a.sb_start[s];
@@ -217,6 +226,24 @@ __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
         a.meta->sb_total = total;
         a.meta->sb_overflow = over ? 1 : 0;
     }
+    // processing order of the per-superblock kernels: largest buckets first
+    // (a counting sort on the size class; order inside a class is arbitrary),
+    // so the long sorts start in the first dispatch round
+    if (threadIdx.x < 64) cls[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) atomicAdd(&cls[size_class(a.sb_count[s])], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned off = 0u;
+        for (int c = 63; c >= 0; --c) {
+            const unsigned t = cls[c];
+            cls[c] = off;
+            off += t;
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x)
+        a.sb_order[atomicAdd(&cls[size_class(a.sb_count[s])], 1u)] = (unsigned)s;
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
@@ -382,8 +409,8 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
     __shared__ unsigned tcnt[kMaxS2];
     __shared__ unsigned wsum[4];
     __shared__ unsigned bits[4];
-    const int sb = blockIdx.x;
-    if (sb >= a.nsb || a.meta->sb_overflow) return;
+    if ((int)blockIdx.x >= a.nsb || a.meta->sb_overflow) return;
+    const int sb = (int)a.sb_order[blockIdx.x];
     const int cnt = (int)a.sb_count[sb];
     if (cnt == 0) return;  // tile counts are pre-zeroed
     unsigned long long* g = a.pool + a.sb_start[sb];
@@ -525,21 +552,23 @@ __global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
     }
 }
 
-// One workgroup per superblock, one wave per tile (S = 4: 16 waves; larger
-// superblocks: each wave handles several tiles).  The sorted bucket is staged
-// through LDS in chunks of 1024 entries (key and tile rectangle), then every
-// wave compacts, in order, the entries whose rectangle covers its tile: an
-// order-preserving ballot compaction, so each tile's list comes out in
-// (depth, id) order.
-constexpr int kFillChunk = 1024;
+// One workgroup per superblock (largest buckets first), one wave per tile
+// (S = 4: 16 waves; larger superblocks: each wave handles several tiles).
+// The sorted bucket is staged through LDS in chunks of 2048 entries (key and
+// tile rectangle); the next chunk's keys and rectangles are loaded into
+// registers while the waves compact the current one.  Every wave keeps, in
+// order, the entries whose rectangle covers its tile: an order-preserving
+// ballot compaction, so each tile's list comes out in (depth, id) order.
+constexpr int kFillThreads = 1024;
+constexpr int kFillChunk = 2048;
+constexpr int kFillPer = kFillChunk / kFillThreads;
 
-__global__ __launch_bounds__(1024) void k_tile_fill(BinArgs a) {
+__global__ __launch_bounds__(kFillThreads) void k_tile_fill(BinArgs a) {
     __shared__ unsigned long long skey[kFillChunk];
     __shared__ ushort4 srect[kFillChunk];
     __shared__ unsigned toff[kMaxS2];
-    int sb, slot;
-    xcd_remap(blockIdx.x, gridDim.x, 1, sb, slot);
-    if (sb >= a.nsb || a.meta->overflow) return;
+    if ((int)blockIdx.x >= a.nsb || a.meta->overflow) return;
+    const int sb = (int)a.sb_order[blockIdx.x];
     const int S = a.S;
     const int tx0 = (sb % a.sbx) * S, ty0 = (sb / a.sbx) * S;
     const unsigned long long* list = a.pool + a.sb_start[sb];
@@ -550,15 +579,32 @@ __global__ __launch_bounds__(1024) void k_tile_fill(BinArgs a) {
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
+    unsigned long long pk[kFillPer];
+    ushort4 pr[kFillPer];
+    auto fetch = [&](int base) {
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            const int e = base + q * kFillThreads + (int)threadIdx.x;
+            pk[q] = e < cnt ? list[e] : 0ull;
+        }
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            const int e = base + q * kFillThreads + (int)threadIdx.x;
+            pr[q] = e < cnt ? a.rect[(unsigned)(pk[q] & 0xffffffffull)] : make_ushort4(0xffff, 0xffff, 0, 0);
+        }
+    };
+    fetch(0);
     for (int base = 0; base < cnt; base += kFillChunk) {
         const int n = min(kFillChunk, cnt - base);
         __syncthreads();  // previous chunk consumed (and toff initialised)
-        for (int e = threadIdx.x; e < n; e += blockDim.x) {
-            const unsigned long long key = list[base + e];
-            skey[e] = key;
-            srect[e] = a.rect[(unsigned)(key & 0xffffffffull)];
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            const int e = q * kFillThreads + (int)threadIdx.x;
+            skey[e] = pk[q];
+            srect[e] = pr[q];
         }
         __syncthreads();
+        if (base + kFillChunk < cnt) fetch(base + kFillChunk);
         for (int t = wave; t < S * S; t += nwaves) {
             const int tx = tx0 + t % S, ty = ty0 + t / S;
             if (tx >= a.cam.tx || ty >= a.cam.ty) continue;
@@ -626,6 +672,7 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.sb_count = reinterpret_cast<unsigned*>(ws + lay.sb_count);
     a.sb_start = reinterpret_cast<unsigned*>(ws + lay.sb_start);
     a.sb_cursor = reinterpret_cast<unsigned*>(ws + lay.sb_cursor);
+    a.sb_order = reinterpret_cast<unsigned*>(ws + lay.sb_order);
     a.tile_count = reinterpret_cast<unsigned*>(ws + lay.tile_count);
     a.rect = reinterpret_cast<ushort4*>(ws + lay.rect);
     a.pool = reinterpret_cast<unsigned long long*>(ws + lay.pool);
@@ -656,8 +703,7 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
     LS2_LAUNCH_CHECK();
     if (n > 0 && max_pairs > 0) {
-        const int fill_threads = g.S * g.S >= 16 ? 1024 : 64 * g.S * g.S;
-        hipLaunchKernelGGL(k_tile_fill, dim3(round_up8(g.nsb)), dim3(fill_threads), 0, stream, a);
+        hipLaunchKernelGGL(k_tile_fill, dim3(g.nsb), dim3(kFillThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
     if (num_pairs) {
