@@ -3,8 +3,9 @@
 
 One step = one feature-map frame of the whole forward hot path over the
 synthetic 1440x1080 scene (300k Gaussians, L=64, K=4, D=512, one level):
-project -> bin_sort -> splat_sparse -> dict_decode (bf16 matrix cores,
-bf16 output), with the scene already resident in HBM.  Prints one JSON line.
+project -> bin_sort -> splat_sparse (float32 accumulation, coefficient map
+stored in bf16) -> dict_decode (bf16 matrix cores, bf16 output), with the
+scene already resident in HBM.  Prints one JSON line.
 
 Also reported: per-stage times (HIP events on the launch stream), the query
 rate (frame + relevancy), the plain FP32 path's rate, the roofline of the
@@ -32,8 +33,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(stage, n, P, H, W, L, D, K, levels, feat_bytes):
-    """HBM bytes the method itself must move per launch of each stage."""
+def algorithmic_bytes(stage, n, P, H, W, L, D, K, levels, feat_bytes, coef_bytes=4):
+    """HBM bytes the method itself must move per launch of each stage
+    (coef_bytes: element size of the stored coefficient map)."""
     M = levels * H * W
     if stage == "project":
         return n * (12 + 12 + 16) + n * (8 + 12 + 4 + 4 + 4)
@@ -43,9 +45,9 @@ def algorithmic_bytes(stage, n, P, H, W, L, D, K, levels, feat_bytes):
         return n * (8 + 4) * 2 + n * 4 + P * 8 + P * 8 + P * 4
     if stage == "splat":
         rec = 8 + 12 + 4 + levels * K * 8
-        return M * L * 4 + H * W * 8 + P * 4 + n * rec
+        return M * L * coef_bytes + H * W * 8 + P * 4 + n * rec
     if stage == "decode":
-        return M * L * 4 + L * D * 4 + M * D * feat_bytes
+        return M * L * coef_bytes + L * D * 4 + M * D * feat_bytes
     if stage == "query":
         return M * D * feat_bytes + M * 4
     return 0
@@ -347,60 +349,64 @@ def main():
     post, negt = torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda()
     n, H, W, L, D, K, levels = scene.n, cam.height, cam.width, scene.L, scene.D, scene.K, scene.levels
 
+    # float32 coefficient map: the float32 path and the coefficient-space query
     pipe = ls2.Pipeline(cam, n, levels=levels, K=K, L=L, D=D)
+    # bf16 coefficient map (the values the bf16 decode rounds to): the bf16 path
+    pipe16 = ls2.Pipeline(cam, n, levels=levels, K=K, L=L, D=D, coef_dtype=torch.bfloat16)
     # first frame sizes the pair buffers (one host sync); later frames run without host syncs
-    pipe.project(t["means"], t["scales"], t["quats"])
-    P = pipe.bin_sort(sync=True)
+    for p_ in (pipe, pipe16):
+        p_.project(t["means"], t["scales"], t["quats"])
+        P = p_.bin_sort(sync=True)
     log("P =", P, "pairs")
 
-    def frame(compute, out_dtype, ev=None, query=False):
+    def frame(p_, compute, out_dtype, ev=None, query=False):
         def mark(i):
             if ev is not None:
                 ev[i].record()
         mark(0)
-        pipe.project(t["means"], t["scales"], t["quats"])
+        p_.project(t["means"], t["scales"], t["quats"])
         mark(1)
-        pipe.bin_sort(sync=False)
+        p_.bin_sort(sync=False)
         mark(2)
-        pipe.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+        p_.splat(t["opacity"], t["topk_idx"], t["topk_w"])
         mark(3)
-        pipe.decode(t["dictionary"], compute, out_dtype)
+        p_.decode(t["dictionary"], compute, out_dtype)
         mark(4)
         if query:
-            pipe.query(post, negt)
+            p_.query(post, negt)
             mark(5)
 
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
-    def run(compute, out_dtype, steps, warmup, query=False):
+    def run(p_, compute, out_dtype, steps, warmup, query=False):
         """Wall-clock rate over `steps` uninstrumented frames, then the same
         number of frames with HIP events between the stages (per-stage
         times; these frames are not part of the rate)."""
         for _ in range(warmup):
-            frame(compute, out_dtype, query=query)
+            frame(p_, compute, out_dtype, query=query)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            frame(compute, out_dtype, query=query)
+            frame(p_, compute, out_dtype, query=query)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         for s in range(steps):
-            frame(compute, out_dtype, evs[s], query=query)
+            frame(p_, compute, out_dtype, evs[s], query=query)
         torch.cuda.synchronize()
         nst = 5 if query else 4
         per = {stages[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                for i in range(nst)}
         return wall, per
 
-    # headline: f32 splat + bf16 decode (bf16 feature map)
-    wall, per = run(ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
-    assert ls2.ls2_bin_sort_count(pipe.workspace) == P
+    # headline: float32 splat accumulation, bf16 coefficient map, bf16 decode (bf16 feature map)
+    wall, per = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
+    assert ls2.ls2_bin_sort_count(pipe16.workspace) == P
     fps = args.steps / wall
     ms = 1000.0 * wall / args.steps
     log("bf16 path: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
 
-    qwall, qper = run(ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
+    qwall, qper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
     query_fps = max(5, args.steps // 2) / qwall
 
     # relevancy straight from the coefficient map (Eq. 7): project, bin, splat, query_coef
@@ -427,7 +433,7 @@ def main():
 
     f32 = None
     if not args.no_f32:
-        fwall, fper = run(ls2.LS2_F32, torch.float32, max(5, args.steps // 2), 3)
+        fwall, fper = run(pipe, ls2.LS2_F32, torch.float32, max(5, args.steps // 2), 3)
         f32 = dict(fps=max(5, args.steps // 2) / fwall, stages_ms=fper)
         log("f32 path: %.1f FPS" % f32["fps"])
 
@@ -435,11 +441,11 @@ def main():
     roof_all = {}
     for st, tms in qper.items():
         fb = 2
-        b = algorithmic_bytes(st, n, P, H, W, L, D, K, levels, fb)
+        b = algorithmic_bytes(st, n, P, H, W, L, D, K, levels, fb, coef_bytes=2)
         gbs = b / (tms * 1e-3) / 1e9
         roof_all[st] = dict(ms=tms, bytes=b, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
     dom = max(per, key=per.get)
-    b = algorithmic_bytes(dom, n, P, H, W, L, D, K, levels, 2)
+    b = algorithmic_bytes(dom, n, P, H, W, L, D, K, levels, 2, coef_bytes=2)
     ach = b / (per[dom] * 1e-3) / 1e9
     traffic = counter_traffic(dom, args.config)
     roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
@@ -452,7 +458,7 @@ def main():
 
     train = None
     if not args.no_train:
-        del pipe
+        del pipe, pipe16
         torch.cuda.empty_cache()
         train = train_step_timing(args, torch, np, gen, ls2)
 
@@ -476,7 +482,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 splat, bf16 decode (fp32 accumulate)",
+        "dtype": "f32 splat accumulation, bf16 coefficient map, bf16 decode (fp32 accumulate), bf16 feature map",
         "data": "synthetic",
         "config": {"workload": "%s: %d Gaussians, %dx%d, L=%d, K=%d, D=%d, %d level(s), 16x16 tiles"
                                % (args.config, n, W, H, L, K, D, levels),

@@ -126,9 +126,13 @@ int ls2_bin_sort_count(const void* workspace, int64_t* num_pairs, hipStream_t st
  * In:  tile_ranges, ids from ls2_bin_sort; mean2d [n,2], conic [n,3] from
  *      ls2_project; opacity [n] in (0,1); topk_idx [n,levels,K] int32 in
  *      [0, L); topk_w [n,levels,K].
- * Out: coef [levels,H,W,L]; final_T [H,W] (optional) = transmittance after
- *      the last blended Gaussian; last [H,W] (optional) = 1 + position in the
- *      tile list of the last blended Gaussian (0 if none).
+ * Out: coef [levels,H,W,L], accumulated in float32 and stored as float32
+ *      (coef_dtype LS2_F32) or bfloat16 (LS2_BF16, rounded nearest-even: the
+ *      values ls2_dict_decode's bf16 compute rounds a float32 map to, so the
+ *      feature map is the same either way); 16-byte aligned.
+ *      final_T [H,W] (optional) = transmittance after the last blended
+ *      Gaussian; last [H,W] (optional) = 1 + position in the tile list of
+ *      the last blended Gaussian (0 if none).
  * Supported: L in {32, 64, 128}, 1 <= K <= 8, levels in {1, 2, 3} with
  * levels * L <= 192.  Out-of-range indices are wrapped modulo L (garbage
  * result, never out-of-bounds access).
@@ -136,7 +140,7 @@ int ls2_bin_sort_count(const void* workspace, int64_t* num_pairs, hipStream_t st
 int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
                      const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
                      const float* conic, const float* opacity, const int32_t* topk_idx,
-                     const float* topk_w, float* coef, float* final_T, int32_t* last,
+                     const float* topk_w, void* coef, int32_t coef_dtype, float* final_T, int32_t* last,
                      hipStream_t stream);
 
 /*
@@ -159,7 +163,9 @@ int ls2_splat_dense(const ls2_camera* cam, int32_t n, int32_t levels, int32_t L,
  * coefficients and multiplying by the global codebook S equals rendering
  * the D-dimensional features).  One product shared by all levels.
  *
- * In:  coef [m,L] f32 (m = levels*H*W rows), dict [L,D] f32.
+ * In:  coef [m,L] (m = levels*H*W rows), float32 (coef_dtype LS2_F32) or
+ *      bfloat16 (LS2_BF16, only with LS2_BF16 compute); dict [L,D] f32.
+ *      coef and feat 16-byte aligned.
  * compute: LS2_F32 (float32 products and accumulation) or LS2_BF16 (both
  *      operands rounded to bfloat16, nearest-even; float32 accumulation on
  *      the matrix cores).
@@ -167,7 +173,7 @@ int ls2_splat_dense(const ls2_camera* cam, int32_t n, int32_t levels, int32_t L,
  *      rounded nearest-even from the float32 accumulator).
  * Supported: L in {32, 64, 128}; D in {128, 256, 384, 512, 1024}.
  */
-int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const void* coef, int32_t coef_dtype, const float* dict,
                     int32_t compute, int32_t out_dtype, void* feat, hipStream_t stream);
 
 /*

@@ -50,8 +50,8 @@ def _load():
         "ls2_bin_sort": ([cam, i32, P, P, P, i64, P, P, P, ctypes.POINTER(ctypes.c_int64), P, ctypes.c_size_t, P],
                          ctypes.c_int),
         "ls2_bin_sort_count": ([P, ctypes.POINTER(ctypes.c_int64), P], ctypes.c_int),
-        "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
-        "ls2_dict_decode": ([i64, i32, i32, P, P, i32, i32, P, P], ctypes.c_int),
+        "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, i32, P, P, P], ctypes.c_int),
+        "ls2_dict_decode": ([i64, i32, i32, P, i32, P, i32, i32, P, P], ctypes.c_int),
         "ls2_splat_dense": ([cam, i32, i32, i32, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_query_coef_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -196,7 +196,7 @@ def ls2_splat_sparse(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity
                                _ptr(conic, f32, "conic", 3 * n), _ptr(opacity, f32, "opacity", n),
                                _ptr(topk_idx, i32, "topk_idx", n * levels * K),
                                _ptr(topk_w, f32, "topk_w", n * levels * K),
-                               _ptr(coef, f32, "coef", levels * HW * L),
+                               _ptr(coef, None, "coef", levels * HW * L), _dtype_code(coef),
                                _ptr(final_T, f32, "final_T", HW, allow_none=True),
                                _ptr(last, i32, "last", HW, allow_none=True), _stream(stream))
     _check("ls2_splat_sparse", st)
@@ -228,7 +228,7 @@ def _dtype_code(t):
 def ls2_dict_decode(coef, dictionary, feat, compute=LS2_F32, stream=None):
     L, D = dictionary.shape
     m = coef.numel() // L
-    st = _lib.ls2_dict_decode(m, L, D, _ptr(coef, torch.float32, "coef", m * L),
+    st = _lib.ls2_dict_decode(m, L, D, _ptr(coef, None, "coef", m * L), _dtype_code(coef),
                               _ptr(dictionary, torch.float32, "dict", L * D), int(compute), _dtype_code(feat),
                               _ptr(feat, None, "feat", m * D), _stream(stream))
     _check("ls2_dict_decode", st)

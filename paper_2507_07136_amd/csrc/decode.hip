@@ -26,7 +26,8 @@ struct DecodeArgs {
     int D;
     int FC;        // features per workgroup chunk (min(D, 512))
     int nchunks;   // D / FC
-    const float* coef;
+    const float* coef;  // float32 map (bfloat16 map: coef16)
+    const unsigned short* coef16;
     const float* dict;
     void* feat;
     long long nblocks;
@@ -94,10 +95,11 @@ __device__ __forceinline__ void load_coef_f32path(const DecodeArgs& a, long long
 // next tile's loads (at most two float4 per thread) are in flight during the
 // current tile's work.  Few registers per wave let 16 waves share a CU, which
 // keeps the HBM write stream busy while single waves wait on their memory
-// counters.
+// counters.  CB: the coefficient map is already bfloat16 (read as is, the
+// same values the float32 map rounds to).
 constexpr int kTileRowBytes(int L) { return L * 2 + 16; }  // padded bf16 coefficient row
 
-template <int L, bool OUT_BF16>
+template <int L, bool OUT_BF16, bool CB>
 __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
     constexpr int KS = L / 16;   // k-steps
     constexpr int MT = 2;        // 32-feature tiles per wave
@@ -136,7 +138,8 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
     // the tile (row i / (L/4), columns 4 (i % (L/4)) ..); rows past the end
     // read the last row (never stored)
     constexpr int PER = (F4 + 127) / 128;  // float4 per thread, at most (workgroups have >= 128 threads)
-    float4 pre[PER];
+    float4 pre[PER];   // 4 float32 coefficients
+    uint2 pre16[PER];  // 4 bfloat16 coefficients
     auto load_tile = [&](long long bk) {
         const long long b = bk < a.nblocks ? bk : 0;
 #pragma unroll
@@ -145,7 +148,10 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
             if (i < F4) {
                 long long p = b * 32 + i / (L / 4);
                 if (p >= a.m) p = a.m - 1;
-                pre[j] = reinterpret_cast<const float4*>(a.coef + p * L)[i % (L / 4)];
+                if (CB)
+                    pre16[j] = reinterpret_cast<const uint2*>(a.coef16 + p * L)[i % (L / 4)];
+                else
+                    pre[j] = reinterpret_cast<const float4*>(a.coef + p * L)[i % (L / 4)];
             }
         }
     };
@@ -155,8 +161,12 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
             const int i = threadIdx.x + j * nthreads;
             if (i < F4) {
                 uint2 v;
-                v.x = pack_bf16x2(pre[j].x, pre[j].y);
-                v.y = pack_bf16x2(pre[j].z, pre[j].w);
+                if (CB) {
+                    v = pre16[j];
+                } else {
+                    v.x = pack_bf16x2(pre[j].x, pre[j].y);
+                    v.y = pack_bf16x2(pre[j].z, pre[j].w);
+                }
                 *reinterpret_cast<uint2*>(t + (i / (L / 4)) * TROW + (i % (L / 4)) * 8) = v;
             }
         }
@@ -544,8 +554,31 @@ static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
     return (int)grid;
 }
 
+template <int L, bool OB, bool CB>
+static int launch_decode_bf16(const DecodeArgs& a, hipStream_t stream) {
+    const int osz = OB ? 2 : 4;
+    const size_t lds = (size_t)32 * (a.FC * osz + 16);
+    const long long need = a.nblocks * a.nchunks;
+    const int threads = (a.FC / 64) * 64;
+    const size_t lds_b = lds + 2 * (size_t)32 * kTileRowBytes(L);
+    static bool attr = false;
+    if (!attr) {
+        if (hipFuncSetAttribute((const void*)k_decode_bf16<L, OB, CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                96 * 1024) != hipSuccess)
+            return LS2_ERR_DEVICE;
+        attr = true;
+    }
+    long long grid = (long long)num_cus() * resident_per_cu((const void*)k_decode_bf16<L, OB, CB>, threads, lds_b);
+    grid -= grid % a.nchunks;
+    if (grid < a.nchunks) grid = a.nchunks;
+    if (grid > need) grid = need;
+    hipLaunchKernelGGL((k_decode_bf16<L, OB, CB>), dim3((unsigned)grid), dim3(threads), lds_b, stream, a);
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
+}
+
 template <int L, bool OB>
-static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) {
+static int launch_decode(const DecodeArgs& a0, int compute, bool cb, hipStream_t stream) {
     DecodeArgs a = a0;
     a.FC = a.D < 512 ? a.D : 512;
     a.nchunks = a.D / a.FC;
@@ -559,20 +592,7 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
         return grid > need ? need : grid;
     };
     if (compute == LS2_BF16) {
-        const int threads = (a.FC / 64) * 64;
-        const size_t lds_b = lds + 2 * (size_t)32 * kTileRowBytes(L);
-        static bool attr = false;
-        if (!attr) {
-            if (hipFuncSetAttribute((const void*)k_decode_bf16<L, OB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    96 * 1024) != hipSuccess)
-                return LS2_ERR_DEVICE;
-            attr = true;
-        }
-        long long grid = (long long)num_cus() * resident_per_cu((const void*)k_decode_bf16<L, OB>, threads, lds_b);
-        grid -= grid % a.nchunks;
-        if (grid < a.nchunks) grid = a.nchunks;
-        if (grid > need) grid = need;
-        hipLaunchKernelGGL((k_decode_bf16<L, OB>), dim3((unsigned)grid), dim3(threads), lds_b, stream, a);
+        return cb ? launch_decode_bf16<L, OB, true>(a, stream) : launch_decode_bf16<L, OB, false>(a, stream);
     } else {
         const int threads = (a.FC / 64) * 64;
         static bool attr = false;
@@ -593,25 +613,34 @@ static int launch_decode(const DecodeArgs& a0, int compute, hipStream_t stream) 
 
 using namespace ls2;
 
-extern "C" int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict, int32_t compute,
-                               int32_t out_dtype, void* feat, hipStream_t stream) {
+extern "C" int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const void* coef, int32_t coef_dtype,
+                               const float* dict, int32_t compute, int32_t out_dtype, void* feat, hipStream_t stream) {
     if (m < 0 || L < 1 || D < 1 || !dict || !feat || !coef) return LS2_ERR_ARG;
-    if ((compute != LS2_F32 && compute != LS2_BF16) || (out_dtype != LS2_F32 && out_dtype != LS2_BF16))
+    if ((compute != LS2_F32 && compute != LS2_BF16) || (out_dtype != LS2_F32 && out_dtype != LS2_BF16) ||
+        (coef_dtype != LS2_F32 && coef_dtype != LS2_BF16))
         return LS2_ERR_ARG;
     if (!(L == 32 || L == 64 || L == 128) || D % 128 != 0 || (D > 512 && D != 1024)) return LS2_ERR_UNSUPPORTED;
+    if (coef_dtype == LS2_BF16 && compute != LS2_BF16) return LS2_ERR_UNSUPPORTED;
+    if (!aligned16(coef) || !aligned16(feat)) return LS2_ERR_ARG;
     if (m == 0) return LS2_OK;
+    const bool cb = coef_dtype == LS2_BF16;
     DecodeArgs a;
     a.m = m;
     a.D = D;
-    a.coef = coef;
+    a.coef = cb ? nullptr : static_cast<const float*>(coef);
+    a.coef16 = cb ? static_cast<const unsigned short*>(coef) : nullptr;
     a.dict = dict;
     a.feat = feat;
     a.nblocks = (m + 31) / 32;
     const bool ob = out_dtype == LS2_BF16;
     switch (L) {
-        case 32: return ob ? launch_decode<32, true>(a, compute, stream) : launch_decode<32, false>(a, compute, stream);
-        case 64: return ob ? launch_decode<64, true>(a, compute, stream) : launch_decode<64, false>(a, compute, stream);
-        default: return ob ? launch_decode<128, true>(a, compute, stream) : launch_decode<128, false>(a, compute, stream);
+        case 32:
+            return ob ? launch_decode<32, true>(a, compute, cb, stream) : launch_decode<32, false>(a, compute, cb, stream);
+        case 64:
+            return ob ? launch_decode<64, true>(a, compute, cb, stream) : launch_decode<64, false>(a, compute, cb, stream);
+        default:
+            return ob ? launch_decode<128, true>(a, compute, cb, stream)
+                      : launch_decode<128, false>(a, compute, cb, stream);
     }
 }
 
@@ -632,6 +661,7 @@ extern "C" int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const fl
     la.d.m = m;
     la.d.D = D;
     la.d.coef = coef;
+    la.d.coef16 = nullptr;
     la.d.dict = dict;
     la.d.feat = nullptr;
     la.d.nblocks = (m + 31) / 32;

@@ -100,6 +100,12 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
+// Two floats rounded to bfloat16 (nearest even), packed low / high.
+__device__ __forceinline__ unsigned bf16_pair(float a, float b) {
+    const __bf16 x = (__bf16)a, y = (__bf16)b;
+    return (unsigned)__builtin_bit_cast(unsigned short, x) | ((unsigned)__builtin_bit_cast(unsigned short, y) << 16);
+}
+
 // Host-side check of the 16-byte alignment that float4 accesses need (a null
 // pointer passes; null arguments are checked separately).
 inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }

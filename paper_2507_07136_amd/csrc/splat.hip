@@ -37,7 +37,7 @@ struct SplatArgs {
     const float* opacity;
     const int* topk_idx;
     const float* topk_w;
-    float* coef;
+    void* coef;  // float32, or bfloat16 (round to nearest even) when CB
     float* final_T;
     int* last;
 };
@@ -56,7 +56,8 @@ struct Rec {
 };
 
 // EXACT: K == KMAX is known at compile time.  NV = L / 32 accumulator vectors.
-template <int NV, int KMAX, bool EXACT>
+// CB: the coefficient map is written in bfloat16.
+template <int NV, int KMAX, bool EXACT, bool CB>
 __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
     using R = Rec<KMAX>;
     __shared__ float4 stage4[64 * R::STRIDE / 4];
@@ -243,12 +244,24 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
     if (!inside) return;
     const size_t HW = (size_t)cam.W * cam.H;
     const size_t pix = (size_t)py * cam.W + px;
-    float4* dst = reinterpret_cast<float4*>(a.coef + ((size_t)lv0 * HW + pix) * (size_t)(NV * 32));
+    const size_t row = ((size_t)lv0 * HW + pix) * (size_t)(NV * 32);
+    if (CB) {
+        uint4* dst = reinterpret_cast<uint4*>(static_cast<unsigned short*>(a.coef) + row);
 #pragma unroll
-    for (int h = 0; h < NV; ++h)
+        for (int h = 0; h < NV; ++h)
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            dst[h * 8 + q] = make_float4(acc[h][4 * q], acc[h][4 * q + 1], acc[h][4 * q + 2], acc[h][4 * q + 3]);
+            for (int q = 0; q < 4; ++q)
+                dst[h * 4 + q] = make_uint4(
+                    bf16_pair(acc[h][8 * q], acc[h][8 * q + 1]), bf16_pair(acc[h][8 * q + 2], acc[h][8 * q + 3]),
+                    bf16_pair(acc[h][8 * q + 4], acc[h][8 * q + 5]), bf16_pair(acc[h][8 * q + 6], acc[h][8 * q + 7]));
+    } else {
+        float4* dst = reinterpret_cast<float4*>(static_cast<float*>(a.coef) + row);
+#pragma unroll
+        for (int h = 0; h < NV; ++h)
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                dst[h * 8 + q] = make_float4(acc[h][4 * q], acc[h][4 * q + 1], acc[h][4 * q + 2], acc[h][4 * q + 3]);
+    }
     if (lv0 == 0) {  // every level wave of the quadrant computes the same T and last
         if (a.final_T) a.final_T[pix] = T;
         if (a.last) a.last[pix] = last;
@@ -256,13 +269,20 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
 }
 
 template <int NV, int KMAX>
-static int launch_splat(const SplatArgs& a, hipStream_t stream) {
+static int launch_splat(const SplatArgs& a, bool cb, hipStream_t stream) {
     const int ntiles = a.cam.tx * a.cam.ty;
     const int grid = round_up8(ntiles * 4 * a.levels);
-    if (a.K == KMAX)
-        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, true>), dim3(grid), dim3(64), 0, stream, a);
-    else
-        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, false>), dim3(grid), dim3(64), 0, stream, a);
+    if (a.K == KMAX) {
+        if (cb)
+            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, true, true>), dim3(grid), dim3(64), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, true, false>), dim3(grid), dim3(64), 0, stream, a);
+    } else {
+        if (cb)
+            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, false, true>), dim3(grid), dim3(64), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, false, false>), dim3(grid), dim3(64), 0, stream, a);
+    }
     LS2_LAUNCH_CHECK();
     return LS2_OK;
 }
@@ -274,10 +294,12 @@ using namespace ls2;
 extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
                                 const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
                                 const float* conic, const float* opacity, const int32_t* topk_idx,
-                                const float* topk_w, float* coef, float* final_T, int32_t* last,
-                                hipStream_t stream) {
+                                const float* topk_w, void* coef, int32_t coef_dtype, float* final_T,
+                                int32_t* last, hipStream_t stream) {
     if (!cam_valid(cam) || n < 0 || levels < 1 || K < 1 || L < 1 || K > L) return LS2_ERR_ARG;
     if (!tile_ranges || !coef) return LS2_ERR_ARG;
+    if (coef_dtype != LS2_F32 && coef_dtype != LS2_BF16) return LS2_ERR_ARG;
+    if (!aligned16(coef)) return LS2_ERR_ARG;
     if (n > 0 && (!ids || !mean2d || !conic || !opacity || !topk_idx || !topk_w)) return LS2_ERR_ARG;
     if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
     SplatArgs a;
@@ -296,8 +318,8 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
     a.coef = coef;
     a.final_T = final_T;
     a.last = last;
-    const bool k8 = K > 4;
-    if (L == 32) return k8 ? launch_splat<1, 8>(a, stream) : launch_splat<1, 4>(a, stream);
-    if (L == 64) return k8 ? launch_splat<2, 8>(a, stream) : launch_splat<2, 4>(a, stream);
-    return k8 ? launch_splat<4, 8>(a, stream) : launch_splat<4, 4>(a, stream);
+    const bool k8 = K > 4, cb = coef_dtype == LS2_BF16;
+    if (L == 32) return k8 ? launch_splat<1, 8>(a, cb, stream) : launch_splat<1, 4>(a, cb, stream);
+    if (L == 64) return k8 ? launch_splat<2, 8>(a, cb, stream) : launch_splat<2, 4>(a, cb, stream);
+    return k8 ? launch_splat<4, 8>(a, cb, stream) : launch_splat<4, 4>(a, cb, stream);
 }

@@ -18,7 +18,12 @@ _TILE = _lib.TILE
 
 class Pipeline:
     def __init__(self, cam, n: int, levels: int = 1, K: int = 4, L: int = 64, D: int = 512,
-                 max_pairs: int | None = None, device="cuda", keep_keys: bool = False):
+                 max_pairs: int | None = None, device="cuda", keep_keys: bool = False,
+                 coef_dtype=torch.float32):
+        """``coef_dtype`` torch.bfloat16 stores the coefficient map in bf16 (the
+        values the bf16 decode rounds a float32 map to): half the map traffic
+        for the bf16 feature-map path; the float32 decode, the coefficient
+        query and training need the float32 map."""
         self.cam = _lib.make_camera(cam)
         self.n, self.levels, self.K, self.L, self.D = n, levels, K, L, D
         self.H, self.W = self.cam.height, self.cam.width
@@ -36,7 +41,7 @@ class Pipeline:
         self.keep_keys = keep_keys
         self.num_pairs = None
         self._alloc_pairs(max_pairs if max_pairs is not None else max(1024, 64 * n))
-        self.coef = torch.empty((levels, self.H, self.W, L), dtype=f32, device=dev)
+        self.coef = torch.empty((levels, self.H, self.W, L), dtype=coef_dtype, device=dev)
         self.final_T = torch.empty((self.H, self.W), dtype=f32, device=dev)
         self.last = torch.empty((self.H, self.W), dtype=i32, device=dev)
         self.feat = None
@@ -97,6 +102,8 @@ class Pipeline:
         """Relevancy straight from the coefficient map (Eq. 7), no feature map."""
         if self.relevancy is None:
             self.relevancy = torch.empty((self.levels, self.H, self.W), dtype=torch.float32, device=self.device)
+        if self.coef.dtype != torch.float32:
+            raise ValueError("query_coef needs the float32 coefficient map (Pipeline(coef_dtype=torch.float32))")
         n_neg = neg.numel() // self.D
         key = (self.L, n_neg)
         if getattr(self, "_qc_key", None) != key:

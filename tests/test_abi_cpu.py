@@ -58,20 +58,26 @@ def test_argument_validation_without_device(L):
     assert L.ls2_project(ctypes.byref(bad), 1, V(16), V(16), V(16), V(16), V(16), V(16), V(16), None, None) == -1
     # n = 0 is a no-op
     assert L.ls2_project(ctypes.byref(c), 0, None, None, None, None, None, None, None, None, None) == 0
-    # splat: K > L, unsupported L, too many levels, null outputs
-    args = [V(16)] * 11
+    # splat: K > L, unsupported L, too many levels, null outputs, bad or
+    # misaligned coefficient map
+    args = [V(16)] * 8 + [0] + [V(16)] * 3
     assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 9, 8, *args) == -1
     assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 4, 48, *args) == -3
     assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 9, 64, *args) == -3
     assert L.ls2_splat_sparse(ctypes.byref(c), 10, 4, 4, 64, *args) == -3
     assert L.ls2_splat_sparse(ctypes.byref(c), 10, 3, 4, 128, *args) == -3
     assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 4, 64, None, *args[1:]) == -1
-    # decode: bad dtype codes, unsupported D / L
-    assert L.ls2_dict_decode(10, 64, 512, V(16), V(16), 7, 0, V(16), None) == -1
-    assert L.ls2_dict_decode(10, 64, 500, V(16), V(16), 0, 0, V(16), None) == -3
-    assert L.ls2_dict_decode(10, 48, 512, V(16), V(16), 0, 0, V(16), None) == -3
-    assert L.ls2_dict_decode(-1, 64, 512, V(16), V(16), 0, 0, V(16), None) == -1
-    assert L.ls2_dict_decode(0, 64, 512, V(16), V(16), 0, 0, V(16), None) == 0
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 4, 64, *args[:8], 5, *args[9:]) == -1
+    assert L.ls2_splat_sparse(ctypes.byref(c), 10, 1, 4, 64, *args[:7], V(24), 1, *args[9:]) == -1
+    # decode: bad dtype codes, unsupported D / L, bf16 map with f32 compute, misaligned map
+    assert L.ls2_dict_decode(10, 64, 512, V(16), 0, V(16), 7, 0, V(16), None) == -1
+    assert L.ls2_dict_decode(10, 64, 512, V(16), 3, V(16), 0, 0, V(16), None) == -1
+    assert L.ls2_dict_decode(10, 64, 500, V(16), 0, V(16), 0, 0, V(16), None) == -3
+    assert L.ls2_dict_decode(10, 48, 512, V(16), 0, V(16), 0, 0, V(16), None) == -3
+    assert L.ls2_dict_decode(10, 64, 512, V(16), 1, V(16), 0, 0, V(16), None) == -3
+    assert L.ls2_dict_decode(10, 64, 512, V(24), 0, V(16), 1, 0, V(16), None) == -1
+    assert L.ls2_dict_decode(-1, 64, 512, V(16), 0, V(16), 0, 0, V(16), None) == -1
+    assert L.ls2_dict_decode(0, 64, 512, V(16), 0, V(16), 0, 0, V(16), None) == 0
     # query: bad n_neg, unsupported D
     assert L.ls2_query(10, 512, V(16), 0, V(16), 0, V(16), ctypes.c_float(1.0), V(16), None) == -1
     assert L.ls2_query(10, 500, V(16), 0, V(16), 4, V(16), ctypes.c_float(1.0), V(16), None) == -3

@@ -353,3 +353,30 @@ def test_dense_splat_equals_sparse(L, K, levels):
     assert np.array_equal(pipe.last.cpu().numpy(), g["last"])
     assert np.array_equal(coef_d, g["coef"])
     assert np.array_equal(pipe.final_T.cpu().numpy(), g["final_T"])
+
+
+@pytest.mark.parametrize("L,K,levels", [(64, 4, 1), (32, 8, 2), (128, 4, 1), (64, 4, 3)])
+def test_bf16_coefficient_map(orc, L, K, levels):
+    """The bf16 coefficient map is the float32 map rounded to nearest even (bit
+    for bit), and decoding it gives the bf16-compute feature map of the float32
+    map bit for bit (bf16 and float32 outputs)."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(404 + L + K + levels, 3000, 120, 90, L=L, K=K, levels=levels, D=256)
+    g = run_forward(cam, scene)
+    pipe, t = g["pipe"], g["t"]
+    p16 = ls2.Pipeline(cam, scene.n, levels=levels, K=K, L=L, D=scene.D, coef_dtype=torch.bfloat16)
+    p16.project(t["means"], t["scales"], t["quats"])
+    p16.bin_sort(sync=True)
+    p16.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+    torch.cuda.synchronize()
+    c32 = torch.from_numpy(g["coef"]).cuda()
+    assert torch.equal(p16.coef, c32.to(torch.bfloat16))
+    assert np.array_equal(p16.last.cpu().numpy(), g["last"])
+    assert np.array_equal(p16.final_T.cpu().numpy(), g["final_T"])
+    for out_dtype in (torch.bfloat16, torch.float32):
+        f16 = p16.decode(t["dictionary"], ls2.LS2_BF16, out_dtype).clone()
+        f32 = pipe.decode(t["dictionary"], ls2.LS2_BF16, out_dtype).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(f16, f32), out_dtype
+    with pytest.raises(ls2.LS2Error):
+        p16.decode(t["dictionary"], ls2.LS2_F32, torch.float32)
