@@ -17,10 +17,11 @@
 //   - every lane then reads each surviving entry back as an LDS broadcast;
 //   - only the K stored coefficients are blended, into the pixel's L
 //     accumulators held in VGPRs as 32-float vectors addressed with the
-//     wave-uniform index through the VGPR index mode (one fused multiply-add
-//     per coefficient and vector; repeated indices of a Gaussian are merged
-//     at staging).  With one level per wave the L accumulators fit in
-//     registers at 4 waves per SIMD.
+//     wave-uniform index through the VGPR index mode.  Staging groups a
+//     Gaussian's coefficients by vector (and merges repeated indices), so
+//     the blend runs one loop per vector with a wave-uniform trip count: one
+//     indexed fused multiply-add per coefficient.  With one level per wave
+//     the L accumulators fit in registers at 4 waves per SIMD.
 #include "splat_common.h"
 
 namespace ls2 {
@@ -42,15 +43,20 @@ struct SplatArgs {
     int* last;
 };
 
-// Staged record (dwords): u, v, A2, B2, C2, o, list position, idx words,
-// weights.  A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e): the
+// Staged record (dwords): u, v, A2, B2, C2, o, list position, index words,
+// group counts, weights.  The K coefficients are stored grouped by
+// accumulator vector (index / 32, in slot order inside a group): the index
+// words hold the low 5 bits of each index (8 bits per slot), the count word
+// 4 bits per group.  A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e): the
 // Gaussian's exponent in base 2 is A2 dx^2 + B2 dx dy + C2 dy^2.
 template <int KMAX>
 struct Rec {
+    static_assert(KMAX == 4 || KMAX == 8, "the blend reads the weights as lanes 0..KMAX-1");
     static constexpr int KW = (KMAX + 3) / 4;  // packed u8 index words
     static constexpr int POS = 6;
     static constexpr int IDX = 7;
-    static constexpr int W = IDX + KW;
+    static constexpr int CNT = IDX + KW;
+    static constexpr int W = CNT + 1;
     static constexpr int RAW = W + KMAX;
     static constexpr int STRIDE = (RAW + 3) & ~3;  // 16-byte aligned records
 };
@@ -174,16 +180,27 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
                         wv[k] = 0.0f;
                         ix[k] = 0xffu;
                     }
-            unsigned wd[R::KW];
+            // grouped by accumulator vector, slot order inside a group
+            unsigned long long packed = 0ull;
+            unsigned cntw = 0u;
+            int pos = 0;
 #pragma unroll
-            for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
+            for (int hh = 0; hh < NV; ++hh) {
+                int nh = 0;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) {
-                wd[k >> 2] |= ix[k] << (8 * (k & 3));
-                r[R::W + k] = wv[k];
+                for (int k = 0; k < KMAX; ++k) {
+                    if (ix[k] != 0xffu && (int)(ix[k] >> 5) == hh) {
+                        packed |= (unsigned long long)(ix[k] & 31u) << (8 * pos);
+                        r[R::W + pos] = wv[k];
+                        ++pos;
+                        ++nh;
+                    }
+                }
+                cntw |= (unsigned)nh << (4 * hh);
             }
 #pragma unroll
-            for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + q] = wd[q];
+            for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + q] = (unsigned)(packed >> (32 * q));
+            reinterpret_cast<unsigned*>(r)[R::CNT] = cntw;
         }
         wave_lds_order();  // single-wave workgroup: orders the LDS writes before the reads
 
@@ -210,6 +227,12 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
             for (int u = 0; u < UNR; ++u) {
                 if (j + u >= nkeep) break;  // wave-uniform
                 const float* r = stage + (j + u) * R::STRIDE;
+                // lane k holds the entry's k-th weight, read here with every
+                // lane active (the empty asm keeps the read out of the
+                // divergent branch below; the blend loop takes the weights
+                // with v_readlane, which reads lanes regardless of EXEC)
+                float wlane = r[R::W + (lane & (KMAX - 1))];
+                asm volatile("" : "+v"(wlane));
                 const float alpha = fminf(0.99f, g[u]);
                 const float c = alpha * T;       // blend weight e_i = alpha_i T_i (Eq. 7)
                 const float testT = T - c;       // T (1 - alpha)
@@ -222,15 +245,17 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
 #pragma unroll
                     for (int q = 0; q < R::KW; ++q)
                         words[q] = __builtin_amdgcn_readfirstlane(reinterpret_cast<const unsigned*>(r)[R::IDX + q]);
+                    const unsigned cntw = __builtin_amdgcn_readfirstlane(reinterpret_cast<const unsigned*>(r)[R::CNT]);
+                    unsigned long long packed = words[0];
+                    if (R::KW > 1) packed |= (unsigned long long)words[R::KW > 1 ? 1 : 0] << 32;
+                    int k = 0;
 #pragma unroll
-                    for (int k = 0; k < KMAX; ++k) {
-                        if (k < K) {
-                            const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
-                            const float w = r[R::W + k];
-                            const unsigned jl = ix & 31u, jh = ix >> 5;
-#pragma unroll
-                            for (int hh = 0; hh < NV; ++hh)
-                                acc[hh][jl] = fmaf(jh == (unsigned)hh ? w : 0.0f, c, acc[hh][jl]);
+                    for (int hh = 0; hh < NV; ++hh) {
+                        const int nh = (int)(cntw >> (4 * hh)) & 15;
+                        for (int q = 0; q < nh; ++q, ++k) {  // wave-uniform trip count
+                            const unsigned jl = (unsigned)(packed >> (8 * k)) & 31u;
+                            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wlane), k));
+                            acc[hh][jl] = fmaf(w, c, acc[hh][jl]);
                         }
                     }
                     T = testT;
