@@ -401,24 +401,24 @@ constexpr int kMaxS2 = 32 * 32;  // tile counters per superblock (S <= 32)
 constexpr int kRadixCap = 16384;
 constexpr int kRadixWaves = 16;
 
-__global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
+struct RadixSmem {
+    unsigned long long xbuf[kRadixCap];
+    unsigned ctr[kRadixWaves][256];
+    unsigned tcnt[kMaxS2];
+    unsigned wsum[4];
+    unsigned bits[4];
+    unsigned chunk_start[257];  // large buckets: key offset of each chunk
+    unsigned nchunks;
+};
+
+// Sorts cnt <= kRadixCap keys from src into dst (may alias) in LDS; on
+// return the sorted keys are also in sm.xbuf[0, cnt).  Called by the whole
+// workgroup.  The caller orders earlier LDS use of sm before the call; the
+// call ends with an LDS barrier (the global writes to dst are not waited for).
+__device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned long long* src, unsigned long long* dst,
+                                               int cnt) {
     constexpr int NW = kRadixWaves;
     constexpr int ITEMS = kRadixCap / (64 * NW);  // chunks per wave, at most
-    __shared__ unsigned long long xbuf[kRadixCap];
-    __shared__ unsigned ctr[NW][256];
-    __shared__ unsigned tcnt[kMaxS2];
-    __shared__ unsigned wsum[4];
-    __shared__ unsigned bits[4];
-    if ((int)blockIdx.x >= a.nsb || a.meta->sb_overflow) return;
-    const int sb = (int)a.sb_order[blockIdx.x];
-    const int cnt = (int)a.sb_count[sb];
-    if (cnt == 0) return;  // tile counts are pre-zeroed
-    unsigned long long* g = a.pool + a.sb_start[sb];
-    if (cnt > kRadixCap) {  // beyond the LDS capacity: bitonic network in global memory
-        flip_bitonic<false>(g, cnt);
-        count_sb_tiles(a, sb, g, cnt, tcnt);
-        return;
-    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nchunk = (cnt + 63) >> 6;
@@ -434,14 +434,14 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
         if (c < mine) {
             const int p = (c0 + c) * 64 + lane;
             if (p < cnt) {
-                key[c] = g[p];
+                key[c] = src[p];
                 kor |= key[c];
                 kand &= key[c];
             }
-            xbuf[p] = key[c];
+            sm.xbuf[p] = key[c];
         }
     }
-    if (threadIdx.x < 4) bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
+    if (threadIdx.x < 4) sm.bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
     __syncthreads();
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -449,23 +449,23 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
         kand &= __shfl_xor(kand, off);
     }
     if (lane == 0 && mine > 0) {
-        atomicOr(&bits[0], (unsigned)kor);
-        atomicOr(&bits[1], (unsigned)(kor >> 32));
-        atomicAnd(&bits[2], (unsigned)kand);
-        atomicAnd(&bits[3], (unsigned)(kand >> 32));
+        atomicOr(&sm.bits[0], (unsigned)kor);
+        atomicOr(&sm.bits[1], (unsigned)(kor >> 32));
+        atomicAnd(&sm.bits[2], (unsigned)kand);
+        atomicAnd(&sm.bits[3], (unsigned)(kand >> 32));
     }
     __syncthreads();
-    const unsigned long long varying = (((unsigned long long)bits[1] << 32) | bits[0]) ^
-                                       (((unsigned long long)bits[3] << 32) | bits[2]);
+    const unsigned long long varying = (((unsigned long long)sm.bits[1] << 32) | sm.bits[0]) ^
+                                       (((unsigned long long)sm.bits[3] << 32) | sm.bits[2]);
 
     for (int shift = 0; shift < 64; shift += 8) {
         if (((varying >> shift) & 0xffull) == 0ull) continue;  // uniform across the workgroup
         // 1. per-wave digit counts
-        for (int i = lane; i < 256; i += 64) ctr[w][i] = 0u;
+        for (int i = lane; i < 256; i += 64) sm.ctr[w][i] = 0u;
         wave_sync();
 #pragma unroll
         for (int c = 0; c < ITEMS; ++c)
-            if (c < mine) atomicAdd(&ctr[w][(unsigned)(key[c] >> shift) & 0xffu], 1u);
+            if (c < mine) atomicAdd(&sm.ctr[w][(unsigned)(key[c] >> shift) & 0xffu], 1u);
         __syncthreads();
         // 2. scatter offsets, digit-major then wave order (waves 0-3 own one digit per lane)
         unsigned total = 0u, incl = 0u;
@@ -473,8 +473,8 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
             const int d = threadIdx.x;
 #pragma unroll
             for (int v = 0; v < NW; ++v) {
-                const unsigned x = ctr[v][d];
-                ctr[v][d] = total;
+                const unsigned x = sm.ctr[v][d];
+                sm.ctr[v][d] = total;
                 total += x;
             }
             incl = total;
@@ -483,15 +483,15 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
                 const unsigned y = __shfl_up(incl, off);
                 if (lane >= off) incl += y;
             }
-            if (lane == 63) wsum[w] = incl;
+            if (lane == 63) sm.wsum[w] = incl;
         }
         __syncthreads();
         if (threadIdx.x < 256) {
             const int d = threadIdx.x;
             unsigned base = incl - total;  // digits below d inside this wave
-            for (int v = 0; v < w; ++v) base += wsum[v];
+            for (int v = 0; v < w; ++v) base += sm.wsum[v];
 #pragma unroll
-            for (int v = 0; v < NW; ++v) ctr[v][d] += base;
+            for (int v = 0; v < NW; ++v) sm.ctr[v][d] += base;
         }
         __syncthreads();
         // 3. stable scatter
@@ -507,25 +507,141 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
                     peers &= bit ? bal : ~bal;
                 }
                 const unsigned rank = (unsigned)__builtin_popcountll(peers & lt);
-                const unsigned base = ctr[w][d];
-                if ((peers & lt) == 0ull) ctr[w][d] = base + (unsigned)__builtin_popcountll(peers);
-                xbuf[base + rank] = key[c];
+                const unsigned base = sm.ctr[w][d];
+                if ((peers & lt) == 0ull) sm.ctr[w][d] = base + (unsigned)__builtin_popcountll(peers);
+                sm.xbuf[base + rank] = key[c];
             }
         }
         __syncthreads();
         // 4. reload in the new order
 #pragma unroll
         for (int c = 0; c < ITEMS; ++c)
-            if (c < mine) key[c] = xbuf[(c0 + c) * 64 + lane];
+            if (c < mine) key[c] = sm.xbuf[(c0 + c) * 64 + lane];
     }
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
         if (c < mine) {
             const int p = (c0 + c) * 64 + lane;
-            if (p < cnt) g[p] = key[c];
+            if (p < cnt) dst[p] = key[c];
         }
     }
-    count_sb_tiles(a, sb, xbuf, cnt, tcnt);  // starts with a workgroup barrier
+    lds_barrier();
+}
+
+// Superblocks with count <= kRadixCap: least-significant-digit radix sort in
+// LDS, then write back and count tiles.
+//
+// The 64-bit keys (float32 depth bits << 32 | id) stay in registers: wave w
+// owns the contiguous chunks [w cpw, (w+1) cpw) of 64 positions, lane l of
+// chunk c holds position 64 c + l (positions past the count hold ~0, which
+// sorts last).  Each pass on an 8-bit digit
+//   1. counts the digits of every wave in wave-private LDS counters,
+//   2. turns the counts into scatter offsets (digit-major, then wave order),
+//   3. scatters: within a chunk the lanes holding the same digit find each
+//      other with eight ballots, so a key's destination is its wave's
+//      running offset for the digit plus its rank among those lanes -- the
+//      order of equal digits is kept (stable), which makes the passes an LSD
+//      sort,
+//   4. reloads the keys in the new order.
+// Digits on which every key of the bucket agrees are skipped: in practice the
+// exponent of the depth and the high bits of the id are constant, leaving
+// about six passes.
+//
+// Larger buckets are first split by their top eight varying key bits (a
+// most-significant-digit pass through a scratch copy in the free part of the
+// pool); runs of consecutive digit bins of at most kRadixCap keys are then
+// sorted as above, in key order, back into the bucket.  Only a bucket with a
+// single digit bin beyond kRadixCap, or a pool without room for the scratch
+// copy, uses the bitonic network in global memory.
+__global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
+    __shared__ RadixSmem sm;
+    if ((int)blockIdx.x >= a.nsb || a.meta->sb_overflow) return;
+    const int sb = (int)a.sb_order[blockIdx.x];
+    const int cnt = (int)a.sb_count[sb];
+    if (cnt == 0) return;  // tile counts are pre-zeroed
+    unsigned long long* g = a.pool + a.sb_start[sb];
+    if (cnt <= kRadixCap) {
+        radix_sort_lds(sm, g, g, cnt);
+        count_sb_tiles(a, sb, sm.xbuf, cnt, sm.tcnt);  // starts with a workgroup barrier
+        return;
+    }
+    const long long total = a.meta->sb_total;
+    if (2 * total > a.max_pairs) {  // no room for the scratch copy
+        flip_bitonic<false>(g, cnt);
+        count_sb_tiles(a, sb, g, cnt, sm.tcnt);
+        return;
+    }
+    unsigned long long* tmp = a.pool + total + a.sb_start[sb];
+    // varying bits of the bucket
+    unsigned long long kor = 0ull, kand = ~0ull;
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const unsigned long long k = g[e];
+        kor |= k;
+        kand &= k;
+    }
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        kor |= __shfl_xor(kor, off);
+        kand &= __shfl_xor(kand, off);
+    }
+    if (threadIdx.x < 4) sm.bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) sm.ctr[0][i] = 0u;
+    __syncthreads();
+    if (lane == 0) {
+        atomicOr(&sm.bits[0], (unsigned)kor);
+        atomicOr(&sm.bits[1], (unsigned)(kor >> 32));
+        atomicAnd(&sm.bits[2], (unsigned)kand);
+        atomicAnd(&sm.bits[3], (unsigned)(kand >> 32));
+    }
+    __syncthreads();
+    const unsigned long long varying = (((unsigned long long)sm.bits[1] << 32) | sm.bits[0]) ^
+                                       (((unsigned long long)sm.bits[3] << 32) | sm.bits[2]);
+    const int top = varying ? 63 - __builtin_clzll(varying) : 0;
+    const int dshift = top >= 7 ? top - 7 : 0;  // the top eight varying bits (or fewer)
+    // histogram of the top digit
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) atomicAdd(&sm.ctr[0][(unsigned)(g[e] >> dshift) & 0xffu], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // digit offsets, and runs of consecutive digits of at most kRadixCap keys
+        unsigned off = 0u, run = 0u, nch = 0u;
+        bool ok = true;
+        for (int d = 0; d < 256; ++d) {
+            const unsigned c = sm.ctr[0][d];
+            if (c > (unsigned)kRadixCap) ok = false;
+            if (run > 0u && run + c > (unsigned)kRadixCap) {  // at most 255 closes: chunk_start fits
+                sm.chunk_start[nch++] = off - run;
+                run = 0u;
+            }
+            sm.ctr[1][d] = off;  // scatter cursor
+            off += c;
+            run += c;
+        }
+        sm.chunk_start[nch++] = off - run;
+        sm.chunk_start[nch] = off;
+        sm.nchunks = ok ? nch : 0u;
+    }
+    __syncthreads();
+    const int nch = (int)sm.nchunks;
+    if (nch == 0) {  // one digit bin holds more keys than the LDS sort: global bitonic network
+        flip_bitonic<false>(g, cnt);
+        count_sb_tiles(a, sb, g, cnt, sm.tcnt);
+        return;
+    }
+    // scatter into the scratch copy by top digit (order inside a bin is not
+    // needed: every chunk is fully sorted next)
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const unsigned long long k = g[e];
+        tmp[atomicAdd(&sm.ctr[1][(unsigned)(k >> dshift) & 0xffu], 1u)] = k;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int b0 = (int)sm.chunk_start[c], b1 = (int)sm.chunk_start[c + 1];
+        if (b1 > b0) radix_sort_lds(sm, tmp + b0, g + b0, b1 - b0);
+    }
+    __threadfence_block();  // the chunks' global writes, before count_sb_tiles reads g
+    count_sb_tiles(a, sb, g, cnt, sm.tcnt);
 }
 
 

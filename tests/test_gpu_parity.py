@@ -272,6 +272,28 @@ def test_long_tile_lists(orc):
     assert lens.max() > 16384
     _check_lists(orc, cam, g)
     _check_coef(orc, cam, scene, g)
+    # a pool of exactly P entries leaves no room for the split's scratch copy:
+    # the global-memory network sorts the bucket instead
+    g2 = run_forward(cam, scene, max_pairs=g["P"])
+    assert g2["P"] == g["P"]
+    _check_lists(orc, cam, g2)
+
+
+def test_bucket_with_one_heavy_depth_bin(orc):
+    """20000 Gaussians at exactly one depth and one much nearer: the top
+    digit of the bucket cannot split the pile, so it takes the global-memory
+    network; lists stay bit-exact."""
+    rng = np.random.default_rng(13)
+    n = 20001
+    scene = gen.make_scene(13, n, D=128)
+    scene.means[:, :2] = rng.normal(0, 0.01, (n, 2)).astype(np.float32)
+    scene.means[:, 2] = 0.0
+    scene.means[0, 2] = -1.5
+    scene.scales[:] = 0.004
+    cam = gen.make_camera(64, 64)
+    g = run_forward(cam, scene)
+    assert len(np.unique(g["depth"][g["radius"] > 0])) == 2
+    _check_lists(orc, cam, g)
 
 
 # ---------------------------------------------------------------- full size, sampled
