@@ -359,7 +359,7 @@ def main():
         P = p_.bin_sort(sync=True)
     log("P =", P, "pairs")
 
-    def frame(p_, compute, out_dtype, ev=None, query=False):
+    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False):
         def mark(i):
             if ev is not None:
                 ev[i].record()
@@ -370,6 +370,10 @@ def main():
         mark(2)
         p_.splat(t["opacity"], t["topk_idx"], t["topk_w"])
         mark(3)
+        if fused:  # bf16 decode with the relevancy formed in its epilogue
+            p_.decode_query(t["dictionary"], post, negt)
+            mark(4)
+            return
         p_.decode(t["dictionary"], compute, out_dtype)
         mark(4)
         if query:
@@ -378,23 +382,23 @@ def main():
 
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
-    def run(p_, compute, out_dtype, steps, warmup, query=False):
+    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False):
         """Wall-clock rate over `steps` uninstrumented frames, then the same
         number of frames with HIP events between the stages (per-stage
         times; these frames are not part of the rate)."""
         for _ in range(warmup):
-            frame(p_, compute, out_dtype, query=query)
+            frame(p_, compute, out_dtype, query=query, fused=fused)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            frame(p_, compute, out_dtype, query=query)
+            frame(p_, compute, out_dtype, query=query, fused=fused)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         for s in range(steps):
-            frame(p_, compute, out_dtype, evs[s], query=query)
+            frame(p_, compute, out_dtype, evs[s], query=query, fused=fused)
         torch.cuda.synchronize()
-        nst = 5 if query else 4
+        nst = 5 if (query and not fused) else 4
         per = {stages[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                for i in range(nst)}
         return wall, per
@@ -406,8 +410,14 @@ def main():
     ms = 1000.0 * wall / args.steps
     log("bf16 path: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
 
+    # query frame, two passes: decode writes the feature map, ls2_query reads it back
     qwall, qper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
-    query_fps = max(5, args.steps // 2) / qwall
+    query_fps_two_pass = max(5, args.steps // 2) / qwall
+    # query frame, fused: the relevancy is formed in the decode's epilogue
+    fqwall, fqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True, fused=True)
+    query_fps = max(5, args.steps // 2) / fqwall
+    log("query frames: fused %.1f FPS (decode+relevancy %.4f ms), two-pass %.1f FPS" % (
+        query_fps, fqper["decode"], query_fps_two_pass))
 
     # relevancy straight from the coefficient map (Eq. 7): project, bin, splat, query_coef
     def coef_query_frame():
@@ -489,6 +499,8 @@ def main():
                    "pairs": P},
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
         "query_fps": round(query_fps, 2),
+        "query_fps_two_pass": round(query_fps_two_pass, 2),
+        "decode_with_relevancy_ms": round(fqper["decode"], 4),
         "query_from_coefficients": query_coef,
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},

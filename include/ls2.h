@@ -177,6 +177,25 @@ int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const void* coef, int32_t c
                     int32_t compute, int32_t out_dtype, void* feat, hipStream_t stream);
 
 /*
+ * ls2_dict_decode_query -- ls2_dict_decode (LS2_BF16 compute, bfloat16
+ * feature map) with the relevancy of ls2_query computed in the decode's
+ * epilogue, while each 32-row tile of F is still on chip (the decode ->
+ * relevancy fusion of Eq. 7 followed by the Section 3.2 score).  The
+ * relevancy equals ls2_query on the bfloat16 feature map bit for bit (same
+ * matrix-core dot products with the bf16-rounded texts, same norms, same
+ * formula), without reading the map back.
+ *
+ * In:  coef [m,L] float32 or bfloat16 (coef_dtype); dict [L,D] f32;
+ *      pos [D]; neg [n_neg,D] f32; tau.
+ * Out: feat [m,D] bfloat16, or NULL to skip writing the feature map;
+ *      relevancy [m] f32.  coef and feat 16-byte aligned.
+ * Supported: L in {32, 64, 128}; D in {128, 256, 384, 512}; 1 <= n_neg <= 8.
+ */
+int ls2_dict_decode_query(int64_t m, int32_t L, int32_t D, const void* coef, int32_t coef_dtype, const float* dict,
+                          void* feat, const float* pos, int32_t n_neg, const float* neg, float tau,
+                          float* relevancy, hipStream_t stream);
+
+/*
  * ls2_query -- relevancy of each feature to a text query.
  *
  * Section 3.2 computes relevancy "following LERF": with cosine similarities

@@ -52,6 +52,7 @@ def _load():
         "ls2_bin_sort_count": ([P, ctypes.POINTER(ctypes.c_int64), P], ctypes.c_int),
         "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, i32, P, P, P], ctypes.c_int),
         "ls2_dict_decode": ([i64, i32, i32, P, i32, P, i32, i32, P, P], ctypes.c_int),
+        "ls2_dict_decode_query": ([i64, i32, i32, P, i32, P, P, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_splat_dense": ([cam, i32, i32, i32, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_query": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_query_coef_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -232,6 +233,21 @@ def ls2_dict_decode(coef, dictionary, feat, compute=LS2_F32, stream=None):
                               _ptr(dictionary, torch.float32, "dict", L * D), int(compute), _dtype_code(feat),
                               _ptr(feat, None, "feat", m * D), _stream(stream))
     _check("ls2_dict_decode", st)
+
+
+def ls2_dict_decode_query(coef, dictionary, pos, neg, relevancy, feat=None, tau=1.0, stream=None):
+    """bf16 decode with the relevancy formed in its epilogue; feat (bf16) optional."""
+    L, D = dictionary.shape
+    m = coef.numel() // L
+    n_neg = neg.numel() // D
+    if feat is not None and feat.dtype != torch.bfloat16:
+        raise TypeError("feat must be bfloat16")
+    st = _lib.ls2_dict_decode_query(m, L, D, _ptr(coef, None, "coef", m * L), _dtype_code(coef),
+                                    _ptr(dictionary, torch.float32, "dict", L * D),
+                                    _ptr(feat, torch.bfloat16, "feat", m * D, allow_none=True),
+                                    _ptr(pos, torch.float32, "pos", D), n_neg, _ptr(neg, torch.float32, "neg", n_neg * D),
+                                    float(tau), _ptr(relevancy, torch.float32, "relevancy", m), _stream(stream))
+    _check("ls2_dict_decode_query", st)
 
 
 def ls2_query(feat, pos, neg, relevancy, tau=1.0, stream=None):

@@ -18,6 +18,7 @@
 namespace ls2 {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4q __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
@@ -28,6 +29,12 @@ struct DecodeArgs {
     int nchunks;   // D / FC
     const float* coef;  // float32 map (bfloat16 map: coef16)
     const unsigned short* coef16;
+    // relevancy epilogue (bf16 compute, one feature chunk): texts and output
+    const float* pos = nullptr;
+    const float* neg = nullptr;
+    int ntext = 0;
+    float tau = 1.0f;
+    float* rel = nullptr;
     const float* dict;
     void* feat;
     long long nblocks;
@@ -97,9 +104,23 @@ __device__ __forceinline__ void load_coef_f32path(const DecodeArgs& a, long long
 // keeps the HBM write stream busy while single waves wait on their memory
 // counters.  CB: the coefficient map is already bfloat16 (read as is, the
 // same values the float32 map rounds to).
+//
+// QRY: relevancy epilogue (bf16 feature tile, D <= 512).  While the 32 x D
+// tile of F sits in LDS, waves 0 and 1 score its two 16-row halves exactly as
+// ls2_query scores a bf16 feature map (the same matrix-core dot products with
+// the bf16-rounded texts, the same Gram diagonal for the squared norms, the
+// same relevancy function), so the result equals ls2_query on the written map
+// bit for bit, without reading the map back.  a.feat may be null: then F is
+// not written at all.
 constexpr int kTileRowBytes(int L) { return L * 2 + 16; }  // padded bf16 coefficient row
+constexpr int kQryTextPad = 8;                             // bf16 text row padding
 
-template <int L, bool OUT_BF16, bool CB>
+// LDS bytes of the relevancy epilogue: bf16 texts, text norms, dot tiles, norms
+inline size_t qry_lds(int D, int ntext) {
+    return (size_t)ntext * (D + kQryTextPad) * 2 + sizeof(float) * (16 + 2 * 16 * 17 + 2 * 16);
+}
+
+template <int L, bool OUT_BF16, bool CB, bool QRY>
 __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
     constexpr int KS = L / 16;   // k-steps
     constexpr int MT = 2;        // 32-feature tiles per wave
@@ -110,6 +131,7 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
     extern __shared__ float4 smem4[];
     char* tiles = reinterpret_cast<char*>(smem4);  // two coefficient tiles
     char* smem = tiles + 2 * TILE;                 // output staging
+    char* qry = smem + 32 * (a.FC * OSZ + 16);     // relevancy epilogue (QRY)
 
     const int D = a.D;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -132,6 +154,28 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
             sa[mt][ks] = v;
         }
 
+    const int qtstride = (D + kQryTextPad) * 2;
+    float* q_tnorm = reinterpret_cast<float*>(qry + a.ntext * qtstride);
+    float* q_dots = q_tnorm + 16;         // [2][16 rows][17]
+    float* q_nrm = q_dots + 2 * 16 * 17;  // [2][16]
+    if (QRY) {
+        // texts rounded to bf16 (the matrix-core operands) and their float32 norms
+        for (int i = threadIdx.x; i < a.ntext * D; i += nthreads) {
+            const int j = i / D, d = i - j * D;
+            const float v = j == 0 ? a.pos[d] : a.neg[(size_t)(j - 1) * D + d];
+            reinterpret_cast<__bf16*>(qry + j * qtstride)[d] = (__bf16)v;
+        }
+        if (threadIdx.x < 64) {
+            for (int j = 0; j < a.ntext; ++j) {
+                float sacc = 0.f;
+                const float* t = j == 0 ? a.pos : a.neg + (size_t)(j - 1) * D;
+                for (int d = threadIdx.x; d < D; d += 64) sacc += t[d] * t[d];
+                for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+                if (threadIdx.x == 0) q_tnorm[j] = fmaxf(sqrtf(sacc), 1e-12f);
+            }
+        }
+        // published by the barrier before the first tile's epilogue
+    }
     const long long bstep = gridDim.x / a.nchunks;
     long long blk = blockIdx.x / a.nchunks;
     // cooperative tile loads: float4 number i = threadIdx.x + j * nthreads of
@@ -220,13 +264,42 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
         const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
         const int nvec = (int)rows * chunks_per_row;
         const long long out_row = (long long)D * OSZ;
-        char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
+        if (!QRY || a.feat) {
+            char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
 #pragma unroll
-        for (int it = 0; it < 2 * OSZ; ++it) {
-            const int c = min((int)threadIdx.x + it * nthreads, nvec - 1);
-            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
-            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+            for (int it = 0; it < 2 * OSZ; ++it) {
+                const int c = min((int)threadIdx.x + it * nthreads, nvec - 1);
+                const int r = c / chunks_per_row, q = c - r * chunks_per_row;
+                const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
+            }
+        }
+        if (QRY && wave < 2) {
+            // rows 16 wave .. 16 wave + 15 of the tile: A = F rows (lane: row
+            // r16, features ks*32 + g*8 ..), B = text columns (lane: text r16)
+            const int r16 = lane & 15, g = lane >> 4;
+            const bool tcol = r16 < a.ntext;
+            const bf16x8 zero8 = {};
+            f32x4q dacc = {0.f, 0.f, 0.f, 0.f}, gram = {0.f, 0.f, 0.f, 0.f};
+            const char* frow = smem + (16 * wave + r16) * srow;
+            for (int ks = 0; ks < D / 32; ++ks) {
+                const bf16x8 fa = *reinterpret_cast<const bf16x8*>(frow + (ks * 32 + g * 8) * 2);
+                const bf16x8 tb = tcol ? *reinterpret_cast<const bf16x8*>(qry + r16 * qtstride + (ks * 32 + g * 8) * 2)
+                                       : zero8;
+                dacc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, tb, dacc, 0, 0, 0);
+                gram = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fa, gram, 0, 0, 0);
+            }
+            float* dw = q_dots + wave * 16 * 17;
+            float* nw = q_nrm + wave * 16;
+            const int i = r16 - g * 4;  // diagonal of the Gram tile: row g*4 + i == column r16
+            if (i >= 0 && i < 4) nw[r16] = gram[i];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) dw[(g * 4 + ii) * 17 + r16] = dacc[ii];
+            wave_lds_order();
+            if (lane < 16) {
+                const long long row = p0 + 16 * wave + lane;
+                if (row < a.m) a.rel[row] = lerf_relevancy(dw + lane * 17, nw[lane], q_tnorm, a.ntext, a.tau);
+            }
         }
         lds_barrier();
         cur ^= 1;
@@ -554,25 +627,25 @@ static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
     return (int)grid;
 }
 
-template <int L, bool OB, bool CB>
+template <int L, bool OB, bool CB, bool QRY = false>
 static int launch_decode_bf16(const DecodeArgs& a, hipStream_t stream) {
     const int osz = OB ? 2 : 4;
     const size_t lds = (size_t)32 * (a.FC * osz + 16);
     const long long need = a.nblocks * a.nchunks;
     const int threads = (a.FC / 64) * 64;
-    const size_t lds_b = lds + 2 * (size_t)32 * kTileRowBytes(L);
+    const size_t lds_b = lds + 2 * (size_t)32 * kTileRowBytes(L) + (QRY ? qry_lds(a.D, a.ntext) : 0);
+    const void* kern = (const void*)k_decode_bf16<L, OB, CB, QRY>;
     static bool attr = false;
     if (!attr) {
-        if (hipFuncSetAttribute((const void*)k_decode_bf16<L, OB, CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                96 * 1024) != hipSuccess)
+        if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024) != hipSuccess)
             return LS2_ERR_DEVICE;
         attr = true;
     }
-    long long grid = (long long)num_cus() * resident_per_cu((const void*)k_decode_bf16<L, OB, CB>, threads, lds_b);
+    long long grid = (long long)num_cus() * resident_per_cu(kern, threads, lds_b);
     grid -= grid % a.nchunks;
     if (grid < a.nchunks) grid = a.nchunks;
     if (grid > need) grid = need;
-    hipLaunchKernelGGL((k_decode_bf16<L, OB, CB>), dim3((unsigned)grid), dim3(threads), lds_b, stream, a);
+    hipLaunchKernelGGL((k_decode_bf16<L, OB, CB, QRY>), dim3((unsigned)grid), dim3(threads), lds_b, stream, a);
     LS2_LAUNCH_CHECK();
     return LS2_OK;
 }
@@ -644,6 +717,37 @@ extern "C" int ls2_dict_decode(int64_t m, int32_t L, int32_t D, const void* coef
     }
 }
 
+
+extern "C" int ls2_dict_decode_query(int64_t m, int32_t L, int32_t D, const void* coef, int32_t coef_dtype,
+                                     const float* dict, void* feat, const float* pos, int32_t n_neg, const float* neg,
+                                     float tau, float* relevancy, hipStream_t stream) {
+    if (m < 0 || L < 1 || D < 1 || !coef || !dict || !pos || !neg || !relevancy || n_neg < 1) return LS2_ERR_ARG;
+    if (coef_dtype != LS2_F32 && coef_dtype != LS2_BF16) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || D % 128 != 0 || D > 512 || n_neg > 8) return LS2_ERR_UNSUPPORTED;
+    if (!aligned16(coef) || !aligned16(feat)) return LS2_ERR_ARG;
+    if (m == 0) return LS2_OK;
+    const bool cb = coef_dtype == LS2_BF16;
+    DecodeArgs a;
+    a.m = m;
+    a.D = D;
+    a.FC = D;
+    a.nchunks = 1;
+    a.coef = cb ? nullptr : static_cast<const float*>(coef);
+    a.coef16 = cb ? static_cast<const unsigned short*>(coef) : nullptr;
+    a.dict = dict;
+    a.feat = feat;
+    a.nblocks = (m + 31) / 32;
+    a.pos = pos;
+    a.neg = neg;
+    a.ntext = 1 + n_neg;
+    a.tau = tau;
+    a.rel = relevancy;
+    switch (L) {
+        case 32: return cb ? launch_decode_bf16<32, true, true, true>(a, stream) : launch_decode_bf16<32, true, false, true>(a, stream);
+        case 64: return cb ? launch_decode_bf16<64, true, true, true>(a, stream) : launch_decode_bf16<64, true, false, true>(a, stream);
+        default: return cb ? launch_decode_bf16<128, true, true, true>(a, stream) : launch_decode_bf16<128, true, false, true>(a, stream);
+    }
+}
 
 extern "C" int ls2_decode_feature_loss_workspace(int64_t m, int32_t D, size_t* bytes) {
     if (!bytes || m < 0 || D < 1) return LS2_ERR_ARG;

@@ -100,6 +100,19 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
+// LERF relevancy of one feature from its dot products with the texts (index
+// 0 the positive, 1.. the negatives), its squared norm and the texts' guarded
+// norms: sigmoid(tau (s_q - max_j s_j)) on cosine similarities, the feature
+// norm guarded below by 1e-12.
+__device__ __forceinline__ float lerf_relevancy(const float* dots, float fnorm2, const float* tnorm, int ntext,
+                                                float tau) {
+    const float nf = fmaxf(sqrtf(fnorm2), 1e-12f);
+    const float sq = dots[0] / (nf * tnorm[0]);
+    float smax = -INFINITY;
+    for (int j = 1; j < ntext; ++j) smax = fmaxf(smax, dots[j] / (nf * tnorm[j]));
+    return 1.0f / (1.0f + expf(-tau * (sq - smax)));
+}
+
 // Two floats rounded to bfloat16 (nearest even), packed low / high.
 __device__ __forceinline__ unsigned bf16_pair(float a, float b) {
     const __bf16 x = (__bf16)a, y = (__bf16)b;

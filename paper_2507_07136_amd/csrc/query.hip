@@ -38,15 +38,6 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float relevancy(const float* dots, float fnorm2, const float* tnorm, int ntext,
-                                           float tau) {
-    const float nf = fmaxf(sqrtf(fnorm2), 1e-12f);
-    const float sq = dots[0] / (nf * tnorm[0]);
-    float smax = -INFINITY;
-    for (int j = 1; j < ntext; ++j) smax = fmaxf(smax, dots[j] / (nf * tnorm[j]));
-    return 1.0f / (1.0f + expf(-tau * (sq - smax)));
-}
-
 // LDS: text rows (f32 or bf16, padded), text norms, per-wave dot tiles.
 template <bool BF16>
 __global__ __launch_bounds__(kQWaves * 64) void k_query(QueryArgs a) {
@@ -130,7 +121,7 @@ __global__ __launch_bounds__(kQWaves * 64) void k_query(QueryArgs a) {
             if (q < a.m) {
                 const float n2 = BF16 ? nrm_w[lane]
                                       : (nrm_w[lane] + nrm_w[16 + lane]) + (nrm_w[32 + lane] + nrm_w[48 + lane]);
-                a.out[q] = relevancy(dots_w + lane * 17, n2, tnorm_s, ntext, a.tau);
+                a.out[q] = lerf_relevancy(dots_w + lane * 17, n2, tnorm_s, ntext, a.tau);
             }
         }
         wave_lds_sync();

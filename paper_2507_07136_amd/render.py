@@ -98,6 +98,22 @@ class Pipeline:
         _lib.ls2_query(self.feat, pos, neg, self.relevancy, tau)
         return self.relevancy
 
+    def decode_query(self, dictionary, pos, neg, tau: float = 1.0, keep_feat: bool = True):
+        """bf16 decode and relevancy in one pass (the relevancy is formed while
+        each tile of F is on chip); with keep_feat=False the feature map is not
+        written at all."""
+        m = self.levels * self.H * self.W
+        if self.relevancy is None:
+            self.relevancy = torch.empty((self.levels, self.H, self.W), dtype=torch.float32, device=self.device)
+        feat = None
+        if keep_feat:
+            if self.feat is None or self.feat.dtype != torch.bfloat16:
+                self.feat = torch.empty((self.levels, self.H, self.W, self.D), dtype=torch.bfloat16,
+                                        device=self.device)
+            feat = self.feat.view(m, self.D)
+        _lib.ls2_dict_decode_query(self.coef.view(m, self.L), dictionary, pos, neg, self.relevancy.view(m), feat, tau)
+        return self.relevancy
+
     def query_coef(self, dictionary, pos, neg, tau: float = 1.0):
         """Relevancy straight from the coefficient map (Eq. 7), no feature map."""
         if self.relevancy is None:

@@ -166,3 +166,16 @@ def test_codes_and_accumulate_validation_without_device(L):
     assert L.ls2_accumulate(8, None, V(16), None) == -1
     assert L.ls2_accumulate(8, V(16), V(20), None) == -1
     assert L.ls2_accumulate(0, None, None, None) == 0
+
+
+def test_decode_query_validation_without_device(L):
+    V = ctypes.c_void_p
+    f1 = ctypes.c_float(1.0)
+    # null text, no negatives, too many negatives, D beyond one chunk, bad coef dtype, misaligned map
+    assert L.ls2_dict_decode_query(10, 64, 512, V(16), 0, V(16), None, None, 4, V(16), f1, V(16), None) == -1
+    assert L.ls2_dict_decode_query(10, 64, 512, V(16), 0, V(16), None, V(16), 0, V(16), f1, V(16), None) == -1
+    assert L.ls2_dict_decode_query(10, 64, 512, V(16), 0, V(16), None, V(16), 9, V(16), f1, V(16), None) == -3
+    assert L.ls2_dict_decode_query(10, 64, 1024, V(16), 0, V(16), None, V(16), 4, V(16), f1, V(16), None) == -3
+    assert L.ls2_dict_decode_query(10, 64, 512, V(16), 2, V(16), None, V(16), 4, V(16), f1, V(16), None) == -1
+    assert L.ls2_dict_decode_query(10, 64, 512, V(16), 0, V(16), V(8), V(16), 4, V(16), f1, V(16), None) == -1
+    assert L.ls2_dict_decode_query(0, 64, 512, V(16), 0, V(16), None, V(16), 4, V(16), f1, V(16), None) == 0

@@ -402,3 +402,38 @@ def test_bf16_coefficient_map(orc, L, K, levels):
         assert torch.equal(f16, f32), out_dtype
     with pytest.raises(ls2.LS2Error):
         p16.decode(t["dictionary"], ls2.LS2_F32, torch.float32)
+
+
+@pytest.mark.parametrize("L,D,n_neg,coef_bf16,keep", [(64, 512, 4, True, True), (64, 512, 4, False, False),
+                                                       (32, 256, 1, False, True), (128, 384, 8, True, False),
+                                                       (64, 128, 2, False, True)])
+def test_decode_query_epilogue(orc, L, D, n_neg, coef_bf16, keep):
+    """Relevancy formed in the bf16 decode's epilogue equals ls2_query on the
+    bf16 feature map bit for bit; the map itself equals the plain bf16 decode;
+    against the oracle it meets the bf16 relevancy bar.  Ragged row count."""
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(L + D + n_neg)
+    m = 3001
+    coef = (rng.random((m, L)) * (rng.random((m, L)) < 0.3)).astype(np.float32)
+    coef[0] = 0.0                                   # empty pixel
+    dct = rng.standard_normal((L, D)).astype(np.float32)
+    dct /= np.linalg.norm(dct, axis=1, keepdims=True)
+    pos, neg = gen.make_text(L + D + 1, D=D, n_neg=n_neg)
+    tc = torch.from_numpy(coef).cuda()
+    if coef_bf16:
+        tc = tc.to(torch.bfloat16)
+    td, tp, tn = (torch.from_numpy(x).cuda() for x in (dct, pos, neg))
+    ref_feat = torch.empty((m, D), dtype=torch.bfloat16, device="cuda")
+    ls2.ls2_dict_decode(tc, td, ref_feat, compute=ls2.LS2_BF16)
+    ref_rel = torch.empty((m,), device="cuda")
+    ls2.ls2_query(ref_feat, tp, tn, ref_rel)
+    rel = torch.empty((m,), device="cuda")
+    feat = torch.empty((m, D), dtype=torch.bfloat16, device="cuda") if keep else None
+    ls2.ls2_dict_decode_query(tc, td, tp, tn, rel, feat=feat)
+    torch.cuda.synchronize()
+    assert torch.equal(rel, ref_rel)
+    if keep:
+        assert torch.equal(feat, ref_feat)
+    r64 = orc.query(orc.decode(coef.astype(np.float64), dct), pos, neg)
+    assert np.abs(rel.cpu().numpy() - r64).max() <= 2e-3
+    assert rel[0].item() == 0.5
