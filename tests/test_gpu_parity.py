@@ -437,3 +437,22 @@ def test_decode_query_epilogue(orc, L, D, n_neg, coef_bf16, keep):
     r64 = orc.query(orc.decode(coef.astype(np.float64), dct), pos, neg)
     assert np.abs(rel.cpu().numpy() - r64).max() <= 2e-3
     assert rel[0].item() == 0.5
+
+
+def test_equal_depth_runs_in_id_order(orc):
+    """Short runs of equal float32 depth (the depth-only radix passes plus the
+    per-run id fix-up) and one run of 300 equal depths (longer than the
+    fix-up handles: the bucket is sorted on every digit): lists bit-exact."""
+    rng = np.random.default_rng(21)
+    n = 3000
+    scene = gen.make_scene(21, n, D=128)
+    scene.means[:] = rng.uniform(-0.15, 0.15, (n, 3)).astype(np.float32)
+    scene.means[1:200:2, 2] = scene.means[0:199:2, 2]   # 100 pairs of equal depth
+    scene.means[500:800, 2] = 0.05                      # one run of 300
+    scene.scales[:] = 0.01
+    cam = gen.make_camera(96, 80)
+    g = run_forward(cam, scene)
+    d = g["depth"][g["radius"] > 0]
+    assert len(d) - len(np.unique(d)) >= 300
+    _check_lists(orc, cam, g)
+    _check_coef(orc, cam, scene, g)
