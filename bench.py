@@ -301,7 +301,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--cpu-frac", type=float, default=0.05, help="pixel fraction for the CPU oracle sample")
+    ap.add_argument("--cpu-frac", type=float, default=0.75,
+                    help="pixel fraction for the CPU oracle sample (about 10-15 s of CPU work at the default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the plain FP32 path measurement")
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward (training step) timing")
