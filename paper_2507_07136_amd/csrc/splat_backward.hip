@@ -145,24 +145,54 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
     }
 
     float S = 0.0f;  // this level's sum over later contributors of c_m e_m
-    for (int bend = maxlast; bend > 0; bend -= 64) {
-        const int b0 = max(0, bend - 64), nb = bend - b0;
-        bool keep = false;
-        unsigned id = 0;
-        float mu = 0.f, mv = 0.f, cA = 0.f, cB = 0.f, cC = 0.f, op = 0.f;
-        if (lane < nb) {
-            id = a.ids[start + b0 + lane];
-            if (id < (unsigned)a.n) {
-                const float2 m = reinterpret_cast<const float2*>(a.mean2d)[id];
-                mu = m.x;
-                mv = m.y;
-                cA = a.conic[3 * id];
-                cB = a.conic[3 * id + 1];
-                cC = a.conic[3 * id + 2];
-                op = a.opacity[id];
-                keep = may_touch(mu, mv, cA, cB, cC, op, bx0, bx1, by0, by1);
+    // Software pipeline over the 64-entry batches (walked backwards): while
+    // a batch is processed, the records and codes of the batch before it in
+    // the list are in flight.
+    struct Rc {
+        unsigned id;
+        float mu, mv, cA, cB, cC, op;
+        int ix[KMAX];
+        float w[KMAX];
+    };
+    auto fetch = [&](int bend_) {
+        Rc q;
+        q.id = 0xffffffffu;
+        q.mu = q.mv = q.cA = q.cB = q.cC = q.op = 0.0f;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            q.ix[k] = 0;
+            q.w[k] = 0.0f;
+        }
+        const int b0_ = max(0, bend_ - 64);
+        if (bend_ > 0 && lane < bend_ - b0_) {
+            q.id = a.ids[start + b0_ + lane];
+            if (q.id < (unsigned)a.n) {
+                const unsigned i = q.id;
+                const float2 m = reinterpret_cast<const float2*>(a.mean2d)[i];
+                q.mu = m.x;
+                q.mv = m.y;
+                q.cA = a.conic[3 * i];
+                q.cB = a.conic[3 * i + 1];
+                q.cC = a.conic[3 * i + 2];
+                q.op = a.opacity[i];
+                const size_t base = ((size_t)i * levels + lv) * K;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k) {
+                    q.ix[k] = k < K ? a.topk_idx[base + k] : 0;
+                    q.w[k] = k < K ? a.topk_w[base + k] : 0.0f;
+                }
             }
         }
+        return q;
+    };
+    Rc nxt = fetch(maxlast);
+    for (int bend = maxlast; bend > 0; bend -= 64) {
+        const int b0 = max(0, bend - 64), nb = bend - b0;
+        const Rc cur = nxt;
+        nxt = fetch(bend - 64);  // the batch before this one in the list
+        const unsigned id = cur.id;
+        const float mu = cur.mu, mv = cur.mv, cA = cur.cA, cB = cur.cB, cC = cur.cC, op = cur.op;
+        const bool keep = lane < nb && id < (unsigned)a.n && may_touch(mu, mv, cA, cB, cC, op, bx0, bx1, by0, by1);
         const unsigned long long kmask = __builtin_amdgcn_ballot_w64(keep);
         const int nkeep = __builtin_popcountll(kmask);
         wave_lds_order();  // single-wave workgroup: previous batch's reads done
@@ -179,15 +209,14 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
             r[R::CA] = cA;
             r[R::CA + 1] = cB;
             r[R::CA + 2] = cC;
-            const size_t base = ((size_t)id * levels + lv) * K;
             unsigned wd[R::KW];
 #pragma unroll
             for (int q = 0; q < R::KW; ++q) wd[q] = 0u;
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                const unsigned ix = k < K ? (unsigned)(a.topk_idx[base + k] & lmask) : 0u;
+                const unsigned ix = k < K ? (unsigned)(cur.ix[k] & lmask) : 0u;
                 wd[k >> 2] |= ix << (8 * (k & 3));
-                r[R::W + k] = k < K ? a.topk_w[base + k] : 0.0f;
+                r[R::W + k] = k < K ? cur.w[k] : 0.0f;
             }
 #pragma unroll
             for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + q] = wd[q];
