@@ -3,13 +3,16 @@
 
 One step = one feature-map frame of the whole forward hot path over the
 synthetic 1440x1080 scene (300k Gaussians, L=64, K=4, D=512, one level):
-project -> bin_sort -> splat_sparse (float32 accumulation, coefficient map
-stored in bf16) -> dict_decode (bf16 matrix cores, bf16 output), with the
-scene already resident in HBM.  Prints one JSON line.
+project -> bin_sort -> splat_decode (float32 compositing of the K sparse
+coefficients, then each pixel's coefficients rounded to bf16 and decoded on
+the matrix cores in the same kernel, bf16 output), with the scene already
+resident in HBM.  Prints one JSON line.
 
-Also reported: per-stage times (HIP events on the launch stream), the query
-rate (frame + relevancy), the plain FP32 path's rate, the roofline of the
-dominant kernel and the FP64 CPU oracle timed on a bounded sample.
+Also reported: the same frame in two passes (splat writing a bf16
+coefficient map, then dict_decode), per-stage times (HIP events on the launch
+stream), the query rate (frame + relevancy), the plain FP32 path's rate, the
+roofline of the dominant kernel and the FP64 CPU oracle timed on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -48,6 +51,11 @@ def algorithmic_bytes(stage, n, P, H, W, L, D, K, levels, feat_bytes, coef_bytes
         return M * L * coef_bytes + H * W * 8 + P * 4 + n * rec
     if stage == "decode":
         return M * L * coef_bytes + L * D * 4 + M * D * feat_bytes
+    if stage == "splat_decode":
+        # the splat's reads, final_T and last, the dictionary and the feature
+        # map; the coefficient map stays on chip
+        rec = 8 + 12 + 4 + levels * K * 8
+        return H * W * 8 + P * 4 + n * rec + L * D * 4 + M * D * feat_bytes
     if stage == "query":
         return M * D * feat_bytes + M * 4
     return 0
@@ -360,7 +368,7 @@ def main():
         P = p_.bin_sort(sync=True)
     log("P =", P, "pairs")
 
-    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False):
+    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False, one_pass=False):
         def mark(i):
             if ev is not None:
                 ev[i].record()
@@ -369,6 +377,10 @@ def main():
         mark(1)
         p_.bin_sort(sync=False)
         mark(2)
+        if one_pass:  # splat and bf16 decode in one kernel: the coefficient map stays on chip
+            p_.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
+            mark(3)
+            return
         p_.splat(t["opacity"], t["topk_idx"], t["topk_w"])
         mark(3)
         if fused:  # bf16 decode with the relevancy formed in its epilogue
@@ -383,33 +395,41 @@ def main():
 
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
-    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False):
+    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False, one_pass=False):
         """Wall-clock rate over `steps` uninstrumented frames, then the same
         number of frames with HIP events between the stages (per-stage
         times; these frames are not part of the rate)."""
+        kw = dict(query=query, fused=fused, one_pass=one_pass)
         for _ in range(warmup):
-            frame(p_, compute, out_dtype, query=query, fused=fused)
+            frame(p_, compute, out_dtype, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            frame(p_, compute, out_dtype, query=query, fused=fused)
+            frame(p_, compute, out_dtype, **kw)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
         for s in range(steps):
-            frame(p_, compute, out_dtype, evs[s], query=query, fused=fused)
+            frame(p_, compute, out_dtype, evs[s], **kw)
         torch.cuda.synchronize()
-        nst = 5 if (query and not fused) else 4
-        per = {stages[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
-               for i in range(nst)}
+        names = ["project", "bin_sort", "splat_decode"] if one_pass else stages[:5 if (query and not fused) else 4]
+        per = {names[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
+               for i in range(len(names))}
         return wall, per
 
-    # headline: float32 splat accumulation, bf16 coefficient map, bf16 decode (bf16 feature map)
-    wall, per = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
+    # headline: float32 splat accumulation, the coefficients rounded to bf16 and
+    # decoded on the matrix cores inside the splat (bf16 feature map)
+    wall, per = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup, one_pass=True)
     assert ls2.ls2_bin_sort_count(pipe16.workspace) == P
     fps = args.steps / wall
     ms = 1000.0 * wall / args.steps
-    log("bf16 path: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
+    log("one-pass bf16 frame: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
+    # the same feature map in two passes: bf16 coefficient map written by the
+    # splat, read back by the decode
+    twall, tper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
+    two_pass = dict(fps=round(args.steps / twall, 2), ms_per_frame=round(1000.0 * twall / args.steps, 4),
+                    stages_ms={k: round(v, 4) for k, v in tper.items()})
+    log("two-pass bf16 frame: %s" % two_pass)
 
     # query frame, two passes: decode writes the feature map, ls2_query reads it back
     qwall, qper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
@@ -455,6 +475,10 @@ def main():
         b = algorithmic_bytes(st, n, P, H, W, L, D, K, levels, fb, coef_bytes=2)
         gbs = b / (tms * 1e-3) / 1e9
         roof_all[st] = dict(ms=tms, bytes=b, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
+    for st in ("splat_decode",):
+        b = algorithmic_bytes(st, n, P, H, W, L, D, K, levels, 2)
+        gbs = b / (per[st] * 1e-3) / 1e9
+        roof_all[st] = dict(ms=per[st], bytes=b, gbs=gbs, frac_hbm=gbs / HBM_PEAK_GBS)
     dom = max(per, key=per.get)
     b = algorithmic_bytes(dom, n, P, H, W, L, D, K, levels, 2, coef_bytes=2)
     ach = b / (per[dom] * 1e-3) / 1e9
@@ -464,8 +488,8 @@ def main():
                     algorithmic_bytes=int(b))
     M = levels * H * W
     decode_flops = 2.0 * M * L * D
-    mfma = dict(decode_tflops=decode_flops / (per["decode"] * 1e-3) / 1e12,
-                decode_frac_bf16_peak=decode_flops / (per["decode"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS)
+    mfma = dict(decode_tflops=decode_flops / (tper["decode"] * 1e-3) / 1e12,
+                decode_frac_bf16_peak=decode_flops / (tper["decode"] * 1e-3) / 1e12 / BF16_PEAK_TFLOPS)
 
     train = None
     if not args.no_train:
@@ -493,12 +517,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 splat accumulation, bf16 coefficient map, bf16 decode (fp32 accumulate), bf16 feature map",
+        "dtype": "f32 splat accumulation, bf16 decode operands (fp32 accumulate), bf16 feature map",
         "data": "synthetic",
         "config": {"workload": "%s: %d Gaussians, %dx%d, L=%d, K=%d, D=%d, %d level(s), 16x16 tiles"
                                % (args.config, n, W, H, L, K, D, levels),
                    "pairs": P},
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
+        "two_pass_frame": two_pass,
         "query_fps": round(query_fps, 2),
         "query_fps_two_pass": round(query_fps_two_pass, 2),
         "decode_with_relevancy_ms": round(fqper["decode"], 4),

@@ -144,6 +144,31 @@ int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K
                      hipStream_t stream);
 
 /*
+ * ls2_splat_decode -- ls2_splat_sparse followed by Eq. 7's decode F = W S in
+ * one pass: each pixel's coefficients, once composited, are rounded to
+ * bfloat16 (nearest even) and multiplied by the bfloat16-rounded dictionary on
+ * the matrix cores (float32 accumulation), and only the feature map is
+ * written.  The features equal ls2_splat_sparse (LS2_BF16 map) followed by
+ * ls2_dict_decode (LS2_BF16 compute and output) bit for bit; final_T, last
+ * and the optional map equal ls2_splat_sparse's.
+ *
+ * In:  as ls2_splat_sparse; dict [L,D] f32.
+ * Out: feat [levels,H,W,D] bfloat16, 16-byte aligned; coef [levels,H,W,L]
+ *      bfloat16 (optional: NULL skips the map), 16-byte aligned; final_T,
+ *      last (optional) as ls2_splat_sparse.
+ * workspace: at least ls2_splat_decode_workspace() bytes (the dictionary in
+ *      bfloat16, repacked by the call), 16-byte aligned, owned by the caller,
+ *      not shared between concurrent calls.
+ * Supported: as ls2_splat_sparse, and D a multiple of 64 up to 1024.
+ */
+int ls2_splat_decode_workspace(int32_t L, int32_t D, size_t* bytes);
+int ls2_splat_decode(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L, int32_t D,
+                     const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                     const float* conic, const float* opacity, const int32_t* topk_idx,
+                     const float* topk_w, const float* dict, void* feat, void* coef, float* final_T,
+                     int32_t* last, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * ls2_splat_dense -- the dense form of the coefficient splatting: every
  * Gaussian blends all L coefficients of each level (the rendering that
  * Section 3.4 avoids by blending only the K non-zero ones; Table 9 times both).

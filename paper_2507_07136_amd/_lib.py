@@ -51,6 +51,8 @@ def _load():
                          ctypes.c_int),
         "ls2_bin_sort_count": ([P, ctypes.POINTER(ctypes.c_int64), P], ctypes.c_int),
         "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, i32, P, P, P], ctypes.c_int),
+        "ls2_splat_decode_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_splat_decode": ([cam, i32, i32, i32, i32, i32] + [P] * 13 + [ctypes.c_size_t, P], ctypes.c_int),
         "ls2_dict_decode": ([i64, i32, i32, P, i32, P, i32, i32, P, P], ctypes.c_int),
         "ls2_dict_decode_query": ([i64, i32, i32, P, i32, P, P, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_splat_dense": ([cam, i32, i32, i32, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -201,6 +203,32 @@ def ls2_splat_sparse(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity
                                _ptr(final_T, f32, "final_T", HW, allow_none=True),
                                _ptr(last, i32, "last", HW, allow_none=True), _stream(stream))
     _check("ls2_splat_sparse", st)
+
+
+def ls2_splat_decode_workspace(L, D) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_splat_decode_workspace", _lib.ls2_splat_decode_workspace(int(L), int(D), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_splat_decode(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, dictionary, feat,
+                     workspace, coef=None, final_T=None, last=None, stream=None):
+    n = opacity.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    HW = c.width * c.height
+    D = dictionary.shape[1]
+    f32, i32, b16 = torch.float32, torch.int32, torch.bfloat16
+    st = _lib.ls2_splat_decode(ctypes.byref(c), n, int(levels), int(K), int(L), int(D),
+                               _ptr(tile_ranges, i32, "tile_ranges"), _ptr(ids, i32, "ids"),
+                               _ptr(mean2d, f32, "mean2d", 2 * n), _ptr(conic, f32, "conic", 3 * n),
+                               _ptr(opacity, f32, "opacity", n), _ptr(topk_idx, i32, "topk_idx", n * levels * K),
+                               _ptr(topk_w, f32, "topk_w", n * levels * K), _ptr(dictionary, f32, "dict", L * D),
+                               _ptr(feat, b16, "feat", levels * HW * D),
+                               _ptr(coef, b16, "coef", levels * HW * L, allow_none=True),
+                               _ptr(final_T, f32, "final_T", HW, allow_none=True),
+                               _ptr(last, i32, "last", HW, allow_none=True),
+                               _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
+    _check("ls2_splat_decode", st)
 
 
 def ls2_splat_dense(cam, levels, L, tile_ranges, ids, mean2d, conic, opacity, weights, coef, final_T=None, last=None,

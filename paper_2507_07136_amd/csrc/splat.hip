@@ -22,11 +22,26 @@
 //     the blend runs one loop per vector with a wave-uniform trip count: one
 //     indexed fused multiply-add per coefficient.  With one level per wave
 //     the L accumulators fit in registers at 4 waves per SIMD.
+//
+// ls2_splat_decode runs the same kernel with Eq. 7's decode as its tail:
+// once a wave's 64 pixels are final, their coefficients (rounded to bf16)
+// are already spread one pixel per lane, which is what the matrix cores take
+// as the B operand of F^T = S^T W^T, after one v_permlane32_swap per register
+// (below).  The wave then writes its pixels' D features directly, so the
+// coefficient map never travels through HBM, and the feature-map stores of
+// finished waves overlap the latency-bound blending of the others.
 #include "splat_common.h"
 
 namespace ls2 {
 
 typedef float v32f __attribute__((ext_vector_type(32)));
+typedef __bf16 bf16x8s __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
+typedef float f32x16s __attribute__((ext_vector_type(16)));
+typedef float f32x4s __attribute__((ext_vector_type(4)));
+
+// Coefficient output of the splat kernel.
+enum SplatOut { kOutF32 = 0, kOutBF16 = 1, kOutDecode = 2 };
 
 struct SplatArgs {
     CamK cam;
@@ -38,10 +53,18 @@ struct SplatArgs {
     const float* opacity;
     const int* topk_idx;
     const float* topk_w;
-    void* coef;  // float32, or bfloat16 (round to nearest even) when CB
+    void* coef;  // float32, or bfloat16 (round to nearest even); optional with kOutDecode
     float* final_T;
     int* last;
+    // kOutDecode: packed bfloat16 dictionary (k_dict_pack) and the feature map
+    int D = 0;
+    const unsigned short* dictp = nullptr;
+    unsigned short* feat = nullptr;
 };
+
+// Feature-map bytes each wave stages at a time in the decode tail: 64 pixels
+// x 64 features in bfloat16 (one 128-byte line per pixel).
+constexpr int kDecStageBytes = 64 * 64 * 2;
 
 // Staged record (dwords): u, v, A2, B2, C2, o, list position, index words,
 // group counts, weights.  The K coefficients are stored grouped by
@@ -61,12 +84,106 @@ struct Rec {
     static constexpr int STRIDE = (RAW + 3) & ~3;  // 16-byte aligned records
 };
 
+// Decode tail of one wave: F = W S (Eq. 7) for the wave's 64 pixels (lane p
+// holds pixel p's L accumulators), written as bfloat16 rows of D features.
+//
+// MFMA 32x32x16 bf16 computes the transposed tile F^T[32 features x 32
+// pixels] with A = S^T (lane (c, h): feature c, k = 16 ks + 8 h + [0,8)) and
+// B = W^T (lane (c, h): pixel c of the 32-pixel tile, the same k).  Lane p
+// owns pixel p; with X = its k-range 16 ks + [0,8) and Y = 16 ks + [8,16),
+// v_permlane32_swap(X, Y) leaves exactly the B operand of pixel tile 0
+// (lanes 0-31 keep X, lanes 32-63 receive Y of lane p - 32) in X and that of
+// pixel tile 1 (lanes 0-31 receive X of lane p + 32, lanes 32-63 keep Y) in
+// Y.  The k-steps accumulate in the same order and with the same operands as
+// ls2_dict_decode's bf16 kernel, so the features are bit-identical to
+// splatting a bfloat16 map and decoding it.  Every lane must be active;
+// lanes outside the image hold zero coefficients and store nothing.
+template <int NV>
+__device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc)[NV], char* st, int lane, int lv0,
+                                            int qx0, int qy0) {
+    constexpr int KS = 2 * NV;  // k-steps of 16
+    const int col = lane & 31, half = lane >> 5;
+    bf16x8s wb[2][KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int h = ks >> 1, jb = (ks & 1) * 16;
+        u32x4s x, y;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned lo = bf16_pair(acc[h][jb + 2 * q], acc[h][jb + 2 * q + 1]);
+            const unsigned hi = bf16_pair(acc[h][jb + 8 + 2 * q], acc[h][jb + 9 + 2 * q]);
+            const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+            x[q] = r[0];
+            y[q] = r[1];
+        }
+        wb[0][ks] = __builtin_bit_cast(bf16x8s, x);
+        wb[1][ks] = __builtin_bit_cast(bf16x8s, y);
+    }
+    const int D = a.D, nft = D / 32;
+    // A operands of feature tile ft: the packed dictionary holds, for feature
+    // f and lane half h, the KS 8-element k-runs contiguously (16 KS bytes)
+    auto load_a = [&](int ft, u32x4s (&o)[KS]) {
+        const u32x4s* src = reinterpret_cast<const u32x4s*>(a.dictp + ((size_t)(ft * 32 + col) * 2 + half) * KS * 8);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) o[ks] = src[ks];
+    };
+    u32x4s sa[KS], sn[KS];
+    load_a(0, sa);
+    const int W = a.cam.W, H = a.cam.H;
+    // store phase: lane (sp, su) writes 16-byte unit su of the pixel in column
+    // sp of each quadrant row; rows are W D elements apart
+    const int sp = lane >> 3, su = lane & 7;
+    const bool xin = qx0 + sp < W;
+    const size_t rstride = (size_t)W * D;
+    unsigned short* fbase = a.feat + ((size_t)lv0 * H + qy0) * rstride + (size_t)(qx0 + sp) * D + su * 8;
+    for (int c = 0; c < D / 64; ++c) {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int ft = 2 * c + cc;
+            load_a(ft + 1 < nft ? ft + 1 : ft, sn);
+            f32x16s f0 = {}, f1 = {};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const bf16x8s av = __builtin_bit_cast(bf16x8s, sa[ks]);
+                f0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[0][ks], f0, 0, 0, 0);
+                f1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[1][ks], f1, 0, 0, 0);
+            }
+            // lane (c, h) holds pixel 32 t + c, features 32 ft + 8 g + 4 h + [0,4):
+            // 16-byte unit 4 cc + g of the pixel's 128-byte chunk line, stored
+            // at unit (4 cc + g) ^ (pixel & 7) to spread the LDS banks
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int u = ((4 * cc + g) ^ (col & 7)) * 16 + half * 8;
+                *reinterpret_cast<uint2*>(st + col * 128 + u) =
+                    make_uint2(bf16_pair(f0[4 * g], f0[4 * g + 1]), bf16_pair(f0[4 * g + 2], f0[4 * g + 3]));
+                *reinterpret_cast<uint2*>(st + (32 + col) * 128 + u) =
+                    make_uint2(bf16_pair(f1[4 * g], f1[4 * g + 1]), bf16_pair(f1[4 * g + 2], f1[4 * g + 3]));
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) sa[ks] = sn[ks];
+        }
+        wave_lds_order();
+        // one quadrant row (8 pixels x 128 bytes) per store instruction
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int p = 8 * i + sp;  // p & 7 == sp
+            const f32x4s v = *reinterpret_cast<const f32x4s*>(st + p * 128 + ((su ^ sp) * 16));
+            if (xin && qy0 + i < H)
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4s*>(fbase + (size_t)i * rstride + c * 64));
+        }
+        wave_lds_order();  // the next chunk overwrites the staged lines
+    }
+}
+
 // EXACT: K == KMAX is known at compile time.  NV = L / 32 accumulator vectors.
-// CB: the coefficient map is written in bfloat16.
-template <int NV, int KMAX, bool EXACT, bool CB>
-__global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
+// OUT: kOutF32 / kOutBF16 write the coefficient map; kOutDecode writes the
+// feature map (and the bfloat16 coefficient map if a.coef is set).
+template <int NV, int KMAX, bool EXACT, int OUT>
+__global__ __launch_bounds__(64, OUT != kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
     using R = Rec<KMAX>;
-    __shared__ float4 stage4[64 * R::STRIDE / 4];
+    constexpr int REC4 = 64 * R::STRIDE / 4;
+    constexpr int STAGE4 = OUT == kOutDecode && kDecStageBytes / 16 > REC4 ? kDecStageBytes / 16 : REC4;
+    __shared__ float4 stage4[STAGE4];
     float* stage = reinterpret_cast<float*>(stage4);
 
     const CamK& cam = a.cam;
@@ -266,50 +383,88 @@ __global__ __launch_bounds__(64) void k_splat_sparse(SplatArgs a) {
         }
     }
 
-    if (!inside) return;
-    const size_t HW = (size_t)cam.W * cam.H;
-    const size_t pix = (size_t)py * cam.W + px;
-    const size_t row = ((size_t)lv0 * HW + pix) * (size_t)(NV * 32);
-    if (CB) {
-        uint4* dst = reinterpret_cast<uint4*>(static_cast<unsigned short*>(a.coef) + row);
+    // the pixel's outputs first: the decode tail below then holds no
+    // accumulator beyond its bfloat16 operands
+    if (inside) {
+        const size_t HW = (size_t)cam.W * cam.H;
+        const size_t pix = (size_t)py * cam.W + px;
+        const size_t row = ((size_t)lv0 * HW + pix) * (size_t)(NV * 32);
+        if (OUT == kOutDecode && !a.coef) {
+            // feature map only
+        } else if (OUT != kOutF32) {
+            uint4* dst = reinterpret_cast<uint4*>(static_cast<unsigned short*>(a.coef) + row);
 #pragma unroll
-        for (int h = 0; h < NV; ++h)
+            for (int h = 0; h < NV; ++h)
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                dst[h * 4 + q] = make_uint4(
-                    bf16_pair(acc[h][8 * q], acc[h][8 * q + 1]), bf16_pair(acc[h][8 * q + 2], acc[h][8 * q + 3]),
-                    bf16_pair(acc[h][8 * q + 4], acc[h][8 * q + 5]), bf16_pair(acc[h][8 * q + 6], acc[h][8 * q + 7]));
-    } else {
-        float4* dst = reinterpret_cast<float4*>(static_cast<float*>(a.coef) + row);
+                for (int q = 0; q < 4; ++q)
+                    dst[h * 4 + q] = make_uint4(
+                        bf16_pair(acc[h][8 * q], acc[h][8 * q + 1]), bf16_pair(acc[h][8 * q + 2], acc[h][8 * q + 3]),
+                        bf16_pair(acc[h][8 * q + 4], acc[h][8 * q + 5]),
+                        bf16_pair(acc[h][8 * q + 6], acc[h][8 * q + 7]));
+        } else {
+            float4* dst = reinterpret_cast<float4*>(static_cast<float*>(a.coef) + row);
 #pragma unroll
-        for (int h = 0; h < NV; ++h)
+            for (int h = 0; h < NV; ++h)
 #pragma unroll
-            for (int q = 0; q < 8; ++q)
-                dst[h * 8 + q] = make_float4(acc[h][4 * q], acc[h][4 * q + 1], acc[h][4 * q + 2], acc[h][4 * q + 3]);
+                for (int q = 0; q < 8; ++q)
+                    dst[h * 8 + q] =
+                        make_float4(acc[h][4 * q], acc[h][4 * q + 1], acc[h][4 * q + 2], acc[h][4 * q + 3]);
+        }
+        if (lv0 == 0) {  // every level wave of the quadrant computes the same T and last
+            if (a.final_T) a.final_T[pix] = T;
+            if (a.last) a.last[pix] = last;
+        }
     }
-    if (lv0 == 0) {  // every level wave of the quadrant computes the same T and last
-        if (a.final_T) a.final_T[pix] = T;
-        if (a.last) a.last[pix] = last;
+    if (OUT == kOutDecode) {
+        wave_lds_order();  // the record reads of the last batch are done
+        decode_tail<NV>(a, acc, reinterpret_cast<char*>(stage4), lane, lv0, qx0, qy0);
     }
 }
 
+template <int NV, int KMAX, bool EXACT>
+static void launch_splat_out(const SplatArgs& a, int out, dim3 grid, hipStream_t stream) {
+    if (out == kOutDecode)
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, EXACT, kOutDecode>), grid, dim3(64), 0, stream, a);
+    else if (out == kOutBF16)
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, EXACT, kOutBF16>), grid, dim3(64), 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, EXACT, kOutF32>), grid, dim3(64), 0, stream, a);
+}
+
 template <int NV, int KMAX>
-static int launch_splat(const SplatArgs& a, bool cb, hipStream_t stream) {
+static int launch_splat(const SplatArgs& a, int out, hipStream_t stream) {
     const int ntiles = a.cam.tx * a.cam.ty;
-    const int grid = round_up8(ntiles * 4 * a.levels);
-    if (a.K == KMAX) {
-        if (cb)
-            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, true, true>), dim3(grid), dim3(64), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, true, false>), dim3(grid), dim3(64), 0, stream, a);
-    } else {
-        if (cb)
-            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, false, true>), dim3(grid), dim3(64), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, false, false>), dim3(grid), dim3(64), 0, stream, a);
-    }
+    const dim3 grid((unsigned)round_up8(ntiles * 4 * a.levels));
+    if (a.K == KMAX)
+        launch_splat_out<NV, KMAX, true>(a, out, grid, stream);
+    else
+        launch_splat_out<NV, KMAX, false>(a, out, grid, stream);
     LS2_LAUNCH_CHECK();
     return LS2_OK;
+}
+
+template <int NV>
+static int launch_splat_k(const SplatArgs& a, int out, hipStream_t stream) {
+    return a.K > 4 ? launch_splat<NV, 8>(a, out, stream) : launch_splat<NV, 4>(a, out, stream);
+}
+
+static int launch_splat_l(const SplatArgs& a, int out, hipStream_t stream) {
+    if (a.L == 32) return launch_splat_k<1>(a, out, stream);
+    if (a.L == 64) return launch_splat_k<2>(a, out, stream);
+    return launch_splat_k<4>(a, out, stream);
+}
+
+// Dictionary [L,D] float32 -> the decode tail's A operands in bfloat16
+// (nearest even): element ((f 2 + h) KS + ks) 8 + e = S[16 ks + 8 h + e][f].
+__global__ __launch_bounds__(256) void k_dict_pack(int L, int D, const float* __restrict__ dict,
+                                                   unsigned short* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L * D) return;
+    const int KS = L / 16;
+    const int e = i & 7, r = i >> 3;
+    const int ks = r % KS, fh = r / KS;
+    const int h = fh & 1, f = fh >> 1;
+    out[i] = __builtin_bit_cast(unsigned short, (__bf16)dict[(size_t)(16 * ks + 8 * h + e) * D + f]);
 }
 
 }  // namespace ls2
@@ -343,8 +498,49 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
     a.coef = coef;
     a.final_T = final_T;
     a.last = last;
-    const bool k8 = K > 4, cb = coef_dtype == LS2_BF16;
-    if (L == 32) return k8 ? launch_splat<1, 8>(a, cb, stream) : launch_splat<1, 4>(a, cb, stream);
-    if (L == 64) return k8 ? launch_splat<2, 8>(a, cb, stream) : launch_splat<2, 4>(a, cb, stream);
-    return k8 ? launch_splat<4, 8>(a, cb, stream) : launch_splat<4, 4>(a, cb, stream);
+    return launch_splat_l(a, coef_dtype == LS2_BF16 ? kOutBF16 : kOutF32, stream);
+}
+
+extern "C" int ls2_splat_decode_workspace(int32_t L, int32_t D, size_t* bytes) {
+    if (!bytes || L < 1 || D < 1) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
+    *bytes = (size_t)L * D * 2;
+    return LS2_OK;
+}
+
+extern "C" int ls2_splat_decode(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L, int32_t D,
+                                const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                const float* conic, const float* opacity, const int32_t* topk_idx,
+                                const float* topk_w, const float* dict, void* feat, void* coef, float* final_T,
+                                int32_t* last, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!cam_valid(cam) || n < 0 || levels < 1 || K < 1 || L < 1 || K > L || D < 1) return LS2_ERR_ARG;
+    if (!tile_ranges || !feat || !dict || !workspace) return LS2_ERR_ARG;
+    if (!aligned16(feat) || !aligned16(coef) || !aligned16(workspace)) return LS2_ERR_ARG;
+    if (n > 0 && (!ids || !mean2d || !conic || !opacity || !topk_idx || !topk_w)) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
+    if (D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
+    if (workspace_bytes < (size_t)L * D * 2) return LS2_ERR_ARG;
+    unsigned short* dictp = static_cast<unsigned short*>(workspace);
+    hipLaunchKernelGGL(k_dict_pack, dim3((unsigned)((L * D + 255) / 256)), dim3(256), 0, stream, L, D, dict, dictp);
+    LS2_LAUNCH_CHECK();
+    SplatArgs a;
+    a.cam = cam_k(*cam);
+    a.n = n;
+    a.levels = levels;
+    a.K = K;
+    a.L = L;
+    a.ranges = tile_ranges;
+    a.ids = ids;
+    a.mean2d = mean2d;
+    a.conic = conic;
+    a.opacity = opacity;
+    a.topk_idx = topk_idx;
+    a.topk_w = topk_w;
+    a.coef = coef;
+    a.final_T = final_T;
+    a.last = last;
+    a.D = D;
+    a.dictp = dictp;
+    a.feat = static_cast<unsigned short*>(feat);
+    return launch_splat_l(a, kOutDecode, stream);
 }

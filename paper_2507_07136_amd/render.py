@@ -80,6 +80,25 @@ class Pipeline:
         _lib.ls2_splat_sparse(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids, self.mean2d,
                               self.conic, opacity, topk_idx, topk_w, self.coef, self.final_T, self.last)
 
+    def splat_decode(self, opacity, topk_idx, topk_w, dictionary, keep_coef: bool = False):
+        """Splat and bf16 decode in one pass (the coefficient map is written
+        only with keep_coef, in bfloat16): the bf16 feature map of
+        splat() (bf16 map) + decode(), bit for bit."""
+        if self.feat is None or self.feat.dtype != torch.bfloat16:
+            self.feat = torch.empty((self.levels, self.H, self.W, self.D), dtype=torch.bfloat16, device=self.device)
+        if getattr(self, "_sd_ws", None) is None:
+            self._sd_ws = torch.empty((_lib.ls2_splat_decode_workspace(self.L, self.D),), dtype=torch.uint8,
+                                      device=self.device)
+        coef = None
+        if keep_coef:
+            if self.coef.dtype != torch.bfloat16:
+                raise ValueError("splat_decode keeps a bfloat16 map (Pipeline(coef_dtype=torch.bfloat16))")
+            coef = self.coef
+        _lib.ls2_splat_decode(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids, self.mean2d,
+                              self.conic, opacity, topk_idx, topk_w, dictionary, self.feat, self._sd_ws, coef,
+                              self.final_T, self.last)
+        return self.feat
+
     def splat_dense(self, opacity, weights):
         """Dense form (all L coefficients per Gaussian) into the same buffers."""
         _lib.ls2_splat_dense(self.cam, self.levels, self.L, self.tile_ranges, self.ids, self.mean2d, self.conic,
@@ -131,10 +150,15 @@ class Pipeline:
         return self.relevancy
 
     def feature_map(self, means, scales, quats, opacity, topk_idx, topk_w, dictionary, compute=LS2_BF16,
-                    out_dtype=torch.bfloat16, sync: bool = True):
-        """One feature-map frame: project, bin and sort, splat, decode."""
+                    out_dtype=torch.bfloat16, sync: bool = True, fused: bool = False):
+        """One feature-map frame: project, bin and sort, splat, decode (with
+        fused=True: bf16 compute and output, splat and decode in one pass)."""
         self.project(means, scales, quats)
         self.bin_sort(sync=sync)
+        if fused:
+            if compute != LS2_BF16 or out_dtype != torch.bfloat16:
+                raise ValueError("the fused frame computes and writes bfloat16")
+            return self.splat_decode(opacity, topk_idx, topk_w, dictionary)
         self.splat(opacity, topk_idx, topk_w)
         return self.decode(dictionary, compute, out_dtype)
 

@@ -179,3 +179,34 @@ def test_decode_query_validation_without_device(L):
     assert L.ls2_dict_decode_query(10, 64, 512, V(16), 2, V(16), None, V(16), 4, V(16), f1, V(16), None) == -1
     assert L.ls2_dict_decode_query(10, 64, 512, V(16), 0, V(16), V(8), V(16), 4, V(16), f1, V(16), None) == -1
     assert L.ls2_dict_decode_query(0, 64, 512, V(16), 0, V(16), None, V(16), 4, V(16), f1, V(16), None) == 0
+
+
+def test_splat_decode_validation_without_device(L):
+    c = _cam()
+    V = ctypes.c_void_p
+    b = ctypes.c_size_t(0)
+    assert L.ls2_splat_decode_workspace(64, 512, ctypes.byref(b)) == 0 and b.value == 64 * 512 * 2
+    assert L.ls2_splat_decode_workspace(64, 500, ctypes.byref(b)) == -3
+    assert L.ls2_splat_decode_workspace(48, 512, ctypes.byref(b)) == -3
+    assert L.ls2_splat_decode_workspace(64, 512, None) == -1
+    ws = 64 * 512 * 2
+    inp = [V(16)] * 7                     # tile_ranges .. topk_w
+
+    def call(n=10, levels=1, K=4, Lc=64, D=512, dct=V(16), feat=V(16), coef=None, wsp=V(16), wsb=ws):
+        return L.ls2_splat_decode(ctypes.byref(c), n, levels, K, Lc, D, *inp, dct, feat, coef, None, None, wsp,
+                                  wsb, None)
+    # every case is rejected before any launch
+    assert call(D=500) == -3              # D not a multiple of 64
+    assert call(D=2048, wsb=64 * 2048 * 2) == -3
+    assert call(Lc=48) == -3
+    assert call(levels=3, Lc=128) == -3
+    assert call(K=9) == -3
+    assert call(K=80) == -1               # K > L
+    assert call(feat=None) == -1
+    assert call(feat=V(24)) == -1         # misaligned feature map
+    assert call(coef=V(24)) == -1         # misaligned optional map
+    assert call(dct=None) == -1
+    assert call(wsp=None) == -1
+    assert call(wsp=V(24)) == -1
+    assert call(wsb=ws - 1) == -1         # workspace too small
+    assert call(n=-1) == -1

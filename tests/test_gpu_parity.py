@@ -404,6 +404,58 @@ def test_bf16_coefficient_map(orc, L, K, levels):
         p16.decode(t["dictionary"], ls2.LS2_F32, torch.float32)
 
 
+@pytest.mark.parametrize("L,K,levels,D,w,h", [(64, 4, 1, 512, 120, 90), (32, 8, 3, 256, 100, 76),
+                                               (128, 4, 1, 384, 72, 56), (64, 8, 2, 128, 33, 47),
+                                               (64, 3, 1, 1024, 64, 48)])
+def test_splat_decode_fused(orc, L, K, levels, D, w, h):
+    """The one-pass splat + decode writes the feature map of splat (bf16 map)
+    followed by the bf16 decode bit for bit, and the same optional map,
+    final_T and last; against the FP64 oracle (its compositing of the GPU's
+    lists, exact decode) every clean pixel meets the bf16 decode bar.  Ragged
+    image sizes leave partial quadrants at the right and bottom edges."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(505 + L + K + levels + D, 3000, w, h, L=L, K=K, levels=levels, D=D)
+    g = run_forward(cam, scene)
+    t = g["t"]
+    p16 = ls2.Pipeline(cam, scene.n, levels=levels, K=K, L=L, D=D, coef_dtype=torch.bfloat16)
+    p16.project(t["means"], t["scales"], t["quats"])
+    p16.bin_sort(sync=True)
+    p16.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+    ref_coef = p16.coef.clone()
+    ref_T, ref_last = p16.final_T.clone(), p16.last.clone()
+    ref_feat = p16.decode(t["dictionary"], ls2.LS2_BF16, torch.bfloat16).clone()
+    # feature map only: stale values everywhere first
+    p16.feat.fill_(7.0)
+    p16.final_T.fill_(-1.0)
+    p16.last.fill_(-5)
+    feat = p16.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
+    torch.cuda.synchronize()
+    assert torch.equal(feat, ref_feat)
+    assert torch.equal(p16.final_T, ref_T) and torch.equal(p16.last, ref_last)
+    # with the map kept
+    p16.coef.fill_(3.0)
+    p16.feat.fill_(-2.0)
+    p16.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"], keep_coef=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p16.coef, ref_coef)
+    assert torch.equal(p16.feat, ref_feat)
+    # against the oracle
+    coef64, fT, last, margin, margin_T = oracle_composite_from_gpu(orc, cam, scene, g)
+    ok = _ok(margin, margin_T)
+    exact = orc.decode(coef64.reshape(-1, L), scene.dictionary).reshape(levels, h, w, D)
+    got = feat.float().cpu().numpy()
+    nrm = np.linalg.norm(exact, axis=3)
+    rel = np.linalg.norm(got - exact, axis=3) / np.maximum(nrm, 1e-6)
+    keep = ok[None] & (nrm > 1e-3)
+    print("fused splat+decode: rel err max %.3e over %d pixel-levels, near-threshold px %d"
+          % (rel[keep].max(), keep.sum(), (~ok).sum()))
+    assert keep.sum() > 0.5 * keep.size
+    assert rel[keep].max() <= 1e-2
+    # pixels nothing reached decode to exact zeros
+    empty = (nrm == 0.0) & ok[None]
+    assert np.all(got[empty] == 0.0)
+
+
 @pytest.mark.parametrize("L,D,n_neg,coef_bf16,keep", [(64, 512, 4, True, True), (64, 512, 4, False, False),
                                                        (32, 256, 1, False, True), (128, 384, 8, True, False),
                                                        (64, 128, 2, False, True)])
