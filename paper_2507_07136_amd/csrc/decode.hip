@@ -40,10 +40,7 @@ struct DecodeArgs {
     long long nblocks;
 };
 
-__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) {
-    __bf16 x = (__bf16)a, y = (__bf16)b;
-    return (unsigned)__builtin_bit_cast(unsigned short, x) | ((unsigned)__builtin_bit_cast(unsigned short, y) << 16);
-}
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b) { return bf16_pair(a, b); }
 
 // Coefficient loads of one 32-pixel block (zeros past the end), issued ahead
 // of use so they overlap the previous block's work.

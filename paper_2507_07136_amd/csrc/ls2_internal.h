@@ -113,10 +113,13 @@ __device__ __forceinline__ float lerf_relevancy(const float* dots, float fnorm2,
     return 1.0f / (1.0f + expf(-tau * (sq - smax)));
 }
 
-// Two floats rounded to bfloat16 (nearest even), packed low / high.
+// Two floats rounded to bfloat16 (nearest even), packed low / high: one
+// v_cvt_pk_bf16_f32 (the same rounding as converting each on its own).
+typedef __bf16 bf16x2_i __attribute__((ext_vector_type(2)));
+typedef float f32x2_i __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned bf16_pair(float a, float b) {
-    const __bf16 x = (__bf16)a, y = (__bf16)b;
-    return (unsigned)__builtin_bit_cast(unsigned short, x) | ((unsigned)__builtin_bit_cast(unsigned short, y) << 16);
+    const f32x2_i v = {a, b};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_i));
 }
 
 // Host-side check of the 16-byte alignment that float4 accesses need (a null

@@ -98,11 +98,29 @@ struct Rec {
 // ls2_dict_decode's bf16 kernel, so the features are bit-identical to
 // splatting a bfloat16 map and decoding it.  Every lane must be active;
 // lanes outside the image hold zero coefficients and store nothing.
-template <int NV>
+//
+// dsrc: the packed dictionary (k_dict_pack), in HBM or in LDS.  The wave
+// stages CF features of its 64 pixels at a time in st (64 CF 2 bytes) and
+// writes them as CF-feature runs of each pixel.
+template <int NV, int CF>
 __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc)[NV], char* st, int lane, int lv0,
-                                            int qx0, int qy0) {
-    constexpr int KS = 2 * NV;  // k-steps of 16
+                                            int qx0, int qy0, const unsigned short* dsrc) {
+    constexpr int KS = 2 * NV;   // k-steps of 16
+    constexpr int U = CF / 8;    // 16-byte units per pixel and chunk
+    constexpr int FT = CF / 32;  // feature tiles per chunk
+    constexpr int PPI = 64 / U;  // pixels per store instruction
+    static_assert(CF == 32 || CF == 64, "decode_tail: 32- or 64-feature chunks");
     const int col = lane & 31, half = lane >> 5;
+    // A operand of lane l at k-step ks of feature tile ft: 16-byte unit
+    // (ft KS + ks) 64 + l of the packed dictionary; the first tile's loads
+    // are issued before the operand conversion
+    const u32x4s* dv = reinterpret_cast<const u32x4s*>(dsrc) + lane;
+    auto load_a = [&](int ft, u32x4s (&o)[KS]) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) o[ks] = dv[(ft * KS + ks) * 64];
+    };
+    u32x4s sa[KS], sn[KS];
+    load_a(0, sa);
     bf16x8s wb[2][KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -120,26 +138,18 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
         wb[1][ks] = __builtin_bit_cast(bf16x8s, y);
     }
     const int D = a.D, nft = D / 32;
-    // A operands of feature tile ft: the packed dictionary holds, for feature
-    // f and lane half h, the KS 8-element k-runs contiguously (16 KS bytes)
-    auto load_a = [&](int ft, u32x4s (&o)[KS]) {
-        const u32x4s* src = reinterpret_cast<const u32x4s*>(a.dictp + ((size_t)(ft * 32 + col) * 2 + half) * KS * 8);
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) o[ks] = src[ks];
-    };
-    u32x4s sa[KS], sn[KS];
-    load_a(0, sa);
     const int W = a.cam.W, H = a.cam.H;
-    // store phase: lane (sp, su) writes 16-byte unit su of the pixel in column
-    // sp of each quadrant row; rows are W D elements apart
-    const int sp = lane >> 3, su = lane & 7;
-    const bool xin = qx0 + sp < W;
+    // store phase: instruction i covers pixels PPI i + pi (quadrant rows
+    // (8 / U) i + yo, column xo), lane writing 16-byte unit su of its pixel
+    const int pi = lane / U, su = lane % U;
+    const int xo = pi & 7, yo = pi >> 3;
+    const bool xin = qx0 + xo < W;
     const size_t rstride = (size_t)W * D;
-    unsigned short* fbase = a.feat + ((size_t)lv0 * H + qy0) * rstride + (size_t)(qx0 + sp) * D + su * 8;
-    for (int c = 0; c < D / 64; ++c) {
+    unsigned short* fbase = a.feat + ((size_t)lv0 * H + qy0 + yo) * rstride + (size_t)(qx0 + xo) * D + su * 8;
+    for (int c = 0; c < D / CF; ++c) {
 #pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-            const int ft = 2 * c + cc;
+        for (int cc = 0; cc < FT; ++cc) {
+            const int ft = FT * c + cc;
             load_a(ft + 1 < nft ? ft + 1 : ft, sn);
             f32x16s f0 = {}, f1 = {};
 #pragma unroll
@@ -149,27 +159,27 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
                 f1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[1][ks], f1, 0, 0, 0);
             }
             // lane (c, h) holds pixel 32 t + c, features 32 ft + 8 g + 4 h + [0,4):
-            // 16-byte unit 4 cc + g of the pixel's 128-byte chunk line, stored
-            // at unit (4 cc + g) ^ (pixel & 7) to spread the LDS banks
+            // 16-byte unit 4 cc + g of the pixel's chunk, stored at unit
+            // (4 cc + g) ^ (pixel % U) to spread the LDS banks
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int u = ((4 * cc + g) ^ (col & 7)) * 16 + half * 8;
-                *reinterpret_cast<uint2*>(st + col * 128 + u) =
+                const int u = ((4 * cc + g) ^ (col & (U - 1))) * 16 + half * 8;
+                *reinterpret_cast<uint2*>(st + col * (U * 16) + u) =
                     make_uint2(bf16_pair(f0[4 * g], f0[4 * g + 1]), bf16_pair(f0[4 * g + 2], f0[4 * g + 3]));
-                *reinterpret_cast<uint2*>(st + (32 + col) * 128 + u) =
+                *reinterpret_cast<uint2*>(st + (32 + col) * (U * 16) + u) =
                     make_uint2(bf16_pair(f1[4 * g], f1[4 * g + 1]), bf16_pair(f1[4 * g + 2], f1[4 * g + 3]));
             }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) sa[ks] = sn[ks];
         }
         wave_lds_order();
-        // one quadrant row (8 pixels x 128 bytes) per store instruction
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = 8 * i + sp;  // p & 7 == sp
-            const f32x4s v = *reinterpret_cast<const f32x4s*>(st + p * 128 + ((su ^ sp) * 16));
-            if (xin && qy0 + i < H)
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4s*>(fbase + (size_t)i * rstride + c * 64));
+        for (int i = 0; i < U; ++i) {
+            const int p = PPI * i + pi;  // p % U == pi % U
+            const f32x4s v = *reinterpret_cast<const f32x4s*>(st + p * (U * 16) + ((su ^ (pi & (U - 1))) * 16));
+            if (xin && qy0 + (8 / U) * i + yo < H)
+                __builtin_nontemporal_store(
+                    v, reinterpret_cast<f32x4s*>(fbase + (size_t)((8 / U) * i) * rstride + c * CF));
         }
         wave_lds_order();  // the next chunk overwrites the staged lines
     }
@@ -178,21 +188,15 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
 // EXACT: K == KMAX is known at compile time.  NV = L / 32 accumulator vectors.
 // OUT: kOutF32 / kOutBF16 write the coefficient map; kOutDecode writes the
 // feature map (and the bfloat16 coefficient map if a.coef is set).
-template <int NV, int KMAX, bool EXACT, int OUT>
-__global__ __launch_bounds__(64, OUT != kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
+// One work item: the wave's (quadrant `slot & 3`, level `slot >> 2`) of
+// `tile`, one pixel per lane.  stage: the wave's LDS (records, and the decode
+// tail's staging of CF-feature chunks); dsrc: the packed dictionary.
+template <int NV, int KMAX, bool EXACT, int OUT, int CF>
+__device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slot, int lane, float* stage,
+                                           const unsigned short* dsrc) {
     using R = Rec<KMAX>;
-    constexpr int REC4 = 64 * R::STRIDE / 4;
-    constexpr int STAGE4 = OUT == kOutDecode && kDecStageBytes / 16 > REC4 ? kDecStageBytes / 16 : REC4;
-    __shared__ float4 stage4[STAGE4];
-    float* stage = reinterpret_cast<float*>(stage4);
-
     const CamK& cam = a.cam;
-    const int ntiles = cam.tx * cam.ty;
-    int tile, slot;
-    xcd_remap(blockIdx.x, gridDim.x, 4 * a.levels, tile, slot);
-    if (tile >= ntiles) return;
     const int quad = slot & 3, lv0 = slot >> 2;
-    const int lane = threadIdx.x;
     const int tx = tile % cam.tx, ty = tile / cam.tx;
     const int qx0 = tx * kTile + (quad & 1) * 8, qy0 = ty * kTile + (quad >> 1) * 8;
     if (qx0 >= cam.W || qy0 >= cam.H) return;  // quadrant fully outside the image
@@ -417,8 +421,25 @@ __global__ __launch_bounds__(64, OUT != kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k
     }
     if (OUT == kOutDecode) {
         wave_lds_order();  // the record reads of the last batch are done
-        decode_tail<NV>(a, acc, reinterpret_cast<char*>(stage4), lane, lv0, qx0, qy0);
+        decode_tail<NV, CF>(a, acc, reinterpret_cast<char*>(stage), lane, lv0, qx0, qy0, dsrc);
     }
+}
+
+// One wave per workgroup and work item (the hardware dispatcher balances the
+// items).  The decode form reads the packed dictionary through L2: keeping it
+// in LDS would need workgroups of many waves sharing one copy, which leaves
+// no room for 128-byte output staging (32-feature staging alone costs more
+// than the L2 reads save).
+template <int NV, int KMAX, bool EXACT, int OUT>
+__global__ __launch_bounds__(64, OUT != kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
+    using R = Rec<KMAX>;
+    constexpr int REC4 = 64 * R::STRIDE / 4;
+    constexpr int STAGE4 = OUT == kOutDecode && kDecStageBytes / 16 > REC4 ? kDecStageBytes / 16 : REC4;
+    __shared__ float4 stage4[STAGE4];
+    int tile, slot;
+    xcd_remap(blockIdx.x, gridDim.x, 4 * a.levels, tile, slot);
+    if (tile >= a.cam.tx * a.cam.ty) return;
+    splat_item<NV, KMAX, EXACT, OUT, 64>(a, tile, slot, threadIdx.x, reinterpret_cast<float*>(stage4), a.dictp);
 }
 
 template <int NV, int KMAX, bool EXACT>
@@ -455,16 +476,18 @@ static int launch_splat_l(const SplatArgs& a, int out, hipStream_t stream) {
 }
 
 // Dictionary [L,D] float32 -> the decode tail's A operands in bfloat16
-// (nearest even): element ((f 2 + h) KS + ks) 8 + e = S[16 ks + 8 h + e][f].
+// (nearest even): 16-byte unit ((ft KS + ks) 2 + h) 32 + c holds
+// S[16 ks + 8 h + e][32 ft + c], e = 0..7, so the 64 lanes of one k-step read
+// 1 KB contiguously.
 __global__ __launch_bounds__(256) void k_dict_pack(int L, int D, const float* __restrict__ dict,
                                                    unsigned short* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L * D) return;
     const int KS = L / 16;
-    const int e = i & 7, r = i >> 3;
-    const int ks = r % KS, fh = r / KS;
-    const int h = fh & 1, f = fh >> 1;
-    out[i] = __builtin_bit_cast(unsigned short, (__bf16)dict[(size_t)(16 * ks + 8 * h + e) * D + f]);
+    const int e = i & 7, unit = i >> 3;
+    const int c = unit & 31, h = (unit >> 5) & 1, r = unit >> 6;
+    const int ks = r % KS, ft = r / KS;
+    out[i] = __builtin_bit_cast(unsigned short, (__bf16)dict[(size_t)(16 * ks + 8 * h + e) * D + 32 * ft + c]);
 }
 
 }  // namespace ls2
@@ -504,7 +527,7 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
 extern "C" int ls2_splat_decode_workspace(int32_t L, int32_t D, size_t* bytes) {
     if (!bytes || L < 1 || D < 1) return LS2_ERR_ARG;
     if (!(L == 32 || L == 64 || L == 128) || D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
-    *bytes = (size_t)L * D * 2;
+    *bytes = (size_t)L * D * 2;  // the packed dictionary
     return LS2_OK;
 }
 
