@@ -38,7 +38,8 @@ struct Meta {
     long long sb_total;     // total (superblock, Gaussian) entries
     long long sb_overflow;  // 1 if sb_total > max_pairs
     unsigned long long P_rect;  // sum of tile-rectangle areas (= P), from pass 1
-    long long pad[3];
+    long long nchunks;      // fill chunks over all buckets (S = 4)
+    long long pad[2];
 };
 
 constexpr size_t kAlign = 256;
@@ -61,11 +62,21 @@ inline Geo geo(const CamK& k) {
     return g;
 }
 
+// Sorted buckets are filled into tile lists in chunks of kFillChunk entries
+// (S = 4), each chunk with its own workgroup pass.
+constexpr int kFillChunk = 2048;
+
+// Fill chunks over all buckets, at most: every non-empty bucket rounds up once.
+inline size_t max_chunks(const Geo& g, int64_t max_pairs) {
+    return (size_t)g.nsb + (size_t)(max_pairs > 0 ? max_pairs : 0) / kFillChunk + 1;
+}
+
 struct Layout {
-    size_t meta, sb_count, tile_count, sb_start, sb_cursor, sb_order, rect, pool, total;
+    size_t meta, sb_count, tile_count, chunk_cnt, sb_start, sb_cursor, sb_order, sb_cbase, chunk_sb, rect, pool,
+        total;
 };
 
-// meta, sb_count and tile_count come first: they are zeroed every call.
+// meta, sb_count, tile_count and chunk_cnt come first: they are zeroed every call.
 inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     const Geo g = geo(k);
     Layout l;
@@ -73,9 +84,12 @@ inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     l.meta = off; off = align_up(off + sizeof(Meta));
     l.sb_count = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.tile_count = off; off = align_up(off + sizeof(unsigned) * (size_t)k.tx * k.ty);
+    l.chunk_cnt = off; off = align_up(off + sizeof(unsigned) * 16 * (g.S == 4 ? max_chunks(g, max_pairs) : 1));
     l.sb_start = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_order = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.sb_cbase = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.chunk_sb = off; off = align_up(off + sizeof(unsigned) * (g.S == 4 ? max_chunks(g, max_pairs) : 1));
     l.rect = off; off = align_up(off + sizeof(ushort4) * (size_t)(n > 0 ? n : 1));
     l.pool = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
     l.total = off;
@@ -97,6 +111,9 @@ struct BinArgs {
     unsigned* sb_cursor;
     unsigned* sb_order;  // superblocks by decreasing bucket size (size classes)
     unsigned* tile_count;
+    unsigned* chunk_cnt;  // S = 4: [chunk][16] entries covering each tile of the chunk's superblock
+    unsigned* sb_cbase;   // S = 4: first fill chunk of each superblock
+    unsigned* chunk_sb;   // S = 4: superblock of each fill chunk
     ushort4* rect;
     unsigned long long* pool;
     unsigned* ranges;
@@ -244,6 +261,19 @@ __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
     __syncthreads();
     for (int s = threadIdx.x; s < a.nsb; s += blockDim.x)
         a.sb_order[atomicAdd(&cls[size_class(a.sb_count[s])], 1u)] = (unsigned)s;
+    if (a.S != 4 || over) return;
+    // fill chunks: kFillChunk entries of each bucket (in place: counts, then
+    // their exclusive prefix), and the superblock of every chunk
+    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x)
+        a.sb_cbase[s] = (a.sb_count[s] + kFillChunk - 1) / kFillChunk;
+    __syncthreads();
+    const long long nch = block_scan(a.sb_cbase, a.sb_cbase, 1, nullptr, a.nsb);
+    __syncthreads();
+    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) {
+        const unsigned c0 = a.sb_cbase[s], c1 = c0 + (a.sb_count[s] + kFillChunk - 1) / kFillChunk;
+        for (unsigned c = c0; c < c1; ++c) a.chunk_sb[c] = (unsigned)s;
+    }
+    if (threadIdx.x == 0) a.meta->nchunks = nch;
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
@@ -322,18 +352,24 @@ __device__ void flip_bitonic(Ptr s, int cnt) {
 // For 4x4-tile superblocks every entry contributes a 16-bit coverage mask and
 // each wave counts with 16 ballots per 64 entries; larger superblocks (only
 // for very large images) use LDS atomics.
-__device__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long long* s, int cnt, unsigned* tcnt) {
+__device__ __forceinline__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long long* s, int cnt,
+                                               unsigned* tcnt) {
     const int S = a.S;
     const int sx = sb % a.sbx, sy = sb / a.sbx;
     const int tx0 = sx * S, ty0 = sy * S;
     for (int t = threadIdx.x; t < S * S; t += blockDim.x) tcnt[t] = 0u;
     __syncthreads();
     if (S == 4) {
-        unsigned wcnt[16];
-#pragma unroll
-        for (int b = 0; b < 16; ++b) wcnt[b] = 0u;
         const int cnt64 = (cnt + 63) & ~63;
         constexpr int G = 4;  // rectangle gathers in flight per thread
+        // Counts per fill chunk: a wave visits the chunks in increasing order,
+        // so it sums one chunk's counts in registers and adds them (to the
+        // chunk's global counters and the tile totals) when the chunk changes.
+        unsigned ccnt[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) ccnt[b] = 0u;
+        int cur = -1;
+        unsigned* const cbase = a.chunk_cnt + (size_t)a.sb_cbase[sb] * 16;
         for (int e0 = threadIdx.x; e0 < cnt64; e0 += G * blockDim.x) {
             ushort4 rr[G];
 #pragma unroll
@@ -352,15 +388,34 @@ __device__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long lon
                     const unsigned rowbits = ((1u << (x1 + 1)) - 1u) & ~((1u << x0) - 1u);
                     for (int y = y0; y <= y1; ++y) cover |= rowbits << (4 * y);
                 }
+                // the wave's 64 entries lie in one fill chunk (64 | kFillChunk)
+                const int chunk = (e0 - (int)(threadIdx.x & 63) + q * (int)blockDim.x) / kFillChunk;
+                if (chunk != cur) {  // wave-uniform
+                    if (cur >= 0 && (threadIdx.x & 63) == 0) {
+#pragma unroll
+                        for (int b = 0; b < 16; ++b)
+                            if (ccnt[b]) {
+                                atomicAdd(cbase + (size_t)cur * 16 + b, ccnt[b]);
+                                atomicAdd(&tcnt[b], ccnt[b]);
+                            }
+                    }
+#pragma unroll
+                    for (int b = 0; b < 16; ++b) ccnt[b] = 0u;
+                    cur = chunk;
+                }
 #pragma unroll
                 for (int b = 0; b < 16; ++b)
-                    wcnt[b] += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cover >> b) & 1u));
+                    ccnt[b] += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cover >> b) & 1u));
             }
         }
-        if ((threadIdx.x & 63) == 0)
+        if (cur >= 0 && (threadIdx.x & 63) == 0) {
 #pragma unroll
             for (int b = 0; b < 16; ++b)
-                if (wcnt[b]) atomicAdd(&tcnt[b], wcnt[b]);
+                if (ccnt[b]) {
+                    atomicAdd(cbase + (size_t)cur * 16 + b, ccnt[b]);
+                    atomicAdd(&tcnt[b], ccnt[b]);
+                }
+        }
     } else {
         for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
             const unsigned id = (unsigned)(s[e] & 0xffffffffull);
@@ -676,7 +731,6 @@ __global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
 // order, the entries whose rectangle covers its tile: an order-preserving
 // ballot compaction, so each tile's list comes out in (depth, id) order.
 constexpr int kFillThreads = 1024;
-constexpr int kFillChunk = 2048;
 constexpr int kFillPer = kFillChunk / kFillThreads;
 
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill(BinArgs a) {
@@ -749,6 +803,71 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(BinArgs a) {
     }
 }
 
+// S = 4: one pass per fill chunk instead of one sequential walk per bucket,
+// so a large bucket's chunks are filled by several workgroups at once.  A
+// chunk's first list position in each tile is the tile's start plus the
+// entries of that tile in the bucket's earlier chunks (counted by the sort
+// kernel); the compaction inside the chunk is the ballot scan above.  A
+// fixed grid strides over the chunks (their number is known on the device
+// only).
+__global__ __launch_bounds__(kFillThreads) void k_tile_fill_chunks(BinArgs a) {
+    __shared__ unsigned long long skey[kFillChunk];
+    __shared__ ushort4 srect[kFillChunk];
+    __shared__ unsigned toff[16];
+    if (a.meta->overflow) return;
+    const long long nch = a.meta->nchunks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const int sb = (int)a.chunk_sb[ch];
+        const unsigned cb = a.sb_cbase[sb];
+        const int c = (int)(ch - cb);
+        const int base = c * kFillChunk;
+        const int n = min(kFillChunk, (int)a.sb_count[sb] - base);
+        const int tx0 = (sb % a.sbx) * 4, ty0 = (sb / a.sbx) * 4;
+        const unsigned long long* list = a.pool + a.sb_start[sb] + base;
+        __syncthreads();  // the previous chunk's LDS reads are done
+        if (threadIdx.x < 16) {
+            const int t = threadIdx.x, x = tx0 + (t & 3), y = ty0 + (t >> 2);
+            toff[t] = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x)] : 0u;
+        }
+        __syncthreads();
+        // plus the tile's entries in the bucket's earlier chunks, all loads at once
+        for (int i = threadIdx.x; i < c * 16; i += blockDim.x)
+            if (const unsigned v = a.chunk_cnt[(size_t)(cb + (i >> 4)) * 16 + (i & 15)]) atomicAdd(&toff[i & 15], v);
+#pragma unroll
+        for (int q = 0; q < kFillPer; ++q) {
+            const int e = q * kFillThreads + (int)threadIdx.x;
+            const unsigned long long k = e < n ? list[e] : 0ull;
+            skey[e] = k;
+            srect[e] = e < n ? a.rect[(unsigned)(k & 0xffffffffull)] : make_ushort4(0xffff, 0xffff, 0, 0);
+        }
+        __syncthreads();
+        const int tx = tx0 + (wave & 3), ty = ty0 + (wave >> 2);  // 16 waves: one tile each
+        if (tx >= a.cam.tx || ty >= a.cam.ty) continue;
+        const unsigned long long tk = (unsigned long long)(ty * a.cam.tx + tx) << 32;
+        const unsigned end = a.ranges[2 * (ty * a.cam.tx + tx) + 1];
+        unsigned out = toff[wave];
+        for (int b = 0; b < n; b += 64) {
+            const int e = b + lane;
+            bool hit = false;
+            unsigned long long key = 0;
+            if (e < n) {
+                key = skey[e];
+                const ushort4 r = srect[e];
+                hit = tx >= (int)r.x && tx <= (int)r.z && ty >= (int)r.y && ty <= (int)r.w;
+            }
+            const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+            const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
+            if (hit && pos < end) {  // the sort kernel's counts use the same test: pos < end always
+                a.ids[pos] = (unsigned)(key & 0xffffffffull);
+                if (a.keys) a.keys[pos] = tk | (key >> 32);
+            }
+            out += (unsigned)__builtin_popcountll(mask);
+        }
+    }
+}
+
 }  // namespace ls2
 
 using namespace ls2;
@@ -790,13 +909,17 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.sb_cursor = reinterpret_cast<unsigned*>(ws + lay.sb_cursor);
     a.sb_order = reinterpret_cast<unsigned*>(ws + lay.sb_order);
     a.tile_count = reinterpret_cast<unsigned*>(ws + lay.tile_count);
+    a.chunk_cnt = reinterpret_cast<unsigned*>(ws + lay.chunk_cnt);
+    a.sb_cbase = reinterpret_cast<unsigned*>(ws + lay.sb_cbase);
+    a.chunk_sb = reinterpret_cast<unsigned*>(ws + lay.chunk_sb);
     a.rect = reinterpret_cast<ushort4*>(ws + lay.rect);
     a.pool = reinterpret_cast<unsigned long long*>(ws + lay.pool);
     a.ranges = tile_ranges;
     a.ids = ids;
     a.keys = reinterpret_cast<unsigned long long*>(keys);
-    // zero meta, superblock counts and tile counts (contiguous; tile counts of
-    // superblocks with no entries are never written by the sort kernels)
+    // zero meta, superblock counts, tile counts and chunk counts (contiguous;
+    // tile counts of superblocks with no entries are never written by the
+    // sort kernels)
     const long long zw = (long long)((lay.sb_start - lay.meta) / sizeof(unsigned));
     const long long zb = (zw + 255) / 256;
     hipLaunchKernelGGL(k_bin_zero, dim3((unsigned)(zb < 1024 ? zb : 1024)), dim3(256), 0, stream,
@@ -819,7 +942,15 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
     LS2_LAUNCH_CHECK();
     if (n > 0 && max_pairs > 0) {
-        hipLaunchKernelGGL(k_tile_fill, dim3(g.nsb), dim3(kFillThreads), 0, stream, a);
+        if (g.S == 4) {
+            int dev = 0, ncu = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+                ncu = 256;
+            hipLaunchKernelGGL(k_tile_fill_chunks, dim3((unsigned)(2 * ncu)), dim3(kFillThreads), 0, stream, a);
+        } else {
+            hipLaunchKernelGGL(k_tile_fill, dim3(g.nsb), dim3(kFillThreads), 0, stream, a);
+        }
         LS2_LAUNCH_CHECK();
     }
     if (num_pairs) {
