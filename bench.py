@@ -374,7 +374,7 @@ def main():
         P = p_.bin_sort(sync=True)
     log("P =", P, "pairs")
 
-    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False, one_pass=False):
+    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False, one_pass=False, keep_feat=True):
         def mark(i):
             if ev is not None:
                 ev[i].record()
@@ -384,7 +384,11 @@ def main():
         p_.bin_sort(sync=False)
         mark(2)
         if one_pass:  # splat and bf16 decode in one kernel: the coefficient map stays on chip
-            p_.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
+            if query:  # and the relevancy formed in the same pass
+                p_.splat_decode_query(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"], post, negt,
+                                      keep_feat=keep_feat)
+            else:
+                p_.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
             mark(3)
             return
         p_.splat(t["opacity"], t["topk_idx"], t["topk_w"])
@@ -401,11 +405,11 @@ def main():
 
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
-    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False, one_pass=False):
+    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False, one_pass=False, keep_feat=True):
         """Wall-clock rate over `steps` uninstrumented frames, then the same
         number of frames with HIP events between the stages (per-stage
         times; these frames are not part of the rate)."""
-        kw = dict(query=query, fused=fused, one_pass=one_pass)
+        kw = dict(query=query, fused=fused, one_pass=one_pass, keep_feat=keep_feat)
         for _ in range(warmup):
             frame(p_, compute, out_dtype, **kw)
         torch.cuda.synchronize()
@@ -418,7 +422,8 @@ def main():
         for s in range(steps):
             frame(p_, compute, out_dtype, evs[s], **kw)
         torch.cuda.synchronize()
-        names = ["project", "bin_sort", "splat_decode"] if one_pass else stages[:5 if (query and not fused) else 4]
+        names = (["project", "bin_sort", "splat_decode_query" if query else "splat_decode"] if one_pass
+                 else stages[:5 if (query and not fused) else 4])
         per = {names[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                for i in range(len(names))}
         return wall, per
@@ -440,11 +445,19 @@ def main():
     # query frame, two passes: decode writes the feature map, ls2_query reads it back
     qwall, qper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
     query_fps_two_pass = max(5, args.steps // 2) / qwall
-    # query frame, fused: the relevancy is formed in the decode's epilogue
-    fqwall, fqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True, fused=True)
-    query_fps = max(5, args.steps // 2) / fqwall
-    log("query frames: fused %.1f FPS (decode+relevancy %.4f ms), two-pass %.1f FPS" % (
-        query_fps, fqper["decode"], query_fps_two_pass))
+    # query frame, relevancy in the decode's epilogue (splat, then decode + relevancy)
+    nqs = max(5, args.steps // 2)
+    fqwall, fqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, fused=True)
+    query_fps_epilogue = nqs / fqwall
+    # query frame in one pass: splat, decode and relevancy in one kernel (feature map written)
+    oqwall, oqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, one_pass=True)
+    query_fps = nqs / oqwall
+    # ... and without writing the feature map at all
+    nqwall, nqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, one_pass=True, keep_feat=False)
+    query_fps_no_feat = nqs / nqwall
+    log("query frames: one pass %.1f FPS (splat+decode+relevancy %.4f ms), without the feature map %.1f FPS, "
+        "decode epilogue %.1f FPS, two-pass %.1f FPS" % (query_fps, oqper["splat_decode_query"], query_fps_no_feat,
+                                                         query_fps_epilogue, query_fps_two_pass))
 
     # relevancy straight from the coefficient map (Eq. 7): project, bin, splat, query_coef
     def coef_query_frame():
@@ -531,8 +544,10 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
         "two_pass_frame": two_pass,
         "query_fps": round(query_fps, 2),
+        "query_fps_without_feature_map": round(query_fps_no_feat, 2),
+        "query_fps_decode_epilogue": round(query_fps_epilogue, 2),
         "query_fps_two_pass": round(query_fps_two_pass, 2),
-        "decode_with_relevancy_ms": round(fqper["decode"], 4),
+        "splat_decode_query_ms": round(oqper["splat_decode_query"], 4),
         "query_from_coefficients": query_coef,
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},

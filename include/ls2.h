@@ -169,6 +169,32 @@ int ls2_splat_decode(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K
                      int32_t* last, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * ls2_splat_decode_query -- ls2_splat_decode with the relevancy of Section
+ * 3.2 (LERF form, as ls2_query) formed in the same pass: while each chunk of
+ * a wave's features is on chip it is scored against the bfloat16-rounded
+ * texts on the matrix cores (dot products and squared norms accumulated over
+ * the features in increasing order), so the relevancy equals ls2_query on
+ * the bfloat16 feature map bit for bit.  The feature map is written only if
+ * feat is given.
+ *
+ * In:  as ls2_splat_decode; pos [D], neg [n_neg,D] f32; tau.
+ * Out: relevancy [levels,H,W] f32; feat [levels,H,W,D] bfloat16 (optional,
+ *      16-byte aligned); coef, final_T, last (optional) as ls2_splat_decode.
+ * workspace: at least ls2_splat_decode_query_workspace() bytes (the repacked
+ *      dictionary, the bfloat16 texts and their norms), 16-byte aligned,
+ *      owned by the caller, not shared between concurrent calls.
+ * Supported: as ls2_splat_decode, and 1 <= n_neg <= 8.
+ */
+int ls2_splat_decode_query_workspace(int32_t L, int32_t D, int32_t n_neg, size_t* bytes);
+int ls2_splat_decode_query(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L, int32_t D,
+                           const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                           const float* conic, const float* opacity, const int32_t* topk_idx,
+                           const float* topk_w, const float* dict, const float* pos, int32_t n_neg,
+                           const float* neg, float tau, float* relevancy, void* feat, void* coef,
+                           float* final_T, int32_t* last, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream);
+
+/*
  * ls2_splat_dense -- the dense form of the coefficient splatting: every
  * Gaussian blends all L coefficients of each level (the rendering that
  * Section 3.4 avoids by blending only the K non-zero ones; Table 9 times both).

@@ -40,8 +40,12 @@ typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
 typedef float f32x16s __attribute__((ext_vector_type(16)));
 typedef float f32x4s __attribute__((ext_vector_type(4)));
 
-// Coefficient output of the splat kernel.
-enum SplatOut { kOutF32 = 0, kOutBF16 = 1, kOutDecode = 2 };
+typedef __bf16 bf16x8q __attribute__((ext_vector_type(8)));
+typedef float f32x4q __attribute__((ext_vector_type(4)));
+
+// Coefficient output of the splat kernel.  kOutDecodeQuery: the decode tail
+// also scores every pixel against the text query (the feature map optional).
+enum SplatOut { kOutF32 = 0, kOutBF16 = 1, kOutDecode = 2, kOutDecodeQuery = 3 };
 
 struct SplatArgs {
     CamK cam;
@@ -59,7 +63,14 @@ struct SplatArgs {
     // kOutDecode: packed bfloat16 dictionary (k_dict_pack) and the feature map
     int D = 0;
     const unsigned short* dictp = nullptr;
-    unsigned short* feat = nullptr;
+    unsigned short* feat = nullptr;  // optional with kOutDecodeQuery
+    // kOutDecodeQuery: texts in bfloat16 [ntext][D] (0 the positive), their
+    // float32 norms, the temperature and the relevancy map [levels,H,W]
+    const unsigned short* texts = nullptr;
+    const float* tnorm = nullptr;
+    int ntext = 0;
+    float tau = 1.0f;
+    float* rel = nullptr;
 };
 
 // Feature-map bytes each wave stages at a time in the decode tail: 64 pixels
@@ -102,7 +113,15 @@ struct Rec {
 // dsrc: the packed dictionary (k_dict_pack), in HBM or in LDS.  The wave
 // stages CF features of its 64 pixels at a time in st (64 CF 2 bytes) and
 // writes them as CF-feature runs of each pixel.
-template <int NV, int CF>
+//
+// QRY: while each chunk is staged, the four 16-pixel blocks of the wave are
+// scored exactly as ls2_query scores a bf16 feature map: MFMA 16x16x32 bf16
+// with A = the block's features (lane (r, g): pixel r, features 32 ks + 8 g
+// + [0,8)) and B = the bf16 texts, plus the Gram tile of A for the squared
+// norms, accumulated over the k-steps in increasing order.  Every output
+// element of these products depends only on its own row and column, so the
+// relevancy equals ls2_query on the written map bit for bit.
+template <int NV, int CF, bool QRY>
 __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc)[NV], char* st, int lane, int lv0,
                                             int qx0, int qy0, const unsigned short* dsrc) {
     constexpr int KS = 2 * NV;   // k-steps of 16
@@ -119,6 +138,8 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) o[ks] = dv[(ft * KS + ks) * 64];
     };
+    // (QRY keeps one buffer: its score accumulators take the registers of
+    // the next tile's operands)
     u32x4s sa[KS], sn[KS];
     load_a(0, sa);
     bf16x8s wb[2][KS];
@@ -146,11 +167,20 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
     const bool xin = qx0 + xo < W;
     const size_t rstride = (size_t)W * D;
     unsigned short* fbase = a.feat + ((size_t)lv0 * H + qy0 + yo) * rstride + (size_t)(qx0 + xo) * D + su * 8;
+    const bool store = !QRY || a.feat != nullptr;
+    // QRY: lane (r16, g) of the 16x16x32 products; dot and Gram tiles of the
+    // four 16-pixel blocks
+    const int r16 = lane & 15, g16 = lane >> 4;
+    const bool tcol = QRY && r16 < a.ntext;
+    f32x4q dq[QRY ? 4 : 1], gq[QRY ? 4 : 1];
+#pragma unroll
+    for (int rb = 0; rb < (QRY ? 4 : 1); ++rb) dq[rb] = gq[rb] = (f32x4q){0.f, 0.f, 0.f, 0.f};
     for (int c = 0; c < D / CF; ++c) {
 #pragma unroll
         for (int cc = 0; cc < FT; ++cc) {
             const int ft = FT * c + cc;
-            load_a(ft + 1 < nft ? ft + 1 : ft, sn);
+            if constexpr (!QRY) load_a(ft + 1 < nft ? ft + 1 : ft, sn);
+            else if (ft > 0) load_a(ft, sa);
             f32x16s f0 = {}, f1 = {};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
@@ -169,19 +199,62 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
                 *reinterpret_cast<uint2*>(st + (32 + col) * (U * 16) + u) =
                     make_uint2(bf16_pair(f1[4 * g], f1[4 * g + 1]), bf16_pair(f1[4 * g + 2], f1[4 * g + 3]));
             }
+            if constexpr (!QRY) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) sa[ks] = sn[ks];
+                for (int ks = 0; ks < KS; ++ks) sa[ks] = sn[ks];
+            }
         }
         wave_lds_order();
+        if (QRY) {
+            const bf16x8q zero8 = {};
 #pragma unroll
-        for (int i = 0; i < U; ++i) {
-            const int p = PPI * i + pi;  // p % U == pi % U
-            const f32x4s v = *reinterpret_cast<const f32x4s*>(st + p * (U * 16) + ((su ^ (pi & (U - 1))) * 16));
-            if (xin && qy0 + (8 / U) * i + yo < H)
-                __builtin_nontemporal_store(
-                    v, reinterpret_cast<f32x4s*>(fbase + (size_t)((8 / U) * i) * rstride + c * CF));
+            for (int kk = 0; kk < CF / 32; ++kk) {
+                const bf16x8q tb = tcol ? *reinterpret_cast<const bf16x8q*>(a.texts + (size_t)r16 * D + c * CF +
+                                                                             kk * 32 + g16 * 8)
+                                        : zero8;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int p = 16 * rb + r16;
+                    const bf16x8q fa = *reinterpret_cast<const bf16x8q*>(
+                        st + p * (U * 16) + (((4 * kk + g16) ^ (p & (U - 1))) * 16));
+                    dq[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, tb, dq[rb], 0, 0, 0);
+                    gq[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fa, gq[rb], 0, 0, 0);
+                }
+            }
+        }
+        if (store) {
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                const int p = PPI * i + pi;  // p % U == pi % U
+                const f32x4s v = *reinterpret_cast<const f32x4s*>(st + p * (U * 16) + ((su ^ (pi & (U - 1))) * 16));
+                if (xin && qy0 + (8 / U) * i + yo < H)
+                    __builtin_nontemporal_store(
+                        v, reinterpret_cast<f32x4s*>(fbase + (size_t)((8 / U) * i) * rstride + c * CF));
+            }
         }
         wave_lds_order();  // the next chunk overwrites the staged lines
+    }
+    if (QRY) {
+        // per block: the dot tile (lane: text r16, pixels 4 g + i) and the
+        // Gram diagonal to LDS, then lanes 0..15 score their pixel
+        float* dots_w = reinterpret_cast<float*>(st);  // [16 pixels][17]
+        float* nrm_w = dots_w + 16 * 17;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int i = r16 - g16 * 4;
+            if (i >= 0 && i < 4) nrm_w[r16] = gq[rb][i];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) dots_w[(g16 * 4 + ii) * 17 + r16] = dq[rb][ii];
+            wave_lds_order();
+            if (lane < 16) {
+                const int p = 16 * rb + lane;
+                const int x = qx0 + (p & 7), y = qy0 + (p >> 3);
+                if (x < W && y < H)
+                    a.rel[((size_t)lv0 * H + y) * W + x] =
+                        lerf_relevancy(dots_w + lane * 17, nrm_w[lane], a.tnorm, a.ntext, a.tau);
+            }
+            wave_lds_order();
+        }
     }
 }
 
@@ -393,7 +466,7 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
         const size_t HW = (size_t)cam.W * cam.H;
         const size_t pix = (size_t)py * cam.W + px;
         const size_t row = ((size_t)lv0 * HW + pix) * (size_t)(NV * 32);
-        if (OUT == kOutDecode && !a.coef) {
+        if (OUT >= kOutDecode && !a.coef) {
             // feature map only
         } else if (OUT != kOutF32) {
             uint4* dst = reinterpret_cast<uint4*>(static_cast<unsigned short*>(a.coef) + row);
@@ -419,9 +492,9 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
             if (a.last) a.last[pix] = last;
         }
     }
-    if (OUT == kOutDecode) {
+    if (OUT == kOutDecode || OUT == kOutDecodeQuery) {
         wave_lds_order();  // the record reads of the last batch are done
-        decode_tail<NV, CF>(a, acc, reinterpret_cast<char*>(stage), lane, lv0, qx0, qy0, dsrc);
+        decode_tail<NV, CF, OUT == kOutDecodeQuery>(a, acc, reinterpret_cast<char*>(stage), lane, lv0, qx0, qy0, dsrc);
     }
 }
 
@@ -431,10 +504,10 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
 // no room for 128-byte output staging (32-feature staging alone costs more
 // than the L2 reads save).
 template <int NV, int KMAX, bool EXACT, int OUT>
-__global__ __launch_bounds__(64, OUT != kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
+__global__ __launch_bounds__(64, OUT < kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
     using R = Rec<KMAX>;
     constexpr int REC4 = 64 * R::STRIDE / 4;
-    constexpr int STAGE4 = OUT == kOutDecode && kDecStageBytes / 16 > REC4 ? kDecStageBytes / 16 : REC4;
+    constexpr int STAGE4 = OUT >= kOutDecode && kDecStageBytes / 16 > REC4 ? kDecStageBytes / 16 : REC4;
     __shared__ float4 stage4[STAGE4];
     int tile, slot;
     xcd_remap(blockIdx.x, gridDim.x, 4 * a.levels, tile, slot);
@@ -444,7 +517,9 @@ __global__ __launch_bounds__(64, OUT != kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k
 
 template <int NV, int KMAX, bool EXACT>
 static void launch_splat_out(const SplatArgs& a, int out, dim3 grid, hipStream_t stream) {
-    if (out == kOutDecode)
+    if (out == kOutDecodeQuery)
+        hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, EXACT, kOutDecodeQuery>), grid, dim3(64), 0, stream, a);
+    else if (out == kOutDecode)
         hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, EXACT, kOutDecode>), grid, dim3(64), 0, stream, a);
     else if (out == kOutBF16)
         hipLaunchKernelGGL((k_splat_sparse<NV, KMAX, EXACT, kOutBF16>), grid, dim3(64), 0, stream, a);
@@ -524,29 +599,48 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
     return launch_splat_l(a, coef_dtype == LS2_BF16 ? kOutBF16 : kOutF32, stream);
 }
 
-extern "C" int ls2_splat_decode_workspace(int32_t L, int32_t D, size_t* bytes) {
-    if (!bytes || L < 1 || D < 1) return LS2_ERR_ARG;
-    if (!(L == 32 || L == 64 || L == 128) || D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
-    *bytes = (size_t)L * D * 2;  // the packed dictionary
-    return LS2_OK;
+// Texts of the query: bfloat16 copies [ntext][D] and float32 norms, the
+// norms summed in the same order as ls2_query's (lane-strided, then an xor
+// butterfly), so that the relevancy matches it bit for bit.
+__global__ __launch_bounds__(256) void k_text_pack(int D, int ntext, const float* __restrict__ pos,
+                                                   const float* __restrict__ neg, unsigned short* __restrict__ texts,
+                                                   float* __restrict__ tnorm) {
+    for (int i = threadIdx.x; i < ntext * D; i += blockDim.x) {
+        const int j = i / D, d = i - j * D;
+        const float v = j == 0 ? pos[d] : neg[(size_t)(j - 1) * D + d];
+        texts[i] = __builtin_bit_cast(unsigned short, (__bf16)v);
+    }
+    if (threadIdx.x < 64) {
+        for (int j = 0; j < ntext; ++j) {
+            float s = 0.f;
+            const float* t = j == 0 ? pos : neg + (size_t)(j - 1) * D;
+            for (int d = threadIdx.x; d < D; d += 64) s += t[d] * t[d];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (threadIdx.x == 0) tnorm[j] = fmaxf(sqrtf(s), 1e-12f);
+        }
+    }
 }
 
-extern "C" int ls2_splat_decode(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L, int32_t D,
-                                const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
-                                const float* conic, const float* opacity, const int32_t* topk_idx,
-                                const float* topk_w, const float* dict, void* feat, void* coef, float* final_T,
-                                int32_t* last, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+static size_t al256s(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Validation and set-up shared by the one-pass entry points; launches the
+// dictionary repack.
+static int splat_decode_setup(SplatArgs& a, const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                              int32_t D, const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                              const float* conic, const float* opacity, const int32_t* topk_idx, const float* topk_w,
+                              const float* dict, void* feat, bool feat_required, void* coef, float* final_T,
+                              int32_t* last, void* workspace, size_t workspace_bytes, size_t ws_need,
+                              hipStream_t stream) {
     if (!cam_valid(cam) || n < 0 || levels < 1 || K < 1 || L < 1 || K > L || D < 1) return LS2_ERR_ARG;
-    if (!tile_ranges || !feat || !dict || !workspace) return LS2_ERR_ARG;
+    if (!tile_ranges || (feat_required && !feat) || !dict || !workspace) return LS2_ERR_ARG;
     if (!aligned16(feat) || !aligned16(coef) || !aligned16(workspace)) return LS2_ERR_ARG;
     if (n > 0 && (!ids || !mean2d || !conic || !opacity || !topk_idx || !topk_w)) return LS2_ERR_ARG;
     if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
     if (D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
-    if (workspace_bytes < (size_t)L * D * 2) return LS2_ERR_ARG;
+    if (workspace_bytes < ws_need) return LS2_ERR_ARG;
     unsigned short* dictp = static_cast<unsigned short*>(workspace);
     hipLaunchKernelGGL(k_dict_pack, dim3((unsigned)((L * D + 255) / 256)), dim3(256), 0, stream, L, D, dict, dictp);
     LS2_LAUNCH_CHECK();
-    SplatArgs a;
     a.cam = cam_k(*cam);
     a.n = n;
     a.levels = levels;
@@ -565,5 +659,62 @@ extern "C" int ls2_splat_decode(const ls2_camera* cam, int32_t n, int32_t levels
     a.D = D;
     a.dictp = dictp;
     a.feat = static_cast<unsigned short*>(feat);
+    return LS2_OK;
+}
+
+extern "C" int ls2_splat_decode_workspace(int32_t L, int32_t D, size_t* bytes) {
+    if (!bytes || L < 1 || D < 1) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
+    *bytes = (size_t)L * D * 2;  // the packed dictionary
+    return LS2_OK;
+}
+
+extern "C" int ls2_splat_decode(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L, int32_t D,
+                                const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                const float* conic, const float* opacity, const int32_t* topk_idx,
+                                const float* topk_w, const float* dict, void* feat, void* coef, float* final_T,
+                                int32_t* last, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    SplatArgs a;
+    const int st = splat_decode_setup(a, cam, n, levels, K, L, D, tile_ranges, ids, mean2d, conic, opacity, topk_idx,
+                                      topk_w, dict, feat, true, coef, final_T, last, workspace, workspace_bytes,
+                                      (size_t)(L > 0 ? L : 0) * (D > 0 ? D : 0) * 2, stream);
+    if (st != LS2_OK) return st;
     return launch_splat_l(a, kOutDecode, stream);
+}
+
+extern "C" int ls2_splat_decode_query_workspace(int32_t L, int32_t D, int32_t n_neg, size_t* bytes) {
+    if (!bytes || L < 1 || D < 1 || n_neg < 1) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64 || L == 128) || D % 64 != 0 || D > 1024 || n_neg > 8) return LS2_ERR_UNSUPPORTED;
+    // packed dictionary, bf16 texts, text norms
+    *bytes = al256s((size_t)L * D * 2) + al256s((size_t)(1 + n_neg) * D * 2) + 64;
+    return LS2_OK;
+}
+
+extern "C" int ls2_splat_decode_query(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                                      int32_t D, const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                      const float* conic, const float* opacity, const int32_t* topk_idx,
+                                      const float* topk_w, const float* dict, const float* pos, int32_t n_neg,
+                                      const float* neg, float tau, float* relevancy, void* feat, void* coef,
+                                      float* final_T, int32_t* last, void* workspace, size_t workspace_bytes,
+                                      hipStream_t stream) {
+    if (!pos || !neg || !relevancy || n_neg < 1) return LS2_ERR_ARG;
+    if (n_neg > 8) return LS2_ERR_UNSUPPORTED;
+    size_t need = 0;
+    if (ls2_splat_decode_query_workspace(L, D, n_neg, &need) != LS2_OK) need = 0;  // the shape checks below report it
+    SplatArgs a;
+    int st = splat_decode_setup(a, cam, n, levels, K, L, D, tile_ranges, ids, mean2d, conic, opacity, topk_idx,
+                                topk_w, dict, feat, false, coef, final_T, last, workspace, workspace_bytes, need,
+                                stream);
+    if (st != LS2_OK) return st;
+    char* w = static_cast<char*>(workspace) + al256s((size_t)L * D * 2);
+    unsigned short* texts = reinterpret_cast<unsigned short*>(w);
+    float* tnorm = reinterpret_cast<float*>(w + al256s((size_t)(1 + n_neg) * D * 2));
+    hipLaunchKernelGGL(k_text_pack, dim3(1), dim3(256), 0, stream, D, 1 + n_neg, pos, neg, texts, tnorm);
+    LS2_LAUNCH_CHECK();
+    a.texts = texts;
+    a.tnorm = tnorm;
+    a.ntext = 1 + n_neg;
+    a.tau = tau;
+    a.rel = relevancy;
+    return launch_splat_l(a, kOutDecodeQuery, stream);
 }

@@ -99,6 +99,29 @@ class Pipeline:
                               self.final_T, self.last)
         return self.feat
 
+    def splat_decode_query(self, opacity, topk_idx, topk_w, dictionary, pos, neg, tau: float = 1.0,
+                           keep_feat: bool = True):
+        """Splat, bf16 decode and relevancy in one pass: the relevancy equals
+        ls2_query on the bf16 feature map bit for bit; with keep_feat=False
+        the feature map is not written at all."""
+        if self.relevancy is None:
+            self.relevancy = torch.empty((self.levels, self.H, self.W), dtype=torch.float32, device=self.device)
+        n_neg = neg.numel() // self.D
+        if getattr(self, "_sdq_key", None) != n_neg:
+            self._sdq_ws = torch.empty((_lib.ls2_splat_decode_query_workspace(self.L, self.D, n_neg),),
+                                       dtype=torch.uint8, device=self.device)
+            self._sdq_key = n_neg
+        feat = None
+        if keep_feat:
+            if self.feat is None or self.feat.dtype != torch.bfloat16:
+                self.feat = torch.empty((self.levels, self.H, self.W, self.D), dtype=torch.bfloat16,
+                                        device=self.device)
+            feat = self.feat
+        _lib.ls2_splat_decode_query(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids, self.mean2d,
+                                    self.conic, opacity, topk_idx, topk_w, dictionary, pos, neg, self.relevancy,
+                                    self._sdq_ws, feat=feat, final_T=self.final_T, last=self.last, tau=tau)
+        return self.relevancy
+
     def splat_dense(self, opacity, weights):
         """Dense form (all L coefficients per Gaussian) into the same buffers."""
         _lib.ls2_splat_dense(self.cam, self.levels, self.L, self.tile_ranges, self.ids, self.mean2d, self.conic,

@@ -210,3 +210,28 @@ def test_splat_decode_validation_without_device(L):
     assert call(wsp=V(24)) == -1
     assert call(wsb=ws - 1) == -1         # workspace too small
     assert call(n=-1) == -1
+
+
+def test_splat_decode_query_validation_without_device(L):
+    c = _cam()
+    V = ctypes.c_void_p
+    b = ctypes.c_size_t(0)
+    assert L.ls2_splat_decode_query_workspace(64, 512, 4, ctypes.byref(b)) == 0 and b.value >= 64 * 512 * 2 + 5 * 1024
+    assert L.ls2_splat_decode_query_workspace(64, 512, 9, ctypes.byref(b)) == -3
+    assert L.ls2_splat_decode_query_workspace(64, 512, 0, ctypes.byref(b)) == -1
+    L.ls2_splat_decode_query_workspace(64, 512, 4, ctypes.byref(b))
+    ws = b.value
+    inp = [V(16)] * 7
+    f1 = ctypes.c_float(1.0)
+
+    def call(n_neg=4, D=512, pos=V(16), neg=V(16), rel=V(16), feat=None, wsp=V(16), wsb=ws):
+        return L.ls2_splat_decode_query(ctypes.byref(c), 10, 1, 4, 64, D, *inp, V(16), pos, n_neg, neg, f1, rel,
+                                        feat, None, None, None, wsp, wsb, None)
+    # every case is rejected before any launch
+    assert call(n_neg=9) == -3
+    assert call(n_neg=0) == -1
+    assert call(pos=None) == -1
+    assert call(rel=None) == -1
+    assert call(feat=V(24)) == -1          # misaligned optional feature map
+    assert call(wsb=ws - 1) == -1
+    assert call(D=500) == -3

@@ -456,6 +456,49 @@ def test_splat_decode_fused(orc, L, K, levels, D, w, h):
     assert np.all(got[empty] == 0.0)
 
 
+@pytest.mark.parametrize("L,K,levels,D,n_neg,w,h,keep", [(64, 4, 1, 512, 4, 120, 90, True),
+                                                         (64, 4, 1, 512, 4, 120, 90, False),
+                                                         (32, 8, 3, 256, 1, 100, 76, True),
+                                                         (128, 4, 1, 384, 8, 72, 56, False),
+                                                         (64, 3, 2, 128, 2, 33, 47, True)])
+def test_splat_decode_query_fused(orc, L, K, levels, D, n_neg, w, h, keep):
+    """The one-pass splat + decode + relevancy equals ls2_query on the
+    one-pass bf16 feature map bit for bit (and writes that map only if asked);
+    against the oracle (exact compositing of the GPU's lists, exact decode,
+    LERF relevancy) every clean pixel meets the bf16 relevancy bar."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(606 + L + K + levels + D + n_neg, 3000, w, h, L=L, K=K, levels=levels, D=D)
+    g = run_forward(cam, scene)
+    t = g["t"]
+    pos, neg = gen.make_text(L + D + n_neg, D=D, n_neg=n_neg)
+    tp, tn = torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda()
+    p16 = ls2.Pipeline(cam, scene.n, levels=levels, K=K, L=L, D=D, coef_dtype=torch.bfloat16)
+    p16.project(t["means"], t["scales"], t["quats"])
+    p16.bin_sort(sync=True)
+    ref_feat = p16.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"]).clone()
+    ref_T, ref_last = p16.final_T.clone(), p16.last.clone()
+    ref_rel = torch.empty((levels, h, w), device="cuda")
+    ls2.ls2_query(ref_feat, tp, tn, ref_rel)
+    p16.feat.fill_(3.0)
+    p16.final_T.fill_(-1.0)
+    p16.last.fill_(-7)
+    rel = p16.splat_decode_query(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"], tp, tn,
+                                 keep_feat=keep).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(rel, ref_rel)
+    assert torch.equal(p16.final_T, ref_T) and torch.equal(p16.last, ref_last)
+    if keep:
+        assert torch.equal(p16.feat, ref_feat)
+    else:
+        assert bool((p16.feat == 3.0).all())       # not written
+    coef64, fT, last, margin, margin_T = oracle_composite_from_gpu(orc, cam, scene, g)
+    ok = _ok(margin, margin_T)
+    r64 = orc.query(orc.decode(coef64.reshape(-1, L), scene.dictionary), pos, neg).reshape(levels, h, w)
+    err = np.abs(rel.cpu().numpy() - r64)[:, ok]
+    print("one-pass relevancy: max err %.3e over %d pixel-levels" % (err.max(), err.size))
+    assert err.max() <= 2e-3
+
+
 @pytest.mark.parametrize("L,D,n_neg,coef_bf16,keep", [(64, 512, 4, True, True), (64, 512, 4, False, False),
                                                        (32, 256, 1, False, True), (128, 384, 8, True, False),
                                                        (64, 128, 2, False, True)])
