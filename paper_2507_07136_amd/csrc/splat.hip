@@ -131,16 +131,16 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
     static_assert(CF == 32 || CF == 64, "decode_tail: 32- or 64-feature chunks");
     const int col = lane & 31, half = lane >> 5;
     // A operand of lane l at k-step ks of feature tile ft: 16-byte unit
-    // (ft KS + ks) 64 + l of the packed dictionary; the first tile's loads
-    // are issued before the operand conversion
+    // (ft KS + ks) 64 + l of the packed dictionary (through L2).  The first
+    // tile's loads are issued before the operand conversion; later tiles load
+    // just before use: a second buffer would cost more (registers spilled)
+    // than the latency it hides, as measured.
     const u32x4s* dv = reinterpret_cast<const u32x4s*>(dsrc) + lane;
     auto load_a = [&](int ft, u32x4s (&o)[KS]) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) o[ks] = dv[(ft * KS + ks) * 64];
     };
-    // (QRY keeps one buffer: its score accumulators take the registers of
-    // the next tile's operands)
-    u32x4s sa[KS], sn[KS];
+    u32x4s sa[KS];
     load_a(0, sa);
     bf16x8s wb[2][KS];
 #pragma unroll
@@ -179,8 +179,7 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
 #pragma unroll
         for (int cc = 0; cc < FT; ++cc) {
             const int ft = FT * c + cc;
-            if constexpr (!QRY) load_a(ft + 1 < nft ? ft + 1 : ft, sn);
-            else if (ft > 0) load_a(ft, sa);
+            if (ft > 0) load_a(ft, sa);
             f32x16s f0 = {}, f1 = {};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
@@ -199,10 +198,7 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
                 *reinterpret_cast<uint2*>(st + (32 + col) * (U * 16) + u) =
                     make_uint2(bf16_pair(f1[4 * g], f1[4 * g + 1]), bf16_pair(f1[4 * g + 2], f1[4 * g + 3]));
             }
-            if constexpr (!QRY) {
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) sa[ks] = sn[ks];
-            }
+
         }
         wave_lds_order();
         if (QRY) {
