@@ -464,8 +464,10 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
     const long long bstep = gridDim.x;
     float4 raw[KS / 4];
     load_coef_f32path<L>(a, blk, col, half, raw);
+    int cur = 0;  // F tile buffer of this block (two, alternating)
     for (; blk < a.nblocks; blk += bstep) {
         const long long p0 = blk * 32;
+        char* ftile = smem + cur * 32 * srow;
         // target rows of this wave's first PF rows: loaded now, used after the
         // matrix-core phase (which hides their latency)
         constexpr int PF = 4;
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int f = f_wave + mt * 32 + g * 8 + half * 4;
-                *reinterpret_cast<float4*>(smem + col * srow + f * 4) =
+                *reinterpret_cast<float4*>(ftile + col * srow + f * 4) =
                     make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
             }
         lds_barrier();
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
         for (int k = 0, r = wave; r < 32; ++k, r += nwaves) {
             const long long row = p0 + r;
             if (row >= a.m) break;
-            const float4* frow = reinterpret_cast<const float4*>(smem + r * srow);
+            const float4* frow = reinterpret_cast<const float4*>(ftile + r * srow);
             float4 f[MAXV], y[MAXV];
             float l1 = 0.f, fy = 0.f, ff = 0.f, yy = 0.f;
 #pragma unroll
@@ -557,7 +559,10 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
                 }
             }
         }
-        lds_barrier();
+        // no barrier: the next block stages F in the other buffer; this one is
+        // rewritten two blocks later, after every wave has passed the next
+        // block's barrier (so has finished reading it)
+        cur ^= 1;
     }
     if (lane == 0) {
         red[0][wave] = l1_acc;
@@ -607,11 +612,11 @@ static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
     DecodeArgs& a = la.d;
     a.FC = a.D;
     a.nchunks = 1;
-    const size_t lds = (size_t)32 * (a.D * 4 + 16);
+    const size_t lds = (size_t)2 * 32 * (a.D * 4 + 16);  // two F tiles
     static bool attr = false;
     if (!attr) {
         if (hipFuncSetAttribute((const void*)k_decode_loss_f32<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                96 * 1024) != hipSuccess)
+                                150 * 1024) != hipSuccess)
             return LS2_ERR_DEVICE;
         attr = true;
     }
