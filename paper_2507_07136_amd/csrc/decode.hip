@@ -505,27 +505,21 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
                     make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
             }
         lds_barrier();
-        // row phase: wave w takes rows w, w + nwaves, ...
-        for (int k = 0, r = wave; r < 32; ++k, r += nwaves) {
+        // row phase: wave w takes rows w, w + nwaves, ...; the first PF of
+        // them use the prefetched target rows (a loop with a fixed trip
+        // count, so the prefetched rows are addressed statically and the
+        // rows' reductions can interleave)
+        auto row_phase = [&](int r, const float4 (&yv)[MAXV]) {
             const long long row = p0 + r;
-            if (row >= a.m) break;
+            if (row >= a.m) return;
             const float4* frow = reinterpret_cast<const float4*>(ftile + r * srow);
             float4 f[MAXV], y[MAXV];
             float l1 = 0.f, fy = 0.f, ff = 0.f, yy = 0.f;
 #pragma unroll
             for (int q = 0; q < MAXV; ++q) {
                 const int v = lane + 64 * q;
-                f[q] = y[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (v < nv4) {
-                    f[q] = frow[v];
-                    if (k < PF) {
-#pragma unroll
-                        for (int kk = 0; kk < PF; ++kk)
-                            if (kk == k) y[q] = ypf[kk][q];
-                    } else {
-                        y[q] = reinterpret_cast<const float4*>(la.target + row * D)[v];
-                    }
-                }
+                f[q] = v < nv4 ? frow[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+                y[q] = yv[q];
                 l1 += fabsf(f[q].x - y[q].x) + fabsf(f[q].y - y[q].y) + fabsf(f[q].z - y[q].z) + fabsf(f[q].w - y[q].w);
                 fy = fmaf(f[q].x, y[q].x, fmaf(f[q].y, y[q].y, fmaf(f[q].z, y[q].z, fmaf(f[q].w, y[q].w, fy))));
                 ff = fmaf(f[q].x, f[q].x, fmaf(f[q].y, f[q].y, fmaf(f[q].z, f[q].z, fmaf(f[q].w, f[q].w, ff))));
@@ -558,6 +552,22 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
                     }
                 }
             }
+        };
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int r = wave + k * nwaves;
+            if (r < 32) row_phase(r, ypf[k]);
+        }
+        for (int r = wave + PF * nwaves; r < 32; r += nwaves) {  // D < 512: more rows per wave
+            const long long row = p0 + r;
+            float4 yv[MAXV];
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) {
+                const int v = lane + 64 * q;
+                yv[q] = (row < a.m && v < nv4) ? reinterpret_cast<const float4*>(la.target + row * D)[v]
+                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            row_phase(r, yv);
         }
         // no barrier: the next block stages F in the other buffer; this one is
         // rewritten two blocks later, after every wave has passed the next
