@@ -332,7 +332,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the splatting path runs on a single MI355X here "
-              "(multi-GPU sharding is described in DESIGN.md but not run); use --gpus 1", file=sys.stderr)
+              "(multi-GPU sharding is not run); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
