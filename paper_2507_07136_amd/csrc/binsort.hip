@@ -26,6 +26,9 @@
 //                   superblock's sorted bucket whose rectangles cover the tile:
 //                   an order-preserving ballot compaction, one wave per tile,
 //                   so every tile list comes out already in (depth, id) order.
+//                   With S = 4 (k_tile_fill_chunks) every 2048-entry chunk of a
+//                   bucket is filled on its own, its list offsets taken from
+//                   per-chunk tile counts that step 4 records.
 #include "ls2_internal.h"
 
 namespace ls2 {

@@ -40,7 +40,6 @@ typedef unsigned u32x4s __attribute__((ext_vector_type(4)));
 typedef float f32x16s __attribute__((ext_vector_type(16)));
 typedef float f32x4s __attribute__((ext_vector_type(4)));
 
-typedef __bf16 bf16x8q __attribute__((ext_vector_type(8)));
 typedef float f32x4q __attribute__((ext_vector_type(4)));
 
 // Coefficient output of the splat kernel.  kOutDecodeQuery: the decode tail
@@ -202,16 +201,16 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
         }
         wave_lds_order();
         if (QRY) {
-            const bf16x8q zero8 = {};
+            const bf16x8s zero8 = {};
 #pragma unroll
             for (int kk = 0; kk < CF / 32; ++kk) {
-                const bf16x8q tb = tcol ? *reinterpret_cast<const bf16x8q*>(a.texts + (size_t)r16 * D + c * CF +
+                const bf16x8s tb = tcol ? *reinterpret_cast<const bf16x8s*>(a.texts + (size_t)r16 * D + c * CF +
                                                                              kk * 32 + g16 * 8)
                                         : zero8;
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb) {
                     const int p = 16 * rb + r16;
-                    const bf16x8q fa = *reinterpret_cast<const bf16x8q*>(
+                    const bf16x8s fa = *reinterpret_cast<const bf16x8s*>(
                         st + p * (U * 16) + (((4 * kk + g16) ^ (p & (U - 1))) * 16));
                     dq[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, tb, dq[rb], 0, 0, 0);
                     gq[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fa, gq[rb], 0, 0, 0);
