@@ -237,6 +237,19 @@ def test_empty_and_culled(orc):
     scene.means[150:, 0] = np.nan
     g = run_forward(cam, scene)
     assert g["P"] == 0 and np.all(g["radius"] == 0) and np.all(g["coef"] == 0)
+    # the one-pass forms on an empty frame: zero features, relevancy 1/2
+    import paper_2507_07136_amd as ls2
+    t = g["t"]
+    p16 = ls2.Pipeline(cam, scene.n, coef_dtype=torch.bfloat16)
+    p16.project(t["means"], t["scales"], t["quats"])
+    assert p16.bin_sort(sync=True) == 0
+    feat = p16.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
+    pos, neg = gen.make_text(6)
+    rel = p16.splat_decode_query(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"],
+                                 torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda())
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(feat).item() == 0
+    assert bool((rel == 0.5).all()) and bool((p16.final_T == 1.0).all()) and bool((p16.last == 0).all())
 
 
 def test_capacity_overflow(orc):
