@@ -442,6 +442,28 @@ def main():
                     stages_ms={k: round(v, 4) for k, v in tper.items()})
     log("two-pass bf16 frame: %s" % two_pass)
 
+    # successive views on two streams (default priority), each with its own
+    # buffers: one view's binning overlaps the previous view's splat tail.
+    # Reported beside the headline, which is the one-stream rate above.
+    pipe_b = ls2.Pipeline(cam, n, levels=levels, K=K, L=L, D=D, coef_dtype=torch.bfloat16)
+    pipe_b.project(t["means"], t["scales"], t["quats"])
+    pipe_b.bin_sort(sync=True)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    pipes2 = [pipe16, pipe_b]
+
+    def two_stream_frames(k):
+        for i in range(k):
+            with torch.cuda.stream(streams[i & 1]):
+                frame(pipes2[i & 1], ls2.LS2_BF16, torch.bfloat16, one_pass=True)
+    two_stream_frames(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    two_stream_frames(args.steps)
+    torch.cuda.synchronize()
+    two_stream_fps = args.steps / (time.perf_counter() - t0)
+    log("one-pass frames on two streams: %.1f FPS" % two_stream_fps)
+    del pipe_b
+
     # query frame, two passes: decode writes the feature map, ls2_query reads it back
     qwall, qper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
     query_fps_two_pass = max(5, args.steps // 2) / qwall
@@ -543,6 +565,7 @@ def main():
                    "pairs": P},
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
         "two_pass_frame": two_pass,
+        "two_stream_fps": round(two_stream_fps, 2),
         "query_fps": round(query_fps, 2),
         "query_fps_without_feature_map": round(query_fps_no_feat, 2),
         "query_fps_decode_epilogue": round(query_fps_epilogue, 2),
