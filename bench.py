@@ -426,20 +426,23 @@ def main():
                  else stages[:5 if (query and not fused) else 4])
         per = {names[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                for i in range(len(names))}
-        return wall, per
+        # per-frame times of the instrumented frames: p10 / median / p90
+        totals = [evs[s][0].elapsed_time(evs[s][len(names)]) for s in range(steps)]
+        pct = [round(float(np.percentile(totals, q)), 4) for q in (10, 50, 90)]
+        return wall, per, pct
 
     # headline: float32 splat accumulation, the coefficients rounded to bf16 and
     # decoded on the matrix cores inside the splat (bf16 feature map)
-    wall, per = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup, one_pass=True)
+    wall, per, per_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup, one_pass=True)
     assert ls2.ls2_bin_sort_count(pipe16.workspace) == P
     fps = args.steps / wall
     ms = 1000.0 * wall / args.steps
     log("one-pass bf16 frame: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
     # the same feature map in two passes: bf16 coefficient map written by the
     # splat, read back by the decode
-    twall, tper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
+    twall, tper, tper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
     two_pass = dict(fps=round(args.steps / twall, 2), ms_per_frame=round(1000.0 * twall / args.steps, 4),
-                    stages_ms={k: round(v, 4) for k, v in tper.items()})
+                    stages_ms={k: round(v, 4) for k, v in tper.items()}, frame_ms_p10_p50_p90=tper_pct)
     log("two-pass bf16 frame: %s" % two_pass)
 
     # successive views on two streams (default priority), each with its own
@@ -465,17 +468,18 @@ def main():
     del pipe_b
 
     # query frame, two passes: decode writes the feature map, ls2_query reads it back
-    qwall, qper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
+    qwall, qper, qper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, max(5, args.steps // 2), 3, query=True)
     query_fps_two_pass = max(5, args.steps // 2) / qwall
     # query frame, relevancy in the decode's epilogue (splat, then decode + relevancy)
     nqs = max(5, args.steps // 2)
-    fqwall, fqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, fused=True)
+    fqwall, fqper, fqper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, fused=True)
     query_fps_epilogue = nqs / fqwall
     # query frame in one pass: splat, decode and relevancy in one kernel (feature map written)
-    oqwall, oqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, one_pass=True)
+    oqwall, oqper, oqper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, one_pass=True)
     query_fps = nqs / oqwall
     # ... and without writing the feature map at all
-    nqwall, nqper = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, one_pass=True, keep_feat=False)
+    nqwall, nqper, nqper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, nqs, 3, query=True, one_pass=True,
+                                   keep_feat=False)
     query_fps_no_feat = nqs / nqwall
     log("query frames: one pass %.1f FPS (splat+decode+relevancy %.4f ms), without the feature map %.1f FPS, "
         "decode epilogue %.1f FPS, two-pass %.1f FPS" % (query_fps, oqper["splat_decode_query"], query_fps_no_feat,
@@ -505,7 +509,7 @@ def main():
 
     f32 = None
     if not args.no_f32:
-        fwall, fper = run(pipe, ls2.LS2_F32, torch.float32, max(5, args.steps // 2), 3)
+        fwall, fper, fper_pct = run(pipe, ls2.LS2_F32, torch.float32, max(5, args.steps // 2), 3)
         f32 = dict(fps=max(5, args.steps // 2) / fwall, stages_ms=fper)
         log("f32 path: %.1f FPS" % f32["fps"])
 
@@ -564,6 +568,7 @@ def main():
                                % (args.config, n, W, H, L, K, D, levels),
                    "pairs": P},
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
+        "frame_ms_p10_p50_p90": per_pct,
         "two_pass_frame": two_pass,
         "two_stream_fps": round(two_stream_fps, 2),
         "query_fps": round(query_fps, 2),
