@@ -15,8 +15,9 @@
 //                   each touched superblock's bucket (LDS histogram again, one
 //                   reserving atomic per workgroup and superblock, LDS cursors);
 //   4. k_sb_sort_radix: one workgroup per superblock sorts its bucket with an
-//                   LSD radix sort in LDS (8-bit digits, stable ballot
-//                   ranking, only the digits that vary within the bucket) and
+//                   LSD radix sort in LDS (8-bit digits of the depth half that
+//                   vary within the bucket, stable ballot ranking; runs of
+//                   equal depth are then put in id order in place) and
 //                   counts, for each of its S x S tiles, the entries whose
 //                   rectangle covers the tile (buckets beyond the LDS
 //                   capacity use a bitonic network in global memory in
@@ -438,24 +439,17 @@ __device__ __forceinline__ void count_sb_tiles(const BinArgs& a, int sb, const u
 
 constexpr int kMaxS2 = 32 * 32;  // tile counters per superblock (S <= 32)
 
-// Superblocks with count <= CAP: least-significant-digit radix sort in LDS,
-// then write back and count tiles.
+// LDS radix sort of one bucket (or one chunk of a large bucket).
 //
-// The 64-bit keys (float32 depth bits << 32 | id) stay in registers: wave w
-// owns the contiguous chunks [w cpw, (w+1) cpw) of 64 positions, lane l of
-// chunk c holds position 64 c + l (positions past the count hold ~0, which
-// sorts last).  Each pass on an 8-bit digit
-//   1. counts the digits of every wave in wave-private LDS counters,
-//   2. turns the counts into scatter offsets (digit-major, then wave order),
-//   3. scatters: within a chunk the lanes holding the same digit find each
-//      other with eight ballots, so a key's destination is its wave's
-//      running offset for the digit plus its rank among those lanes -- the
-//      order of equal digits is kept (stable), which makes the passes an LSD
-//      sort,
-//   4. reloads the keys in the new order.
-// Digits on which every key of the bucket agrees are skipped: in practice the
-// exponent of the depth and the high bits of the id are constant, leaving
-// about six passes.
+// A key is (float32 depth bits << 32 | id); ids are unique inside a bucket,
+// so the keys are too.  The passes run over the digits of the depth half
+// only.  That leaves the keys ordered by depth, with equal depths in arbitrary
+// order.  A fix-up step then orders each run of equal depth by id: a key's
+// place is the start of its run plus the number of the run's keys below it.
+// Equal float32 depths are rare and their runs short.  So the fix-up replaces
+// the id passes: three passes at 10^5..10^6 Gaussians.  A run longer than 16
+// keys (degenerate scenes, e.g. every depth equal) falls back to the full
+// LSD sort over every varying digit of the key.
 constexpr int kRadixCap = 16384;
 constexpr int kRadixWaves = 16;
 
@@ -465,6 +459,7 @@ struct RadixSmem {
     unsigned tcnt[kMaxS2];
     unsigned wsum[4];
     unsigned bits[4];
+    unsigned longrun;           // fix-up found a run of equal depth beyond 64 keys
     unsigned chunk_start[257];  // large buckets: key offset of each chunk
     unsigned nchunks;
 };
@@ -500,6 +495,7 @@ __device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned lon
         }
     }
     if (threadIdx.x < 4) sm.bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
+    if (threadIdx.x == 0) sm.longrun = 0u;
     __syncthreads();
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -516,7 +512,12 @@ __device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned lon
     const unsigned long long varying = (((unsigned long long)sm.bits[1] << 32) | sm.bits[0]) ^
                                        (((unsigned long long)sm.bits[3] << 32) | sm.bits[2]);
 
-    for (int shift = 0; shift < 64; shift += 8) {
+    // Digit sequence: it = 0..3 are the depth half (shift 32..56); after a
+    // fix-up that found a run beyond 64 keys, it = 4..11 are every digit.
+    int it = 0, it_end = 4;
+    for (;;) {
+    for (; it < it_end; ++it) {
+        const int shift = it < 4 ? 32 + 8 * it : 8 * (it - 4);
         if (((varying >> shift) & 0xffull) == 0ull) continue;  // uniform across the workgroup
         // 1. per-wave digit counts
         for (int i = lane; i < 256; i += 64) sm.ctr[w][i] = 0u;
@@ -576,6 +577,43 @@ __device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned lon
         for (int c = 0; c < ITEMS; ++c)
             if (c < mine) key[c] = sm.xbuf[(c0 + c) * 64 + lane];
     }
+    if (it_end == 12 || (unsigned)varying == 0u) break;  // full sort done, or the id half is uniform
+    // Fix-up of equal-depth runs in sm.xbuf (depth-ordered; the last pass, or
+    // the initial copy, ended with a workgroup barrier).  The lane that holds
+    // the first position of a run sorts the run in place by insertion.  Other
+    // lanes only compare depth halves with their neighbours, and every key of
+    // a run has the same depth half, so no barrier is needed in between.
+    constexpr int kRun = 16;  // longest run resolved here
+    bool longrun = false;
+    for (int p = threadIdx.x; p + 1 < cnt; p += blockDim.x) {
+        const unsigned hi = (unsigned)(sm.xbuf[p] >> 32);
+        if ((unsigned)(sm.xbuf[p + 1] >> 32) != hi || (p > 0 && (unsigned)(sm.xbuf[p - 1] >> 32) == hi)) continue;
+        int e = p + 2;
+        while (e < cnt && e - p <= kRun && (unsigned)(sm.xbuf[e] >> 32) == hi) ++e;
+        if (e - p > kRun) {
+            longrun = true;
+            continue;
+        }
+        for (int q = p + 1; q < e; ++q) {
+            const unsigned long long v = sm.xbuf[q];
+            int t = q - 1;
+            while (t >= p && sm.xbuf[t] > v) {
+                sm.xbuf[t + 1] = sm.xbuf[t];
+                --t;
+            }
+            sm.xbuf[t + 1] = v;
+        }
+    }
+    if (__builtin_amdgcn_ballot_w64(longrun) != 0ull && lane == 0) atomicOr(&sm.longrun, 1u);
+    __syncthreads();  // the runs are sorted; the flag is set
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c)
+        if (c < mine) key[c] = sm.xbuf[(c0 + c) * 64 + lane];
+    if (sm.longrun == 0u) break;
+    // Runs beyond kRun keys: every varying digit (it = 4..11), starting from
+    // the current order (a permutation of the keys).
+    it_end = 12;
+    }
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
         if (c < mine) {
@@ -601,9 +639,9 @@ __device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned lon
 //      order of equal digits is kept (stable), which makes the passes an LSD
 //      sort,
 //   4. reloads the keys in the new order.
-// Digits on which every key of the bucket agrees are skipped: in practice the
-// exponent of the depth and the high bits of the id are constant, leaving
-// about six passes.
+// Digits on which every key of the bucket agrees are skipped, and the id half
+// is ordered by the fix-up of equal-depth runs described at radix_sort_lds:
+// in practice three or four passes over the depth digits.
 //
 // Larger buckets are first split by their top eight varying key bits (a
 // most-significant-digit pass through a scratch copy in the free part of the
