@@ -564,3 +564,30 @@ def test_equal_depth_runs_in_id_order(orc):
     assert len(d) - len(np.unique(d)) >= 300
     _check_lists(orc, cam, g)
     _check_coef(orc, cam, scene, g)
+
+
+def test_many_equal_depth_runs_across_buckets(orc):
+    """Depths on a coarse grid across 12 superblocks: buckets hold many runs
+    of 2-16 equal depths (ordered by id by the in-place fix-up after the
+    depth-half passes) and, where 40 Gaussians share one depth in one place,
+    runs beyond 16 (sorted on every key digit instead): lists bit-exact."""
+    rng = np.random.default_rng(31)
+    n_base, n_a, n_b = 20000, 30 * 12, 3 * 40
+    n = n_base + n_a + n_b
+    scene = gen.make_scene(31, n, D=128)
+    m = rng.uniform(-1.0, 1.0, (n, 3))
+    m[:n_base, 2] = np.round(rng.uniform(-1.0, 1.0, n_base) * 1000.0) / 1000.0  # 2001 depth levels
+    off = n_base
+    for size, groups in ((12, 30), (40, 3)):
+        for _ in range(groups):
+            c = rng.uniform(-0.8, 0.8, 2)
+            m[off:off + size, :2] = c + rng.normal(0.0, 0.03, (size, 2))
+            m[off:off + size, 2] = rng.uniform(-1.0, 1.0)
+            off += size
+    scene.means[:] = m.astype(np.float32)
+    scene.scales[:] = 0.02
+    cam = gen.make_camera(256, 192)
+    g = run_forward(cam, scene, keep_keys=True)
+    _, mult = np.unique(g["depth"][g["radius"] > 0], return_counts=True)
+    assert ((mult >= 2) & (mult <= 16)).sum() >= 1000 and mult.max() >= 40
+    _check_lists(orc, cam, g)
