@@ -159,7 +159,7 @@ __device__ __forceinline__ bool sb_rect_of(const BinArgs& a, int i, int& sx0, in
 }
 
 constexpr int kBinThreads = 1024;
-constexpr int kBinPerThread = 4;  // Gaussians per thread in the histogram passes
+constexpr int kBinPerThread = 2;  // Gaussians per thread in the histogram passes (147 workgroups at 300k)
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
