@@ -14,17 +14,20 @@
 // backwards from the largest `last` of its pixels, recovering each pixel's
 // transmittance as T_i = T_{i+1} / (1 - alpha_i) from the stored final
 // transmittance (no per-pixel lists are stored), with alpha recomputed by the
-// same instructions as the forward.  Its level's dL/dW vectors sit in LDS
-// columns so the K wave-uniform indices read them directly.  dL/dalpha is a
-// sum over levels of T_i c_il - S_il / (1 - alpha_i) (S_il: the level's share
-// of S_i), so each level wave adds its own share of the mean / conic /
-// opacity gradients; with one level per wave the LDS footprint stays small
-// enough for several waves per SIMD.  Per Gaussian the wave's 6 + K values are
+// same instructions as the forward.  Each lane holds its pixel's dL/dW vector
+// of the level in registers, and the K wave-uniform indices select from it by
+// register indexing; LDS holds only the staged records, so occupancy is set by
+// registers.  dL/dalpha is a sum over levels of T_i c_il - S_il / (1 - alpha_i)
+// (S_il: the level's share of S_i), so each level wave adds its own share of
+// the mean / conic / opacity gradients; with one level per wave the L-float
+// vector fits in registers with room for several waves per SIMD.  Per Gaussian the wave's 6 + K values are
 // summed over its 64 pixels in one reduce-scatter and added with one atomic
 // instruction (one lane per value).
 #include "splat_common.h"
 
 namespace ls2 {
+
+typedef float v32f_bw __attribute__((ext_vector_type(32)));  // 32 lanes' worth of one pixel's dL/dW
 
 struct SplatBwArgs {
     CamK cam;
@@ -57,13 +60,10 @@ struct BwRec {
 };
 
 template <int NV, int KMAX, bool EXACT>
-__global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
+__global__ __launch_bounds__(64, NV <= 2 ? 3 : 2) void k_splat_backward(SplatBwArgs a) {
     using R = BwRec<KMAX>;
-    constexpr int kStride = 65;
-    constexpr int kRows = NV * 32;  // L
     constexpr int NG = 6 + KMAX;    // gradient values per Gaussian
     __shared__ float4 stage4[64 * R::STRIDE / 4];
-    __shared__ float gcol[(kRows + 1) * kStride];
     float* stage = reinterpret_cast<float*>(stage4);
 
     const CamK& cam = a.cam;
@@ -121,27 +121,23 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
         out_stride = levels * K;
     }
 
-    // dL/dW of the quadrant's pixels at this level into LDS columns
-    for (int i = lane; i < (kRows + 1) * kStride; i += 64) gcol[i] = 0.0f;
-    __syncthreads();
-    {
-        const int f4_per_px = L / 4, f4_per_row = 8 * f4_per_px;
-        for (int ry = 0; ry < 8; ++ry) {
-            const int gy = qy0 + ry;
-            if (gy >= cam.H) break;
-            const float4* rowbase =
-                reinterpret_cast<const float4*>(a.d_coef + ((size_t)lv * HW + (size_t)gy * cam.W + qx0) * L);
-            for (int f = lane; f < f4_per_row; f += 64) {
-                const int pxl = f / f4_per_px, c4 = f - pxl * f4_per_px;
-                if (qx0 + pxl >= cam.W) continue;
-                const float4 v = rowbase[f];
-                float* dst = gcol + (4 * c4) * kStride + ry * 8 + pxl;
-                dst[0] = v.x;
-                dst[kStride] = v.y;
-                dst[2 * kStride] = v.z;
-                dst[3 * kStride] = v.w;
+    // dL/dW of this lane's pixel at this level, in registers: the K
+    // wave-uniform indices of a Gaussian select from it by register indexing
+    v32f_bw gv[NV];
+#pragma unroll
+    for (int h = 0; h < NV; ++h) gv[h] = (v32f_bw){};
+    if (inside) {
+        const float4* src = reinterpret_cast<const float4*>(a.d_coef + ((size_t)lv * HW + pix) * (size_t)(NV * 32));
+#pragma unroll
+        for (int h = 0; h < NV; ++h)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float4 v = src[h * 8 + q];
+                gv[h][4 * q] = v.x;
+                gv[h][4 * q + 1] = v.y;
+                gv[h][4 * q + 2] = v.z;
+                gv[h][4 * q + 3] = v.w;
             }
-        }
     }
 
     float S = 0.0f;  // this level's sum over later contributors of c_m e_m
@@ -247,14 +243,16 @@ __global__ __launch_bounds__(64) void k_splat_backward(SplatBwArgs a) {
                 T = T * inv_one_m;  // transmittance in front of this Gaussian
                 const float e = alpha * T;
                 float c = 0.0f;
-                const float* col = gcol + lane;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k) {
                     if (k < K) {
-                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;
-                        const float gv = col[(int)ix * kStride];
-                        c = fmaf(gv, r[R::W + k], c);
-                        vals[6 + k] = gv * e;
+                        const unsigned ix = (words[k >> 2] >> (8 * (k & 3))) & 0xffu;  // < L, wave-uniform
+                        float gk = 0.0f;
+#pragma unroll
+                        for (int h = 0; h < NV; ++h)
+                            if ((int)(ix >> 5) == h) gk = gv[h][ix & 31u];
+                        c = fmaf(gk, r[R::W + k], c);
+                        vals[6 + k] = gk * e;
                     }
                 }
                 const float dalpha = T * c - S * inv_one_m;
