@@ -459,7 +459,8 @@ struct RadixSmem {
     unsigned tcnt[kMaxS2];
     unsigned wsum[4];
     unsigned bits[4];
-    unsigned longrun;           // fix-up found a run of equal depth beyond 64 keys
+    unsigned longrun;           // fix-up found a run of equal depth beyond 16 keys
+    unsigned hmin, hmax;        // large buckets: range of the keys' depth halves
     unsigned chunk_start[257];  // large buckets: key offset of each chunk
     unsigned nchunks;
 };
@@ -643,9 +644,9 @@ __device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned lon
 // is ordered by the fix-up of equal-depth runs described at radix_sort_lds:
 // in practice three or four passes over the depth digits.
 //
-// Larger buckets are first split by their top eight varying key bits (a
-// most-significant-digit pass through a scratch copy in the free part of the
-// pool); runs of consecutive digit bins of at most kRadixCap keys are then
+// Larger buckets are first split into 256 bins over the range of their depth
+// bits (a most-significant-digit pass through a scratch copy in the free part
+// of the pool); runs of consecutive digit bins of at most kRadixCap keys are then
 // sorted as above, in key order, back into the bucket.  Only a bucket with a
 // single digit bin beyond kRadixCap, or a pool without room for the scratch
 // copy, uses the bitonic network in global memory.
@@ -668,20 +669,29 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
         return;
     }
     unsigned long long* tmp = a.pool + total + a.sb_start[sb];
-    // varying bits of the bucket
+    // varying bits of the bucket, and the range of its depth halves
     unsigned long long kor = 0ull, kand = ~0ull;
+    unsigned hlo = 0xffffffffu, hhi = 0u;
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
         const unsigned long long k = g[e];
         kor |= k;
         kand &= k;
+        hlo = min(hlo, (unsigned)(k >> 32));
+        hhi = max(hhi, (unsigned)(k >> 32));
     }
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         kor |= __shfl_xor(kor, off);
         kand &= __shfl_xor(kand, off);
+        hlo = min(hlo, (unsigned)__shfl_xor((int)hlo, off));
+        hhi = max(hhi, (unsigned)__shfl_xor((int)hhi, off));
     }
     if (threadIdx.x < 4) sm.bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
+    if (threadIdx.x == 0) {
+        sm.hmin = 0xffffffffu;
+        sm.hmax = 0u;
+    }
     for (int i = threadIdx.x; i < 256; i += blockDim.x) sm.ctr[0][i] = 0u;
     __syncthreads();
     if (lane == 0) {
@@ -689,14 +699,28 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
         atomicOr(&sm.bits[1], (unsigned)(kor >> 32));
         atomicAnd(&sm.bits[2], (unsigned)kand);
         atomicAnd(&sm.bits[3], (unsigned)(kand >> 32));
+        atomicMin(&sm.hmin, hlo);
+        atomicMax(&sm.hmax, hhi);
     }
     __syncthreads();
     const unsigned long long varying = (((unsigned long long)sm.bits[1] << 32) | sm.bits[0]) ^
                                        (((unsigned long long)sm.bits[3] << 32) | sm.bits[2]);
     const int top = varying ? 63 - __builtin_clzll(varying) : 0;
-    const int dshift = top >= 7 ? top - 7 : 0;  // the top eight varying bits (or fewer)
-    // histogram of the top digit
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) atomicAdd(&sm.ctr[0][(unsigned)(g[e] >> dshift) & 0xffu], 1u);
+    // Split digit, non-decreasing in the key so that the digit bins are
+    // consecutive key ranges.  With varying depths it spreads the depth
+    // halves' range over 256 bins; a power-of-two window of the key bits
+    // would mostly see the float exponent (e.g. depths 1.5..4.5 give three
+    // values), leaving bins too full for the LDS sort.  If every depth is
+    // equal, the top eight varying bits (of the id) instead.
+    const unsigned hmin = sm.hmin, hrange = sm.hmax - sm.hmin;
+    const float hscale = 256.0f / ((float)hrange + 1.0f);
+    const int dshift = top >= 7 ? top - 7 : 0;
+    auto split_digit = [=](unsigned long long k) -> unsigned {
+        if (hrange == 0u) return (unsigned)(k >> dshift) & 0xffu;
+        return min(255u, (unsigned)((float)((unsigned)(k >> 32) - hmin) * hscale));
+    };
+    // histogram of the split digit
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) atomicAdd(&sm.ctr[0][split_digit(g[e])], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         // digit offsets, and runs of consecutive digits of at most kRadixCap keys
@@ -724,11 +748,11 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
         count_sb_tiles(a, sb, g, cnt, sm.tcnt);
         return;
     }
-    // scatter into the scratch copy by top digit (order inside a bin is not
+    // scatter into the scratch copy by split digit (order inside a bin is not
     // needed: every chunk is fully sorted next)
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
         const unsigned long long k = g[e];
-        tmp[atomicAdd(&sm.ctr[1][(unsigned)(k >> dshift) & 0xffu], 1u)] = k;
+        tmp[atomicAdd(&sm.ctr[1][split_digit(k)], 1u)] = k;
     }
     __threadfence_block();
     __syncthreads();
