@@ -20,8 +20,10 @@
 //                   equal depth are then put in id order in place) and
 //                   counts, for each of its S x S tiles, the entries whose
 //                   rectangle covers the tile (buckets beyond the LDS
-//                   capacity use a bitonic network in global memory in
-//                   the same workgroup);
+//                   capacity are first split into 256 bins over their depth
+//                   range, and runs of bins are sorted in LDS; only a single
+//                   over-full bin falls back to a bitonic network in global
+//                   memory in the same workgroup);
 //   5. k_tile_scan: one workgroup: tile ranges (row-major) and P;
 //   6. k_tile_fill: each tile's list is the ordered subsequence of its
 //                   superblock's sorted bucket whose rectangles cover the tile:
