@@ -292,6 +292,28 @@ def test_long_tile_lists(orc):
     _check_lists(orc, cam, g2)
 
 
+def test_large_bucket_depths_across_exponents(orc):
+    """40000 Gaussians in one superblock with depths from 1.5 to 4.5, across
+    three float exponents: the bucket is split into bins over its depth range
+    (the float exponent alone would give three over-full bins) and each run of
+    bins is sorted in LDS; lists bit-exact."""
+    rng = np.random.default_rng(14)
+    n = 40000
+    scene = gen.make_scene(14, n, D=128)
+    m = np.empty((n, 3))
+    m[:, :2] = rng.normal(0, 0.01, (n, 2))
+    m[:, 2] = rng.uniform(-1.5, 1.5, n)
+    scene.means[:] = m.astype(np.float32)
+    scene.scales[:] = 0.002
+    cam = gen.make_camera(64, 64)
+    g = run_forward(cam, scene)
+    d = g["depth"][g["radius"] > 0]
+    assert d.min() < 2.0 and d.max() > 4.0
+    lens = g["ranges"][:, 1] - g["ranges"][:, 0]
+    assert lens.max() > 16384
+    _check_lists(orc, cam, g)
+
+
 def test_bucket_with_one_heavy_depth_bin(orc):
     """20000 Gaussians at exactly one depth and one much nearer: the top
     digit of the bucket cannot split the pile, so it takes the global-memory
