@@ -367,6 +367,73 @@ static int walk_pixel(double pxc, double pyc, uint32_t start, uint32_t end, cons
     return cnt;
 }
 
+/* ------------------------------------------------------------------ */
+/* The same walk with chosen alternatives at its near decisions.       */
+/* A float32 evaluation of a decision whose float64 value lies within   */
+/* rounding of its threshold may legitimately come out the other way,  */
+/* so a parity check compares the kernel with every outcome the walk    */
+/* can take when such decisions are flipped.  Three decisions of Eq. 3  */
+/* are discontinuous in the inputs and can flip:                       */
+/*   - the skip of a non-positive-definite exponent (power > 0), near   */
+/*     when |power| <= thr * (|A| dx^2 / 2 + |B dx dy| + |C| dy^2 / 2);   */
+/*   - the skip of alpha < 1/255, near when |alpha - 1/255| <= thr/255;   */
+/*   - the stop once T (1 - alpha) < 1e-4, near when its condition-     */
+/*     scaled margin (as in walk_pixel) is below thr.                   */
+/* The clamp at 0.99 is continuous in the inputs and is not flipped.    */
+/* Bit b of `flips` takes the b-th near decision met along this walk    */
+/* the other way (bits past the last near decision are ignored);        */
+/* *n_near = the number of near decisions met.  With flips = 0 the walk */
+/* is walk_pixel's.                                                     */
+/* ------------------------------------------------------------------ */
+static int walk_pixel_alt(double pxc, double pyc, uint32_t start, uint32_t end, const uint32_t* ids,
+                          const double* mean2d, const double* conic, const double* opacity, double thr,
+                          uint32_t flips, int32_t* pos_out, double* e_out, double* T_out, int32_t* last_out,
+                          int* n_near) {
+    double T = 1.0;
+    int cnt = 0, near = 0;
+    int32_t last = 0;
+    double cond = 1.0;
+    for (uint32_t pos = start; pos < end; ++pos) {
+        uint32_t i = ids[pos];
+        double dx = mean2d[2 * i] - pxc;
+        double dy = mean2d[2 * i + 1] - pyc;
+        double A = conic[3 * i], B = conic[3 * i + 1], C = conic[3 * i + 2];
+        double power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
+        int skip = power > 0;
+        double scale = 0.5 * fabs(A) * dx * dx + fabs(B * dx * dy) + 0.5 * fabs(C) * dy * dy;
+        if (fabs(power) <= thr * scale) {
+            if ((flips >> near) & 1u) skip = !skip;
+            ++near;
+        }
+        if (skip) continue;
+        double g = opacity[i] * exp(power);
+        double alpha = g < ALPHA_MAX ? g : ALPHA_MAX;
+        skip = alpha < ALPHA_MIN;
+        if (fabs(alpha - ALPHA_MIN) <= thr * ALPHA_MIN) {
+            if ((flips >> near) & 1u) skip = !skip;
+            ++near;
+        }
+        if (skip) continue;
+        double testT = T * (1.0 - alpha);
+        int stop = testT < T_MIN;
+        if (fabs(testT - T_MIN) / T_MIN / (cond + alpha / (1.0 - alpha) + 0.02) < thr) {
+            if ((flips >> near) & 1u) stop = !stop;
+            ++near;
+        }
+        if (stop) break;
+        cond += alpha / (1.0 - alpha) + 0.02;
+        if (pos_out) pos_out[cnt] = (int32_t)(pos - start);
+        if (e_out) e_out[cnt] = alpha * T;
+        ++cnt;
+        T = testT;
+        last = (int32_t)(pos - start + 1);
+    }
+    *T_out = T;
+    *last_out = last;
+    *n_near = near;
+    return cnt;
+}
+
 static uint32_t max_range(const uint32_t* ranges, int ntiles) {
     uint32_t m = 0;
     for (int t = 0; t < ntiles; ++t) {
@@ -503,6 +570,49 @@ void orc_composite_pixels(const double* cam_arr, int levels, int K, int L, const
             last[q] = lst;
             margin[q] = mg;
             margin_T[q] = mgT;
+        }
+        free(pos);
+        free(e);
+    }
+}
+
+/* orc_composite_pixels with the near decisions of pixel q taken as     */
+/* flips[q] selects (walk_pixel_alt); n_near[q] = the number of near    */
+/* decisions that pixel's walk met.  coef: [npix, levels, L].           */
+void orc_composite_pixels_alt(const double* cam_arr, int levels, int K, int L, const uint32_t* ranges,
+                              const uint32_t* ids, const double* mean2d, const double* conic,
+                              const double* opacity, const int32_t* topk_idx, const double* topk_w,
+                              int64_t npix, const int64_t* pix, const uint32_t* flips, double thr, double* coef,
+                              double* final_T, int32_t* last, int32_t* n_near) {
+    cam_t cam = cam_from(cam_arr);
+    uint32_t maxlen = max_range(ranges, cam.tx * cam.ty);
+    memset(coef, 0, sizeof(double) * (size_t)npix * levels * L);
+    #pragma omp parallel
+    {
+        int32_t* pos = (int32_t*)malloc(sizeof(int32_t) * (maxlen + 1));
+        double* e = (double*)malloc(sizeof(double) * (maxlen + 1));
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < npix; ++q) {
+            int px = (int)(pix[q] % cam.W), py = (int)(pix[q] / cam.W);
+            int t = (py / ORC_TILE) * cam.tx + px / ORC_TILE;
+            double T;
+            int32_t lst;
+            int nn;
+            int cnt = walk_pixel_alt(px + 0.5, py + 0.5, ranges[2 * t], ranges[2 * t + 1], ids, mean2d, conic,
+                                     opacity, thr, flips[q], pos, e, &T, &lst, &nn);
+            for (int c = 0; c < cnt; ++c) {
+                uint32_t i = ids[ranges[2 * t] + pos[c]];
+                for (int lv = 0; lv < levels; ++lv) {
+                    double* W = coef + ((size_t)q * levels + lv) * L;
+                    for (int k = 0; k < K; ++k) {
+                        size_t o = ((size_t)i * levels + lv) * K + k;
+                        W[topk_idx[o]] += topk_w[o] * e[c];
+                    }
+                }
+            }
+            final_T[q] = T;
+            last[q] = lst;
+            n_near[q] = nn;
         }
         free(pos);
         free(e);

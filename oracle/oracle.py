@@ -61,6 +61,9 @@ def _declare(L):
     L.orc_composite_pixels.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P,
                                        _P, _P, i64, _P, _P, _P, _P, _P, _P]
     L.orc_composite_pixels.restype = None
+    L.orc_composite_pixels_alt.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P,
+                                           _P, _P, i64, _P, _P, f64, _P, _P, _P, _P]
+    L.orc_composite_pixels_alt.restype = None
     L.orc_composite_bruteforce.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]
     L.orc_composite_bruteforce.restype = None
@@ -195,6 +198,30 @@ def composite_pixels(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
     if with_margin_T:
         return coef, fT, last, margin, margin_T
     return coef, fT, last, margin
+
+
+def composite_pixels_alt(cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L, pix, flips, thr=1e-5):
+    """``composite_pixels`` with the near decisions of Eq. 3 (a skip of a
+    positive exponent, a skip below alpha = 1/255, the transmittance stop;
+    near = within ``thr`` of the threshold, relative, the stop's margin
+    divided by the transmittance's condition number) taken the other way
+    where bit b of ``flips[q]`` is set, b counting the near decisions met
+    along pixel q's walk.  Returns coef (npix, levels, L), final_T, last and
+    n_near (npix,): the number of near decisions each walk met."""
+    n, levels, K = topk_idx.shape
+    pix = _c(pix, np.int64)
+    npix = pix.shape[0]
+    fl = _c(np.broadcast_to(np.asarray(flips, np.uint32), (npix,)), np.uint32)
+    coef = np.zeros((npix, levels, L))
+    fT = np.zeros(npix)
+    last = np.zeros(npix, np.int32)
+    n_near = np.zeros(npix, np.int32)
+    ids = _c(ids, np.uint32)
+    args = [_c(ranges, np.uint32), ids if ids.size else np.zeros(1, np.uint32), _c(mean2d, np.float64),
+            _c(conic, np.float64), _c(opacity, np.float64), _c(topk_idx, np.int32), _c(topk_w, np.float64)]
+    lib().orc_composite_pixels_alt(_p(cam_array(cam)), levels, K, L, *[_p(a) for a in args], npix, _p(pix),
+                                   _p(fl), float(thr), _p(coef), _p(fT), _p(last), _p(n_near))
+    return coef, fT, last, n_near
 
 
 def composite_dense(cam, ranges, ids, mean2d, conic, opacity, feat):
