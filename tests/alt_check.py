@@ -25,8 +25,9 @@ def check_flips(orc, cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
     array over sel: whether the kernel's outputs of pixels pix[sel] match the
     given oracle outcome (coef [len(sel), levels, L], final_T, last).  base:
     the plain walk of every pixel of pix (coef [npix, levels, L], final_T,
-    last) if already computed.  Returns a dict of counts and the indices
-    (into pix) of the unmatched pixels; asserts the 0.1 % bar."""
+    last) if already computed.  Returns a dict of counts, the indices (into
+    pix) of the unmatched pixels, the mask of pixels that match the plain walk
+    (base_ok) and that walk (base); asserts the 0.1 % bar."""
     args = (cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w, L)
     pix = np.asarray(pix, np.int64)
     npix = pix.shape[0]
@@ -53,7 +54,7 @@ def check_flips(orc, cam, ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
             matched[sel] |= np.asarray(close(bad[sel], c2, t2, l2), bool)
     unmatched = bad[~matched]
     res = dict(checked=npix, base_mismatch=int(bad.size), matched_flip=int(matched.sum()),
-               unmatched=int(unmatched.size), unmatched_idx=unmatched)
+               unmatched=int(unmatched.size), unmatched_idx=unmatched, base_ok=ok, base=(coef, fT, last))
     print("%s%d pixels checked: %d match the oracle walk, %d match it with near decisions flipped, %d match neither"
           % (label + ": " if label else "", npix, npix - bad.size, res["matched_flip"], res["unmatched"]))
     assert unmatched.size <= UNMATCHED_FRAC * npix, (

@@ -51,6 +51,24 @@ def oracle_composite_from_gpu(orc, cam, scene, g):
                          with_margin_T=True)
 
 
+def by_pixel(a):
+    """[levels, H, W, C] -> [H W, levels, C] (pixel-major, as the flip check
+    takes outcomes)."""
+    lv, H, W, C = a.shape
+    return np.ascontiguousarray(a.transpose(1, 2, 0, 3)).reshape(H * W, lv, C)
+
+
+def flip_check_gpu_lists(orc, cam, scene, g, close, pix=None, base=None, label=""):
+    """check_flips on the GPU's own lists and float32 projection (stage
+    isolation); pix defaults to every pixel."""
+    from alt_check import check_flips
+    if pix is None:
+        pix = np.arange(cam.width * cam.height)
+    return check_flips(orc, cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64),
+                       g["conic"].astype(np.float64), scene.opacity, scene.topk_idx, scene.topk_w, scene.L, pix,
+                       close, base=base, label=label)
+
+
 def small_scene(seed, n, w, h, L=64, K=4, levels=1, D=512):
     scene = gen.make_scene(seed, n, L=L, K=K, D=D, levels=levels)
     cam = gen.make_camera(w, h)

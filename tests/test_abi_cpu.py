@@ -84,6 +84,31 @@ def test_argument_validation_without_device(L):
     assert L.ls2_query(10, 512, V(16), 0, V(16), 9, V(16), ctypes.c_float(1.0), V(16), None) == -3
 
 
+def test_camera_validation_without_device(L):
+    """A near plane that is not finite and positive, or non-finite
+    intrinsics, is rejected before any launch (sort keys are the bits of a
+    positive depth)."""
+    V = ctypes.c_void_p
+    args = [V(16)] * 7 + [None]
+    for field, value in (("znear", 0.0), ("znear", -0.2), ("znear", float("nan")), ("znear", float("inf")),
+                         ("fx", float("inf")), ("cy", float("nan"))):
+        c = _cam()
+        setattr(c, field, value)
+        assert L.ls2_project(ctypes.byref(c), 1, *args, None) == -1, (field, value)
+    c = _cam()
+    c.world_to_cam[3] = float("nan")
+    assert L.ls2_project(ctypes.byref(c), 1, *args, None) == -1
+    c = _cam()
+    c.znear = 1e-3
+    assert L.ls2_project(ctypes.byref(c), 0, *args, None) == 0
+
+
+def test_set_check_toggles(L):
+    prev = L.ls2_set_check(1)
+    assert L.ls2_set_check(0) == 1
+    assert L.ls2_set_check(prev) == 0
+
+
 def test_bin_sort_workspace_and_validation(L):
     c = _cam()
     b = ctypes.c_size_t(0)

@@ -12,7 +12,10 @@ parity tests (each stage consumes the GPU's own float32 upstream state):
     within 4 float32 ulps of max(|u - cx|, cx), depth 1e-6 relative, conic
     1e-4 relative, radius exact away from integer extents;
   - binning: ids and tile ranges bit-exact over all 48M pairs;
-  - compositing of 3000 sampled pixels, all levels: |dW| <= 2e-5;
+  - compositing of 3000 sampled pixels, all levels: |dW| <= 1e-5, |dT| <=
+    1e-5, last exact; every sampled pixel checked, a pixel that misses the
+    oracle's walk matching it with some near decisions flipped, at most
+    0.1 % matching neither (tests/alt_check.py);
   - float32 decode fused with the L1 + cosine loss: feature rows |dF| <=
     1e-5 and dL/dF rows of 2000 sampled rows (the loss is a mean over rows,
     so a row's gradient is the oracle's gradient over the sampled rows times
@@ -35,7 +38,8 @@ import pytest
 import torch
 
 import gen
-from gpu_common import gpu_available, grad_close
+from alt_check import coef_close
+from gpu_common import flip_check_gpu_lists, gpu_available, grad_close
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -106,7 +110,9 @@ def test_full_form_bin_sort_bit_exact(orc, c5):
 
 @pytest.fixture(scope="module")
 def c5_pixels(orc, c5):
-    """Oracle compositing of 3000 sampled pixels from the GPU's lists."""
+    """Oracle compositing of 3000 sampled pixels from the GPU's lists; ok
+    marks those with no decision within 1e-5 of its threshold (the backward
+    check draws its pixels from them)."""
     scene, cam, tr, t, Y, g = c5
     rng = np.random.default_rng(52)
     pix = rng.choice(cam.width * cam.height, 3000, replace=False)
@@ -114,21 +120,20 @@ def c5_pixels(orc, c5):
         cam, g["ranges"], g["ids"], g["mean2d"].astype(np.float64), g["conic"].astype(np.float64), scene.opacity,
         scene.topk_idx, scene.topk_w, scene.L, pix, with_margin_T=True)
     ok = (margin >= MARGIN) & (margin_T >= MARGIN)
-    print("near-threshold pixels excluded: %d of %d" % ((~ok).sum(), ok.size))
-    assert (~ok).sum() <= 0.01 * ok.size
+    print("pixels with a decision near its threshold: %d of %d" % ((~ok).sum(), ok.size))
     return pix, coef, fT, last, ok
 
 
-def test_full_form_splat_sampled(c5, c5_pixels):
+def test_full_form_splat_sampled(orc, c5, c5_pixels):
     scene, cam, tr, t, Y, g = c5
     pix, coef, fT, last, ok = c5_pixels
     HW = cam.width * cam.height
-    for lv in range(scene.levels):
-        got = _rows(tr.coef[lv].reshape(HW, scene.L), pix)
-        err = np.abs(got - coef[:, lv]).max(axis=1)
-        assert err[ok].max() <= 2e-5, (lv, err[ok].max())
-    assert np.abs(_rows(tr.final_T.reshape(HW, 1), pix)[:, 0] - fT)[ok].max() <= 2e-5
-    assert np.array_equal(_rows(tr.last.reshape(HW, 1), pix)[:, 0].astype(np.int64)[ok], last[ok])
+    got = np.stack([_rows(tr.coef[lv].reshape(HW, scene.L), pix) for lv in range(scene.levels)], axis=1)
+    err = np.abs(got - coef).reshape(len(pix), -1).max(axis=1)
+    print("full-form coefficient max err %.3e" % err.max())
+    close = coef_close(got, _rows(tr.final_T.reshape(HW, 1), pix)[:, 0],
+                       _rows(tr.last.reshape(HW, 1), pix)[:, 0].astype(np.int64), 1e-5)
+    flip_check_gpu_lists(orc, cam, scene, g, close, pix=pix, base=(coef, fT, last), label="full form")
 
 
 def test_full_form_decode_loss_sampled(orc, c5):

@@ -201,3 +201,28 @@ def test_project_grad_quat_scale_invariance(orc):
     _, _, dq = orc.project_backward(cam, means, scales, quats, pr["radius"], rng.normal(size=(n, 2)),
                                     rng.normal(size=(n, 3)), f64=True)
     np.testing.assert_allclose(np.sum(dq * quats, 1), 0.0, atol=1e-10)
+
+
+def test_chain_fd_config3_scene(orc):
+    """The oracle's composed backward (loss -> decode -> splat -> project,
+    Sections 3.1-3.4) against central differences of its whole float64
+    forward on the finite-difference scene of the differentiation workload
+    (500 Gaussians, 64x64, L = 64, K = 4, D = 512, L1 + cosine loss against
+    a smooth random target), for sampled parameters of every kind: means,
+    scales, quaternions, opacities, code weights and the codebook.
+    Perturbations that change a decision are excluded and counted."""
+    from fd_chain import KINDS, Chain
+    ch = Chain(orc)
+    fw = ch.forward(ch.p0)
+    g = ch.analytic(fw=fw)
+    idx = ch.sample(g, 12, 7)
+    res = ch.fd(idx)
+    for k in KINDS:
+        vals, kept = res[k]
+        assert kept.sum() >= 0.8 * len(kept), (k, int(kept.sum()))
+        a = g[k].flat[idx[k]][kept]
+        v = vals[kept]
+        # float64 differences: truncation O(h^2) and term rounding, far below
+        print("%-10s %d/%d kept, max rel err %.2e" % (k, kept.sum(), len(kept),
+                                                      (np.abs(a - v) / np.abs(v)).max()))
+        assert np.all(np.abs(a - v) <= 1e-5 * np.abs(v) + 1e-8 * np.abs(g[k]).max()), k
