@@ -14,6 +14,14 @@
  *     LS2_ERR_UNSUPPORTED.  A HIP launch failure returns LS2_ERR_DEVICE.
  *   - Pixel (px, py) is sampled at (px + 0.5, py + 0.5).  Screen tiles are
  *     16 x 16 pixels, numbered row-major: tile = ty * ceil(W/16) + tx.
+ *   - Code indices (topk_idx) must lie in [0, L).  By default they are taken
+ *     modulo L (L is a power of two), so a bad index never reads or writes
+ *     out of bounds but lands on another atom.  With the environment variable
+ *     LS2_CHECK=1, or after ls2_set_check(1), every entry point that reads
+ *     topk_idx first scans it and returns LS2_ERR_ARG if any index is out of
+ *     range; the scan synchronises the stream once (a debugging mode, not for
+ *     stream capture, and concurrent checking calls on one device share one
+ *     flag word).
  */
 #ifndef LS2_H
 #define LS2_H
@@ -47,12 +55,19 @@ typedef struct ls2_camera {
     float world_to_cam[12];
     float znear;               /* Gaussians with camera z <= znear are culled */
 } ls2_camera;
+/* Every entry point taking a camera returns LS2_ERR_ARG unless width and
+ * height are in [1, 32768], the intrinsics and world_to_cam are finite and
+ * znear is finite and > 0. */
 
 /* Human-readable text for a status code (static storage). */
 const char* ls2_status_string(int status);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int ls2_version(void);
+
+/* Turns the code-index check on (enabled != 0) or off for the whole process,
+ * overriding LS2_CHECK; returns the previous setting (0 or 1). */
+int ls2_set_check(int enabled);
 
 /*
  * ls2_project -- per-Gaussian projection to the image plane.
@@ -82,7 +97,7 @@ int ls2_project(const ls2_camera* cam, int32_t n, const float* means, const floa
 /*
  * ls2_bin_sort -- tile binning and per-tile depth order.
  *
- * Eq. 3 composites "the ordered Gaussian points within a tile": every visible
+ * Eq. 3 composites each tile's Gaussians in front-to-back order: every visible
  * Gaussian contributes one (tile, Gaussian) pair per tile of its rectangle
  * (same float32 rule as ls2_project), and each tile's pairs are ordered by
  * float32 depth, ties broken by Gaussian id (a unique, total order).
@@ -249,7 +264,7 @@ int ls2_dict_decode_query(int64_t m, int32_t L, int32_t D, const void* coef, int
 /*
  * ls2_query -- relevancy of each feature to a text query.
  *
- * Section 3.2 computes relevancy "following LERF": with cosine similarities
+ * Section 3.2 scores relevancy as LERF does: with cosine similarities
  * s_q = cos(F, pos), s_j = cos(F, neg_j) against n_neg canonical negatives,
  *     r = min_j exp(tau s_q) / (exp(tau s_q) + exp(tau s_j))
  *       = sigmoid(tau (s_q - max_j s_j)).

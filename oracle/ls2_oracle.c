@@ -232,8 +232,8 @@ void orc_project_f64(const double* cam_arr, int n, const double* means, const do
 }
 
 /* ------------------------------------------------------------------ */
-/* Tile binning and depth order (the "ordered Gaussian points within a  */
-/* tile" of Eq. 3).  One (tile, Gaussian) pair per tile of the         */
+/* Tile binning and depth order (Eq. 3 composites each tile's          */
+/* Gaussians front to back).  One (tile, Gaussian) pair per tile of the */
 /* rectangle; pairs ordered by tile, then float32 depth, then id.       */
 /* Outputs keys = tile << 32 | float32 bits of depth, ids, and per-tile */
 /* [start, end) ranges.  Returns 0, or -2 when cap < P (num_pairs = P). */
@@ -747,7 +747,7 @@ void orc_decode_bf16(int64_t M, int L, int D, const float* coef, const float* di
 }
 
 /* ------------------------------------------------------------------ */
-/* Relevancy (Section 3.2, "following LERF"): with cosine similarities  */
+/* Relevancy (Section 3.2, which takes LERF's score): with cosine      */
 /* s_q = cos(F, q) and s_j = cos(F, c_j) against the canonical          */
 /* negatives, r = min_j exp(tau s_q) / (exp(tau s_q) + exp(tau s_j)).  */
 /* A zero feature (norm below 1e-12) has cosine 0 with everything.     */

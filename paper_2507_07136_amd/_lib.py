@@ -45,6 +45,7 @@ def _load():
     sig = {
         "ls2_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "ls2_version": ([], ctypes.c_int),
+        "ls2_set_check": ([ctypes.c_int], ctypes.c_int),
         "ls2_project": ([cam, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_bin_sort_workspace": ([cam, i32, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_bin_sort": ([cam, i32, P, P, P, i64, P, P, P, ctypes.POINTER(ctypes.c_int64), P, ctypes.c_size_t, P],
@@ -98,6 +99,12 @@ def status_string(status: int) -> str:
 
 def version() -> int:
     return int(_lib.ls2_version())
+
+
+def set_check(enabled: bool) -> bool:
+    """Code-index check on or off for the process (LS2_CHECK); returns the
+    previous setting."""
+    return bool(_lib.ls2_set_check(int(bool(enabled))))
 
 
 def _check(fn, status):

@@ -1,6 +1,6 @@
 // ls2_bin_sort: (tile, Gaussian) pairs grouped by tile and ordered by
-// (float32 depth, id) inside each tile -- the "ordered Gaussian points within
-// a tile" that Eq. 3 composites.
+// (float32 depth, id) inside each tile: the front-to-back order in which
+// Eq. 3 composites a tile's Gaussians.
 //
 // The P (tile, Gaussian) pairs (about 33 per Gaussian at 1440x1080) are never
 // sorted or counted with atomics one by one.  The expensive part works on

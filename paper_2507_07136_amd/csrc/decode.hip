@@ -430,7 +430,8 @@ struct DecodeLossArgs {
     const float* target;
     float* d_feat;
     float* feat;        // optional
-    double* partial;    // [gridDim.x][2]
+    CSum* partial;      // [gridDim.x][2]
+    float inv_md, inv_m;
 };
 
 __device__ __forceinline__ float sgn_dl(float e) { return e > 0.f ? 1.f : (e < 0.f ? -1.f : 0.f); }
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
     constexpr int MT = 2;
     constexpr int MAXV = 2;  // float4s per lane in a row: D <= 512
     extern __shared__ float4 smem4[];
-    __shared__ double red[2][8];
+    __shared__ CSum red[2][8];
     char* smem = reinterpret_cast<char*>(smem4);
     const DecodeArgs& a = la.d;
     const int D = a.D;  // == FC: one chunk
@@ -451,8 +452,8 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
     const int col = lane & 31, half = lane >> 5;
     const int f_wave = wave * (MT * 32);
     const int nv4 = D / 4;
-    const float inv_md = (float)(1.0 / ((double)a.m * D)), inv_m = (float)(1.0 / (double)a.m);
-    double l1_acc = 0.0, lc_acc = 0.0;
+    const float inv_md = la.inv_md, inv_m = la.inv_m;
+    CSum l1_acc{}, lc_acc{};
 
     float sa[MT][KS];
 #pragma unroll
@@ -532,8 +533,8 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
             const float nf = sqrtf(ff), ny = sqrtf(yy);
             const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
             const float cs = fy / (gf * gy);
-            l1_acc += (double)l1;
-            lc_acc += (double)(1.0f - cs);
+            l1_acc.add(l1);
+            lc_acc.add(1.0f - cs);
             const float ay = inv_m / (gf * gy);
             const float bf = nf > 1e-12f ? inv_m * fy / (nf * nf * nf * gy) : 0.f;
 #pragma unroll
@@ -580,38 +581,13 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s0 = 0.0, s1 = 0.0;
+        CSum s0{}, s1{};
         for (int w = 0; w < nwaves; ++w) {
-            s0 += red[0][w];
-            s1 += red[1][w];
+            s0.add(red[0][w]);
+            s1.add(red[1][w]);
         }
         la.partial[2 * blockIdx.x] = s0;
         la.partial[2 * blockIdx.x + 1] = s1;
-    }
-}
-
-__global__ __launch_bounds__(64) void k_decode_loss_final(const double* __restrict__ partial, int nblocks,
-                                                  long long m, int D, double* __restrict__ loss) {
-    // lane t adds the partials t, t + 64, ... in order; lane 0 then adds the
-    // 64 lane sums in order: a fixed summation order, so the loss is
-    // reproducible
-    __shared__ double s[2][64];
-    const int t = threadIdx.x;
-    double l1 = 0.0, lc = 0.0;
-    for (int b = t; b < nblocks; b += 64) {
-        l1 += partial[2 * b];
-        lc += partial[2 * b + 1];
-    }
-    s[0][t] = l1;
-    s[1][t] = lc;
-    __syncthreads();
-    if (t == 0) {
-        double a = 0.0, c = 0.0;
-        for (int k = 0; k < 64; ++k) {
-            a += s[0][k];
-            c += s[1][k];
-        }
-        *loss = a / ((double)m * D) + c / (double)m;
     }
 }
 
@@ -763,7 +739,7 @@ extern "C" int ls2_dict_decode_query(int64_t m, int32_t L, int32_t D, const void
 
 extern "C" int ls2_decode_feature_loss_workspace(int64_t m, int32_t D, size_t* bytes) {
     if (!bytes || m < 0 || D < 1) return LS2_ERR_ARG;
-    *bytes = (size_t)kDecodeLossMaxBlocks * 2 * sizeof(double);
+    *bytes = (size_t)kDecodeLossMaxBlocks * 2 * sizeof(CSum);
     return LS2_OK;
 }
 
@@ -771,7 +747,7 @@ extern "C" int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const fl
                                        const float* target, double* loss, float* d_feat, float* feat,
                                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
     if (m < 1 || L < 1 || D < 1 || !coef || !dict || !target || !loss || !d_feat || !workspace) return LS2_ERR_ARG;
-    if (workspace_bytes < (size_t)kDecodeLossMaxBlocks * 2 * sizeof(double)) return LS2_ERR_ARG;
+    if (workspace_bytes < (size_t)kDecodeLossMaxBlocks * 2 * sizeof(CSum)) return LS2_ERR_ARG;
     if (!(L == 32 || L == 64) || D % 128 != 0 || D > 512) return LS2_ERR_UNSUPPORTED;
     DecodeLossArgs la;
     la.d.m = m;
@@ -784,11 +760,11 @@ extern "C" int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const fl
     la.target = target;
     la.d_feat = d_feat;
     la.feat = feat;
-    la.partial = static_cast<double*>(workspace);
+    la.partial = static_cast<CSum*>(workspace);
+    la.inv_md = loss_inv_md(m, D);
+    la.inv_m = loss_inv_m(m);
     int grid;
     grid = L == 32 ? launch_decode_loss<32>(la, stream) : launch_decode_loss<64>(la, stream);
     if (grid < 0) return grid;
-    hipLaunchKernelGGL(k_decode_loss_final, dim3(1), dim3(64), 0, stream, la.partial, grid, m, D, loss);
-    LS2_LAUNCH_CHECK();
-    return LS2_OK;
+    return launch_loss_final(la.partial, grid, m, D, loss, stream);
 }

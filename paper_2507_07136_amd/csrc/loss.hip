@@ -8,9 +8,10 @@
 // and its gradient
 //   dF = sign(F - Y) / (m D) - (Y / (|F|_g |Y|_g) - [|F| > eps] (F.Y) F / (|F|^3 |Y|_g)) / m.
 //
-// One wave per row.  Each workgroup writes its partial sums (in double) to the
-// workspace and a one-workgroup kernel adds them in a fixed order, so the
-// loss is deterministic.
+// One wave per row.  The row sums are accumulated in compensated float32
+// (CSum); each workgroup writes its partial sums to the workspace and a
+// one-workgroup kernel adds them in a fixed order, so the loss is
+// deterministic.  Only the final scalar is widened to double.
 #include "ls2_internal.h"
 
 namespace ls2 {
@@ -20,14 +21,13 @@ constexpr int kLossMaxV = 4;  // float4s per lane: D <= 1024
 
 __device__ __forceinline__ float sgn(float e) { return e > 0.f ? 1.f : (e < 0.f ? -1.f : 0.f); }
 
-__global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, const float* __restrict__ F,
-                                                      const float* __restrict__ Y, float* __restrict__ dF,
-                                                      double* __restrict__ partial) {
-    __shared__ double red[2][4];
+__global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, float inv_md, float inv_m,
+                                                      const float* __restrict__ F, const float* __restrict__ Y,
+                                                      float* __restrict__ dF, CSum* __restrict__ partial) {
+    __shared__ CSum red[2][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nv4 = D / 4;
-    const float inv_md = (float)(1.0 / ((double)m * D)), inv_m = (float)(1.0 / (double)m);
-    double l1_acc = 0.0, lc_acc = 0.0;
+    CSum l1_acc{}, lc_acc{};
     const long long wstride = (long long)gridDim.x * 4;
     for (long long row = (long long)blockIdx.x * 4 + wave; row < m; row += wstride) {
         float4 f[kLossMaxV], y[kLossMaxV];
@@ -52,8 +52,8 @@ __global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, const 
         const float nf = sqrtf(ff), ny = sqrtf(yy);
         const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
         const float c = fy / (gf * gy);
-        l1_acc += (double)l1;
-        lc_acc += (double)(1.0f - c);
+        l1_acc.add(l1);
+        lc_acc.add(1.0f - c);
         if (dF) {
             const float ay = inv_m / (gf * gy);
             const float bf = nf > 1e-12f ? inv_m * fy / (nf * nf * nf * gy) : 0.f;
@@ -77,34 +77,46 @@ __global__ __launch_bounds__(256) void k_feature_loss(long long m, int D, const 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-        partial[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+        CSum a = red[0][0], b = red[1][0];
+        for (int w = 1; w < 4; ++w) {
+            a.add(red[0][w]);
+            b.add(red[1][w]);
+        }
+        partial[2 * blockIdx.x] = a;
+        partial[2 * blockIdx.x + 1] = b;
     }
 }
 
-__global__ __launch_bounds__(64) void k_feature_loss_final(const double* __restrict__ partial, int nblocks,
-                                                  long long m, int D, double* __restrict__ loss) {
-    // lane t adds the partials t, t + 64, ... in order; lane 0 then adds the
-    // 64 lane sums in order: a fixed summation order, so the loss is
-    // reproducible
-    __shared__ double s[2][64];
+// Adds the per-workgroup partials of the two loss terms in a fixed order
+// (lane t the partials t, t + 64, ..., then lane 0 the 64 lane sums), so the
+// loss is reproducible, and writes mean |F - Y| + mean (1 - cos).
+__global__ __launch_bounds__(64) void k_loss_final(const CSum* __restrict__ partial, int nblocks, float inv_md,
+                                                   float inv_m, double* __restrict__ loss) {
+    __shared__ CSum s[2][64];
     const int t = threadIdx.x;
-    double l1 = 0.0, lc = 0.0;
+    CSum l1{}, lc{};
     for (int b = t; b < nblocks; b += 64) {
-        l1 += partial[2 * b];
-        lc += partial[2 * b + 1];
+        l1.add(partial[2 * b]);
+        lc.add(partial[2 * b + 1]);
     }
     s[0][t] = l1;
     s[1][t] = lc;
     __syncthreads();
     if (t == 0) {
-        double a = 0.0, c = 0.0;
+        CSum a{}, c{};
         for (int k = 0; k < 64; ++k) {
-            a += s[0][k];
-            c += s[1][k];
+            a.add(s[0][k]);
+            c.add(s[1][k]);
         }
-        *loss = a / ((double)m * D) + c / (double)m;
+        *loss = (double)(a.value() * inv_md + c.value() * inv_m);
     }
+}
+
+int launch_loss_final(const CSum* partial, int nblocks, long long m, int D, double* loss, hipStream_t stream) {
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, stream, partial, nblocks, loss_inv_md(m, D),
+                       loss_inv_m(m), loss);
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
 }
 
 static int loss_blocks(long long m) {
@@ -118,7 +130,7 @@ using namespace ls2;
 
 extern "C" int ls2_feature_loss_workspace(int64_t m, size_t* bytes) {
     if (!bytes || m < 0) return LS2_ERR_ARG;
-    *bytes = (size_t)loss_blocks(m) * 2 * sizeof(double);
+    *bytes = (size_t)loss_blocks(m) * 2 * sizeof(CSum);
     return LS2_OK;
 }
 
@@ -127,11 +139,10 @@ extern "C" int ls2_feature_loss(int64_t m, int32_t D, const float* feat, const f
     if (m < 1 || D < 1 || !feat || !target || !loss || !workspace) return LS2_ERR_ARG;
     if (D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
     const int nb = loss_blocks(m);
-    if (workspace_bytes < (size_t)nb * 2 * sizeof(double)) return LS2_ERR_ARG;
-    double* partial = static_cast<double*>(workspace);
-    hipLaunchKernelGGL(k_feature_loss, dim3(nb), dim3(256), 0, stream, m, D, feat, target, d_feat, partial);
+    if (workspace_bytes < (size_t)nb * 2 * sizeof(CSum)) return LS2_ERR_ARG;
+    CSum* partial = static_cast<CSum*>(workspace);
+    hipLaunchKernelGGL(k_feature_loss, dim3(nb), dim3(256), 0, stream, m, D, loss_inv_md(m, D), loss_inv_m(m),
+                       feat, target, d_feat, partial);
     LS2_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_feature_loss_final, dim3(1), dim3(64), 0, stream, partial, nb, m, D, loss);
-    LS2_LAUNCH_CHECK();
-    return LS2_OK;
+    return launch_loss_final(partial, nb, m, D, loss, stream);
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "ls2.h"
 
 namespace ls2 {
@@ -34,8 +36,16 @@ inline CamK cam_k(const ls2_camera& c) {
     return k;
 }
 
+// A usable camera: image size in [1, 32768]^2, finite intrinsics, and a near
+// plane that is finite and positive (sort keys are the bits of a positive
+// float32 depth, and z near 0 would make the projection Jacobian blow up).
 inline bool cam_valid(const ls2_camera* c) {
-    return c && c->width > 0 && c->height > 0 && c->width <= (1 << 15) && c->height <= (1 << 15);
+    if (!c || c->width <= 0 || c->height <= 0 || c->width > (1 << 15) || c->height > (1 << 15)) return false;
+    if (!std::isfinite(c->fx) || !std::isfinite(c->fy) || !std::isfinite(c->cx) || !std::isfinite(c->cy))
+        return false;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(c->world_to_cam[i])) return false;
+    return std::isfinite(c->znear) && c->znear > 0.0f;
 }
 
 // Tile rectangle [x0,x1] x [y0,y1] of a Gaussian with float32 mean (u, v) and
@@ -121,6 +131,39 @@ __device__ __forceinline__ unsigned bf16_pair(float a, float b) {
     const f32x2_i v = {a, b};
     return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2_i));
 }
+
+// Compensated float32 sum (Neumaier): s + c holds the running total to about
+// twice float32's precision, so a sum over many rows or partials stays within
+// a few float32 roundings of the exact sum whatever its length (scalar
+// results such as the loss are accumulated this way, not in float64).
+// Trivial (usable in LDS); start from CSum{} for zero.
+struct CSum {
+    float s, c;
+    __device__ __forceinline__ void add(float x) {
+        const float t = s + x;
+        c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    __device__ __forceinline__ void add(const CSum& o) {
+        add(o.s);
+        c += o.c;
+    }
+    __device__ __forceinline__ float value() const { return s + c; }
+};
+
+// The loss's mean weights 1 / (m D) and 1 / m, rounded once on the host.
+inline float loss_inv_md(long long m, int D) { return (float)(1.0 / ((double)m * (double)D)); }
+inline float loss_inv_m(long long m) { return (float)(1.0 / (double)m); }
+
+// Final sum of per-workgroup loss partials (two CSum per workgroup: the L1
+// and the cosine term) into the scalar loss; defined with ls2_feature_loss.
+int launch_loss_final(const CSum* partial, int nblocks, long long m, int D, double* loss, hipStream_t stream);
+
+// LS2_CHECK mode (check.hip): whether it is on, and the scan of n levels K
+// code indices against [0, L) that the entry points reading topk_idx run
+// first when it is (LS2_ERR_ARG if any lies outside; synchronises stream).
+bool check_mode();
+int check_code_indices(long long count, int L, const int32_t* topk_idx, hipStream_t stream);
 
 // Host-side check of the 16-byte alignment that float4 accesses need (a null
 // pointer passes; null arguments are checked separately).

@@ -33,7 +33,7 @@ inline PpLayout pp_layout(int levels, int H, int W) {
     l.pmax = off; off = al(off + sizeof(float) * kPpBlocks * levels);
     l.parg = off; off = al(off + sizeof(int) * kPpBlocks * levels);
     l.pmin = off; off = al(off + sizeof(float) * kPpBlocks * levels);
-    l.psum = off; off = al(off + sizeof(double) * kPpBlocks * levels);
+    l.psum = off; off = al(off + sizeof(CSum) * kPpBlocks * levels);
     l.pcnt = off; off = al(off + sizeof(int) * kPpBlocks * levels);
     l.stats = off; off = al(off + sizeof(float) * 4 * kPpMaxLevels + sizeof(int) * 2 * kPpMaxLevels);
     l.total = off;
@@ -142,25 +142,28 @@ __device__ __forceinline__ bool in_mask(float s, float mn, float mx, float thr) 
 
 __global__ __launch_bounds__(256) void k_pp_maskstats(int levels, long long HW, const float* __restrict__ S,
                                                       const float* __restrict__ stats, float thr,
-                                                      double* __restrict__ psum, int* __restrict__ pcnt) {
-    __shared__ double ssum[4];
+                                                      CSum* __restrict__ psum, int* __restrict__ pcnt) {
+    __shared__ CSum ssum[4];
     __shared__ int scnt[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int l = 0; l < levels; ++l) {
         const float* s = S + l * HW;
         const float mx = stats[4 * l], mn = stats[4 * l + 1];
-        double sum = 0.0;
+        CSum sum{};
         int cnt = 0;
         for (long long p = blockIdx.x * 256LL + threadIdx.x; p < HW; p += (long long)gridDim.x * 256) {
             const float v = s[p];
             if (in_mask(v, mn, mx, thr)) {
-                sum += (double)v;
+                sum.add(v);
                 ++cnt;
             }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            sum += __shfl_xor(sum, off);
+            CSum o;
+            o.s = __shfl_xor(sum.s, off);
+            o.c = __shfl_xor(sum.c, off);
+            sum.add(o);
             cnt += __shfl_xor(cnt, off);
         }
         if (lane == 0) {
@@ -169,27 +172,29 @@ __global__ __launch_bounds__(256) void k_pp_maskstats(int levels, long long HW, 
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            psum[l * gridDim.x + blockIdx.x] = ssum[0] + ssum[1] + ssum[2] + ssum[3];
+            CSum t = ssum[0];
+            for (int w = 1; w < 4; ++w) t.add(ssum[w]);
+            psum[l * gridDim.x + blockIdx.x] = t;
             pcnt[l * gridDim.x + blockIdx.x] = scnt[0] + scnt[1] + scnt[2] + scnt[3];
         }
         __syncthreads();
     }
 }
 
-__global__ void k_pp_select(int levels, int nb, int W, int select_mode, const double* __restrict__ psum,
+__global__ void k_pp_select(int levels, int nb, int W, int select_mode, const CSum* __restrict__ psum,
                             const int* __restrict__ pcnt, float* __restrict__ stats, const int* __restrict__ sarg,
                             int* __restrict__ sel, int32_t* __restrict__ result, float* __restrict__ level_stats) {
     if (threadIdx.x != 0) return;
     int best = 0;
     float bestv = -INFINITY;
     for (int l = 0; l < levels; ++l) {
-        double sum = 0.0;
+        CSum sum{};
         long long cnt = 0;
         for (int b = 0; b < nb; ++b) {
-            sum += psum[l * nb + b];
+            sum.add(psum[l * nb + b]);
             cnt += pcnt[l * nb + b];
         }
-        stats[4 * l + 2] = cnt > 0 ? (float)(sum / (double)cnt) : -INFINITY;
+        stats[4 * l + 2] = cnt > 0 ? sum.value() / (float)cnt : -INFINITY;
         stats[4 * l + 3] = (float)cnt;
         const float key = select_mode == LS2_SELECT_MAX ? stats[4 * l] : stats[4 * l + 2];
         if (l == 0 || key > bestv) {
@@ -249,7 +254,7 @@ extern "C" int ls2_postprocess(int32_t levels, int32_t H, int32_t W, const float
     float* pmax = reinterpret_cast<float*>(ws + lay.pmax);
     int* parg = reinterpret_cast<int*>(ws + lay.parg);
     float* pmin = reinterpret_cast<float*>(ws + lay.pmin);
-    double* psum = reinterpret_cast<double*>(ws + lay.psum);
+    CSum* psum = reinterpret_cast<CSum*>(ws + lay.psum);
     int* pcnt = reinterpret_cast<int*>(ws + lay.pcnt);
     float* stats = reinterpret_cast<float*>(ws + lay.stats);
     int* sarg = reinterpret_cast<int*>(stats + 4 * kPpMaxLevels);

@@ -575,6 +575,7 @@ extern "C" int ls2_splat_sparse(const ls2_camera* cam, int32_t n, int32_t levels
     if (!aligned16(coef)) return LS2_ERR_ARG;
     if (n > 0 && (!ids || !mean2d || !conic || !opacity || !topk_idx || !topk_w)) return LS2_ERR_ARG;
     if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
+    if (const int st = check_code_indices((long long)n * levels * K, L, topk_idx, stream)) return st;
     SplatArgs a;
     a.cam = cam_k(*cam);
     a.n = n;
@@ -633,6 +634,7 @@ static int splat_decode_setup(SplatArgs& a, const ls2_camera* cam, int32_t n, in
     if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
     if (D % 64 != 0 || D > 1024) return LS2_ERR_UNSUPPORTED;
     if (workspace_bytes < ws_need) return LS2_ERR_ARG;
+    if (const int st = check_code_indices((long long)n * levels * K, L, topk_idx, stream)) return st;
     unsigned short* dictp = static_cast<unsigned short*>(workspace);
     hipLaunchKernelGGL(k_dict_pack, dim3((unsigned)((L * D + 255) / 256)), dim3(256), 0, stream, L, D, dict, dictp);
     LS2_LAUNCH_CHECK();

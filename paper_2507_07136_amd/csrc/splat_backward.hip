@@ -318,6 +318,7 @@ extern "C" int ls2_splat_sparse_backward(const ls2_camera* cam, int32_t n, int32
         return LS2_ERR_ARG;
     if (!(L == 32 || L == 64 || L == 128) || K > 8 || levels > 3 || levels * L > 192) return LS2_ERR_UNSUPPORTED;
     if (n == 0) return LS2_OK;
+    if (const int st = check_code_indices((long long)n * levels * K, L, topk_idx, stream)) return st;
     int st;
     if ((st = zero_f32(d_mean2d, 2LL * n, stream)) != LS2_OK) return st;
     if ((st = zero_f32(d_conic, 3LL * n, stream)) != LS2_OK) return st;

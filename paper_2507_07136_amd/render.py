@@ -202,10 +202,30 @@ class Gradients:
         self.quats = torch.empty((n, 4), dtype=f32, device=device)
 
 
+class ForwardState:
+    """What the backward of one forward frame reads: the camera, the tile
+    lists, the projected Gaussians and the compositing state (coefficient
+    map, final T and the position of each pixel's last contributor).  Either
+    views of a trainer's buffers (valid until its next frame) or a copy that
+    stays valid whatever the trainer renders afterwards."""
+
+    FIELDS = ("coef", "tile_ranges", "ids", "final_T", "last", "mean2d", "conic", "radius")
+
+    def __init__(self, cam, **tensors):
+        self.cam = type(cam).from_buffer_copy(cam)
+        for k in self.FIELDS:
+            setattr(self, k, tensors[k])
+
+    def copy(self):
+        return ForwardState(self.cam, **{k: getattr(self, k).clone() for k in self.FIELDS})
+
+
 class Trainer(Pipeline):
     """Forward + backward of the feature-map objective (float32 throughout):
     project -> bin_sort -> splat -> decode -> feature loss, then
-    decode_backward -> splat_backward -> project_backward."""
+    decode_backward -> splat_backward -> project_backward.  With codes given
+    as logits (Section 3.3), ls2_sparse_codes forms the K (index, weight)
+    pairs first and ls2_sparse_codes_backward closes the chain."""
 
     def __init__(self, cam, n, levels=1, K=4, L=64, D=512, max_pairs=None, device="cuda"):
         super().__init__(cam, n, levels, K, L, D, max_pairs, device)
@@ -222,6 +242,27 @@ class Trainer(Pipeline):
         if self.fused_loss:
             self.fused_ws = torch.empty((_lib.ls2_decode_feature_loss_workspace(m, D),), dtype=torch.uint8,
                                         device=dev)
+        self.topk_idx = None   # codes formed from logits (codes())
+        self.topk_w = None
+        self.d_logits = None
+
+    def state(self) -> ForwardState:
+        """The forward state of the last frame, as views of this trainer's
+        buffers (``.copy()`` keeps it past the next frame)."""
+        P = self.num_pairs if self.num_pairs is not None else self.max_pairs
+        return ForwardState(self.cam, coef=self.coef, tile_ranges=self.tile_ranges, ids=self.ids[:max(P, 1)],
+                            final_T=self.final_T, last=self.last, mean2d=self.mean2d, conic=self.conic,
+                            radius=self.radius)
+
+    def codes(self, logits):
+        """Sparse codes of logits [n, levels, L] (softmax, top K, renormalise):
+        (topk_idx, topk_w) in this trainer's buffers."""
+        if self.topk_idx is None:
+            shape = (self.n, self.levels, self.K)
+            self.topk_idx = torch.empty(shape, dtype=torch.int32, device=self.device)
+            self.topk_w = torch.empty(shape, dtype=torch.float32, device=self.device)
+        _lib.ls2_sparse_codes(logits, self.K, self.topk_idx, self.topk_w)
+        return self.topk_idx, self.topk_w
 
     def decode_loss(self, dictionary, target, keep_feat=False):
         """Float32 decode + loss + dL/dF; the feature map is kept only if asked."""
@@ -241,26 +282,37 @@ class Trainer(Pipeline):
         return self.loss
 
     def forward_loss(self, scene, target, sync=True, keep_feat=False):
-        """Renders the scene and evaluates the loss and dL/dF (float32)."""
+        """Renders the scene and evaluates the loss and dL/dF (float32).  A
+        scene with "logits" [n, levels, L] instead of topk_idx / topk_w gets
+        its codes from them first."""
+        if "logits" in scene:
+            scene["topk_idx"], scene["topk_w"] = self.codes(scene["logits"])
         self.project(scene["means"], scene["scales"], scene["quats"])
         self.bin_sort(sync=sync)
         self.splat(scene["opacity"], scene["topk_idx"], scene["topk_w"])
         return self.decode_loss(scene["dictionary"], target, keep_feat=keep_feat)
 
-    def backward(self, scene, d_feat=None):
+    def backward(self, scene, d_feat=None, state: ForwardState | None = None):
         """Gradients of the loss (or of any dL/dF given as d_feat) with
-        respect to every differentiable input, into ``self.grad``."""
+        respect to every differentiable input, into ``self.grad``; ``state``
+        is the forward frame to differentiate (default: the last one).  A
+        scene with "logits" also gets dL/dlogits (``self.d_logits``)."""
         g = self.grad
+        st = self.state() if state is None else state
         m = self.levels * self.H * self.W
         G = (self.d_feat if d_feat is None else d_feat).view(m, self.D)
-        _lib.ls2_dict_decode_backward(self.coef.view(m, self.L), scene["dictionary"], G, g.coef.view(m, self.L),
+        _lib.ls2_dict_decode_backward(st.coef.view(m, self.L), scene["dictionary"], G, g.coef.view(m, self.L),
                                       g.dictionary, self.dec_ws)
-        _lib.ls2_splat_sparse_backward(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids,
-                                       self.mean2d, self.conic, scene["opacity"], scene["topk_idx"],
-                                       scene["topk_w"], self.final_T, self.last, g.coef, g.mean2d, g.conic,
+        _lib.ls2_splat_sparse_backward(st.cam, self.levels, self.K, self.L, st.tile_ranges, st.ids,
+                                       st.mean2d, st.conic, scene["opacity"], scene["topk_idx"],
+                                       scene["topk_w"], st.final_T, st.last, g.coef, g.mean2d, g.conic,
                                        g.opacity, g.topk_w)
-        _lib.ls2_project_backward(self.cam, scene["means"], scene["scales"], scene["quats"], self.radius, g.mean2d,
+        _lib.ls2_project_backward(st.cam, scene["means"], scene["scales"], scene["quats"], st.radius, g.mean2d,
                                   g.conic, g.means, g.scales, g.quats)
+        if "logits" in scene:
+            if self.d_logits is None:
+                self.d_logits = torch.empty((self.n, self.levels, self.L), dtype=torch.float32, device=self.device)
+            _lib.ls2_sparse_codes_backward(scene["topk_idx"], scene["topk_w"], g.topk_w, self.d_logits)
         return g
 
     def set_camera(self, cam):
@@ -281,28 +333,58 @@ class Trainer(Pipeline):
         return loss, self.backward(scene)
 
 
+def _render_forward(ctx, trainer, scene):
+    feat = trainer.feature_map(scene["means"], scene["scales"], scene["quats"], scene["opacity"],
+                               scene["topk_idx"], scene["topk_w"], scene["dictionary"], compute=LS2_F32,
+                               out_dtype=torch.float32)
+    # the backward differentiates this frame even if the trainer renders
+    # other views (or other scenes) before it runs
+    ctx.trainer = trainer
+    ctx.state = trainer.state().copy()
+    ctx.scene = scene
+    return feat.clone()
+
+
 class LS2Render(torch.autograd.Function):
     """Differentiable feature map F (float32, [levels, H, W, D]) of a scene,
     with the hand-written HIP backward.  ``trainer`` supplies the buffers;
-    topk_idx is discrete and carries no gradient."""
+    each call keeps its own copy of the forward state, so several frames
+    (views) may be rendered before one backward.  topk_idx is discrete and
+    carries no gradient."""
 
     @staticmethod
     def forward(ctx, trainer, means, scales, quats, opacity, topk_idx, topk_w, dictionary):
         scene = dict(means=means.contiguous(), scales=scales.contiguous(), quats=quats.contiguous(),
                      opacity=opacity.contiguous(), topk_idx=topk_idx.contiguous(), topk_w=topk_w.contiguous(),
                      dictionary=dictionary.contiguous())
-        feat = trainer.feature_map(scene["means"], scene["scales"], scene["quats"], scene["opacity"],
-                                   scene["topk_idx"], scene["topk_w"], scene["dictionary"], compute=LS2_F32,
-                                   out_dtype=torch.float32)
-        ctx.trainer = trainer
-        ctx.scene = scene
-        return feat.clone()
+        return _render_forward(ctx, trainer, scene)
 
     @staticmethod
     def backward(ctx, d_feat):
-        g = ctx.trainer.backward(ctx.scene, d_feat.contiguous())
+        g = ctx.trainer.backward(ctx.scene, d_feat.contiguous(), state=ctx.state)
         return (None, g.means.clone(), g.scales.clone(), g.quats.clone(), g.opacity.clone(), None,
                 g.topk_w.clone(), g.dictionary.clone())
+
+
+class LS2RenderLogits(torch.autograd.Function):
+    """LS2Render with the codes given as logits [n, levels, L] (Section 3.3:
+    softmax, top K, renormalise, learned jointly with the codebook): the
+    gradient reaches the logits through ls2_sparse_codes_backward."""
+
+    @staticmethod
+    def forward(ctx, trainer, means, scales, quats, opacity, logits, dictionary):
+        idx, w = trainer.codes(logits.contiguous())
+        scene = dict(means=means.contiguous(), scales=scales.contiguous(), quats=quats.contiguous(),
+                     opacity=opacity.contiguous(), topk_idx=idx.clone(), topk_w=w.clone(),
+                     dictionary=dictionary.contiguous(), logits=logits)
+        return _render_forward(ctx, trainer, scene)
+
+    @staticmethod
+    def backward(ctx, d_feat):
+        tr = ctx.trainer
+        g = tr.backward(ctx.scene, d_feat.contiguous(), state=ctx.state)
+        return (None, g.means.clone(), g.scales.clone(), g.quats.clone(), g.opacity.clone(), tr.d_logits.clone(),
+                g.dictionary.clone())
 
 
 def to_device(scene, device="cuda"):
@@ -314,4 +396,5 @@ def to_device(scene, device="cuda"):
                 dictionary=t(scene.dictionary, torch.float32))
 
 
-__all__ = ["Pipeline", "Trainer", "Gradients", "LS2Render", "to_device", "LS2_F32", "LS2_BF16"]
+__all__ = ["Pipeline", "Trainer", "Gradients", "ForwardState", "LS2Render", "LS2RenderLogits", "to_device",
+           "LS2_F32", "LS2_BF16"]
