@@ -6,9 +6,12 @@
  *   - Pointers are DEVICE pointers unless marked (host).  Arrays are
  *     row-major and contiguous.  The caller owns all memory; the library
  *     never allocates or frees (scratch comes in through a caller-sized
- *     workspace where one is needed).
- *   - Calls are asynchronous on `stream` unless documented otherwise.  There
- *     is no global state: calls on different streams do not interact.
+ *     workspace where one is needed).  The one exception is
+ *     ls2_splat_decode_query_noalloc, which uses a fixed scratch array the
+ *     library holds per GPU.
+ *   - Calls are asynchronous on `stream` unless documented otherwise.  Apart
+ *     from that scratch array and the check mode's flag word, there is no
+ *     global state: calls on different streams do not interact.
  *   - Invalid sizes or null required pointers return LS2_ERR_ARG before any
  *     work is enqueued.  Shapes outside the compiled kernel set return
  *     LS2_ERR_UNSUPPORTED.  A HIP launch failure returns LS2_ERR_DEVICE.
@@ -39,7 +42,7 @@ extern "C" {
 enum {
     LS2_OK = 0,
     LS2_ERR_ARG = -1,          /* invalid argument (null pointer, negative size, K > L, ...) */
-    LS2_ERR_CAPACITY = -2,     /* ls2_bin_sort: more pairs than max_pairs */
+    LS2_ERR_CAPACITY = -2,     /* more pairs than max_pairs (ls2_bin_sort); shape beyond the fixed scratch (_noalloc) */
     LS2_ERR_UNSUPPORTED = -3,  /* shape outside the compiled set */
     LS2_ERR_DEVICE = -4        /* HIP runtime error */
 };
@@ -208,6 +211,31 @@ int ls2_splat_decode_query(const ls2_camera* cam, int32_t n, int32_t levels, int
                            const float* neg, float tau, float* relevancy, void* feat, void* coef,
                            float* final_T, int32_t* last, void* workspace, size_t workspace_bytes,
                            hipStream_t stream);
+
+/*
+ * ls2_splat_decode_query_noalloc -- ls2_splat_decode_query for callers that
+ * cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  It takes no workspace and calls
+ * no allocating routine: the repacked dictionary and texts go to a scratch
+ * array of 160 KiB that the library holds on each GPU it runs on until the
+ * process ends.  The caller still passes inputs and outputs, with the same
+ * meaning, layout and ownership as ls2_splat_decode_query; the outputs are
+ * bit-identical to it.
+ *
+ * Limit: the scratch must hold ls2_splat_decode_query_workspace(L, D, n_neg)
+ * bytes (for example L = 128 with D <= 512, or L = 64 with D <= 1024);
+ * larger shapes return LS2_ERR_CAPACITY before any device call.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (concurrent streams or host threads) race and must be serialised by
+ * the caller.  The first call on a device looks up its scratch address
+ * (LS2_ERR_DEVICE if that fails).
+ */
+int ls2_splat_decode_query_noalloc(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                                   int32_t D, const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                   const float* conic, const float* opacity, const int32_t* topk_idx,
+                                   const float* topk_w, const float* dict, const float* pos, int32_t n_neg,
+                                   const float* neg, float tau, float* relevancy, void* feat, void* coef,
+                                   float* final_T, int32_t* last, hipStream_t stream);
 
 /*
  * ls2_splat_dense -- the dense form of the coefficient splatting: every

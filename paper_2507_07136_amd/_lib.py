@@ -57,6 +57,8 @@ def _load():
         "ls2_splat_decode_query_workspace": ([i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_splat_decode_query": ([cam, i32, i32, i32, i32, i32] + [P] * 9 + [i32, P, ctypes.c_float] + [P] * 6
                                    + [ctypes.c_size_t, P], ctypes.c_int),
+        "ls2_splat_decode_query_noalloc": ([cam, i32, i32, i32, i32, i32] + [P] * 9 + [i32, P, ctypes.c_float]
+                                           + [P] * 5, ctypes.c_int),
         "ls2_dict_decode": ([i64, i32, i32, P, i32, P, i32, i32, P, P], ctypes.c_int),
         "ls2_dict_decode_query": ([i64, i32, i32, P, i32, P, P, P, i32, P, ctypes.c_float, P, P], ctypes.c_int),
         "ls2_splat_dense": ([cam, i32, i32, i32, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
@@ -271,6 +273,33 @@ def ls2_splat_decode_query(cam, levels, K, L, tile_ranges, ids, mean2d, conic, o
                                      _ptr(last, i32, "last", HW, allow_none=True),
                                      _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
     _check("ls2_splat_decode_query", st)
+
+
+def ls2_splat_decode_query_noalloc(cam, levels, K, L, tile_ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
+                                   dictionary, pos, neg, relevancy, feat=None, coef=None, final_T=None, last=None,
+                                   tau=1.0, stream=None):
+    """ls2_splat_decode_query with the library's own fixed scratch (no
+    workspace argument, nothing allocated)."""
+    n = opacity.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    HW = c.width * c.height
+    D = dictionary.shape[1]
+    n_neg = neg.numel() // D
+    f32, i32, b16 = torch.float32, torch.int32, torch.bfloat16
+    st = _lib.ls2_splat_decode_query_noalloc(ctypes.byref(c), n, int(levels), int(K), int(L), int(D),
+                                             _ptr(tile_ranges, i32, "tile_ranges"), _ptr(ids, i32, "ids"),
+                                             _ptr(mean2d, f32, "mean2d", 2 * n), _ptr(conic, f32, "conic", 3 * n),
+                                             _ptr(opacity, f32, "opacity", n),
+                                             _ptr(topk_idx, i32, "topk_idx", n * levels * K),
+                                             _ptr(topk_w, f32, "topk_w", n * levels * K),
+                                             _ptr(dictionary, f32, "dict", L * D),
+                                             _ptr(pos, f32, "pos", D), n_neg, _ptr(neg, f32, "neg", n_neg * D),
+                                             float(tau), _ptr(relevancy, f32, "relevancy", levels * HW),
+                                             _ptr(feat, b16, "feat", levels * HW * D, allow_none=True),
+                                             _ptr(coef, b16, "coef", levels * HW * L, allow_none=True),
+                                             _ptr(final_T, f32, "final_T", HW, allow_none=True),
+                                             _ptr(last, i32, "last", HW, allow_none=True), _stream(stream))
+    _check("ls2_splat_decode_query_noalloc", st)
 
 
 def ls2_splat_dense(cam, levels, L, tile_ranges, ids, mean2d, conic, opacity, weights, coef, final_T=None, last=None,

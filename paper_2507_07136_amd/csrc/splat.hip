@@ -30,6 +30,8 @@
 // (below).  The wave then writes its pixels' D features directly, so the
 // coefficient map never travels through HBM, and the feature-map stores of
 // finished waves overlap the latency-bound blending of the others.
+#include <mutex>
+
 #include "splat_common.h"
 
 namespace ls2 {
@@ -687,17 +689,16 @@ extern "C" int ls2_splat_decode_query_workspace(int32_t L, int32_t D, int32_t n_
     return LS2_OK;
 }
 
-extern "C" int ls2_splat_decode_query(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
-                                      int32_t D, const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
-                                      const float* conic, const float* opacity, const int32_t* topk_idx,
-                                      const float* topk_w, const float* dict, const float* pos, int32_t n_neg,
-                                      const float* neg, float tau, float* relevancy, void* feat, void* coef,
-                                      float* final_T, int32_t* last, void* workspace, size_t workspace_bytes,
-                                      hipStream_t stream) {
-    if (!pos || !neg || !relevancy || n_neg < 1) return LS2_ERR_ARG;
-    if (n_neg > 8) return LS2_ERR_UNSUPPORTED;
-    size_t need = 0;
-    if (ls2_splat_decode_query_workspace(L, D, n_neg, &need) != LS2_OK) need = 0;  // the shape checks below report it
+// The query frame given its scratch: the packed dictionary at w, the bf16
+// texts and their norms after it (the layout ls2_splat_decode_query_workspace
+// sizes).
+static int splat_decode_query_run(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L, int32_t D,
+                                  const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                  const float* conic, const float* opacity, const int32_t* topk_idx,
+                                  const float* topk_w, const float* dict, const float* pos, int32_t n_neg,
+                                  const float* neg, float tau, float* relevancy, void* feat, void* coef,
+                                  float* final_T, int32_t* last, void* workspace, size_t workspace_bytes,
+                                  size_t need, hipStream_t stream) {
     SplatArgs a;
     int st = splat_decode_setup(a, cam, n, levels, K, L, D, tile_ranges, ids, mean2d, conic, opacity, topk_idx,
                                 topk_w, dict, feat, false, coef, final_T, last, workspace, workspace_bytes, need,
@@ -714,4 +715,70 @@ extern "C" int ls2_splat_decode_query(const ls2_camera* cam, int32_t n, int32_t 
     a.tau = tau;
     a.rel = relevancy;
     return launch_splat_l(a, kOutDecodeQuery, stream);
+}
+
+extern "C" int ls2_splat_decode_query(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K, int32_t L,
+                                      int32_t D, const uint32_t* tile_ranges, const uint32_t* ids, const float* mean2d,
+                                      const float* conic, const float* opacity, const int32_t* topk_idx,
+                                      const float* topk_w, const float* dict, const float* pos, int32_t n_neg,
+                                      const float* neg, float tau, float* relevancy, void* feat, void* coef,
+                                      float* final_T, int32_t* last, void* workspace, size_t workspace_bytes,
+                                      hipStream_t stream) {
+    if (!pos || !neg || !relevancy || n_neg < 1) return LS2_ERR_ARG;
+    if (n_neg > 8) return LS2_ERR_UNSUPPORTED;
+    size_t need = 0;
+    if (ls2_splat_decode_query_workspace(L, D, n_neg, &need) != LS2_OK) need = 0;  // the shape checks report it
+    return splat_decode_query_run(cam, n, levels, K, L, D, tile_ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
+                                  dict, pos, n_neg, neg, tau, relevancy, feat, coef, final_T, last, workspace,
+                                  workspace_bytes, need, stream);
+}
+
+// ---- ls2_splat_decode_query_noalloc: the same frame with the library's own
+// scratch, for callers that cannot allocate (stream capture, serving loops).
+//
+// The scratch is a fixed device array.  In host code its name only stands in
+// for the symbol; the device address of each GPU's copy is looked up once per
+// device (hipGetSymbolAddress, with that device current) and only that
+// address is passed to kernels.  Every call on a device shares that device's
+// copy, so calls that overlap on one GPU race; the repack kernels rewrite
+// everything the frame reads on every call, so nothing needs clearing.
+constexpr size_t kNoAllocScratchBytes = 160 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kNoAllocMaxDevices = 64;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+void* scratch_ptr() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int ls2_splat_decode_query_noalloc(const ls2_camera* cam, int32_t n, int32_t levels, int32_t K,
+                                              int32_t L, int32_t D, const uint32_t* tile_ranges, const uint32_t* ids,
+                                              const float* mean2d, const float* conic, const float* opacity,
+                                              const int32_t* topk_idx, const float* topk_w, const float* dict,
+                                              const float* pos, int32_t n_neg, const float* neg, float tau,
+                                              float* relevancy, void* feat, void* coef, float* final_T,
+                                              int32_t* last, hipStream_t stream) {
+    if (!pos || !neg || !relevancy || n_neg < 1) return LS2_ERR_ARG;
+    if (n_neg > 8) return LS2_ERR_UNSUPPORTED;
+    size_t need = 0;
+    const int ws = ls2_splat_decode_query_workspace(L, D, n_neg, &need);
+    if (ws != LS2_OK) return ws;
+    if (need > kNoAllocScratchBytes) return LS2_ERR_CAPACITY;  // before any device call
+    void* w = scratch_ptr();
+    if (!w) return LS2_ERR_DEVICE;
+    return splat_decode_query_run(cam, n, levels, K, L, D, tile_ranges, ids, mean2d, conic, opacity, topk_idx, topk_w,
+                                  dict, pos, n_neg, neg, tau, relevancy, feat, coef, final_T, last, w,
+                                  kNoAllocScratchBytes, need, stream);
 }

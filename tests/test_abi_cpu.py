@@ -260,3 +260,25 @@ def test_splat_decode_query_validation_without_device(L):
     assert call(feat=V(24)) == -1          # misaligned optional feature map
     assert call(wsb=ws - 1) == -1
     assert call(D=500) == -3
+
+
+def test_splat_decode_query_noalloc_validation_without_device(L):
+    """The no-allocation query frame rejects bad texts and shapes, and shapes
+    whose repacked dictionary and texts exceed its fixed scratch, before any
+    device call."""
+    c = _cam()
+    V = ctypes.c_void_p
+    inp = [V(16)] * 7
+    f1 = ctypes.c_float(1.0)
+
+    def call(n_neg=4, Lc=64, D=512, pos=V(16), neg=V(16), rel=V(16)):
+        return L.ls2_splat_decode_query_noalloc(ctypes.byref(c), 10, 1, 4, Lc, D, *inp, V(16), pos, n_neg, neg, f1,
+                                                rel, None, None, None, None, None)
+    assert call(n_neg=9) == -3
+    assert call(n_neg=0) == -1
+    assert call(pos=None) == -1
+    assert call(neg=None) == -1
+    assert call(rel=None) == -1
+    assert call(D=500) == -3
+    assert call(Lc=48) == -3
+    assert call(Lc=128, D=1024, n_neg=8) == -2   # 288 KB of scratch needed, 160 KiB held
