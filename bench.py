@@ -134,6 +134,69 @@ def cpu_baseline(cam, scene, frac):
                                                decode=(t4 - t3) * scale))
 
 
+def cpu_model():
+    """The host CPU's model name and logical core count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline_one_core(config, frac):
+    """The same oracle frame on one host thread (OpenMP limited to 1 in a
+    child process), on a pixel fraction `frac` (extrapolated)."""
+    import subprocess
+    code = ("import json, sys; sys.path.insert(0, %r); import gen, bench; s, c = gen.config_scene(%r); "
+            "r = bench.cpu_baseline(c, s, %r); print(json.dumps(r))" % (ROOT, config, frac))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        log("one-core oracle run failed: %s" % r.stderr[-2000:])
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return dict(value=d["value"], cores=d["cores"], frame_s=round(d["frame_s"], 3),
+                stages_s={k: round(v, 3) for k, v in d["stages_s"].items()}, sample=d["sample"])
+
+
+def c4_oracle_errors(samples):
+    """Maximum error of every output of the precision workload against the
+    FP64 oracle, on the sampled pixels each (L, K) run kept: the oracle
+    composites those pixels from the GPU's lists and projection (stage
+    isolated), decodes them in FP64 and forms their relevancy.  Pixels with a
+    compositing decision within 1e-5 of its threshold are left out of the
+    maxima and counted."""
+    import numpy as np
+    from oracle import oracle as orc
+    out = {}
+    for key, s in samples.items():
+        sc = s["scene"]
+        c, fT, last, margin, margin_T = orc.composite_pixels(s["cam"], s["ranges"], s["ids"], s["mean2d"], s["conic"],
+                                                             sc.opacity, sc.topk_idx, sc.topk_w, sc.L, s["pix"],
+                                                             with_margin_T=True)
+        c = c.reshape(len(s["pix"]), -1)
+        F = orc.decode(c, sc.dictionary)
+        r = orc.query(F, s["pos"], s["neg"])
+        ok = (margin.reshape(-1) >= 1e-5) & (margin_T.reshape(-1) >= 1e-5)
+        nF = np.linalg.norm(F, axis=1)
+        okn = ok & (nF > 1e-6)
+        e = dict(coef_f32_abs=np.abs(s["coef"] - c).max(axis=1)[ok].max(),
+                 feat_f32_abs=np.abs(s["f32"] - F).max(axis=1)[ok].max(),
+                 feat_bf16_rel_l2=(np.linalg.norm(s["bf"] - F, axis=1)[okn] / nF[okn]).max(),
+                 relevancy_f32_abs=np.abs(s["r32"] - r)[ok].max(),
+                 relevancy_bf16_abs=np.abs(s["rbf"] - r)[ok].max(),
+                 T_abs=np.abs(s["T"] - fT.reshape(-1))[ok].max())
+        out[key] = {k: float("%.3e" % v) for k, v in e.items()}
+        out[key]["pixels"] = int(len(s["pix"]))
+        out[key]["near_threshold_left_out"] = int((~ok).sum())
+    return out
+
+
 def train_step_timing(args, torch, np, gen, ls2):
     """Forward + backward of the feature-map objective on the differentiation
     workload (float32 throughout): project, bin_sort, splat, decode, loss,
@@ -272,6 +335,132 @@ def full_form(args, torch, np, gen, ls2, steps=2):
     return out
 
 
+def precision_form(args, torch, np, gen, ls2, n_pix=400):
+    """The precision workload (1440x1080, 300k Gaussians, D=512) at L in
+    {64, 128} and K in {4, 8}: the bf16 one-pass frame (project, bin_sort,
+    splat_decode) and the plain float32 path (project, bin_sort, float32
+    splat, float32 decode) timed on the same scene.  Keeps every output at
+    n_pix random pixels for the FP64 comparison of the oracle leg."""
+    out, samples = {}, {}
+    steps = max(5, args.steps // 2)
+    for L, K in ((64, 4), (64, 8), (128, 4), (128, 8)):
+        scene, cam = gen.config_scene("c4", L=L, K=K)
+        t = ls2.to_device(scene)
+        n, D = scene.n, scene.D
+        p16 = ls2.Pipeline(cam, n, levels=1, K=K, L=L, D=D, coef_dtype=torch.bfloat16)
+        p32 = ls2.Pipeline(cam, n, levels=1, K=K, L=L, D=D)
+        for p_ in (p16, p32):
+            p_.project(t["means"], t["scales"], t["quats"])
+            p_.bin_sort(sync=True)
+
+        def f16():
+            p16.project(t["means"], t["scales"], t["quats"])
+            p16.bin_sort(sync=False)
+            p16.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
+
+        def f32():
+            p32.project(t["means"], t["scales"], t["quats"])
+            p32.bin_sort(sync=False)
+            p32.splat(t["opacity"], t["topk_idx"], t["topk_w"])
+            p32.decode(t["dictionary"], ls2.LS2_F32, torch.float32)
+
+        row = {}
+        for name, fn in (("bf16_one_pass_fps", f16), ("f32_path_fps", f32)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            row[name] = round(steps / (time.perf_counter() - t0), 2)
+        out["L%d_K%d" % (L, K)] = row
+        log("precision form L=%d K=%d: %s" % (L, K, row))
+        # sampled outputs of both paths (outside the timed frames)
+        pos, neg = gen.make_text(1004 + 7, D=D)
+        tp, tn = torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda()
+        pix = np.random.default_rng(L + K).choice(cam.width * cam.height, n_pix, replace=False)
+        sel = torch.from_numpy(pix).cuda()
+        rbf = p16.splat_decode_query(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"], tp, tn)
+        bf = p16.feat
+        r32 = p32.query(tp, tn)
+        torch.cuda.synchronize()
+
+        def rows(x, w):
+            return x.reshape(-1, w)[sel].double().cpu().numpy()
+        samples["L%d_K%d" % (L, K)] = dict(
+            scene=scene, cam=cam, pix=pix, pos=pos, neg=neg,
+            ranges=p32.tile_ranges.cpu().numpy().view(np.uint32),
+            ids=p32.ids[:p32.num_pairs].cpu().numpy().view(np.uint32),
+            mean2d=p32.mean2d.double().cpu().numpy(), conic=p32.conic.double().cpu().numpy(),
+            coef=rows(p32.coef, L), f32=rows(p32.feat, D), bf=rows(bf, D), r32=rows(r32, 1)[:, 0],
+            rbf=rows(rbf, 1)[:, 0], T=rows(p32.final_T, 1)[:, 0])
+        del p16, p32, t
+        torch.cuda.empty_cache()
+    return out, samples
+
+
+def query_post_frames(args, torch, np, gen, ls2, kernel=29):
+    """Query frames with the relevancy post-processing of Section 3.2 and
+    the evaluation appendix: project, bin_sort, splat + bf16 decode +
+    relevancy in one pass (the feature map not written), then the box mean
+    over each level's map, the level selection, the argmax point and the
+    mask (ls2_postprocess, a kernel x kernel window).  On the 1440x1080
+    scene (one level) and on a 1920x1080 view of the 1M-Gaussian, 3-level
+    scene."""
+    out = {}
+    steps = max(5, args.steps // 2)
+    for name, cfg, levels in (("c2_1level", "c2", 1), ("c5_view0_3levels", "c5", 3)):
+        scene, cam = gen.config_scene(cfg)
+        if cfg == "c5":
+            cam = gen.orbit_camera(cam.width, cam.height, 0, 8)
+        t = ls2.to_device(scene)
+        pos, neg = gen.make_text(gen.CONFIGS[cfg]["seed"] + 7, D=scene.D)
+        tp, tn = torch.from_numpy(pos).cuda(), torch.from_numpy(neg).cuda()
+        p = ls2.Pipeline(cam, scene.n, levels=levels, K=scene.K, L=scene.L, D=scene.D, coef_dtype=torch.bfloat16)
+        p.project(t["means"], t["scales"], t["quats"])
+        p.bin_sort(sync=True)
+        H, W = cam.height, cam.width
+        sm = torch.empty((levels, H, W), dtype=torch.float32, device="cuda")
+        mask = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        res = torch.empty((4,), dtype=torch.int32, device="cuda")
+        ws = torch.empty((ls2.ls2_postprocess_workspace(levels, H, W),), dtype=torch.uint8, device="cuda")
+
+        def frame(ev=None):
+            if ev is not None:
+                ev[0].record()
+            p.project(t["means"], t["scales"], t["quats"])
+            p.bin_sort(sync=False)
+            rel = p.splat_decode_query(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"], tp, tn,
+                                       keep_feat=False)
+            if ev is not None:
+                ev[1].record()
+            ls2.ls2_postprocess(rel, kernel, sm, mask, res, ws)
+            if ev is not None:
+                ev[2].record()
+        for _ in range(3):
+            frame()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            frame()
+        torch.cuda.synchronize()
+        fps = steps / (time.perf_counter() - t0)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        for i in range(steps):
+            frame(evs[i])
+        torch.cuda.synchronize()
+        out[name] = dict(fps=round(fps, 2), workload="%d Gaussians, %dx%d, %d level(s)" % (scene.n, W, H, levels),
+                         render_decode_relevancy_ms=round(float(np.mean([e[0].elapsed_time(e[1]) for e in evs])), 4),
+                         postprocess_ms=round(float(np.mean([e[1].elapsed_time(e[2]) for e in evs])), 4),
+                         window=kernel)
+        log("query + post-processing %s: %s" % (name, out[name]))
+        del p, t, sm, mask, ws
+        torch.cuda.empty_cache()
+    out["paper_table1_context"] = "384.6 FPS querying (A100, its own scenes and resolution): context, not a target"
+    return out
+
+
 def dense_ablation(args, torch, np, gen, ls2):
     """Sparse (K of L blended) against dense (all L blended) splatting on the
     1440x1080 scene with one level (L = 64) and three levels (3 x 64 = 192,
@@ -322,6 +511,11 @@ def main():
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward (training step) timing")
     ap.add_argument("--train-config", default="c3")
     ap.add_argument("--no-ablation", action="store_true", help="skip the sparse-vs-dense splat timing")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the L in {64,128} x K in {4,8} timings and their FP64 comparison")
+    ap.add_argument("--no-query-post", action="store_true", help="skip the query + post-processing frames")
+    ap.add_argument("--cpu-frac-one-core", type=float, default=0.05,
+                    help="pixel fraction of the one-thread oracle run (extrapolated to the frame)")
     ap.add_argument("--no-full-form", action="store_true",
                     help="skip the 1M-Gaussian, 3-level, 8-view training step")
     ap.add_argument("--full-form-only", action="store_true",
@@ -374,14 +568,15 @@ def main():
         P = p_.bin_sort(sync=True)
     log("P =", P, "pairs")
 
-    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False, one_pass=False, keep_feat=True):
+    def frame(p_, compute, out_dtype, ev=None, query=False, fused=False, one_pass=False, keep_feat=True,
+              sync=False):
         def mark(i):
             if ev is not None:
                 ev[i].record()
         mark(0)
         p_.project(t["means"], t["scales"], t["quats"])
         mark(1)
-        p_.bin_sort(sync=False)
+        p_.bin_sort(sync=sync)  # sync: the pair count is read back to the host (one round trip)
         mark(2)
         if one_pass:  # splat and bf16 decode in one kernel: the coefficient map stays on chip
             if query:  # and the relevancy formed in the same pass
@@ -405,11 +600,12 @@ def main():
 
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
-    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False, one_pass=False, keep_feat=True):
+    def run(p_, compute, out_dtype, steps, warmup, query=False, fused=False, one_pass=False, keep_feat=True,
+            sync=False):
         """Wall-clock rate over `steps` uninstrumented frames, then the same
         number of frames with HIP events between the stages (per-stage
         times; these frames are not part of the rate)."""
-        kw = dict(query=query, fused=fused, one_pass=one_pass, keep_feat=keep_feat)
+        kw = dict(query=query, fused=fused, one_pass=one_pass, keep_feat=keep_feat, sync=sync)
         for _ in range(warmup):
             frame(p_, compute, out_dtype, **kw)
         torch.cuda.synchronize()
@@ -438,6 +634,13 @@ def main():
     fps = args.steps / wall
     ms = 1000.0 * wall / args.steps
     log("one-pass bf16 frame: %.1f FPS, %.3f ms/frame, stages %s" % (fps, ms, per))
+    # the same frames with bin_sort's host synchronisation (the pair count read
+    # back every frame, as a caller that sizes its buffers per frame would)
+    swall, sper, sper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup, one_pass=True,
+                                sync=True)
+    sync_frame = dict(fps=round(args.steps / swall, 2), ms_per_frame=round(1000.0 * swall / args.steps, 4),
+                      frame_ms_p10_p50_p90=sper_pct)
+    log("one-pass bf16 frame with the host sync: %s" % sync_frame)
     # the same feature map in two passes: bf16 coefficient map written by the
     # splat, read back by the decode
     twall, tper, tper_pct = run(pipe16, ls2.LS2_BF16, torch.bfloat16, args.steps, args.warmup)
@@ -543,6 +746,8 @@ def main():
         train = train_step_timing(args, torch, np, gen, ls2)
 
     ablation = None if args.no_ablation else dense_ablation(args, torch, np, gen, ls2)
+    precision, prec_samples = (None, None) if args.no_precision else precision_form(args, torch, np, gen, ls2)
+    query_post = None if args.no_query_post else query_post_frames(args, torch, np, gen, ls2)
     full = None if args.no_full_form else full_form(args, torch, np, gen, ls2)
 
     cpu = None
@@ -550,6 +755,13 @@ def main():
         log("timing the CPU oracle on a sample ...")
         cpu = cpu_baseline(cam, scene, args.cpu_frac)
         log("cpu oracle: %.4f FPS (%d threads)" % (cpu["value"], cpu["cores"]))
+        cpu["cpu_model"], cpu["logical_cpus"] = cpu_model()
+        cpu["stages_s"] = {k: round(v, 3) for k, v in cpu["stages_s"].items()}
+        cpu["one_core"] = cpu_baseline_one_core(args.config, args.cpu_frac_one_core)
+        log("cpu oracle, one thread: %s" % cpu["one_core"])
+        if prec_samples is not None:
+            precision["max_error_vs_fp64_oracle"] = c4_oracle_errors(prec_samples)
+            log("precision form errors: %s" % precision["max_error_vs_fp64_oracle"])
 
     out = {
         "metric": METRIC,
@@ -569,6 +781,7 @@ def main():
                    "pairs": P},
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
         "frame_ms_p10_p50_p90": per_pct,
+        "with_host_sync": sync_frame,
         "two_pass_frame": two_pass,
         "two_stream_fps": round(two_stream_fps, 2),
         "query_fps": round(query_fps, 2),
@@ -580,6 +793,8 @@ def main():
         "fp32_path": None if f32 is None else {"fps": round(f32["fps"], 2),
                                                "stages_ms": {k: round(v, 4) for k, v in f32["stages_ms"].items()}},
         "sparse_vs_dense_splat": ablation,
+        "precision_form": precision,
+        "query_postprocess": query_post,
         "full_form": full,
         "fwd_bwd_ms": None if train is None else round(train["ms"], 4),
         "fwd_bwd": train,
@@ -587,7 +802,9 @@ def main():
         "roofline_stages": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                             for k, v in roof_all.items()},
         "mfma": {k: round(v, 4) for k, v in mfma.items()},
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                                     "cpu_model", "logical_cpus", "stages_s",
+                                                                     "one_core")},
     }
     print(json.dumps(out), flush=True)
 

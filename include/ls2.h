@@ -68,6 +68,11 @@ const char* ls2_status_string(int status);
 /* Library version, major * 10000 + minor * 100 + patch. */
 int ls2_version(void);
 
+/* Fingerprint of the sources the library was built from (16 hex digits, or
+ * "unknown"); the Python binding refuses a library whose fingerprint differs
+ * from the sources beside it.  Static storage. */
+const char* ls2_source_hash(void);
+
 /* Turns the code-index check on (enabled != 0) or off for the whole process,
  * overriding LS2_CHECK; returns the previous setting (0 or 1). */
 int ls2_set_check(int enabled);

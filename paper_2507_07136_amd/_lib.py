@@ -45,6 +45,7 @@ def _load():
     sig = {
         "ls2_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "ls2_version": ([], ctypes.c_int),
+        "ls2_source_hash": ([], ctypes.c_char_p),
         "ls2_set_check": ([ctypes.c_int], ctypes.c_int),
         "ls2_project": ([cam, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
         "ls2_bin_sort_workspace": ([cam, i32, i64, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -89,6 +90,20 @@ def _load():
 
 
 _lib = _load()
+
+
+def _check_fresh():
+    """A library built from other sources than the ones beside it (a
+    forgotten rebuild) is refused."""
+    from ._srchash import source_hash
+    want = source_hash()
+    got = _lib.ls2_source_hash().decode()
+    if want is not None and got != want:
+        raise ImportError("libls2.so was built from other sources (fingerprint %s) than csrc/ holds (%s): rebuild it "
+                          "with `python paper_2507_07136_amd/build.py` or __graft_entry__.build()" % (got, want))
+
+
+_check_fresh()
 
 
 def lib():

@@ -13,3 +13,8 @@ extern "C" const char* ls2_status_string(int status) {
 }
 
 extern "C" int ls2_version(void) { return 100; }
+
+#ifndef LS2_SOURCE_HASH
+#define LS2_SOURCE_HASH "unknown"
+#endif
+extern "C" const char* ls2_source_hash(void) { return LS2_SOURCE_HASH; }

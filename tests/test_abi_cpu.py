@@ -282,3 +282,11 @@ def test_splat_decode_query_noalloc_validation_without_device(L):
     assert call(D=500) == -3
     assert call(Lc=48) == -3
     assert call(Lc=128, D=1024, n_neg=8) == -2   # 288 KB of scratch needed, 160 KiB held
+
+
+def test_library_built_from_these_sources():
+    """The loaded library's source fingerprint is the one of csrc/ and
+    include/ls2.h beside it (the binding refuses a stale build)."""
+    import paper_2507_07136_amd._lib as lib
+    from paper_2507_07136_amd._srchash import source_hash
+    assert lib._lib.ls2_source_hash().decode() == source_hash()
