@@ -78,22 +78,31 @@ struct SplatArgs {
 // x 64 features in bfloat16 (one 128-byte line per pixel).
 constexpr int kDecStageBytes = 64 * 64 * 2;
 
-// Staged record (dwords): u, v, A2, B2, C2, o, list position, index words,
-// group counts, weights.  The K coefficients are stored grouped by
-// accumulator vector (index / 32, in slot order inside a group): the index
-// words hold the low 5 bits of each index (8 bits per slot), the count word
-// 4 bits per group.  A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e): the
-// Gaussian's exponent in base 2 is A2 dx^2 + B2 dx dy + C2 dy^2.
-template <int KMAX>
+// Staged record (dwords): u, v, A2, B2, C2, o, list position, the first
+// code word, then the weights, then the remaining code words.
+//
+// The K coefficients go to accumulator vector h = index / 32 (NV vectors of
+// 32).  Vectors 2p and 2p + 1 share slot array p (KMAX weight slots): vector
+// 2p fills it from the front, vector 2p + 1 from the back, each in slot
+// order, so every slot a blend reads sits at a compile-time position.  Code
+// word 0 of array p holds slots 0-3 as 5-bit indices within the vector (bits
+// 0-19), the front count (bits 24-27) and the back count (bits 28-31); code
+// word 1 (KMAX = 8) holds slots 4-7.  Repeated indices of a Gaussian are
+// merged into their first slot (the sum of their weights, in slot order).
+// A2 = -0.5 A log2(e), B2 = -B log2(e), C2 = -0.5 C log2(e): the Gaussian's
+// exponent in base 2 is A2 dx^2 + B2 dx dy + C2 dy^2.
+template <int KMAX, int NV>
 struct Rec {
-    static_assert(KMAX == 4 || KMAX == 8, "the blend reads the weights as lanes 0..KMAX-1");
-    static constexpr int KW = (KMAX + 3) / 4;  // packed u8 index words
+    static_assert(KMAX == 4 || KMAX == 8, "weights are read as float4");
+    static constexpr int NP = (NV + 1) / 2;  // slot arrays
+    static constexpr int CW = KMAX / 4;      // code words per slot array
     static constexpr int POS = 6;
-    static constexpr int IDX = 7;
-    static constexpr int CNT = IDX + KW;
-    static constexpr int W = CNT + 1;
-    static constexpr int RAW = W + KMAX;
+    static constexpr int CODE0 = 7;          // code word 0 of slot array 0
+    static constexpr int W = 8;              // weights of slot array p at W + KMAX p
+    static constexpr int CODE = W + NP * KMAX;  // code word q of array p (but array 0, word 0) at CODE + p CW + q - 1
+    static constexpr int RAW = CODE + NP * CW - 1;
     static constexpr int STRIDE = (RAW + 3) & ~3;  // 16-byte aligned records
+    __device__ static int code_at(int p, int q) { return p == 0 && q == 0 ? CODE0 : CODE + p * CW + q - 1; }
 };
 
 // Decode tail of one wave: F = W S (Eq. 7) for the wave's 64 pixels (lane p
@@ -264,7 +273,7 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
 template <int NV, int KMAX, bool EXACT, int OUT, int CF>
 __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slot, int lane, float* stage,
                                            const unsigned short* dsrc) {
-    using R = Rec<KMAX>;
+    using R = Rec<KMAX, NV>;
     const CamK& cam = a.cam;
     const int quad = slot & 3, lv0 = slot >> 2;
     const int tx = tile % cam.tx, ty = tile / cam.tx;
@@ -354,44 +363,55 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
             reinterpret_cast<unsigned*>(r)[R::POS] = b - start + lane;
             unsigned ix[KMAX];
             float wv[KMAX];
+            bool live[KMAX];
 #pragma unroll
             for (int k = 0; k < KMAX; ++k) {
-                ix[k] = k < K ? (unsigned)(c_ix[k] & lmask) : 0xffu;
+                live[k] = k < K;
+                ix[k] = k < K ? (unsigned)(c_ix[k] & lmask) : 0u;
                 wv[k] = k < K ? c_w[k] : 0.0f;
             }
             // merge repeated indices into their first slot (the sum of their
-            // weights, in slot order); freed slots get index 0xff, which no
-            // accumulator vector matches
+            // weights, in slot order)
 #pragma unroll
             for (int k = 1; k < KMAX; ++k)
 #pragma unroll
                 for (int k2 = 0; k2 < k; ++k2)
-                    if (ix[k2] == ix[k] && ix[k] != 0xffu) {
+                    if (live[k2] && live[k] && ix[k2] == ix[k]) {
                         wv[k2] += wv[k];
-                        wv[k] = 0.0f;
-                        ix[k] = 0xffu;
+                        live[k] = false;
                     }
-            // grouped by accumulator vector, slot order inside a group
-            unsigned long long packed = 0ull;
-            unsigned cntw = 0u;
-            int pos = 0;
+            // slot arrays: vector 2p from the front, vector 2p + 1 from the back
+            unsigned code[R::NP][R::CW];
+            int nf[R::NP], nb[R::NP];
 #pragma unroll
-            for (int hh = 0; hh < NV; ++hh) {
-                int nh = 0;
+            for (int p = 0; p < R::NP; ++p) {
+                nf[p] = nb[p] = 0;
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k) {
-                    if (ix[k] != 0xffu && (int)(ix[k] >> 5) == hh) {
-                        packed |= (unsigned long long)(ix[k] & 31u) << (8 * pos);
-                        r[R::W + pos] = wv[k];
-                        ++pos;
-                        ++nh;
-                    }
-                }
-                cntw |= (unsigned)nh << (4 * hh);
+                for (int q = 0; q < R::CW; ++q) code[p][q] = 0u;
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q) r[R::W + p * KMAX + q] = 0.0f;
             }
 #pragma unroll
-            for (int q = 0; q < R::KW; ++q) reinterpret_cast<unsigned*>(r)[R::IDX + q] = (unsigned)(packed >> (32 * q));
-            reinterpret_cast<unsigned*>(r)[R::CNT] = cntw;
+            for (int k = 0; k < KMAX; ++k) {
+                if (!live[k]) continue;
+                const int h = (int)(ix[k] >> 5);
+#pragma unroll
+                for (int p = 0; p < R::NP; ++p) {
+                    if ((h >> 1) != p) continue;
+                    const int sl = (h & 1) ? KMAX - 1 - nb[p]++ : nf[p]++;
+                    r[R::W + p * KMAX + sl] = wv[k];
+#pragma unroll
+                    for (int q = 0; q < R::CW; ++q)
+                        if ((sl >> 2) == q) code[p][q] |= (ix[k] & 31u) << (5 * (sl & 3));
+                }
+            }
+            unsigned* ru = reinterpret_cast<unsigned*>(r);
+#pragma unroll
+            for (int p = 0; p < R::NP; ++p) {
+                code[p][0] |= (unsigned)nf[p] << 24 | (unsigned)nb[p] << 28;
+#pragma unroll
+                for (int q = 0; q < R::CW; ++q) ru[R::code_at(p, q)] = code[p][q];
+            }
         }
         wave_lds_order();  // single-wave workgroup: orders the LDS writes before the reads
 
@@ -418,12 +438,6 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
             for (int u = 0; u < UNR; ++u) {
                 if (j + u >= nkeep) break;  // wave-uniform
                 const float* r = stage + (j + u) * R::STRIDE;
-                // lane k holds the entry's k-th weight, read here with every
-                // lane active (the empty asm keeps the read out of the
-                // divergent branch below; the blend loop takes the weights
-                // with v_readlane, which reads lanes regardless of EXEC)
-                float wlane = r[R::W + (lane & (KMAX - 1))];
-                asm volatile("" : "+v"(wlane));
                 const float alpha = fminf(0.99f, g[u]);
                 const float c = alpha * T;       // blend weight e_i = alpha_i T_i (Eq. 7)
                 const float testT = T - c;       // T (1 - alpha)
@@ -432,21 +446,35 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
                 const bool contrib = hit && !stop;
                 active = active && !stop;
                 if (contrib) {  // divergent: only contributing lanes blend (exec mask)
-                    unsigned words[R::KW];
 #pragma unroll
-                    for (int q = 0; q < R::KW; ++q)
-                        words[q] = __builtin_amdgcn_readfirstlane(reinterpret_cast<const unsigned*>(r)[R::IDX + q]);
-                    const unsigned cntw = __builtin_amdgcn_readfirstlane(reinterpret_cast<const unsigned*>(r)[R::CNT]);
-                    unsigned long long packed = words[0];
-                    if (R::KW > 1) packed |= (unsigned long long)words[R::KW > 1 ? 1 : 0] << 32;
-                    int k = 0;
+                    for (int p = 0; p < R::NP; ++p) {
+                        unsigned cw[R::CW];
 #pragma unroll
-                    for (int hh = 0; hh < NV; ++hh) {
-                        const int nh = (int)(cntw >> (4 * hh)) & 15;
-                        for (int q = 0; q < nh; ++q, ++k) {  // wave-uniform trip count
-                            const unsigned jl = (unsigned)(packed >> (8 * k)) & 31u;
-                            const float w = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wlane), k));
-                            acc[hh][jl] = fmaf(w, c, acc[hh][jl]);
+                        for (int q = 0; q < R::CW; ++q)
+                            cw[q] = __builtin_amdgcn_readfirstlane(
+                                p == 0 && q == 0 ? __float_as_uint(h1[u].w)
+                                                 : reinterpret_cast<const unsigned*>(r)[R::code_at(p, q)]);
+                        f32x4s wq[KMAX / 4];
+#pragma unroll
+                        for (int q = 0; q < KMAX / 4; ++q)
+                            wq[q] = *reinterpret_cast<const f32x4s*>(r + R::W + p * KMAX + 4 * q);
+                        const int nfr = (int)(cw[0] >> 24) & 15, nbk = (int)(cw[0] >> 28);
+                        // vector 2p: slots 0, 1, ... (front)
+#pragma unroll
+                        for (int q = 0; q < KMAX; ++q) {
+                            if (q >= nfr) break;  // wave-uniform
+                            const unsigned jl = (cw[q >> 2] >> (5 * (q & 3))) & 31u;
+                            acc[2 * p][jl] = fmaf(wq[q >> 2][q & 3], c, acc[2 * p][jl]);
+                        }
+                        if (2 * p + 1 < NV) {
+                            // vector 2p + 1: slots KMAX - 1, KMAX - 2, ... (back)
+#pragma unroll
+                            for (int q = 0; q < KMAX; ++q) {
+                                if (q >= nbk) break;  // wave-uniform
+                                const int sl = KMAX - 1 - q;
+                                const unsigned jl = (cw[sl >> 2] >> (5 * (sl & 3))) & 31u;
+                                acc[(2 * p + 1) % NV][jl] = fmaf(wq[sl >> 2][sl & 3], c, acc[(2 * p + 1) % NV][jl]);
+                            }
                         }
                     }
                     T = testT;
@@ -501,8 +529,8 @@ __device__ __forceinline__ void splat_item(const SplatArgs& a, int tile, int slo
 // no room for 128-byte output staging (32-feature staging alone costs more
 // than the L2 reads save).
 template <int NV, int KMAX, bool EXACT, int OUT>
-__global__ __launch_bounds__(64, OUT < kOutDecode ? 1 : NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
-    using R = Rec<KMAX>;
+__global__ __launch_bounds__(64, NV <= 2 ? 4 : 2) void k_splat_sparse(SplatArgs a) {
+    using R = Rec<KMAX, NV>;
     constexpr int REC4 = 64 * R::STRIDE / 4;
     constexpr int STAGE4 = OUT >= kOutDecode && kDecStageBytes / 16 > REC4 ? kDecStageBytes / 16 : REC4;
     __shared__ float4 stage4[STAGE4];
