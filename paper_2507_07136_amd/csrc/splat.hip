@@ -141,17 +141,19 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
     static_assert(CF == 32 || CF == 64, "decode_tail: 32- or 64-feature chunks");
     const int col = lane & 31, half = lane >> 5;
     // A operand of lane l at k-step ks of feature tile ft: 16-byte unit
-    // (ft KS + ks) 64 + l of the packed dictionary (through L2).  The first
-    // tile's loads are issued before the operand conversion; later tiles load
-    // just before use: a second buffer would cost more (registers spilled)
-    // than the latency it hides, as measured.
+    // (ft KS + ks) 64 + l of the packed dictionary (through L2).  Both tiles
+    // of a chunk are loaded at once: the first chunk's before the operand
+    // conversion, each later chunk's as soon as the previous chunk's results
+    // are staged, so the L2 latency hides behind the store phase.  With QRY,
+    // whose scoring needs those registers, each tile loads just before use.
     const u32x4s* dv = reinterpret_cast<const u32x4s*>(dsrc) + lane;
-    auto load_a = [&](int ft, u32x4s (&o)[KS]) {
+    auto load_tile = [&](int ft, u32x4s (&o)[KS]) {
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) o[ks] = dv[(ft * KS + ks) * 64];
     };
-    u32x4s sa[KS];
-    load_a(0, sa);
+    u32x4s sa[FT][KS];  // QRY: one tile at a time, in sa[0]
+#pragma unroll
+    for (int cc = 0; cc < (QRY ? 1 : FT); ++cc) load_tile(cc, sa[cc]);
     bf16x8s wb[2][KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -188,12 +190,11 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
     for (int c = 0; c < D / CF; ++c) {
 #pragma unroll
         for (int cc = 0; cc < FT; ++cc) {
-            const int ft = FT * c + cc;
-            if (ft > 0) load_a(ft, sa);
+            if (QRY && FT * c + cc > 0) load_tile(FT * c + cc, sa[0]);
             f32x16s f0 = {}, f1 = {};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const bf16x8s av = __builtin_bit_cast(bf16x8s, sa[ks]);
+                const bf16x8s av = __builtin_bit_cast(bf16x8s, sa[QRY ? 0 : cc][ks]);
                 f0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[0][ks], f0, 0, 0, 0);
                 f1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, wb[1][ks], f1, 0, 0, 0);
             }
@@ -210,6 +211,11 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
             }
 
         }
+        // the chunk's operands are consumed: the next chunk's load from L2
+        // while this chunk is scored and stored
+        if (!QRY && c + 1 < D / CF)
+#pragma unroll
+            for (int cc = 0; cc < FT; ++cc) load_tile(FT * (c + 1) + cc, sa[cc]);
         wave_lds_order();
         if (QRY) {
             const bf16x8s zero8 = {};
@@ -229,14 +235,18 @@ __device__ __forceinline__ void decode_tail(const SplatArgs& a, const v32f (&acc
             }
         }
         if (store) {
+            // every staged line read first (one LDS wait), then the stores
+            f32x4s v[U];
 #pragma unroll
             for (int i = 0; i < U; ++i) {
                 const int p = PPI * i + pi;  // p % U == pi % U
-                const f32x4s v = *reinterpret_cast<const f32x4s*>(st + p * (U * 16) + ((su ^ (pi & (U - 1))) * 16));
+                v[i] = *reinterpret_cast<const f32x4s*>(st + p * (U * 16) + ((su ^ (pi & (U - 1))) * 16));
+            }
+#pragma unroll
+            for (int i = 0; i < U; ++i)
                 if (xin && qy0 + (8 / U) * i + yo < H)
                     __builtin_nontemporal_store(
-                        v, reinterpret_cast<f32x4s*>(fbase + (size_t)((8 / U) * i) * rstride + c * CF));
-            }
+                        v[i], reinterpret_cast<f32x4s*>(fbase + (size_t)((8 / U) * i) * rstride + c * CF));
         }
         wave_lds_order();  // the next chunk overwrites the staged lines
     }
