@@ -308,46 +308,55 @@ __global__ __launch_bounds__(512) void k_decode_bf16(DecodeArgs a) {
 // B (2 x 32) lane l holds column l%32, k = l/32; C as above.  The reduction
 // index is permuted so that lane half h covers k in [h*L/2, (h+1)*L/2): step s
 // pairs k = s (half 0) with k = L/2 + s (half 1), letting each lane read its
-// pixel's coefficients as contiguous float4s.  Each wave owns FW = 64
-// features (2 row tiles).
+// pixel's coefficients as contiguous float4s.
+//
+// Every wave works on its own: it owns one 64-feature slice of S (2 row
+// tiles, in VGPRs) and walks its own sequence of 32-pixel blocks, staging
+// each 32 x 64 result in a private LDS slice and writing it as 256-byte (128
+// for bf16 output) row segments.  With no workgroup barrier the waves that
+// share a SIMD drift into different phases, so one wave's matrix-core chain
+// runs while another stages and stores: the matrix cores are the bound.
+constexpr int kF32Waves = 8;  // waves per workgroup (independent)
+
 template <int L, bool OUT_BF16>
-__global__ __launch_bounds__(512, 1) void k_decode_f32(DecodeArgs a) {
+__global__ __launch_bounds__(kF32Waves * 64) void k_decode_f32(DecodeArgs a) {
     constexpr int KS = L / 2;
     constexpr int MT = 2;
     constexpr int OSZ = OUT_BF16 ? 2 : 4;
+    constexpr int SEG = 64 * OSZ;      // bytes of one pixel's slice
+    constexpr int SROW = SEG + 16;     // LDS row (padded against bank conflicts)
+    constexpr int U = SEG / 16;        // 16-byte units per pixel slice
+    constexpr int PPI = 64 / U;        // pixels per store instruction
     extern __shared__ float4 smem4[];
-    char* smem = reinterpret_cast<char*>(smem4);
-
     const int D = a.D;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
-    const int chunk = blockIdx.x % a.nchunks;
-    const int row_bytes = a.FC * OSZ;
-    const int srow = row_bytes + 16;
+    char* st = reinterpret_cast<char*>(smem4) + wave * 32 * SROW;
     const int col = lane & 31, half = lane >> 5;
-    const int f_wave = chunk * a.FC + wave * (MT * 32);
+    const int nfg = D / 64;
+    const long long gw = (long long)blockIdx.x * kF32Waves + wave;
+    const int fg = (int)(gw % nfg);
+    const long long bstep = (long long)gridDim.x * kF32Waves / nfg;
+    long long blk = gw / nfg;
+    const int f0 = fg * 64;
 
     float sa[MT][KS];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int s = 0; s < KS; ++s) sa[mt][s] = a.dict[(size_t)(half * KS + s) * D + f_wave + mt * 32 + col];
+        for (int s = 0; s < KS; ++s) sa[mt][s] = a.dict[(size_t)(half * KS + s) * D + f0 + mt * 32 + col];
 
-    const long long bstep = gridDim.x / a.nchunks;
-    long long blk = blockIdx.x / a.nchunks;
+    // store phase: instruction i covers pixels PPI i + lane / U, unit lane % U
+    const int sp = lane / U, su = lane % U;
     float4 raw[KS / 4];
-    float wv[KS];
-    auto convert = [&]() {
+    load_coef_f32path<L>(a, blk, col, half, raw);
+    for (; blk < a.nblocks; blk += bstep) {
+        const long long p0 = blk * 32;
+        float wv[KS];
 #pragma unroll
         for (int q = 0; q < KS / 4; ++q) {
             wv[4 * q] = raw[q].x; wv[4 * q + 1] = raw[q].y; wv[4 * q + 2] = raw[q].z; wv[4 * q + 3] = raw[q].w;
         }
-    };
-    load_coef_f32path<L>(a, blk, col, half, raw);
-    convert();
-    for (; blk < a.nblocks; blk += bstep) {
-        const long long p0 = blk * 32;
-        load_coef_f32path<L>(a, blk + bstep, col, half, raw);  // converted before this block's stores
+        load_coef_f32path<L>(a, blk + bstep, col, half, raw);  // the next block's, during this one
         f32x16 acc[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -355,43 +364,32 @@ __global__ __launch_bounds__(512, 1) void k_decode_f32(DecodeArgs a) {
 #pragma unroll
             for (int s = 0; s < KS; ++s) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[mt][s], wv[s], acc[mt], 0, 0, 0);
         }
+        // lane holds pixel col, features mt*32 + g*8 + half*4 + [0,4) of the slice
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int f = f_wave - chunk * a.FC + mt * 32 + g * 8 + half * 4;  // within the chunk
-                char* dst = smem + col * srow + f * OSZ;
+                char* dst = st + col * SROW + (mt * 32 + g * 8 + half * 4) * OSZ;
                 if (OUT_BF16) {
-                    uint2 v;
-                    v.x = pack_bf16x2(acc[mt][4 * g], acc[mt][4 * g + 1]);
-                    v.y = pack_bf16x2(acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
-                    *reinterpret_cast<uint2*>(dst) = v;
+                    *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16x2(acc[mt][4 * g], acc[mt][4 * g + 1]),
+                                                                pack_bf16x2(acc[mt][4 * g + 2], acc[mt][4 * g + 3]));
                 } else {
                     *reinterpret_cast<float4*>(dst) =
                         make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
                 }
             }
-        lds_barrier();
-        convert();
+        wave_lds_order();
+        f32x4v v[32 / PPI];
 #pragma unroll
-        for (int k = 0; k < KS; ++k) asm volatile("" : "+v"(wv[k]));  // before the stores, as above
-        const int chunks_per_row = row_bytes / 16;
-        const long long rows = (a.m - p0) < 32 ? (a.m - p0) : 32;
-        const int nvec = (int)rows * chunks_per_row;
-        const long long out_row = (long long)D * OSZ;
-        char* out = reinterpret_cast<char*>(a.feat) + p0 * out_row + (long long)chunk * row_bytes;
-        // 32 rows x FC*OSZ/16 vectors over FC threads: exactly 2*OSZ per thread
+        for (int i = 0; i < 32 / PPI; ++i)
+            v[i] = *reinterpret_cast<const f32x4v*>(st + (PPI * i + sp) * SROW + su * 16);
+        char* out = reinterpret_cast<char*>(a.feat) + (p0 + sp) * (long long)D * OSZ + (long long)f0 * OSZ + su * 16;
 #pragma unroll
-        for (int it = 0; it < 2 * OSZ; ++it) {
-            // unconditional: in a partial last block the surplus lanes store the
-            // block's final vector again (same data, same address), which keeps
-            // the store count fixed so the waits above stay exact
-            const int c = min(threadIdx.x + it * nwaves * 64, nvec - 1);
-            const int r = c / chunks_per_row, q = c - r * chunks_per_row;
-            const f32x4v v = *reinterpret_cast<const f32x4v*>(smem + r * srow + q * 16);
-            __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(out + (long long)r * out_row + q * 16));
-        }
-        lds_barrier();
+        for (int i = 0; i < 32 / PPI; ++i)
+            if (p0 + PPI * i + sp < a.m)
+                __builtin_nontemporal_store(
+                    v[i], reinterpret_cast<f32x4v*>(out + (long long)(PPI * i) * D * OSZ));
+        wave_lds_order();  // the slice's reads are done before the next block overwrites it
     }
 }
 
@@ -655,16 +653,20 @@ static int launch_decode(const DecodeArgs& a0, int compute, bool cb, hipStream_t
     if (compute == LS2_BF16) {
         return cb ? launch_decode_bf16<L, OB, true>(a, stream) : launch_decode_bf16<L, OB, false>(a, stream);
     } else {
-        const int threads = (a.FC / 64) * 64;
-        static bool attr = false;
-        if (!attr) {
-            if (hipFuncSetAttribute((const void*)k_decode_f32<L, OB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    96 * 1024) != hipSuccess)
-                return LS2_ERR_DEVICE;
-            attr = true;
-        }
-        const long long grid = grid_for((const void*)k_decode_f32<L, OB>, threads);
-        hipLaunchKernelGGL((k_decode_f32<L, OB>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+        // independent waves: every wave owns a 64-feature slice and its own
+        // 32-pixel blocks; the grid is a whole number of feature groups
+        const int nfg = a.D / 64;
+        const size_t lds32 = (size_t)kF32Waves * 32 * (64 * osz + 16);
+        const void* kern = (const void*)k_decode_f32<L, OB>;
+        long long grid = (long long)num_cus() * resident_per_cu(kern, kF32Waves * 64, lds32);
+        long long waves = grid * kF32Waves;
+        waves -= waves % nfg;
+        if (waves < nfg) waves = nfg;
+        if (waves > a.nblocks * nfg) waves = a.nblocks * nfg;
+        // whole workgroups with a whole number of feature groups (nfg is a power of two)
+        while ((waves % kF32Waves) != 0 || (waves % nfg) != 0) ++waves;
+        grid = waves / kF32Waves;
+        hipLaunchKernelGGL((k_decode_f32<L, OB>), dim3((unsigned)grid), dim3(kF32Waves * 64), lds32, stream, a);
     }
     LS2_LAUNCH_CHECK();
     return LS2_OK;
