@@ -15,9 +15,15 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ls2_oracle.c")
-_LIB = os.path.join(_HERE, "libls2_oracle.so")
-
 _CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp"]
+# LS2_ORACLE_SANITIZE=1: a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; the process must preload the
+# gcc sanitizer runtimes), used by the sanitizer test
+_SANITIZE = os.environ.get("LS2_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libls2_oracle_san.so" if _SANITIZE else "libls2_oracle.so")
+if _SANITIZE:
+    _CFLAGS = [f for f in _CFLAGS if f != "-O2"] + ["-O1", "-g", "-fno-omit-frame-pointer",
+                                                   "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
 
 
 def build(force: bool = False) -> str:

@@ -14,7 +14,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libls2.so")
+# LS2_LIB_SANITIZED=1 loads the host-sanitized build instead (a debugging
+# build of the same sources; the process must preload the sanitizer runtimes)
+LIB_PATH = os.path.join(_HERE, "libls2_san.so" if os.environ.get("LS2_LIB_SANITIZED") == "1" else "libls2.so")
 
 LS2_OK, LS2_ERR_ARG, LS2_ERR_CAPACITY, LS2_ERR_UNSUPPORTED, LS2_ERR_DEVICE = 0, -1, -2, -3, -4
 LS2_F32, LS2_BF16 = 0, 1

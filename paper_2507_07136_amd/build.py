@@ -41,34 +41,45 @@ def _source_hash():
     return m.source_hash()
 
 
-def _compile(src, src_hash):
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, '-DLS2_SOURCE_HASH="%s"' % src_hash, "-c", src, "-o", obj]
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build (libls2_san.so,
+# device code unchanged): for the CPU checks of the argument validation.
+SAN_LIB = os.path.join(PKG, "libls2_san.so")
+SAN_BUILD_DIR = os.path.join(ROOT, "_build_san")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src, src_hash, sanitize=False):
+    obj = os.path.join(SAN_BUILD_DIR if sanitize else BUILD_DIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *CFLAGS, *(SAN_FLAGS if sanitize else []), '-DLS2_SOURCE_HASH="%s"' % src_hash, "-c", src,
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library.  Always rebuilds."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source and link the shared library (sanitize: the
+    host-sanitized libls2_san.so).  Always rebuilds."""
+    os.makedirs(SAN_BUILD_DIR if sanitize else BUILD_DIR, exist_ok=True)
+    lib = SAN_LIB if sanitize else LIB
     srcs = sources()
     jobs = min(len(srcs), max(1, min(16, os.cpu_count() or 1)))
     src_hash = _source_hash()
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda f: _compile(f, src_hash), srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
+        objs = list(ex.map(lambda f: _compile(f, src_hash, sanitize), srcs))
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *(SAN_FLAGS if sanitize else []), *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv)
     sys.exit(0)
