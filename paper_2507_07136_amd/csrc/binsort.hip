@@ -14,12 +14,11 @@
 //   3. k_sb_emit  : per Gaussian, the 64-bit key (depth bits << 32 | id) into
 //                   each touched superblock's bucket (LDS histogram again, one
 //                   reserving atomic per workgroup and superblock, LDS cursors);
-//   4. k_sb_sort_radix: one workgroup per superblock sorts its bucket with an
-//                   LSD radix sort in LDS (8-bit digits of the depth half that
-//                   vary within the bucket, stable ballot ranking; runs of
-//                   equal depth are then put in id order in place) and
-//                   counts, for each of its S x S tiles, the entries whose
-//                   rectangle covers the tile (buckets beyond the LDS
+//   4. k_sb_sort  : one workgroup per superblock sorts its bucket in LDS
+//                   (keys binned over the bucket's depth range, each short
+//                   bin sorted by insertion, long bins by a bitonic network)
+//                   and counts, for each of its S x S tiles, the entries
+//                   whose rectangle covers the tile (buckets beyond the LDS
 //                   capacity are first split into 256 bins over their depth
 //                   range, and runs of bins are sorted in LDS; only a single
 //                   over-full bin falls back to a bitonic network in global
@@ -27,11 +26,12 @@
 //   5. k_tile_scan: one workgroup: tile ranges (row-major) and P;
 //   6. k_tile_fill: each tile's list is the ordered subsequence of its
 //                   superblock's sorted bucket whose rectangles cover the tile:
-//                   an order-preserving ballot compaction, one wave per tile,
-//                   so every tile list comes out already in (depth, id) order.
-//                   With S = 4 (k_tile_fill_chunks) every 2048-entry chunk of a
-//                   bucket is filled on its own, its list offsets taken from
-//                   per-chunk tile counts that step 4 records.
+//                   an order-preserving ballot compaction, so every tile list
+//                   comes out already in (depth, id) order.  With S = 4
+//                   (k_tile_fill_chunks) every 2048-entry chunk of a bucket is
+//                   filled on its own, its list offsets taken from per-chunk
+//                   tile counts that step 4 records, each wave emitting its
+//                   slice of the chunk into all 16 tiles.
 #include "ls2_internal.h"
 
 namespace ls2 {
@@ -441,236 +441,197 @@ __device__ __forceinline__ void count_sb_tiles(const BinArgs& a, int sb, const u
 
 constexpr int kMaxS2 = 32 * 32;  // tile counters per superblock (S <= 32)
 
-// LDS radix sort of one bucket (or one chunk of a large bucket).
-//
-// A key is (float32 depth bits << 32 | id); ids are unique inside a bucket,
-// so the keys are too.  The passes run over the digits of the depth half
-// only.  That leaves the keys ordered by depth, with equal depths in arbitrary
-// order.  A fix-up step then orders each run of equal depth by id: a key's
-// place is the start of its run plus the number of the run's keys below it.
-// Equal float32 depths are rare and their runs short.  So the fix-up replaces
-// the id passes: three passes at 10^5..10^6 Gaussians.  A run longer than 16
-// keys (degenerate scenes, e.g. every depth equal) falls back to the full
-// LSD sort over every varying digit of the key.
-constexpr int kRadixCap = 16384;
-constexpr int kRadixWaves = 16;
+// LDS sort of one bucket (or one chunk of a large bucket).  A key is
+// (float32 depth bits << 32 | id); ids are unique inside a bucket, so the
+// keys are too, and their order is total.
+constexpr int kSortCap = 16384;
+constexpr int kSortWaves = 16;
 
-struct RadixSmem {
-    unsigned long long xbuf[kRadixCap];
-    unsigned ctr[kRadixWaves][256];
+struct SortSmem {
+    unsigned long long xbuf[kSortCap];
+    unsigned ctr[kSortWaves][256];
     unsigned tcnt[kMaxS2];
-    unsigned wsum[4];
-    unsigned bits[4];
-    unsigned longrun;           // fix-up found a run of equal depth beyond 16 keys
+    unsigned bits[4];           // large buckets: OR and AND of the keys
     unsigned hmin, hmax;        // large buckets: range of the keys' depth halves
     unsigned chunk_start[257];  // large buckets: key offset of each chunk
     unsigned nchunks;
+    unsigned wred[kSortWaves][4];  // per-wave key ranges
+    unsigned wscan[kSortWaves];    // per-wave bin totals
+    unsigned big[kMaxS2];           // long bins: start | count << 15
+    unsigned nbig;
 };
 
-// Sorts cnt <= kRadixCap keys from src into dst (may alias) in LDS; on
-// return the sorted keys are also in sm.xbuf[0, cnt).  Called by the whole
-// workgroup.  The caller orders earlier LDS use of sm before the call; the
-// call ends with an LDS barrier (the global writes to dst are not waited for).
-__device__ __forceinline__ void radix_sort_lds(RadixSmem& sm, const unsigned long long* src, unsigned long long* dst,
-                                               int cnt) {
-    constexpr int NW = kRadixWaves;
-    constexpr int ITEMS = kRadixCap / (64 * NW);  // chunks per wave, at most
+// Sort of one bucket (or one chunk of a large bucket) in LDS: cnt <=
+// kSortCap unique keys from src into dst (may alias); the sorted keys are
+// also left in sm.xbuf[0, cnt).
+//
+// The keys are distributed over nb bins (the power of two >= cnt, within
+// [64, 4096]) by a bin number that is non-decreasing in the key: the key's
+// depth half mapped linearly onto the bucket's depth range (if every depth is
+// equal, its id half onto the id range).  Every key of a lower bin is then
+// smaller than every key of a higher one.  A histogram and its scan give each
+// bin its place, and the keys are scattered there.  The thread that owns a
+// bin in the scan sorts it in place by insertion, comparing whole 64-bit
+// keys, so ties of depth are ordered by id with no extra step.  Bins of more
+// than kBinSortMax keys (depths clustered more tightly than the bin width)
+// are instead sorted one after another by the whole workgroup with the
+// bitonic network in LDS.
+//
+// Called by the whole workgroup; the caller orders earlier LDS use of sm
+// before the call, and the call ends with an LDS barrier (the global writes
+// to dst are not waited for).
+constexpr int kBinSortMax = 16;
+
+__device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long* src, unsigned long long* dst,
+                                         int cnt) {
+    constexpr int NW = kSortWaves;
+    constexpr int ITEMS = kSortCap / (64 * NW);  // chunks per wave, at most
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
     const int nchunk = (cnt + 63) >> 6;
     const int cpw = (nchunk + NW - 1) / NW;
     const int c0 = w * cpw;
     const int mine = max(0, min(cpw, nchunk - c0));  // this wave's chunks (wave-uniform)
+    int nb = 64;
+    while (nb < cnt && nb < 4096) nb <<= 1;
+    unsigned* const bins = &sm.ctr[0][0];  // NW * 256 = 4096 counters
 
     unsigned long long key[ITEMS];
-    unsigned long long kor = 0ull, kand = ~0ull;
+    unsigned hlo = 0xffffffffu, hhi = 0u, ilo = 0xffffffffu, ihi = 0u;
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
-        key[c] = ~0ull;
-        if (c < mine) {
-            const int p = (c0 + c) * 64 + lane;
-            if (p < cnt) {
-                key[c] = src[p];
-                kor |= key[c];
-                kand &= key[c];
-            }
-            sm.xbuf[p] = key[c];
+        key[c] = 0ull;
+        const int p = (c0 + c) * 64 + lane;
+        if (c < mine && p < cnt) {
+            key[c] = src[p];
+            const unsigned h = (unsigned)(key[c] >> 32), id = (unsigned)key[c];
+            hlo = min(hlo, h);
+            hhi = max(hhi, h);
+            ilo = min(ilo, id);
+            ihi = max(ihi, id);
         }
     }
-    if (threadIdx.x < 4) sm.bits[threadIdx.x] = threadIdx.x < 2 ? 0u : ~0u;
-    if (threadIdx.x == 0) sm.longrun = 0u;
-    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) bins[i] = 0u;
+    if (threadIdx.x == 0) sm.nbig = 0u;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        kor |= __shfl_xor(kor, off);
-        kand &= __shfl_xor(kand, off);
+        hlo = min(hlo, (unsigned)__shfl_xor((int)hlo, off));
+        hhi = max(hhi, (unsigned)__shfl_xor((int)hhi, off));
+        ilo = min(ilo, (unsigned)__shfl_xor((int)ilo, off));
+        ihi = max(ihi, (unsigned)__shfl_xor((int)ihi, off));
     }
-    if (lane == 0 && mine > 0) {
-        atomicOr(&sm.bits[0], (unsigned)kor);
-        atomicOr(&sm.bits[1], (unsigned)(kor >> 32));
-        atomicAnd(&sm.bits[2], (unsigned)kand);
-        atomicAnd(&sm.bits[3], (unsigned)(kand >> 32));
+    if (lane == 0) {
+        sm.wred[w][0] = hlo;
+        sm.wred[w][1] = hhi;
+        sm.wred[w][2] = ilo;
+        sm.wred[w][3] = ihi;
     }
     __syncthreads();
-    const unsigned long long varying = (((unsigned long long)sm.bits[1] << 32) | sm.bits[0]) ^
-                                       (((unsigned long long)sm.bits[3] << 32) | sm.bits[2]);
-
-    // Digit sequence: it = 0..3 are the depth half (shift 32..56); after a
-    // fix-up that found a run beyond 64 keys, it = 4..11 are every digit.
-    int it = 0, it_end = 4;
-    for (;;) {
-    for (; it < it_end; ++it) {
-        const int shift = it < 4 ? 32 + 8 * it : 8 * (it - 4);
-        if (((varying >> shift) & 0xffull) == 0ull) continue;  // uniform across the workgroup
-        // 1. per-wave digit counts
-        for (int i = lane; i < 256; i += 64) sm.ctr[w][i] = 0u;
-        wave_sync();
 #pragma unroll
-        for (int c = 0; c < ITEMS; ++c)
-            if (c < mine) atomicAdd(&sm.ctr[w][(unsigned)(key[c] >> shift) & 0xffu], 1u);
-        __syncthreads();
-        // 2. scatter offsets, digit-major then wave order (waves 0-3 own one digit per lane)
-        unsigned total = 0u, incl = 0u;
-        if (threadIdx.x < 256) {
-            const int d = threadIdx.x;
-#pragma unroll
-            for (int v = 0; v < NW; ++v) {
-                const unsigned x = sm.ctr[v][d];
-                sm.ctr[v][d] = total;
-                total += x;
-            }
-            incl = total;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const unsigned y = __shfl_up(incl, off);
-                if (lane >= off) incl += y;
-            }
-            if (lane == 63) sm.wsum[w] = incl;
-        }
-        __syncthreads();
-        if (threadIdx.x < 256) {
-            const int d = threadIdx.x;
-            unsigned base = incl - total;  // digits below d inside this wave
-            for (int v = 0; v < w; ++v) base += sm.wsum[v];
-#pragma unroll
-            for (int v = 0; v < NW; ++v) sm.ctr[v][d] += base;
-        }
-        __syncthreads();
-        // 3. stable scatter
-#pragma unroll
-        for (int c = 0; c < ITEMS; ++c) {
-            if (c < mine) {
-                const unsigned d = (unsigned)(key[c] >> shift) & 0xffu;
-                unsigned long long peers = ~0ull;
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const bool bit = (d >> b) & 1u;
-                    const unsigned long long bal = __builtin_amdgcn_ballot_w64(bit);
-                    peers &= bit ? bal : ~bal;
-                }
-                const unsigned rank = (unsigned)__builtin_popcountll(peers & lt);
-                const unsigned base = sm.ctr[w][d];
-                if ((peers & lt) == 0ull) sm.ctr[w][d] = base + (unsigned)__builtin_popcountll(peers);
-                sm.xbuf[base + rank] = key[c];
-            }
-        }
-        __syncthreads();
-        // 4. reload in the new order
-#pragma unroll
-        for (int c = 0; c < ITEMS; ++c)
-            if (c < mine) key[c] = sm.xbuf[(c0 + c) * 64 + lane];
+    for (int v = 0; v < NW; ++v) {
+        hlo = min(hlo, sm.wred[v][0]);
+        hhi = max(hhi, sm.wred[v][1]);
+        ilo = min(ilo, sm.wred[v][2]);
+        ihi = max(ihi, sm.wred[v][3]);
     }
-    if (it_end == 12 || (unsigned)varying == 0u) break;  // full sort done, or the id half is uniform
-    // Fix-up of equal-depth runs in sm.xbuf (depth-ordered; the last pass, or
-    // the initial copy, ended with a workgroup barrier).  The lane that holds
-    // the first position of a run sorts the run in place by insertion.  Other
-    // lanes only compare depth halves with their neighbours, and every key of
-    // a run has the same depth half, so no barrier is needed in between.
-    constexpr int kRun = 16;  // longest run resolved here
-    bool longrun = false;
-    for (int p = threadIdx.x; p + 1 < cnt; p += blockDim.x) {
-        const unsigned hi = (unsigned)(sm.xbuf[p] >> 32);
-        if ((unsigned)(sm.xbuf[p + 1] >> 32) != hi || (p > 0 && (unsigned)(sm.xbuf[p - 1] >> 32) == hi)) continue;
-        int e = p + 2;
-        while (e < cnt && e - p <= kRun && (unsigned)(sm.xbuf[e] >> 32) == hi) ++e;
-        if (e - p > kRun) {
-            longrun = true;
-            continue;
-        }
-        for (int q = p + 1; q < e; ++q) {
-            const unsigned long long v = sm.xbuf[q];
-            int t = q - 1;
-            while (t >= p && sm.xbuf[t] > v) {
-                sm.xbuf[t + 1] = sm.xbuf[t];
-                --t;
-            }
-            sm.xbuf[t + 1] = v;
-        }
-    }
-    if (__builtin_amdgcn_ballot_w64(longrun) != 0ull && lane == 0) atomicOr(&sm.longrun, 1u);
-    __syncthreads();  // the runs are sorted; the flag is set
+    // bin number: non-decreasing in the key (every conversion and the
+    // product by a positive factor are monotone; the clamp absorbs rounding)
+    const bool by_id = hlo == hhi;
+    const unsigned vbase = by_id ? ilo : hlo;
+    const float vscale = (float)nb / ((float)(by_id ? ihi - ilo : hhi - hlo) + 1.0f);
+    auto bin_of = [=](unsigned long long k) -> unsigned {
+        const unsigned v = by_id ? (unsigned)k : (unsigned)(k >> 32);
+        return min((unsigned)(nb - 1), (unsigned)((float)(v - vbase) * vscale));
+    };
+    // 1. histogram
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c)
-        if (c < mine) key[c] = sm.xbuf[(c0 + c) * 64 + lane];
-    if (sm.longrun == 0u) break;
-    // Runs beyond kRun keys: every varying digit (it = 4..11), starting from
-    // the current order (a permutation of the keys).
-    it_end = 12;
-    }
+        if (c < mine && (c0 + c) * 64 + lane < cnt) atomicAdd(&bins[bin_of(key[c])], 1u);
+    __syncthreads();
+    // 2. exclusive scan of the bin counts: thread t owns bins [t per, t per + per)
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;  // 1, 2 or 4
+    unsigned bc[4], loc = 0u;
 #pragma unroll
-    for (int c = 0; c < ITEMS; ++c) {
-        if (c < mine) {
-            const int p = (c0 + c) * 64 + lane;
-            if (p < cnt) dst[p] = key[c];
+    for (int q = 0; q < 4; ++q) {
+        const int i = (int)threadIdx.x * per + q;
+        bc[q] = (q < per && i < nb) ? bins[i] : 0u;
+        loc += bc[q];
+    }
+    unsigned incl = loc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) sm.wscan[w] = incl;
+    __syncthreads();
+    unsigned run = incl - loc;
+#pragma unroll
+    for (int v = 0; v < NW; ++v)
+        if (v < w) run += sm.wscan[v];
+    unsigned st[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        st[q] = run;
+        const int i = (int)threadIdx.x * per + q;
+        if (q < per && i < nb) bins[i] = run;  // this thread alone read bins[i] above
+        if (bc[q] > (unsigned)kBinSortMax)     // at most cnt / (kBinSortMax + 1) < kMaxS2 such bins
+            sm.big[atomicAdd(&sm.nbig, 1u)] = run | bc[q] << 15;
+        run += bc[q];
+    }
+    __syncthreads();
+    // 3. scatter: each key to the next free place of its bin (the counters
+    // are now cursors)
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c)
+        if (c < mine && (c0 + c) * 64 + lane < cnt) sm.xbuf[atomicAdd(&bins[bin_of(key[c])], 1u)] = key[c];
+    __syncthreads();
+    // 4. each thread sorts the short bins it owns
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (bc[q] > (unsigned)kBinSortMax) continue;
+        const int b0 = (int)st[q], b1 = b0 + (int)bc[q];
+        for (int i = b0 + 1; i < b1; ++i) {
+            const unsigned long long v = sm.xbuf[i];
+            int j = i - 1;
+            while (j >= b0 && sm.xbuf[j] > v) {
+                sm.xbuf[j + 1] = sm.xbuf[j];
+                --j;
+            }
+            sm.xbuf[j + 1] = v;
         }
     }
+    // 5. long bins, one at a time, by the whole workgroup (each network ends
+    // with a workgroup barrier; they touch disjoint ranges, none a short bin)
+    const unsigned nbig = sm.nbig;  // stored before the last barrier
+    for (unsigned k = 0; k < nbig; ++k) {
+        const unsigned e = sm.big[k];
+        flip_bitonic<true>(sm.xbuf + (e & 0x7fffu), (int)(e >> 15));
+    }
     lds_barrier();
+    for (int p = threadIdx.x; p < cnt; p += blockDim.x) dst[p] = sm.xbuf[p];
 }
 
-// Superblocks with count <= kRadixCap: least-significant-digit radix sort in
-// LDS, then write back and count tiles.
-//
-// The 64-bit keys (float32 depth bits << 32 | id) stay in registers: wave w
-// owns the contiguous chunks [w cpw, (w+1) cpw) of 64 positions, lane l of
-// chunk c holds position 64 c + l (positions past the count hold ~0, which
-// sorts last).  Each pass on an 8-bit digit
-//   1. counts the digits of every wave in wave-private LDS counters,
-//   2. turns the counts into scatter offsets (digit-major, then wave order),
-//   3. scatters: within a chunk the lanes holding the same digit find each
-//      other with eight ballots, so a key's destination is its wave's
-//      running offset for the digit plus its rank among those lanes -- the
-//      order of equal digits is kept (stable), which makes the passes an LSD
-//      sort,
-//   4. reloads the keys in the new order.
-// Digits on which every key of the bucket agrees are skipped, and the id half
-// is ordered by the fix-up of equal-depth runs described at radix_sort_lds:
-// in practice three or four passes over the depth digits.
+// One workgroup per superblock (largest buckets first): buckets of at most
+// kSortCap keys are sorted in LDS (sort_lds), written back and their tiles
+// counted.
 //
 // Larger buckets are first split into 256 bins over the range of their depth
 // bits (a most-significant-digit pass through a scratch copy in the free part
-// of the pool); runs of consecutive digit bins of at most kRadixCap keys are then
-// sorted as above, in key order, back into the bucket.  Only a bucket with a
-// single digit bin beyond kRadixCap, or a pool without room for the scratch
+// of the pool); runs of consecutive digit bins of at most kSortCap keys are
+// then sorted in LDS, in key order, back into the bucket.  Only a bucket with
+// a single digit bin beyond kSortCap, or a pool without room for the scratch
 // copy, uses the bitonic network in global memory.
-__global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
-    __shared__ RadixSmem sm;
-    if ((int)blockIdx.x >= a.nsb || a.meta->sb_overflow) return;
-    const int sb = (int)a.sb_order[blockIdx.x];
-    const int cnt = (int)a.sb_count[sb];
-    if (cnt == 0) return;  // tile counts are pre-zeroed
-    unsigned long long* g = a.pool + a.sb_start[sb];
-    if (cnt <= kRadixCap) {
-        radix_sort_lds(sm, g, g, cnt);
-        count_sb_tiles(a, sb, sm.xbuf, cnt, sm.tcnt);  // starts with a workgroup barrier
-        return;
-    }
+// A bucket beyond kSortCap keys: split into the scratch copy by a digit over
+// its depth range and return the number of LDS-sized chunks (their key offsets
+// in sm.chunk_start); 0 if it was sorted here instead, with the global bitonic
+// network (no room for the scratch copy, or one digit bin beyond kSortCap).
+__device__ int split_bucket(const BinArgs& a, SortSmem& sm, unsigned long long* g, int cnt) {
     const long long total = a.meta->sb_total;
     if (2 * total > a.max_pairs) {  // no room for the scratch copy
         flip_bitonic<false>(g, cnt);
-        count_sb_tiles(a, sb, g, cnt, sm.tcnt);
-        return;
+        return 0;
     }
-    unsigned long long* tmp = a.pool + total + a.sb_start[sb];
+    unsigned long long* tmp = a.pool + total + (g - a.pool);
     // varying bits of the bucket, and the range of its depth halves
     unsigned long long kor = 0ull, kand = ~0ull;
     unsigned hlo = 0xffffffffu, hhi = 0u;
@@ -725,13 +686,13 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) atomicAdd(&sm.ctr[0][split_digit(g[e])], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
-        // digit offsets, and runs of consecutive digits of at most kRadixCap keys
+        // digit offsets, and runs of consecutive digits of at most kSortCap keys
         unsigned off = 0u, run = 0u, nch = 0u;
         bool ok = true;
         for (int d = 0; d < 256; ++d) {
             const unsigned c = sm.ctr[0][d];
-            if (c > (unsigned)kRadixCap) ok = false;
-            if (run > 0u && run + c > (unsigned)kRadixCap) {  // at most 255 closes: chunk_start fits
+            if (c > (unsigned)kSortCap) ok = false;
+            if (run > 0u && run + c > (unsigned)kSortCap) {  // at most 255 closes: chunk_start fits
                 sm.chunk_start[nch++] = off - run;
                 run = 0u;
             }
@@ -747,8 +708,7 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
     const int nch = (int)sm.nchunks;
     if (nch == 0) {  // one digit bin holds more keys than the LDS sort: global bitonic network
         flip_bitonic<false>(g, cnt);
-        count_sb_tiles(a, sb, g, cnt, sm.tcnt);
-        return;
+        return 0;
     }
     // scatter into the scratch copy by split digit (order inside a bin is not
     // needed: every chunk is fully sorted next)
@@ -758,14 +718,34 @@ __global__ __launch_bounds__(kRadixWaves * 64) void k_sb_sort_radix(BinArgs a) {
     }
     __threadfence_block();
     __syncthreads();
-    for (int c = 0; c < nch; ++c) {
-        const int b0 = (int)sm.chunk_start[c], b1 = (int)sm.chunk_start[c + 1];
-        if (b1 > b0) radix_sort_lds(sm, tmp + b0, g + b0, b1 - b0);
-    }
-    __threadfence_block();  // the chunks' global writes, before count_sb_tiles reads g
-    count_sb_tiles(a, sb, g, cnt, sm.tcnt);
+    return nch;
 }
 
+
+
+__global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
+    __shared__ SortSmem sm;
+    if ((int)blockIdx.x >= a.nsb || a.meta->sb_overflow) return;
+    const int sb = (int)a.sb_order[blockIdx.x];
+    const int cnt = (int)a.sb_count[sb];
+    if (cnt == 0) return;  // tile counts are pre-zeroed
+    unsigned long long* g = a.pool + a.sb_start[sb];
+    // units sorted in LDS: the whole bucket, or the chunks of a split bucket
+    const unsigned long long* src = g;
+    int nunits = 1;
+    bool in_lds = true;  // the sorted bucket is also in sm.xbuf
+    if (cnt > kSortCap) {
+        in_lds = false;
+        nunits = split_bucket(a, sm, g, cnt);
+        src = a.pool + a.meta->sb_total + a.sb_start[sb];
+    }
+    for (int u = 0; u < nunits; ++u) {
+        const int b0 = in_lds ? 0 : (int)sm.chunk_start[u], b1 = in_lds ? cnt : (int)sm.chunk_start[u + 1];
+        if (b1 > b0) sort_lds(sm, src + b0, g + b0, b1 - b0);
+    }
+    if (!in_lds) __threadfence_block();  // the global writes, before count_sb_tiles reads g
+    count_sb_tiles(a, sb, in_lds ? sm.xbuf : g, cnt, sm.tcnt);  // starts with a workgroup barrier
+}
 
 __global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
     const int ntiles = a.cam.tx * a.cam.ty;
@@ -874,13 +854,20 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill(BinArgs a) {
 // so a large bucket's chunks are filled by several workgroups at once.  A
 // chunk's first list position in each tile is the tile's start plus the
 // entries of that tile in the bucket's earlier chunks (counted by the sort
-// kernel); the compaction inside the chunk is the ballot scan above.  A
-// fixed grid strides over the chunks (their number is known on the device
-// only).
+// kernel).  Inside the chunk, wave w takes the 128 entries [128 w, 128 w +
+// 128), two per lane, and emits each into every tile of the superblock its
+// rectangle covers: per tile one ballot, the lane's place among the covering
+// lanes, and a store.  The waves' per-tile counts, exchanged through LDS,
+// give every wave its starting place in each tile, so each tile's list keeps
+// the bucket's (depth, id) order.  A fixed grid strides over the chunks
+// (their number is known on the device only).
+constexpr int kFillWaves = kFillThreads / 64;
+constexpr int kFillPerLane = kFillChunk / kFillThreads;  // entries per lane
+static_assert(kFillWaves == 16 && kFillPerLane == 2, "one 128-entry slice per wave");
+
 __global__ __launch_bounds__(kFillThreads) void k_tile_fill_chunks(BinArgs a) {
-    __shared__ unsigned long long skey[kFillChunk];
-    __shared__ ushort4 srect[kFillChunk];
     __shared__ unsigned toff[16];
+    __shared__ unsigned wcnt[kFillWaves][16];
     if (a.meta->overflow) return;
     const long long nch = a.meta->nchunks;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -893,44 +880,74 @@ __global__ __launch_bounds__(kFillThreads) void k_tile_fill_chunks(BinArgs a) {
         const int n = min(kFillChunk, (int)a.sb_count[sb] - base);
         const int tx0 = (sb % a.sbx) * 4, ty0 = (sb / a.sbx) * 4;
         const unsigned long long* list = a.pool + a.sb_start[sb] + base;
+        unsigned long long key[kFillPerLane];
+#pragma unroll
+        for (int q = 0; q < kFillPerLane; ++q) {
+            const int e = wave * 64 * kFillPerLane + q * 64 + lane;
+            key[q] = e < n ? list[e] : 0ull;
+        }
         __syncthreads();  // the previous chunk's LDS reads are done
         if (threadIdx.x < 16) {
             const int t = threadIdx.x, x = tx0 + (t & 3), y = ty0 + (t >> 2);
             toff[t] = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x)] : 0u;
         }
-        __syncthreads();
-        // plus the tile's entries in the bucket's earlier chunks, all loads at once
+        // coverage of the superblock's 16 tiles (bit 4 y + x)
+        unsigned cover[kFillPerLane];
+#pragma unroll
+        for (int q = 0; q < kFillPerLane; ++q) {
+            const int e = wave * 64 * kFillPerLane + q * 64 + lane;
+            cover[q] = 0u;
+            if (e < n) {
+                const ushort4 r = a.rect[(unsigned)(key[q] & 0xffffffffull)];
+                const int x0 = max((int)r.x - tx0, 0), x1 = min((int)r.z - tx0, 3);
+                const int y0 = max((int)r.y - ty0, 0), y1 = min((int)r.w - ty0, 3);
+                if (x0 <= x1 && y0 <= y1) {
+                    const unsigned rowbits = ((1u << (x1 + 1)) - 1u) & ~((1u << x0) - 1u);
+                    for (int y = y0; y <= y1; ++y) cover[q] |= rowbits << (4 * y);
+                }
+            }
+        }
+        // this wave's entries per tile (lane t keeps tile t's count)
+        unsigned mycnt = 0u;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            unsigned ct = 0u;
+#pragma unroll
+            for (int q = 0; q < kFillPerLane; ++q)
+                ct += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cover[q] >> t) & 1u));
+            if (lane == t) mycnt = ct;
+        }
+        if (lane < 16) wcnt[wave][lane] = mycnt;
+        __syncthreads();  // toff initialised, wave counts stored
+        // plus the tile's entries in the bucket's earlier chunks
         for (int i = threadIdx.x; i < c * 16; i += blockDim.x)
             if (const unsigned v = a.chunk_cnt[(size_t)(cb + (i >> 4)) * 16 + (i & 15)]) atomicAdd(&toff[i & 15], v);
-#pragma unroll
-        for (int q = 0; q < kFillPer; ++q) {
-            const int e = q * kFillThreads + (int)threadIdx.x;
-            const unsigned long long k = e < n ? list[e] : 0ull;
-            skey[e] = k;
-            srect[e] = e < n ? a.rect[(unsigned)(k & 0xffffffffull)] : make_ushort4(0xffff, 0xffff, 0, 0);
-        }
         __syncthreads();
-        const int tx = tx0 + (wave & 3), ty = ty0 + (wave >> 2);  // 16 waves: one tile each
-        if (tx >= a.cam.tx || ty >= a.cam.ty) continue;
-        const unsigned long long tk = (unsigned long long)(ty * a.cam.tx + tx) << 32;
-        const unsigned end = a.ranges[2 * (ty * a.cam.tx + tx) + 1];
-        unsigned out = toff[wave];
-        for (int b = 0; b < n; b += 64) {
-            const int e = b + lane;
-            bool hit = false;
-            unsigned long long key = 0;
-            if (e < n) {
-                key = skey[e];
-                const ushort4 r = srect[e];
-                hit = tx >= (int)r.x && tx <= (int)r.z && ty >= (int)r.y && ty <= (int)r.w;
+        // lane t: this wave's first place in tile t, and the tile's end
+        unsigned start = 0u, end = 0u;
+        if (lane < 16) {
+            const int x = tx0 + (lane & 3), y = ty0 + (lane >> 2);
+            start = toff[lane];
+            for (int v = 0; v < wave; ++v) start += wcnt[v][lane];
+            end = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x) + 1] : 0u;
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            unsigned out = (unsigned)__builtin_amdgcn_readlane((int)start, t);
+            const unsigned tend = (unsigned)__builtin_amdgcn_readlane((int)end, t);
+            const unsigned long long tk =
+                (unsigned long long)((ty0 + (t >> 2)) * a.cam.tx + tx0 + (t & 3)) << 32;
+#pragma unroll
+            for (int q = 0; q < kFillPerLane; ++q) {
+                const bool hit = (cover[q] >> t) & 1u;
+                const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+                const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
+                if (hit && pos < tend) {  // the sort kernel's counts use the same test: pos < tend always
+                    a.ids[pos] = (unsigned)(key[q] & 0xffffffffull);
+                    if (a.keys) a.keys[pos] = tk | (key[q] >> 32);
+                }
+                out += (unsigned)__builtin_popcountll(mask);
             }
-            const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
-            const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
-            if (hit && pos < end) {  // the sort kernel's counts use the same test: pos < end always
-                a.ids[pos] = (unsigned)(key & 0xffffffffull);
-                if (a.keys) a.keys[pos] = tk | (key >> 32);
-            }
-            out += (unsigned)__builtin_popcountll(mask);
         }
     }
 }
@@ -1003,7 +1020,7 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     if (n > 0 && max_pairs > 0) {
         hipLaunchKernelGGL(k_sb_emit, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sb_sort_radix, dim3(g.nsb), dim3(kRadixWaves * 64), 0, stream, a);
+        hipLaunchKernelGGL(k_sb_sort, dim3(g.nsb), dim3(kSortWaves * 64), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
