@@ -113,9 +113,14 @@ int ls2_project(const ls2_camera* cam, int32_t n, const float* means, const floa
  * In:  mean2d [n,2], radius [n], depth [n] from ls2_project.
  * Out: ids [P] (Gaussian id of each pair, grouped by tile, depth-ordered);
  *      keys [P] = (tile << 32) | float32 bits of depth (optional: may be NULL);
- *      tile_ranges [tiles,2] = [start, end) of each tile in ids; start is the
- *      number of pairs in all tiles before it (an empty tile has start = end).
- *      P is at most max_pairs.
+ *      tile_ranges [tiles,2] = [start, end) of each tile's list in ids (tiles
+ *      row-major).  The lists are stored superblock by superblock: the tile
+ *      grid is cut into superblocks of S x S tiles (S = 4, or the smallest
+ *      larger power of two that keeps the superblocks within 4096),
+ *      superblocks in row-major order and the tiles of one superblock
+ *      row-major inside it; start is the number of pairs of all tiles before
+ *      it in this order (an empty tile has start = end).  P is at most
+ *      max_pairs.  If P > max_pairs every range is [0, 0).
  * workspace: device scratch of at least ls2_bin_sort_workspace() bytes,
  *      256-byte aligned, owned by the caller, not shared between concurrent
  *      calls.

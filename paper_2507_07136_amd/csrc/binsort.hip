@@ -3,35 +3,32 @@
 // Eq. 3 composites a tile's Gaussians.
 //
 // The P (tile, Gaussian) pairs (about 33 per Gaussian at 1440x1080) are never
-// sorted or counted with atomics one by one.  The expensive part works on
+// sorted or counted with atomics one by one.  The work is done on
 // superblocks of S x S tiles (S = 4: 64 x 64 pixels), which a Gaussian touches
-// only 1-4 of:
-//   1. k_sb_count : per Gaussian, its tile rectangle (stored as 4 x u16) and
-//                   +1 for every superblock it touches, aggregated per
-//                   workgroup in an LDS histogram (one global atomic per
-//                   workgroup and superblock); also the exact pair count P;
-//   2. k_sb_scan  : one workgroup: superblock bucket offsets;
+// only 1-4 of, and the lists are laid out superblock by superblock
+// (superblocks row-major, tiles row-major inside each), so that every
+// superblock's list positions are known before its bucket is sorted:
+//   1. k_sb_count : per Gaussian, its tile rectangle (stored as 4 x u16), +1
+//                   for every superblock it touches and the number of its
+//                   tiles inside that superblock, aggregated per workgroup in
+//                   LDS histograms (one global atomic per workgroup and
+//                   superblock); also the exact pair count P;
+//   2. k_sb_scan  : one workgroup: superblock bucket offsets and list
+//                   offsets, the overflow decision, and the processing order;
 //   3. k_sb_emit  : per Gaussian, the 64-bit key (depth bits << 32 | id) into
 //                   each touched superblock's bucket (LDS histogram again, one
 //                   reserving atomic per workgroup and superblock, LDS cursors);
 //   4. k_sb_sort  : one workgroup per superblock sorts its bucket in LDS
 //                   (keys binned over the bucket's depth range, each short
-//                   bin sorted by insertion, long bins by a bitonic network)
-//                   and counts, for each of its S x S tiles, the entries
-//                   whose rectangle covers the tile (buckets beyond the LDS
-//                   capacity are first split into 256 bins over their depth
-//                   range, and runs of bins are sorted in LDS; only a single
-//                   over-full bin falls back to a bitonic network in global
-//                   memory in the same workgroup);
-//   5. k_tile_scan: one workgroup: tile ranges (row-major) and P;
-//   6. k_tile_fill: each tile's list is the ordered subsequence of its
-//                   superblock's sorted bucket whose rectangles cover the tile:
-//                   an order-preserving ballot compaction, so every tile list
-//                   comes out already in (depth, id) order.  With S = 4
-//                   (k_tile_fill_chunks) every 2048-entry chunk of a bucket is
-//                   filled on its own, its list offsets taken from per-chunk
-//                   tile counts that step 4 records, each wave emitting its
-//                   slice of the chunk into all 16 tiles.
+//                   bin sorted by insertion, long bins by a bitonic network;
+//                   buckets beyond the LDS capacity are first split into 256
+//                   bins over their depth range, and runs of bins are sorted
+//                   in LDS; only a single over-full bin falls back to a
+//                   bitonic network in global memory), then writes its tiles'
+//                   ranges and lists: each tile's list is the ordered
+//                   subsequence of the sorted bucket whose rectangles cover
+//                   the tile, an order-preserving ballot compaction, so every
+//                   list comes out already in (depth, id) order.
 #include "ls2_internal.h"
 
 namespace ls2 {
@@ -44,8 +41,7 @@ struct Meta {
     long long sb_total;     // total (superblock, Gaussian) entries
     long long sb_overflow;  // 1 if sb_total > max_pairs
     unsigned long long P_rect;  // sum of tile-rectangle areas (= P), from pass 1
-    long long nchunks;      // fill chunks over all buckets (S = 4)
-    long long pad[2];
+    long long pad[3];
 };
 
 constexpr size_t kAlign = 256;
@@ -68,34 +64,22 @@ inline Geo geo(const CamK& k) {
     return g;
 }
 
-// Sorted buckets are filled into tile lists in chunks of kFillChunk entries
-// (S = 4), each chunk with its own workgroup pass.
-constexpr int kFillChunk = 2048;
-
-// Fill chunks over all buckets, at most: every non-empty bucket rounds up once.
-inline size_t max_chunks(const Geo& g, int64_t max_pairs) {
-    return (size_t)g.nsb + (size_t)(max_pairs > 0 ? max_pairs : 0) / kFillChunk + 1;
-}
-
 struct Layout {
-    size_t meta, sb_count, tile_count, chunk_cnt, sb_start, sb_cursor, sb_order, sb_cbase, chunk_sb, rect, pool,
-        total;
+    size_t meta, sb_count, sb_pairs, sb_start, sb_pstart, sb_cursor, sb_order, rect, pool, total;
 };
 
-// meta, sb_count, tile_count and chunk_cnt come first: they are zeroed every call.
+// meta, sb_count and sb_pairs come first: they are zeroed every call.
 inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     const Geo g = geo(k);
     Layout l;
     size_t off = 0;
     l.meta = off; off = align_up(off + sizeof(Meta));
     l.sb_count = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
-    l.tile_count = off; off = align_up(off + sizeof(unsigned) * (size_t)k.tx * k.ty);
-    l.chunk_cnt = off; off = align_up(off + sizeof(unsigned) * 16 * (g.S == 4 ? max_chunks(g, max_pairs) : 1));
+    l.sb_pairs = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_start = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.sb_pstart = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_order = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
-    l.sb_cbase = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
-    l.chunk_sb = off; off = align_up(off + sizeof(unsigned) * (g.S == 4 ? max_chunks(g, max_pairs) : 1));
     l.rect = off; off = align_up(off + sizeof(ushort4) * (size_t)(n > 0 ? n : 1));
     l.pool = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
     l.total = off;
@@ -112,14 +96,12 @@ struct BinArgs {
     const int* radius;
     const float* depth;
     Meta* meta;
-    unsigned* sb_count;
-    unsigned* sb_start;
+    unsigned* sb_count;   // (superblock, Gaussian) entries of each superblock
+    unsigned* sb_pairs;   // (tile, Gaussian) pairs inside each superblock
+    unsigned* sb_start;   // bucket offset of each superblock in the pool
+    unsigned* sb_pstart;  // first list position of each superblock's tiles
     unsigned* sb_cursor;
     unsigned* sb_order;  // superblocks by decreasing bucket size (size classes)
-    unsigned* tile_count;
-    unsigned* chunk_cnt;  // S = 4: [chunk][16] entries covering each tile of the chunk's superblock
-    unsigned* sb_cbase;   // S = 4: first fill chunk of each superblock
-    unsigned* chunk_sb;   // S = 4: superblock of each fill chunk
     ushort4* rect;
     unsigned long long* pool;
     unsigned* ranges;
@@ -142,9 +124,9 @@ __global__ void k_bin_zero(unsigned* __restrict__ p, long long n) {
 // Superblock rectangle of Gaussian i; optionally stores its tile rectangle
 // (x0, y0, x1, y1), or an empty one (0xffff, 0xffff, 0, 0) if culled.
 __device__ __forceinline__ bool sb_rect_of(const BinArgs& a, int i, int& sx0, int& sy0, int& sx1, int& sy1,
-                                           int& area, bool store) {
+                                           int& x0, int& y0, int& x1, int& y1, bool store) {
     bool vis = false;
-    int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+    x0 = 0, y0 = 0, x1 = -1, y1 = -1;
     const int r = a.radius[i];
     if (r > 0) {
         const float2 m = reinterpret_cast<const float2*>(a.mean2d)[i];
@@ -154,7 +136,6 @@ __device__ __forceinline__ bool sb_rect_of(const BinArgs& a, int i, int& sx0, in
         a.rect[i] = vis ? make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1)
                         : make_ushort4(0xffff, 0xffff, 0, 0);
     if (!vis) return false;
-    area = (x1 - x0 + 1) * (y1 - y0 + 1);
     const int sh = __builtin_ctz((unsigned)a.S);
     sx0 = x0 >> sh; sy0 = y0 >> sh; sx1 = x1 >> sh; sy1 = y1 >> sh;
     return true;
@@ -165,25 +146,37 @@ constexpr int kBinPerThread = 2;  // Gaussians per thread in the histogram passe
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
+    __shared__ unsigned area[kMaxSB];
     __shared__ unsigned long long area_sum;
-    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = area[s] = 0u;
     if (threadIdx.x == 0) area_sum = 0ull;
     __syncthreads();
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
-    unsigned my_area = 0;
+    const int S = a.S;
+    unsigned long long my_area = 0;
     for (int q = 0; q < kBinPerThread; ++q) {
         const int i = base + q * kBinThreads + threadIdx.x;
-        int sx0, sy0, sx1, sy1, area;
-        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, area, true)) {
-            my_area += (unsigned)area;
-            for (int sy = sy0; sy <= sy1; ++sy)
-                for (int sx = sx0; sx <= sx1; ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
+        int sx0, sy0, sx1, sy1, x0, y0, x1, y1;
+        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, x0, y0, x1, y1, true)) {
+            my_area += (unsigned long long)(x1 - x0 + 1) * (unsigned long long)(y1 - y0 + 1);
+            for (int sy = sy0; sy <= sy1; ++sy) {
+                const int h = min(y1, sy * S + S - 1) - max(y0, sy * S) + 1;
+                for (int sx = sx0; sx <= sx1; ++sx) {
+                    const int w = min(x1, sx * S + S - 1) - max(x0, sx * S) + 1;
+                    atomicAdd(&hist[sy * a.sbx + sx], 1u);
+                    atomicAdd(&area[sy * a.sbx + sx], (unsigned)(w * h));  // the pairs inside the superblock
+                }
+            }
         }
     }
-    if (my_area) atomicAdd(&area_sum, (unsigned long long)my_area);
+    if (my_area) atomicAdd(&area_sum, my_area);
     __syncthreads();
-    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads)
-        if (hist[s]) atomicAdd(&a.sb_count[s], hist[s]);
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) {
+        if (hist[s]) {
+            atomicAdd(&a.sb_count[s], hist[s]);
+            atomicAdd(&a.sb_pairs[s], area[s]);  // exact whenever P fits the lists (P < 2^32)
+        }
+    }
     if (threadIdx.x == 0 && area_sum) atomicAdd(&a.meta->P_rect, area_sum);
 }
 
@@ -243,13 +236,19 @@ __device__ __forceinline__ int size_class(unsigned c) {
 __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
     __shared__ unsigned cls[64];
     const long long total = block_scan(a.sb_count, a.sb_start, 1, nullptr, a.nsb);
-    const bool over = total > a.max_pairs;
+    // P is exact in 64 bits; the per-superblock pair counts are exact whenever
+    // P fits the lists, which is the only case in which their offsets are used
+    const long long P = (long long)a.meta->P_rect;
+    const bool over = P > a.max_pairs;  // sb_total <= P: covers the pool too
+    block_scan(a.sb_pairs, a.sb_pstart, 1, nullptr, a.nsb);
     for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) a.sb_cursor[s] = a.sb_start[s];
     if (threadIdx.x == 0) {
         a.meta->sb_total = total;
-        a.meta->sb_overflow = over ? 1 : 0;
+        a.meta->sb_overflow = total > a.max_pairs ? 1 : 0;
+        a.meta->P = P;
+        a.meta->overflow = over ? 1 : 0;
     }
-    // processing order of the per-superblock kernels: largest buckets first
+    // processing order of the per-superblock kernel: largest buckets first
     // (a counting sort on the size class; order inside a class is arbitrary),
     // so the long sorts start in the first dispatch round
     if (threadIdx.x < 64) cls[threadIdx.x] = 0u;
@@ -267,31 +266,18 @@ __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
     __syncthreads();
     for (int s = threadIdx.x; s < a.nsb; s += blockDim.x)
         a.sb_order[atomicAdd(&cls[size_class(a.sb_count[s])], 1u)] = (unsigned)s;
-    if (a.S != 4 || over) return;
-    // fill chunks: kFillChunk entries of each bucket (in place: counts, then
-    // their exclusive prefix), and the superblock of every chunk
-    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x)
-        a.sb_cbase[s] = (a.sb_count[s] + kFillChunk - 1) / kFillChunk;
-    __syncthreads();
-    const long long nch = block_scan(a.sb_cbase, a.sb_cbase, 1, nullptr, a.nsb);
-    __syncthreads();
-    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) {
-        const unsigned c0 = a.sb_cbase[s], c1 = c0 + (a.sb_count[s] + kFillChunk - 1) / kFillChunk;
-        for (unsigned c = c0; c < c1; ++c) a.chunk_sb[c] = (unsigned)s;
-    }
-    if (threadIdx.x == 0) a.meta->nchunks = nch;
 }
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
-    if (a.meta->sb_overflow) return;
+    if (a.meta->overflow) return;  // the lists will not be filled
     for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
     __syncthreads();
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
     for (int q = 0; q < kBinPerThread; ++q) {
         const int i = base + q * kBinThreads + threadIdx.x;
-        int sx0, sy0, sx1, sy1, area;
-        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, area, false))
+        int sx0, sy0, sx1, sy1, x0, y0, x1, y1;
+        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, x0, y0, x1, y1, false))
             for (int sy = sy0; sy <= sy1; ++sy)
                 for (int sx = sx0; sx <= sx1; ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
     }
@@ -302,8 +288,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
     __syncthreads();
     for (int q = 0; q < kBinPerThread; ++q) {
         const int i = base + q * kBinThreads + threadIdx.x;
-        int sx0, sy0, sx1, sy1, area;
-        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, area, false)) {
+        int sx0, sy0, sx1, sy1, x0, y0, x1, y1;
+        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, x0, y0, x1, y1, false)) {
             const unsigned long long key = ((unsigned long long)__float_as_uint(a.depth[i]) << 32) | (unsigned)i;
             for (int sy = sy0; sy <= sy1; ++sy)
                 for (int sx = sx0; sx <= sx1; ++sx) {
@@ -354,91 +340,6 @@ __device__ void flip_bitonic(Ptr s, int cnt) {
     __syncthreads();
 }
 
-// Per-tile counts of one superblock's entries (tcnt: S*S LDS counters).
-// For 4x4-tile superblocks every entry contributes a 16-bit coverage mask and
-// each wave counts with 16 ballots per 64 entries; larger superblocks (only
-// for very large images) use LDS atomics.
-__device__ __forceinline__ void count_sb_tiles(const BinArgs& a, int sb, const unsigned long long* s, int cnt,
-                                               unsigned* tcnt) {
-    const int S = a.S;
-    const int sx = sb % a.sbx, sy = sb / a.sbx;
-    const int tx0 = sx * S, ty0 = sy * S;
-    for (int t = threadIdx.x; t < S * S; t += blockDim.x) tcnt[t] = 0u;
-    __syncthreads();
-    if (S == 4) {
-        const int cnt64 = (cnt + 63) & ~63;
-        constexpr int G = 4;  // rectangle gathers in flight per thread
-        // Counts per fill chunk: a wave visits the chunks in increasing order,
-        // so it sums one chunk's counts in registers and adds them (to the
-        // chunk's global counters and the tile totals) when the chunk changes.
-        unsigned ccnt[16];
-#pragma unroll
-        for (int b = 0; b < 16; ++b) ccnt[b] = 0u;
-        int cur = -1;
-        unsigned* const cbase = a.chunk_cnt + (size_t)a.sb_cbase[sb] * 16;
-        for (int e0 = threadIdx.x; e0 < cnt64; e0 += G * blockDim.x) {
-            ushort4 rr[G];
-#pragma unroll
-            for (int q = 0; q < G; ++q) {
-                const int e = e0 + q * blockDim.x;
-                rr[q] = e < cnt ? a.rect[(unsigned)(s[e] & 0xffffffffull)] : make_ushort4(0xffff, 0xffff, 0, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < G; ++q) {
-                if (e0 + q * blockDim.x >= cnt64) break;  // wave-uniform
-                const ushort4 r = rr[q];
-                unsigned cover = 0u;
-                const int x0 = max((int)r.x - tx0, 0), x1 = min((int)r.z - tx0, 3);
-                const int y0 = max((int)r.y - ty0, 0), y1 = min((int)r.w - ty0, 3);
-                if (x0 <= x1 && y0 <= y1) {
-                    const unsigned rowbits = ((1u << (x1 + 1)) - 1u) & ~((1u << x0) - 1u);
-                    for (int y = y0; y <= y1; ++y) cover |= rowbits << (4 * y);
-                }
-                // the wave's 64 entries lie in one fill chunk (64 | kFillChunk)
-                const int chunk = (e0 - (int)(threadIdx.x & 63) + q * (int)blockDim.x) / kFillChunk;
-                if (chunk != cur) {  // wave-uniform
-                    if (cur >= 0 && (threadIdx.x & 63) == 0) {
-#pragma unroll
-                        for (int b = 0; b < 16; ++b)
-                            if (ccnt[b]) {
-                                atomicAdd(cbase + (size_t)cur * 16 + b, ccnt[b]);
-                                atomicAdd(&tcnt[b], ccnt[b]);
-                            }
-                    }
-#pragma unroll
-                    for (int b = 0; b < 16; ++b) ccnt[b] = 0u;
-                    cur = chunk;
-                }
-#pragma unroll
-                for (int b = 0; b < 16; ++b)
-                    ccnt[b] += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cover >> b) & 1u));
-            }
-        }
-        if (cur >= 0 && (threadIdx.x & 63) == 0) {
-#pragma unroll
-            for (int b = 0; b < 16; ++b)
-                if (ccnt[b]) {
-                    atomicAdd(cbase + (size_t)cur * 16 + b, ccnt[b]);
-                    atomicAdd(&tcnt[b], ccnt[b]);
-                }
-        }
-    } else {
-        for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-            const unsigned id = (unsigned)(s[e] & 0xffffffffull);
-            const ushort4 r = a.rect[id];
-            const int x0 = max((int)r.x, tx0), x1 = min((int)r.z, tx0 + S - 1);
-            const int y0 = max((int)r.y, ty0), y1 = min((int)r.w, ty0 + S - 1);
-            for (int y = y0; y <= y1; ++y)
-                for (int x = x0; x <= x1; ++x) atomicAdd(&tcnt[(y - ty0) * S + (x - tx0)], 1u);
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
-        const int x = tx0 + t % S, y = ty0 + t / S;
-        if (x < a.cam.tx && y < a.cam.ty) a.tile_count[y * a.cam.tx + x] = tcnt[t];
-    }
-}
-
 constexpr int kMaxS2 = 32 * 32;  // tile counters per superblock (S <= 32)
 
 // LDS sort of one bucket (or one chunk of a large bucket).  A key is
@@ -450,15 +351,16 @@ constexpr int kSortWaves = 16;
 struct SortSmem {
     unsigned long long xbuf[kSortCap];
     unsigned ctr[kSortWaves][256];
-    unsigned tcnt[kMaxS2];
+    unsigned tcnt[kMaxS2];          // list fill: tile counts, then tile list starts
     unsigned bits[4];           // large buckets: OR and AND of the keys
     unsigned hmin, hmax;        // large buckets: range of the keys' depth halves
     unsigned chunk_start[257];  // large buckets: key offset of each chunk
     unsigned nchunks;
     unsigned wred[kSortWaves][4];  // per-wave key ranges
     unsigned wscan[kSortWaves];    // per-wave bin totals
-    unsigned big[kMaxS2];           // long bins: start | count << 15
+    unsigned big[kMaxS2];           // long bins: start | count << 15; then tile list ends
     unsigned nbig;
+    unsigned wcnt[kSortWaves][16];  // list fill: entries of each wave's slice per tile of a block
 };
 
 // Sort of one bucket (or one chunk of a large bucket) in LDS: cnt <=
@@ -611,16 +513,6 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) dst[p] = sm.xbuf[p];
 }
 
-// One workgroup per superblock (largest buckets first): buckets of at most
-// kSortCap keys are sorted in LDS (sort_lds), written back and their tiles
-// counted.
-//
-// Larger buckets are first split into 256 bins over the range of their depth
-// bits (a most-significant-digit pass through a scratch copy in the free part
-// of the pool); runs of consecutive digit bins of at most kSortCap keys are
-// then sorted in LDS, in key order, back into the bucket.  Only a bucket with
-// a single digit bin beyond kSortCap, or a pool without room for the scratch
-// copy, uses the bitonic network in global memory.
 // A bucket beyond kSortCap keys: split into the scratch copy by a digit over
 // its depth range and return the number of LDS-sized chunks (their key offsets
 // in sm.chunk_start); 0 if it was sorted here instead, with the global bitonic
@@ -721,14 +613,205 @@ __device__ int split_bucket(const BinArgs& a, SortSmem& sm, unsigned long long* 
     return nch;
 }
 
+// Tile lists of one superblock from its sorted bucket s[0, cnt) (in LDS or in
+// global memory).  The superblock's pairs occupy [sb_pstart, sb_pstart +
+// sb_pairs) of the lists, its tiles in row-major order inside it.  The
+// superblock is taken as (S/4)^2 blocks of 4 x 4 tiles, and an entry's
+// coverage of a block is a 16-bit mask (bit 4 y + x).  Wave w owns the slice
+// [w len, (w + 1) len) of the bucket (len a multiple of 64).  In a block,
+// lane t of every wave counts the slice's entries that cover tile t (one
+// ballot per tile and 64 entries); the waves' counts give each wave its first
+// place in every tile; a second pass emits the entries in bucket order (per
+// tile one ballot, the lane's place among the covering lanes, one store), so
+// every tile list is the ordered subsequence of the sorted bucket.
+constexpr int kFillGroups = 4;  // 64-entry groups loaded at once
 
+// Emits the entries [e0, e1) of a sorted bucket into the 16 tiles of one
+// 4 x 4-tile block at (ox, oy): lane t of cur holds tile t's next place, lane
+// t of end its list end.  Per tile and 64 entries: one ballot, the lane's
+// rank among the covering lanes (mbcnt), one store.
+template <bool KEYS, typename Cover>
+__device__ __forceinline__ void emit_slice(const unsigned long long* s, const ushort4* __restrict__ rect,
+                                           __attribute__((address_space(1))) unsigned* ids,
+                                           unsigned long long* __restrict__ keys, int e0, int e1, unsigned& cur,
+                                           unsigned end, int tiles_x, int ox, int oy, Cover cover_rect, int bx,
+                                           int by) {
+    const int lane = threadIdx.x & 63;
+    for (int e = e0; e < e1; e += 64 * kFillGroups) {
+        unsigned long long kk[kFillGroups];
+        ushort4 r[kFillGroups];
+        unsigned cv[kFillGroups];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) kk[q] = s[min(e + 64 * q + lane, e1 - 1)];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) r[q] = rect[(unsigned)(kk[q] & 0xffffffffull)];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) cv[q] = e + 64 * q + lane < e1 ? cover_rect(r[q], bx, by) : 0u;
+        // one tile at a time: its cursor and end are the only per-tile scalars live
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            unsigned out = (unsigned)__builtin_amdgcn_readlane((int)cur, t);
+            const unsigned tend = (unsigned)__builtin_amdgcn_readlane((int)end, t);
+            const unsigned long long tk = (unsigned long long)((oy + (t >> 2)) * tiles_x + ox + (t & 3)) << 32;
+#pragma unroll
+            for (int q = 0; q < kFillGroups; ++q) {
+                const unsigned long long mask = __builtin_amdgcn_ballot_w64((cv[q] >> t) & 1u);
+                const unsigned pos = out + __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                if (((mask >> lane) & 1ull) && pos < tend) {  // the counts use the same test: pos < tend always
+                    ids[pos] = (unsigned)(kk[q] & 0xffffffffull);
+                    if (KEYS) keys[pos] = tk | (kk[q] >> 32);
+                }
+                out += (unsigned)__builtin_popcountll(mask);
+            }
+            if (lane == t) cur = out;
+        }
+    }
+}
 
+__device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, int sb,
+                                              const unsigned long long* s, int cnt) {
+    const int S = a.S, nsub = S >> 2;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int tx0 = (sb % a.sbx) * S, ty0 = (sb / a.sbx) * S;
+    const int len = (cnt + 64 * kSortWaves - 1) / (64 * kSortWaves) * 64;
+    // the list base lives in vector registers (global address space): the
+    // scalar file is full here, and a scalar copy would be reloaded from the
+    // kernel arguments before every store
+    __attribute__((address_space(1))) unsigned* ids = (__attribute__((address_space(1))) unsigned*)a.ids;
+    asm volatile("" : "+v"(ids));
+    unsigned long long* __restrict__ const keys = a.keys;
+    const ushort4* __restrict__ const rect = a.rect;
+    const int e0 = min(cnt, w * len), e1 = min(cnt, e0 + len);
+    // coverage of the block at tile offset (bx, by) of the superblock
+    // (branch-free: the covered columns' bits times one bit 4 y per covered
+    // row y; bounds clamped to [0, 4] and [-1, 3], so an empty range gives 0)
+    auto cover_rect = [&](const ushort4 r, int bx, int by) -> unsigned {
+        const int ox = tx0 + bx, oy = ty0 + by;
+        const int x0 = min(max((int)r.x - ox, 0), 4), x1 = max(min((int)r.z - ox, 3), -1);
+        const int y0 = min(max((int)r.y - oy, 0), 4), y1 = max(min((int)r.w - oy, 3), -1);
+        const unsigned cols = ((1u << (x1 + 1)) - 1u) & ~((1u << x0) - 1u);
+        const unsigned rows = 0x1111u & ((1u << (4 * (y1 + 1))) - 1u) & ~((1u << (4 * y0)) - 1u);
+        return cols * rows;
+    };
+    // entries of this wave's slice covering each tile of a block (lane t: tile t)
+    auto count_block = [&](int bx, int by) -> unsigned {
+        unsigned mine = 0u;
+        for (int e = e0; e < e1; e += 64 * kFillGroups) {
+            // every load issued at once (positions past the slice read its last entry)
+            unsigned long long k[kFillGroups];
+            ushort4 r[kFillGroups];
+#pragma unroll
+            for (int q = 0; q < kFillGroups; ++q) k[q] = s[min(e + 64 * q + lane, e1 - 1)];
+#pragma unroll
+            for (int q = 0; q < kFillGroups; ++q) r[q] = rect[(unsigned)(k[q] & 0xffffffffull)];
+#pragma unroll
+            for (int q = 0; q < kFillGroups; ++q) {
+                const unsigned cv = e + 64 * q + lane < e1 ? cover_rect(r[q], bx, by) : 0u;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const unsigned c = (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cv >> t) & 1u));
+                    if (lane == t) mine += c;
+                }
+            }
+        }
+        return mine;
+    };
+    // 1. tile totals, row-major in the superblock
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) sm.tcnt[t] = 0u;
+    __syncthreads();
+    for (int k = 0; k < nsub * nsub; ++k) {
+        const int bx = (k % nsub) * 4, by = (k / nsub) * 4;
+        const unsigned c = count_block(bx, by);
+        if (nsub == 1 && lane < 16) sm.wcnt[w][lane] = c;
+        if (lane < 16 && c) atomicAdd(&sm.tcnt[(by + (lane >> 2)) * S + bx + (lane & 3)], c);
+    }
+    __syncthreads();
+    // 2. list start and end of every tile; the tile ranges
+    if (w == 0) {
+        const int nt = S * S, per = (nt + 63) / 64;  // at most 16
+        unsigned loc = 0u;
+        for (int q = 0; q < per; ++q)
+            if (lane * per + q < nt) loc += sm.tcnt[lane * per + q];
+        unsigned incl = loc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const unsigned y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        unsigned run = a.sb_pstart[sb] + incl - loc;
+        for (int q = 0; q < per; ++q) {
+            const int t = lane * per + q;
+            if (t >= nt) break;
+            const unsigned c = sm.tcnt[t];
+            sm.tcnt[t] = run;
+            sm.big[t] = run + c;
+            const int x = tx0 + t % S, y = ty0 + t / S;
+            if (x < a.cam.tx && y < a.cam.ty) {
+                a.ranges[2 * (y * a.cam.tx + x)] = run;
+                a.ranges[2 * (y * a.cam.tx + x) + 1] = run + c;
+            }
+            run += c;
+        }
+    }
+    __syncthreads();
+    // 3. emit, block by block
+    for (int k = 0; k < nsub * nsub; ++k) {
+        const int bx = (k % nsub) * 4, by = (k / nsub) * 4;
+        if (nsub > 1) {
+            const unsigned c = count_block(bx, by);
+            if (lane < 16) sm.wcnt[w][lane] = c;
+            __syncthreads();
+        }
+        // lane t: this wave's next place in tile t of the block, and the tile's end
+        unsigned cur = 0u, end = 0u;
+        if (lane < 16) {
+            const int t = (by + (lane >> 2)) * S + bx + (lane & 3);
+            cur = sm.tcnt[t];
+            for (int v = 0; v < w; ++v) cur += sm.wcnt[v][lane];
+            end = min(sm.big[t], (unsigned)a.max_pairs);  // P <= max_pairs here; the clamp only guards
+        }
+        if (keys)
+            emit_slice<true>(s, rect, ids, keys, e0, e1, cur, end, a.cam.tx, tx0 + bx, ty0 + by, cover_rect, bx, by);
+        else
+            emit_slice<false>(s, rect, ids, keys, e0, e1, cur, end, a.cam.tx, tx0 + bx, ty0 + by, cover_rect, bx, by);
+        if (nsub > 1) __syncthreads();  // sm.wcnt is rewritten for the next block
+    }
+}
+
+// Empty tile ranges for every tile of superblock sb: [first, first).
+__device__ __forceinline__ void empty_sb_ranges(const BinArgs& a, int sb, unsigned first) {
+    const int S = a.S, tx0 = (sb % a.sbx) * S, ty0 = (sb / a.sbx) * S;
+    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
+        const int x = tx0 + t % S, y = ty0 + t / S;
+        if (x < a.cam.tx && y < a.cam.ty) a.ranges[2 * (y * a.cam.tx + x)] = a.ranges[2 * (y * a.cam.tx + x) + 1] = first;
+    }
+}
+
+// One workgroup per superblock (largest buckets first): the bucket is sorted
+// and the superblock's tile lists and ranges are written from it.  Buckets of
+// at most kSortCap keys are sorted in LDS (sort_lds).  Larger buckets are
+// first split into 256 bins over the range of their depth bits (a
+// most-significant-digit pass through a scratch copy in the free part of the
+// pool); runs of consecutive digit bins of at most kSortCap keys are then
+// sorted in LDS, in key order, back into the bucket.  Only a bucket with a
+// single digit bin beyond kSortCap, or a pool without room for the scratch
+// copy, uses the bitonic network in global memory.  If the pairs exceed the
+// lists every range is left empty.
 __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
     __shared__ SortSmem sm;
-    if ((int)blockIdx.x >= a.nsb || a.meta->sb_overflow) return;
+    if ((int)blockIdx.x >= a.nsb) return;
     const int sb = (int)a.sb_order[blockIdx.x];
+    if (a.meta->overflow) {
+        empty_sb_ranges(a, sb, 0u);
+        return;
+    }
     const int cnt = (int)a.sb_count[sb];
-    if (cnt == 0) return;  // tile counts are pre-zeroed
+    if (cnt == 0) {
+        empty_sb_ranges(a, sb, a.sb_pstart[sb]);
+        return;
+    }
     unsigned long long* g = a.pool + a.sb_start[sb];
     // units sorted in LDS: the whole bucket, or the chunks of a split bucket
     const unsigned long long* src = g;
@@ -743,213 +826,8 @@ __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
         const int b0 = in_lds ? 0 : (int)sm.chunk_start[u], b1 = in_lds ? cnt : (int)sm.chunk_start[u + 1];
         if (b1 > b0) sort_lds(sm, src + b0, g + b0, b1 - b0);
     }
-    if (!in_lds) __threadfence_block();  // the global writes, before count_sb_tiles reads g
-    count_sb_tiles(a, sb, in_lds ? sm.xbuf : g, cnt, sm.tcnt);  // starts with a workgroup barrier
-}
-
-__global__ __launch_bounds__(1024) void k_tile_scan(BinArgs a) {
-    const int ntiles = a.cam.tx * a.cam.ty;
-    if (a.meta->sb_overflow) {
-        // the superblock buckets overflowed, hence P > max_pairs too: clear
-        // every range; P itself is known from the rectangle areas
-        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) a.ranges[2 * t] = a.ranges[2 * t + 1] = 0u;
-        if (threadIdx.x == 0) {
-            a.meta->P = (long long)a.meta->P_rect;
-            a.meta->overflow = 1;
-        }
-        return;
-    }
-    const long long total = block_scan(a.tile_count, a.ranges, 2, a.ranges + 1, ntiles);
-    const bool over = total > a.max_pairs;
-    __syncthreads();
-    if (over)
-        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) a.ranges[2 * t] = a.ranges[2 * t + 1] = 0u;
-    if (threadIdx.x == 0) {
-        a.meta->P = total;
-        a.meta->overflow = over ? 1 : 0;
-    }
-}
-
-// One workgroup per superblock (largest buckets first), one wave per tile
-// (S = 4: 16 waves; larger superblocks: each wave handles several tiles).
-// The sorted bucket is staged through LDS in chunks of 2048 entries (key and
-// tile rectangle); the next chunk's keys and rectangles are loaded into
-// registers while the waves compact the current one.  Every wave keeps, in
-// order, the entries whose rectangle covers its tile: an order-preserving
-// ballot compaction, so each tile's list comes out in (depth, id) order.
-constexpr int kFillThreads = 1024;
-constexpr int kFillPer = kFillChunk / kFillThreads;
-
-__global__ __launch_bounds__(kFillThreads) void k_tile_fill(BinArgs a) {
-    __shared__ unsigned long long skey[kFillChunk];
-    __shared__ ushort4 srect[kFillChunk];
-    __shared__ unsigned toff[kMaxS2];
-    if ((int)blockIdx.x >= a.nsb || a.meta->overflow) return;
-    const int sb = (int)a.sb_order[blockIdx.x];
-    const int S = a.S;
-    const int tx0 = (sb % a.sbx) * S, ty0 = (sb / a.sbx) * S;
-    const unsigned long long* list = a.pool + a.sb_start[sb];
-    const int cnt = (int)a.sb_count[sb];
-    for (int t = threadIdx.x; t < S * S; t += blockDim.x) {
-        const int x = tx0 + t % S, y = ty0 + t / S;
-        toff[t] = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x)] : 0u;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    unsigned long long pk[kFillPer];
-    ushort4 pr[kFillPer];
-    auto fetch = [&](int base) {
-#pragma unroll
-        for (int q = 0; q < kFillPer; ++q) {
-            const int e = base + q * kFillThreads + (int)threadIdx.x;
-            pk[q] = e < cnt ? list[e] : 0ull;
-        }
-#pragma unroll
-        for (int q = 0; q < kFillPer; ++q) {
-            const int e = base + q * kFillThreads + (int)threadIdx.x;
-            pr[q] = e < cnt ? a.rect[(unsigned)(pk[q] & 0xffffffffull)] : make_ushort4(0xffff, 0xffff, 0, 0);
-        }
-    };
-    fetch(0);
-    for (int base = 0; base < cnt; base += kFillChunk) {
-        const int n = min(kFillChunk, cnt - base);
-        __syncthreads();  // previous chunk consumed (and toff initialised)
-#pragma unroll
-        for (int q = 0; q < kFillPer; ++q) {
-            const int e = q * kFillThreads + (int)threadIdx.x;
-            skey[e] = pk[q];
-            srect[e] = pr[q];
-        }
-        __syncthreads();
-        if (base + kFillChunk < cnt) fetch(base + kFillChunk);
-        for (int t = wave; t < S * S; t += nwaves) {
-            const int tx = tx0 + t % S, ty = ty0 + t / S;
-            if (tx >= a.cam.tx || ty >= a.cam.ty) continue;
-            const unsigned long long tk = (unsigned long long)(ty * a.cam.tx + tx) << 32;
-            const unsigned end = a.ranges[2 * (ty * a.cam.tx + tx) + 1];
-            unsigned out = toff[t];
-            for (int b = 0; b < n; b += 64) {
-                const int e = b + lane;
-                bool hit = false;
-                unsigned long long key = 0;
-                if (e < n) {
-                    key = skey[e];
-                    const ushort4 r = srect[e];
-                    hit = tx >= (int)r.x && tx <= (int)r.z && ty >= (int)r.y && ty <= (int)r.w;
-                }
-                const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
-                const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
-                if (hit && pos < end) {  // the sort kernel's counts use the same test: pos < end always
-                    a.ids[pos] = (unsigned)(key & 0xffffffffull);
-                    if (a.keys) a.keys[pos] = tk | (key >> 32);
-                }
-                out += (unsigned)__builtin_popcountll(mask);
-            }
-            if (lane == 0) toff[t] = out;  // only this wave touches tile t
-        }
-    }
-}
-
-// S = 4: one pass per fill chunk instead of one sequential walk per bucket,
-// so a large bucket's chunks are filled by several workgroups at once.  A
-// chunk's first list position in each tile is the tile's start plus the
-// entries of that tile in the bucket's earlier chunks (counted by the sort
-// kernel).  Inside the chunk, wave w takes the 128 entries [128 w, 128 w +
-// 128), two per lane, and emits each into every tile of the superblock its
-// rectangle covers: per tile one ballot, the lane's place among the covering
-// lanes, and a store.  The waves' per-tile counts, exchanged through LDS,
-// give every wave its starting place in each tile, so each tile's list keeps
-// the bucket's (depth, id) order.  A fixed grid strides over the chunks
-// (their number is known on the device only).
-constexpr int kFillWaves = kFillThreads / 64;
-constexpr int kFillPerLane = kFillChunk / kFillThreads;  // entries per lane
-static_assert(kFillWaves == 16 && kFillPerLane == 2, "one 128-entry slice per wave");
-
-__global__ __launch_bounds__(kFillThreads) void k_tile_fill_chunks(BinArgs a) {
-    __shared__ unsigned toff[16];
-    __shared__ unsigned wcnt[kFillWaves][16];
-    if (a.meta->overflow) return;
-    const long long nch = a.meta->nchunks;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-        const int sb = (int)a.chunk_sb[ch];
-        const unsigned cb = a.sb_cbase[sb];
-        const int c = (int)(ch - cb);
-        const int base = c * kFillChunk;
-        const int n = min(kFillChunk, (int)a.sb_count[sb] - base);
-        const int tx0 = (sb % a.sbx) * 4, ty0 = (sb / a.sbx) * 4;
-        const unsigned long long* list = a.pool + a.sb_start[sb] + base;
-        unsigned long long key[kFillPerLane];
-#pragma unroll
-        for (int q = 0; q < kFillPerLane; ++q) {
-            const int e = wave * 64 * kFillPerLane + q * 64 + lane;
-            key[q] = e < n ? list[e] : 0ull;
-        }
-        __syncthreads();  // the previous chunk's LDS reads are done
-        if (threadIdx.x < 16) {
-            const int t = threadIdx.x, x = tx0 + (t & 3), y = ty0 + (t >> 2);
-            toff[t] = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x)] : 0u;
-        }
-        // coverage of the superblock's 16 tiles (bit 4 y + x)
-        unsigned cover[kFillPerLane];
-#pragma unroll
-        for (int q = 0; q < kFillPerLane; ++q) {
-            const int e = wave * 64 * kFillPerLane + q * 64 + lane;
-            cover[q] = 0u;
-            if (e < n) {
-                const ushort4 r = a.rect[(unsigned)(key[q] & 0xffffffffull)];
-                const int x0 = max((int)r.x - tx0, 0), x1 = min((int)r.z - tx0, 3);
-                const int y0 = max((int)r.y - ty0, 0), y1 = min((int)r.w - ty0, 3);
-                if (x0 <= x1 && y0 <= y1) {
-                    const unsigned rowbits = ((1u << (x1 + 1)) - 1u) & ~((1u << x0) - 1u);
-                    for (int y = y0; y <= y1; ++y) cover[q] |= rowbits << (4 * y);
-                }
-            }
-        }
-        // this wave's entries per tile (lane t keeps tile t's count)
-        unsigned mycnt = 0u;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            unsigned ct = 0u;
-#pragma unroll
-            for (int q = 0; q < kFillPerLane; ++q)
-                ct += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cover[q] >> t) & 1u));
-            if (lane == t) mycnt = ct;
-        }
-        if (lane < 16) wcnt[wave][lane] = mycnt;
-        __syncthreads();  // toff initialised, wave counts stored
-        // plus the tile's entries in the bucket's earlier chunks
-        for (int i = threadIdx.x; i < c * 16; i += blockDim.x)
-            if (const unsigned v = a.chunk_cnt[(size_t)(cb + (i >> 4)) * 16 + (i & 15)]) atomicAdd(&toff[i & 15], v);
-        __syncthreads();
-        // lane t: this wave's first place in tile t, and the tile's end
-        unsigned start = 0u, end = 0u;
-        if (lane < 16) {
-            const int x = tx0 + (lane & 3), y = ty0 + (lane >> 2);
-            start = toff[lane];
-            for (int v = 0; v < wave; ++v) start += wcnt[v][lane];
-            end = (x < a.cam.tx && y < a.cam.ty) ? a.ranges[2 * (y * a.cam.tx + x) + 1] : 0u;
-        }
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            unsigned out = (unsigned)__builtin_amdgcn_readlane((int)start, t);
-            const unsigned tend = (unsigned)__builtin_amdgcn_readlane((int)end, t);
-            const unsigned long long tk =
-                (unsigned long long)((ty0 + (t >> 2)) * a.cam.tx + tx0 + (t & 3)) << 32;
-#pragma unroll
-            for (int q = 0; q < kFillPerLane; ++q) {
-                const bool hit = (cover[q] >> t) & 1u;
-                const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
-                const unsigned pos = out + (unsigned)__builtin_popcountll(mask & lt);
-                if (hit && pos < tend) {  // the sort kernel's counts use the same test: pos < tend always
-                    a.ids[pos] = (unsigned)(key[q] & 0xffffffffull);
-                    if (a.keys) a.keys[pos] = tk | (key[q] >> 32);
-                }
-                out += (unsigned)__builtin_popcountll(mask);
-            }
-        }
-    }
+    if (!in_lds) __threadfence_block();  // the global writes, before the fill reads g
+    fill_sb_lists(a, sm, sb, in_lds ? sm.xbuf : g, cnt);  // starts with a workgroup barrier
 }
 
 }  // namespace ls2
@@ -989,21 +867,17 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.depth = depth;
     a.meta = reinterpret_cast<Meta*>(ws + lay.meta);
     a.sb_count = reinterpret_cast<unsigned*>(ws + lay.sb_count);
+    a.sb_pairs = reinterpret_cast<unsigned*>(ws + lay.sb_pairs);
     a.sb_start = reinterpret_cast<unsigned*>(ws + lay.sb_start);
+    a.sb_pstart = reinterpret_cast<unsigned*>(ws + lay.sb_pstart);
     a.sb_cursor = reinterpret_cast<unsigned*>(ws + lay.sb_cursor);
     a.sb_order = reinterpret_cast<unsigned*>(ws + lay.sb_order);
-    a.tile_count = reinterpret_cast<unsigned*>(ws + lay.tile_count);
-    a.chunk_cnt = reinterpret_cast<unsigned*>(ws + lay.chunk_cnt);
-    a.sb_cbase = reinterpret_cast<unsigned*>(ws + lay.sb_cbase);
-    a.chunk_sb = reinterpret_cast<unsigned*>(ws + lay.chunk_sb);
     a.rect = reinterpret_cast<ushort4*>(ws + lay.rect);
     a.pool = reinterpret_cast<unsigned long long*>(ws + lay.pool);
     a.ranges = tile_ranges;
     a.ids = ids;
     a.keys = reinterpret_cast<unsigned long long*>(keys);
-    // zero meta, superblock counts, tile counts and chunk counts (contiguous;
-    // tile counts of superblocks with no entries are never written by the
-    // sort kernels)
+    // zero meta and the superblock entry and pair counts (contiguous)
     const long long zw = (long long)((lay.sb_start - lay.meta) / sizeof(unsigned));
     const long long zb = (zw + 255) / 256;
     hipLaunchKernelGGL(k_bin_zero, dim3((unsigned)(zb < 1024 ? zb : 1024)), dim3(256), 0, stream,
@@ -1020,23 +894,10 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     if (n > 0 && max_pairs > 0) {
         hipLaunchKernelGGL(k_sb_emit, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sb_sort, dim3(g.nsb), dim3(kSortWaves * 64), 0, stream, a);
-        LS2_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, stream, a);
+    // every superblock writes its tiles' ranges (empty ones included)
+    hipLaunchKernelGGL(k_sb_sort, dim3(g.nsb), dim3(kSortWaves * 64), 0, stream, a);
     LS2_LAUNCH_CHECK();
-    if (n > 0 && max_pairs > 0) {
-        if (g.S == 4) {
-            int dev = 0, ncu = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-                ncu = 256;
-            hipLaunchKernelGGL(k_tile_fill_chunks, dim3((unsigned)(2 * ncu)), dim3(kFillThreads), 0, stream, a);
-        } else {
-            hipLaunchKernelGGL(k_tile_fill, dim3(g.nsb), dim3(kFillThreads), 0, stream, a);
-        }
-        LS2_LAUNCH_CHECK();
-    }
     if (num_pairs) {
         Meta h;
         if (hipMemcpyAsync(&h, a.meta, sizeof(Meta), hipMemcpyDeviceToHost, stream) != hipSuccess)

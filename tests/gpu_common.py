@@ -43,6 +43,47 @@ def oracle_lists_from_gpu(orc, cam, g):
     return orc.tile_lists(cam, g["mean2d"], g["radius"], g["depth"])
 
 
+def superblock_list_ranges(ranges, tiles_x, tiles_y):
+    """The library's placement of the tile lists (include/ls2.h, ls2_bin_sort):
+    superblocks of S x S tiles (S = 4, doubled while there are more than 4096
+    superblocks) in row-major order, tiles row-major inside each.  Given the
+    per-tile list lengths of `ranges` (any placement), returns the [start, end)
+    ranges of that layout."""
+    ranges = np.asarray(ranges, np.int64)
+    lens = ranges[:, 1] - ranges[:, 0]
+    S = 4
+    while ((tiles_x + S - 1) // S) * ((tiles_y + S - 1) // S) > 4096:
+        S *= 2
+    t = np.arange(tiles_x * tiles_y)
+    x, y = t % tiles_x, t // tiles_x
+    sb = (y // S) * ((tiles_x + S - 1) // S) + x // S
+    order = np.lexsort(((y % S) * S + x % S, sb))
+    start = np.empty_like(lens)
+    start[order] = np.concatenate([[0], np.cumsum(lens[order])[:-1]])
+    return np.stack([start, start + lens], axis=1)
+
+
+def compare_tile_lists(g, keys, ids, ranges, tiles_x, tiles_y):
+    """The GPU lists g (P, ranges, ids, optional keys) against the oracle's
+    (keys, ids, ranges in row-major tile order): the same pair count, the
+    documented placement of every tile's list, and every list bit for bit.
+    Returns None if equal, else what differs."""
+    if g["P"] != len(ids):
+        return "P %d, oracle %d" % (g["P"], len(ids))
+    exp = superblock_list_ranges(ranges, tiles_x, tiles_y)
+    if not np.array_equal(np.asarray(g["ranges"], np.int64), exp):
+        return "tile ranges differ at %d tiles" % int((np.asarray(g["ranges"], np.int64) != exp).any(axis=1).sum())
+    ranges = np.asarray(ranges, np.int64)
+    lens = ranges[:, 1] - ranges[:, 0]
+    # oracle position p of tile t sits at exp[t, 0] + (p - ranges[t, 0]) in the GPU lists
+    gpos = np.arange(len(ids), dtype=np.int64) + np.repeat(exp[:, 0] - ranges[:, 0], lens)
+    if not np.array_equal(g["ids"][gpos], ids):
+        return "ids differ at %d positions" % int((g["ids"][gpos] != ids).sum())
+    if g.get("keys") is not None and not np.array_equal(g["keys"][gpos], keys):
+        return "keys differ at %d positions" % int((g["keys"][gpos] != keys).sum())
+    return None
+
+
 def oracle_composite_from_gpu(orc, cam, scene, g):
     """Stage-isolated splat: the oracle composites the GPU's lists and float32
     projected Gaussians in float64."""

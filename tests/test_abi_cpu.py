@@ -290,3 +290,27 @@ def test_library_built_from_these_sources():
     import paper_2507_07136_amd._lib as lib
     from paper_2507_07136_amd._srchash import source_hash
     assert lib._lib.ls2_source_hash().decode() == source_hash()
+
+
+def test_list_layout_reference():
+    """The test helper that places oracle tile lists in the library's layout
+    (superblocks of S x S tiles row-major, tiles row-major inside each),
+    against a direct walk over superblocks and tiles."""
+    import numpy as np
+    from gpu_common import superblock_list_ranges
+    rng = np.random.default_rng(5)
+    for tx, ty, S in ((9, 7, 4), (90, 68, 4), (260, 260, 8)):
+        lens = rng.integers(0, 5, tx * ty)
+        lens[rng.random(tx * ty) < 0.3] = 0
+        row_major = np.concatenate([[0], np.cumsum(lens)])
+        ranges = np.stack([row_major[:-1], row_major[1:]], axis=1)
+        want = np.zeros((tx * ty, 2), np.int64)
+        pos = 0
+        for sy in range(0, ty, S):
+            for sx in range(0, tx, S):
+                for y in range(sy, min(sy + S, ty)):
+                    for x in range(sx, min(sx + S, tx)):
+                        t = y * tx + x
+                        want[t] = (pos, pos + lens[t])
+                        pos += lens[t]
+        assert np.array_equal(superblock_list_ranges(ranges, tx, ty), want)

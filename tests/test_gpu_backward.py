@@ -29,7 +29,7 @@ import torch
 
 import gen
 from gpu_common import grad_close as _grad_close
-from gpu_common import gpu_available, oracle_composite_from_gpu, run_forward, small_scene
+from gpu_common import compare_tile_lists, gpu_available, oracle_composite_from_gpu, run_forward, small_scene
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -412,8 +412,10 @@ def test_train_step_fd_config3(orc):
         dF *= M / float(M - risky.sum())
     grads = tr.backward(t, dF)
     torch.cuda.synchronize()
-    same_lists = (tr.num_pairs == len(fw["ids"]) and
-                  np.array_equal(tr.ids[:tr.num_pairs].cpu().numpy().view(np.uint32), fw["ids"]))
+    same_lists = compare_tile_lists(
+        dict(P=tr.num_pairs, ranges=tr.tile_ranges.cpu().numpy().view(np.uint32),
+             ids=tr.ids[:tr.num_pairs].cpu().numpy().view(np.uint32)),
+        None, fw["ids"], fw["ranges"], cam.tiles_x, cam.tiles_y) is None
     print("fd scene: loss %.6f (oracle %.6f), %d risky pixels, GPU lists equal the oracle's: %s"
           % (loss.item(), fw["loss"], int(risky.sum()), same_lists))
     if not risky.any():

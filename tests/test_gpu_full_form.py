@@ -39,7 +39,7 @@ import torch
 
 import gen
 from alt_check import coef_close
-from gpu_common import flip_check_gpu_lists, gpu_available, grad_close
+from gpu_common import compare_tile_lists, flip_check_gpu_lists, gpu_available, grad_close
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
@@ -104,8 +104,8 @@ def test_full_form_bin_sort_bit_exact(orc, c5):
     scene, cam, tr, t, Y, g = c5
     keys, ids, ranges = orc.tile_lists(cam, g["mean2d"], g["radius"], g["depth"])
     assert g["P"] == len(ids) and g["P"] > 2 ** 25
-    assert np.array_equal(g["ranges"], ranges)
-    assert np.array_equal(g["ids"], ids)
+    diff = compare_tile_lists(dict(g, keys=None), keys, ids, ranges, cam.tiles_x, cam.tiles_y)
+    assert diff is None, diff
 
 
 @pytest.fixture(scope="module")

@@ -27,8 +27,8 @@ import torch
 
 import gen
 from alt_check import check_flips, coef_close
-from gpu_common import (by_pixel, flip_check_gpu_lists, oracle_composite_from_gpu, oracle_lists_from_gpu,
-                        run_forward, small_scene)
+from gpu_common import (by_pixel, compare_tile_lists, flip_check_gpu_lists, oracle_composite_from_gpu,
+                        oracle_lists_from_gpu, run_forward, small_scene)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,11 +37,8 @@ ATOL = 1e-5        # float32 coefficients, transmittance and features (absolute)
 
 def _check_lists(orc, cam, g):
     keys, ids, ranges = oracle_lists_from_gpu(orc, cam, g)
-    assert g["P"] == len(ids)
-    assert np.array_equal(g["ranges"], ranges)
-    assert np.array_equal(g["ids"], ids)
-    if g["keys"] is not None:
-        assert np.array_equal(g["keys"], keys)
+    diff = compare_tile_lists(g, keys, ids, ranges, cam.tiles_x, cam.tiles_y)
+    assert diff is None, diff
 
 
 def _check_coef(orc, cam, scene, g, atol=ATOL):
@@ -270,8 +267,10 @@ def test_capacity_overflow(orc):
 
 
 def test_long_tile_lists(orc):
-    """Thousands of Gaussians piled onto one tile exercise the large LDS sort
-    class and the global-memory fallback."""
+    """Thousands of Gaussians piled onto one tile: a bucket beyond the LDS
+    capacity is split over its depth range and sorted in LDS-sized runs, and
+    with a pool of exactly P entries (no room for the split) it is sorted by
+    the global-memory network; lists bit-exact."""
     rng = np.random.default_rng(12)
     n = 40000
     scene = gen.make_scene(12, n, D=128)
@@ -604,9 +603,9 @@ def test_decode_query_epilogue(orc, L, D, n_neg, coef_bf16, keep):
 
 
 def test_equal_depth_runs_in_id_order(orc):
-    """Short runs of equal float32 depth (the depth-only radix passes plus the
-    per-run id fix-up) and one run of 300 equal depths (longer than the
-    fix-up handles: the bucket is sorted on every digit): lists bit-exact."""
+    """Short runs of equal float32 depth (ordered by id inside their depth
+    bin by the insertion sort) and one run of 300 equal depths (a depth bin
+    beyond 16 keys: sorted by the LDS bitonic network): lists bit-exact."""
     rng = np.random.default_rng(21)
     n = 3000
     scene = gen.make_scene(21, n, D=128)
@@ -624,9 +623,10 @@ def test_equal_depth_runs_in_id_order(orc):
 
 def test_many_equal_depth_runs_across_buckets(orc):
     """Depths on a coarse grid across 12 superblocks: buckets hold many runs
-    of 2-16 equal depths (ordered by id by the in-place fix-up after the
-    depth-half passes) and, where 40 Gaussians share one depth in one place,
-    runs beyond 16 (sorted on every key digit instead): lists bit-exact."""
+    of 2-16 equal depths (ordered by id inside their depth bins by the
+    insertion sort) and, where 40 Gaussians share one depth in one place,
+    bins beyond 16 keys (sorted by the LDS bitonic network): lists
+    bit-exact."""
     rng = np.random.default_rng(31)
     n_base, n_a, n_b = 20000, 30 * 12, 3 * 40
     n = n_base + n_a + n_b
@@ -698,8 +698,8 @@ def test_index_check_mode(orc):
 
 def test_large_image_superblock_geometry(orc):
     """An image above 4096 x 4096 (4160 x 4160: 260 x 260 tiles) bins by
-    superblocks of 8 x 8 tiles and fills every tile list in one pass per
-    bucket: lists bit-exact over the whole image; 3000 sampled pixels (most
+    superblocks of 8 x 8 tiles, each filled as four blocks of 4 x 4 tiles:
+    lists bit-exact over the whole image; 3000 sampled pixels (most
     of them in covered tiles) composited against the oracle."""
     import paper_2507_07136_amd as ls2
     W = H = 4160
