@@ -65,7 +65,7 @@ inline Geo geo(const CamK& k) {
 }
 
 struct Layout {
-    size_t meta, sb_count, sb_pairs, sb_start, sb_pstart, sb_cursor, sb_order, rect, pool, total;
+    size_t meta, sb_count, sb_pairs, sb_start, sb_pstart, sb_cursor, sb_order, rect, pool, cov, total;
 };
 
 // meta, sb_count and sb_pairs come first: they are zeroed every call.
@@ -82,6 +82,7 @@ inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     l.sb_order = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.rect = off; off = align_up(off + sizeof(ushort4) * (size_t)(n > 0 ? n : 1));
     l.pool = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
+    l.cov = off; off = align_up(off + sizeof(unsigned short) * (size_t)(max_pairs > 0 ? max_pairs : 1));
     l.total = off;
     return l;
 }
@@ -104,6 +105,7 @@ struct BinArgs {
     unsigned* sb_order;  // superblocks by decreasing bucket size (size classes)
     ushort4* rect;
     unsigned long long* pool;
+    unsigned short* cov;  // S = 4: each pool entry's coverage of its superblock's tiles (bit 4 y + x)
     unsigned* ranges;
     unsigned* ids;
     unsigned long long* keys;
@@ -295,6 +297,13 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
                 for (int sx = sx0; sx <= sx1; ++sx) {
                     const unsigned pos = atomicAdd(&hist[sy * a.sbx + sx], 1u);
                     a.pool[pos] = key;
+                    if (a.S == 4) {  // the tiles of the superblock the rectangle covers
+                        const int cx0 = max(x0 - 4 * sx, 0), cx1 = min(x1 - 4 * sx, 3);
+                        const int cy0 = max(y0 - 4 * sy, 0), cy1 = min(y1 - 4 * sy, 3);
+                        const unsigned cols = ((2u << cx1) - 1u) & ~((1u << cx0) - 1u);
+                        const unsigned rows = 0x1111u & ((1u << (4 * cy1 + 4)) - 1u) & ~((1u << (4 * cy0)) - 1u);
+                        a.cov[pos] = (unsigned short)(cols * rows);
+                    }
                 }
         }
     }
@@ -308,7 +317,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
 // comparator whose partner lies at or beyond `cnt`: such a comparator would
 // never move anything.  No padding is stored.
 template <bool WAVE_LOCAL, typename Ptr>
-__device__ void flip_bitonic(Ptr s, int cnt) {
+__device__ void flip_bitonic(Ptr s, int cnt, unsigned short* pay = nullptr) {
     int m = 1;
     while (m < cnt) m <<= 1;
     for (int k = 2; k <= m; k <<= 1) {
@@ -331,6 +340,11 @@ __device__ void flip_bitonic(Ptr s, int cnt) {
                     if (x > y) {
                         s[i] = y;
                         s[p] = x;
+                        if (pay) {  // the payload moves with its key
+                            const unsigned short t = pay[i];
+                            pay[i] = pay[p];
+                            pay[p] = t;
+                        }
                     }
                 }
             }
@@ -384,8 +398,18 @@ struct SortSmem {
 // to dst are not waited for).
 constexpr int kBinSortMax = 16;
 
+// A 16-bit payload per key (the coverage masks) rides along with the sort
+// when the bucket leaves room in sm.xbuf: the sorted payload follows the cnt
+// keys, and the payload in bucket order follows it (12 bytes per key).
+constexpr int kPayCap = 10240;
+__device__ __forceinline__ unsigned short* pay_sorted(SortSmem& sm, int cnt) {
+    return reinterpret_cast<unsigned short*>(sm.xbuf + cnt);  // 8-byte aligned
+}
+static_assert(kPayCap * (sizeof(unsigned long long) + 2 * sizeof(unsigned short)) + 8 <= sizeof(SortSmem::xbuf),
+              "keys, payloads and a 4-mask read past the sorted payload fit the key buffer");
+
 __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long* src, unsigned long long* dst,
-                                         int cnt) {
+                                         int cnt, const unsigned short* pay_src = nullptr) {
     constexpr int NW = kSortWaves;
     constexpr int ITEMS = kSortCap / (64 * NW);  // chunks per wave, at most
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -414,6 +438,18 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
     }
     for (int i = threadIdx.x; i < nb; i += blockDim.x) bins[i] = 0u;
     if (threadIdx.x == 0) sm.nbig = 0u;
+    // payload (cnt <= kPayCap): staged in bucket order, then moved with the keys
+    unsigned short* const pay = pay_src ? pay_sorted(sm, cnt) : nullptr;
+    unsigned short* const pay_in = pay ? pay + cnt : nullptr;
+    if (pay)
+        for (int p0 = threadIdx.x; p0 < cnt; p0 += 4 * (int)blockDim.x) {  // four loads in flight
+            unsigned short v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = pay_src[min(p0 + q * (int)blockDim.x, cnt - 1)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (p0 + q * (int)blockDim.x < cnt) pay_in[p0 + q * (int)blockDim.x] = v[q];
+        }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         hlo = min(hlo, (unsigned)__shfl_xor((int)hlo, off));
@@ -470,10 +506,8 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
 #pragma unroll
     for (int v = 0; v < NW; ++v)
         if (v < w) run += sm.wscan[v];
-    unsigned st[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        st[q] = run;
         const int i = (int)threadIdx.x * per + q;
         if (q < per && i < nb) bins[i] = run;  // this thread alone read bins[i] above
         if (bc[q] > (unsigned)kBinSortMax)     // at most cnt / (kBinSortMax + 1) < kMaxS2 such bins
@@ -485,21 +519,29 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
     // are now cursors)
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c)
-        if (c < mine && (c0 + c) * 64 + lane < cnt) sm.xbuf[atomicAdd(&bins[bin_of(key[c])], 1u)] = key[c];
+        if (c < mine && (c0 + c) * 64 + lane < cnt) {
+            const unsigned slot = atomicAdd(&bins[bin_of(key[c])], 1u);
+            sm.xbuf[slot] = key[c];
+            if (pay) pay[slot] = pay_in[(c0 + c) * 64 + lane];
+        }
     __syncthreads();
-    // 4. each thread sorts the short bins it owns
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (bc[q] > (unsigned)kBinSortMax) continue;
-        const int b0 = (int)st[q], b1 = b0 + (int)bc[q];
+    // 4. the short bins, sorted by insertion: thread t takes bins t, t + T, ...
+    // (neighbouring lanes work on neighbouring bins, so their LDS accesses
+    // fall in different banks); the cursors now hold each bin's end
+    for (int bi = threadIdx.x; bi < nb; bi += blockDim.x) {
+        const int b0 = bi ? (int)bins[bi - 1] : 0, b1 = (int)bins[bi];
+        if (b1 - b0 > kBinSortMax) continue;
         for (int i = b0 + 1; i < b1; ++i) {
             const unsigned long long v = sm.xbuf[i];
+            const unsigned short pv = pay ? pay[i] : 0;
             int j = i - 1;
             while (j >= b0 && sm.xbuf[j] > v) {
                 sm.xbuf[j + 1] = sm.xbuf[j];
+                if (pay) pay[j + 1] = pay[j];
                 --j;
             }
             sm.xbuf[j + 1] = v;
+            if (pay) pay[j + 1] = pv;
         }
     }
     // 5. long bins, one at a time, by the whole workgroup (each network ends
@@ -507,7 +549,7 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
     const unsigned nbig = sm.nbig;  // stored before the last barrier
     for (unsigned k = 0; k < nbig; ++k) {
         const unsigned e = sm.big[k];
-        flip_bitonic<true>(sm.xbuf + (e & 0x7fffu), (int)(e >> 15));
+        flip_bitonic<true>(sm.xbuf + (e & 0x7fffu), (int)(e >> 15), pay ? pay + (e & 0x7fffu) : nullptr);
     }
     lds_barrier();
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) dst[p] = sm.xbuf[p];
@@ -780,6 +822,102 @@ __device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, in
     }
 }
 
+// Tile lists of a 4 x 4-tile superblock whose bucket (cnt <= kPayCap) was
+// sorted in sm.xbuf together with its coverage masks (bit 4 y + x, written by
+// k_sb_emit).  Wave w owns the slice [w len, (w + 1) len) of the bucket (len
+// a multiple of 64): it counts the slice's entries per tile (one ballot per
+// tile and 64 entries), the waves' counts give each wave its first place in
+// every tile, and a second pass emits the slice in order (per tile one
+// ballot, the lane's rank among the covering lanes, one store), so every
+// tile list is the ordered subsequence of the sorted bucket.  Masks and keys
+// come from LDS: nothing is gathered.
+__device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, int sb, int cnt) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tx0 = (sb % a.sbx) * 4, ty0 = (sb / a.sbx) * 4;
+    const unsigned short* const cov = pay_sorted(sm, cnt);
+    const int len = (cnt + 64 * kSortWaves - 1) / (64 * kSortWaves) * 64;
+    const int e0 = min(cnt, w * len), e1 = min(cnt, e0 + len);
+    // 1. this wave's entries per tile (lane t: tile t)
+    unsigned mine = 0u;
+    for (int e = e0; e < e1; e += 64 * kFillGroups) {
+        unsigned cv[kFillGroups];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) cv[q] = e + 64 * q + lane < e1 ? cov[e + 64 * q + lane] : 0u;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            unsigned c = 0u;
+#pragma unroll
+            for (int q = 0; q < kFillGroups; ++q)
+                c += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cv[q] >> t) & 1u));
+            if (lane == t) mine += c;
+        }
+    }
+    if (lane < 16) sm.wcnt[w][lane] = mine;
+    __syncthreads();
+    // 2. tile totals, list starts (row-major tiles of the superblock), ranges
+    if (w == 0 && lane < 16) {
+        unsigned tot = 0u;
+#pragma unroll
+        for (int v = 0; v < kSortWaves; ++v) tot += sm.wcnt[v][lane];
+        unsigned incl = tot;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const unsigned y = __shfl_up(incl, off, 16);
+            if (lane >= off) incl += y;
+        }
+        const unsigned start = a.sb_pstart[sb] + incl - tot;
+        sm.tcnt[lane] = start;
+        sm.big[lane] = start + tot;
+        const int x = tx0 + (lane & 3), y = ty0 + (lane >> 2);
+        if (x < a.cam.tx && y < a.cam.ty) {
+            a.ranges[2 * (y * a.cam.tx + x)] = start;
+            a.ranges[2 * (y * a.cam.tx + x) + 1] = start + tot;
+        }
+    }
+    __syncthreads();
+    // 3. emit the slice; lane t: this wave's next place in tile t, and the tile's end
+    unsigned cur = 0u, end = 0u;
+    if (lane < 16) {
+        cur = sm.tcnt[lane];
+        for (int v = 0; v < w; ++v) cur += sm.wcnt[v][lane];
+        end = min(sm.big[lane], (unsigned)a.max_pairs);  // P <= max_pairs here; the clamp only guards
+    }
+    __attribute__((address_space(1))) unsigned* ids = (__attribute__((address_space(1))) unsigned*)a.ids;
+    asm volatile("" : "+v"(ids));  // the base in vector registers: the scalar file is full here
+    unsigned long long* __restrict__ const keys = a.keys;
+    for (int e = e0; e < e1; e += 64 * kFillGroups) {
+        unsigned cv[kFillGroups];
+        unsigned long long kk[kFillGroups];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) {
+            const int ee = e + 64 * q + lane;
+            cv[q] = ee < e1 ? cov[ee] : 0u;
+            kk[q] = sm.xbuf[min(ee, e1 - 1)];
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            unsigned out = (unsigned)__builtin_amdgcn_readlane((int)cur, t);
+            const unsigned tend = (unsigned)__builtin_amdgcn_readlane((int)end, t);
+            const unsigned long long tk = (unsigned long long)((ty0 + (t >> 2)) * a.cam.tx + tx0 + (t & 3)) << 32;
+#pragma unroll
+            for (int q = 0; q < kFillGroups; ++q) {
+                const bool hit = (cv[q] >> t) & 1u;
+                const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+                if (hit) {
+                    const unsigned pos = out + __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                    if (pos < tend) {  // the counts above use the same test: pos < tend always
+                        ids[pos] = (unsigned)(kk[q] & 0xffffffffull);
+                        if (keys) keys[pos] = tk | (kk[q] >> 32);
+                    }
+                }
+                out += (unsigned)__builtin_popcountll(mask);
+            }
+            if (lane == t) cur = out;
+        }
+    }
+}
+
 // Empty tile ranges for every tile of superblock sb: [first, first).
 __device__ __forceinline__ void empty_sb_ranges(const BinArgs& a, int sb, unsigned first) {
     const int S = a.S, tx0 = (sb % a.sbx) * S, ty0 = (sb / a.sbx) * S;
@@ -822,9 +960,15 @@ __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
         nunits = split_bucket(a, sm, g, cnt);
         src = a.pool + a.meta->sb_total + a.sb_start[sb];
     }
+    // S = 4 buckets of at most kPayCap keys sort their coverage masks along
+    const bool lds_fill = in_lds && a.S == 4 && cnt <= kPayCap;
     for (int u = 0; u < nunits; ++u) {
         const int b0 = in_lds ? 0 : (int)sm.chunk_start[u], b1 = in_lds ? cnt : (int)sm.chunk_start[u + 1];
-        if (b1 > b0) sort_lds(sm, src + b0, g + b0, b1 - b0);
+        if (b1 > b0) sort_lds(sm, src + b0, g + b0, b1 - b0, lds_fill ? a.cov + a.sb_start[sb] : nullptr);
+    }
+    if (lds_fill) {
+        fill_tiles_lds(a, sm, sb, cnt);  // starts after sort_lds's closing LDS barrier
+        return;
     }
     if (!in_lds) __threadfence_block();  // the global writes, before the fill reads g
     fill_sb_lists(a, sm, sb, in_lds ? sm.xbuf : g, cnt);  // starts with a workgroup barrier
@@ -874,6 +1018,7 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.sb_order = reinterpret_cast<unsigned*>(ws + lay.sb_order);
     a.rect = reinterpret_cast<ushort4*>(ws + lay.rect);
     a.pool = reinterpret_cast<unsigned long long*>(ws + lay.pool);
+    a.cov = reinterpret_cast<unsigned short*>(ws + lay.cov);
     a.ranges = tile_ranges;
     a.ids = ids;
     a.keys = reinterpret_cast<unsigned long long*>(keys);
