@@ -416,13 +416,20 @@ static int num_cus() {
 }
 
 // ---------------------------------------------------------------------------
-// Decode fused with the feature loss (float32 compute).  The MFMA part is the
-// f32 kernel above; instead of streaming the 32 x D tile of F out, each wave
-// takes four of its rows, reads the matching target rows (coalesced), forms
-// the row's L1 / cosine terms and writes dL/dF.  Lane layout and reduction
-// order of the row phase are those of ls2_feature_loss, so dL/dF matches
-// decoding and then calling the loss up to float32 rounding.  F is written
-// only if asked for.
+// Decode fused with the feature loss (float32 compute).  The workgroup's
+// D/64 waves each own a 64-feature slice of S (in VGPRs) and compute the same
+// 32-pixel block; F never leaves the matrix-core accumulators.  Each wave
+// forms its slice's per-pixel partial sums (|F - Y|, F.Y, F.F, Y.Y), the
+// waves exchange them through LDS (one barrier per block), and every wave
+// then writes its slice of dL/dF.  The target comes in, and dL/dF goes out,
+// as 256-byte row segments through a per-wave LDS tile (the accumulator
+// layout would touch 32 rows per instruction).  The next block's matrix-core
+// chain is issued in two halves around the barrier, so it runs while this
+// block's sums, gradient and stores are formed; its coefficients and target
+// rows are loaded a block ahead.  The row sums follow the loss's definition
+// (ls2_feature_loss) in another summation order, so dL/dF matches decoding
+// and then calling the loss up to float32 rounding.  F is written only if
+// asked for.
 struct DecodeLossArgs {
     DecodeArgs d;
     const float* target;
@@ -438,19 +445,19 @@ template <int L>
 __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
     constexpr int KS = L / 2;
     constexpr int MT = 2;
-    constexpr int MAXV = 2;  // float4s per lane in a row: D <= 512
+    constexpr int SROW = 64 * 4 + 16;  // LDS row of a wave's tile: 64 floats, padded
     extern __shared__ float4 smem4[];
-    __shared__ CSum red[2][8];
-    char* smem = reinterpret_cast<char*>(smem4);
+    __shared__ float4 red[2][8][32];  // per block parity, wave, pixel: (l1, fy, ff, yy) over the wave's 64 features
+    __shared__ CSum lred[2][64];
     const DecodeArgs& a = la.d;
-    const int D = a.D;  // == FC: one chunk
+    const int D = a.D;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    const int srow = D * 4 + 16;
     const int col = lane & 31, half = lane >> 5;
     const int f_wave = wave * (MT * 32);
-    const int nv4 = D / 4;
     const float inv_md = la.inv_md, inv_m = la.inv_m;
+    char* const tile = reinterpret_cast<char*>(smem4) + wave * 32 * SROW;  // this wave's 32 x 64 staging tile
+    const int sp = lane >> 4, su = lane & 15;  // row-segment access: rows 4 i + sp, 16-byte unit su
     CSum l1_acc{}, lc_acc{};
 
     float sa[MT][KS];
@@ -459,130 +466,148 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_f32(DecodeLossArgs la) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) sa[mt][s] = a.dict[(size_t)(half * KS + s) * D + f_wave + mt * 32 + col];
 
-    long long blk = blockIdx.x;
-    const long long bstep = gridDim.x;
-    float4 raw[KS / 4];
-    load_coef_f32path<L>(a, blk, col, half, raw);
-    int cur = 0;  // F tile buffer of this block (two, alternating)
-    for (; blk < a.nblocks; blk += bstep) {
-        const long long p0 = blk * 32;
-        char* ftile = smem + cur * 32 * srow;
-        // target rows of this wave's first PF rows: loaded now, used after the
-        // matrix-core phase (which hides their latency)
-        constexpr int PF = 4;
-        float4 ypf[PF][MAXV];
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const long long row = p0 + wave + k * nwaves;
-#pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                const int v = lane + 64 * q;
-                ypf[k][q] = (wave + k * nwaves < 32 && row < a.m && v < nv4)
-                                ? reinterpret_cast<const float4*>(la.target + row * D)[v]
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        }
-        float wv[KS];
+    auto load_coef = [&](long long bk, float (&wv)[KS]) {
+        float4 raw[KS / 4];
+        load_coef_f32path<L>(a, bk, col, half, raw);
 #pragma unroll
         for (int q = 0; q < KS / 4; ++q) {
             wv[4 * q] = raw[q].x; wv[4 * q + 1] = raw[q].y; wv[4 * q + 2] = raw[q].z; wv[4 * q + 3] = raw[q].w;
         }
-        load_coef_f32path<L>(a, blk + bstep, col, half, raw);
-        f32x16 acc[MT];
+    };
+    // the target's 32 x 64 slice of block bk as 256-byte row segments
+    auto load_target_rows = [&](long long bk, f32x4v (&yr)[8]) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            acc[mt] = (f32x16){};
-#pragma unroll
-            for (int s = 0; s < KS; ++s) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[mt][s], wv[s], acc[mt], 0, 0, 0);
+        for (int i = 0; i < 8; ++i) {
+            const long long row = bk * 32 + 4 * i + sp;
+            yr[i] = (bk < a.nblocks && row < a.m)
+                        ? __builtin_nontemporal_load(reinterpret_cast<const f32x4v*>(la.target + row * D + f_wave) + su)
+                        : (f32x4v){0.f, 0.f, 0.f, 0.f};
         }
+    };
+
+    long long blk = blockIdx.x;
+    const long long bstep = gridDim.x;
+    float wv[KS];
+    f32x16 acc[MT];
+    load_coef(blk, wv);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        acc[mt] = (f32x16){};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[mt][s], wv[s], acc[mt], 0, 0, 0);
+    }
+    load_coef(blk + bstep, wv);
+    f32x4v yr[8];
+    load_target_rows(blk, yr);
+    int cur = 0;
+    for (; blk < a.nblocks; blk += bstep) {
+        const long long row = blk * 32 + col;
+        const bool rok = row < a.m;
+        // the target rows through the tile into the accumulator layout
+#pragma unroll
+        for (int i = 0; i < 8; ++i) *reinterpret_cast<f32x4v*>(tile + (4 * i + sp) * SROW + su * 16) = yr[i];
+        load_target_rows(blk + bstep, yr);  // the next block's rows: a whole block to arrive
+        wave_lds_order();
+        // the target is read from the tile where it is used (accumulator layout)
+        auto ytile = [&](int mt, int g) -> float4* {
+            return reinterpret_cast<float4*>(tile + col * SROW + (mt * 32 + g * 8 + half * 4) * 4);
+        };
+        f32x16 nacc[MT];
+        // next block, first feature tile: its matrix-core chain overlaps this block's partial sums
+        nacc[0] = (f32x16){};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) nacc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[0][s], wv[s], nacc[0], 0, 0, 0);
+        float l1 = 0.f, fy = 0.f, ff = 0.f, yy = 0.f;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int f = f_wave + mt * 32 + g * 8 + half * 4;
-                *reinterpret_cast<float4*>(ftile + col * srow + f * 4) =
-                    make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+                const float f0 = acc[mt][4 * g], f1 = acc[mt][4 * g + 1], f2 = acc[mt][4 * g + 2], f3 = acc[mt][4 * g + 3];
+                const float4 yv = *ytile(mt, g);
+                l1 += fabsf(f0 - yv.x) + fabsf(f1 - yv.y) + fabsf(f2 - yv.z) + fabsf(f3 - yv.w);
+                fy = fmaf(f0, yv.x, fmaf(f1, yv.y, fmaf(f2, yv.z, fmaf(f3, yv.w, fy))));
+                ff = fmaf(f0, f0, fmaf(f1, f1, fmaf(f2, f2, fmaf(f3, f3, ff))));
+                yy = fmaf(yv.x, yv.x, fmaf(yv.y, yv.y, fmaf(yv.z, yv.z, fmaf(yv.w, yv.w, yy))));
             }
-        lds_barrier();
-        // row phase: wave w takes rows w, w + nwaves, ...; the first PF of
-        // them use the prefetched target rows (a loop with a fixed trip
-        // count, so the prefetched rows are addressed statically and the
-        // rows' reductions can interleave)
-        auto row_phase = [&](int r, const float4 (&yv)[MAXV]) {
-            const long long row = p0 + r;
-            if (row >= a.m) return;
-            const float4* frow = reinterpret_cast<const float4*>(ftile + r * srow);
-            float4 f[MAXV], y[MAXV];
-            float l1 = 0.f, fy = 0.f, ff = 0.f, yy = 0.f;
+        // the two lane halves hold the same pixel's other 32 features
+        l1 += __shfl_xor(l1, 32);
+        fy += __shfl_xor(fy, 32);
+        ff += __shfl_xor(ff, 32);
+        yy += __shfl_xor(yy, 32);
+        if (half == 0) red[cur][wave][col] = make_float4(l1, fy, ff, yy);
+        __syncthreads();
+        // next block, second feature tile: overlaps this block's gradient and stores
+        nacc[1] = (f32x16){};
 #pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                const int v = lane + 64 * q;
-                f[q] = v < nv4 ? frow[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-                y[q] = yv[q];
-                l1 += fabsf(f[q].x - y[q].x) + fabsf(f[q].y - y[q].y) + fabsf(f[q].z - y[q].z) + fabsf(f[q].w - y[q].w);
-                fy = fmaf(f[q].x, y[q].x, fmaf(f[q].y, y[q].y, fmaf(f[q].z, y[q].z, fmaf(f[q].w, y[q].w, fy))));
-                ff = fmaf(f[q].x, f[q].x, fmaf(f[q].y, f[q].y, fmaf(f[q].z, f[q].z, fmaf(f[q].w, f[q].w, ff))));
-                yy = fmaf(y[q].x, y[q].x, fmaf(y[q].y, y[q].y, fmaf(y[q].z, y[q].z, fmaf(y[q].w, y[q].w, yy))));
-            }
-            l1 = wave_allsum(l1);
-            fy = wave_allsum(fy);
-            ff = wave_allsum(ff);
-            yy = wave_allsum(yy);
-            const float nf = sqrtf(ff), ny = sqrtf(yy);
-            const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
-            const float cs = fy / (gf * gy);
-            l1_acc.add(l1);
+        for (int s = 0; s < KS; ++s) nacc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[1][s], wv[s], nacc[1], 0, 0, 0);
+        load_coef(blk + 2 * bstep, wv);  // the operand registers are free once the chain has issued
+        float4 t = red[cur][0][col];
+        for (int w = 1; w < nwaves; ++w) {
+            const float4 u = red[cur][w][col];
+            t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+        }
+        const float nf = sqrtf(t.z), ny = sqrtf(t.w);
+        const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
+        const float cs = t.y / (gf * gy);
+        if (wave == 0 && half == 0 && rok) {
+            l1_acc.add(t.x);
             lc_acc.add(1.0f - cs);
-            const float ay = inv_m / (gf * gy);
-            const float bf = nf > 1e-12f ? inv_m * fy / (nf * nf * nf * gy) : 0.f;
-#pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                const int v = lane + 64 * q;
-                if (v < nv4) {
-                    f32x4v o;
-                    o.x = sgn_dl(f[q].x - y[q].x) * inv_md - ay * y[q].x + bf * f[q].x;
-                    o.y = sgn_dl(f[q].y - y[q].y) * inv_md - ay * y[q].y + bf * f[q].y;
-                    o.z = sgn_dl(f[q].z - y[q].z) * inv_md - ay * y[q].z + bf * f[q].z;
-                    o.w = sgn_dl(f[q].w - y[q].w) * inv_md - ay * y[q].w + bf * f[q].w;
-                    __builtin_nontemporal_store(o, reinterpret_cast<f32x4v*>(la.d_feat + row * D) + v);
-                    if (la.feat) {
-                        const f32x4v fv = {f[q].x, f[q].y, f[q].z, f[q].w};
-                        __builtin_nontemporal_store(fv, reinterpret_cast<f32x4v*>(la.feat + row * D) + v);
-                    }
-                }
-            }
-        };
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int r = wave + k * nwaves;
-            if (r < 32) row_phase(r, ypf[k]);
         }
-        for (int r = wave + PF * nwaves; r < 32; r += nwaves) {  // D < 512: more rows per wave
-            const long long row = p0 + r;
-            float4 yv[MAXV];
+        const float ay = inv_m / (gf * gy);
+        const float bf = nf > 1e-12f ? inv_m * t.y / (nf * nf * nf * gy) : 0.f;
+        // dL/dF into the tile (the target is in registers by now), out as row segments
 #pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                const int v = lane + 64 * q;
-                yv[q] = (row < a.m && v < nv4) ? reinterpret_cast<const float4*>(la.target + row * D)[v]
-                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float f0 = acc[mt][4 * g], f1 = acc[mt][4 * g + 1], f2 = acc[mt][4 * g + 2], f3 = acc[mt][4 * g + 3];
+                const float4 yv = *ytile(mt, g);
+                float4 o;
+                o.x = sgn_dl(f0 - yv.x) * inv_md - ay * yv.x + bf * f0;
+                o.y = sgn_dl(f1 - yv.y) * inv_md - ay * yv.y + bf * f1;
+                o.z = sgn_dl(f2 - yv.z) * inv_md - ay * yv.z + bf * f2;
+                o.w = sgn_dl(f3 - yv.w) * inv_md - ay * yv.w + bf * f3;
+                *ytile(mt, g) = o;  // in place: this lane alone reads and writes these 16 bytes
             }
-            row_phase(r, yv);
+        wave_lds_order();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const long long r = blk * 32 + 4 * i + sp;
+            const f32x4v v = *reinterpret_cast<const f32x4v*>(tile + (4 * i + sp) * SROW + su * 16);
+            if (r < a.m) __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(la.d_feat + r * D + f_wave) + su);
         }
-        // no barrier: the next block stages F in the other buffer; this one is
-        // rewritten two blocks later, after every wave has passed the next
-        // block's barrier (so has finished reading it)
-        cur ^= 1;
+        if (la.feat) {  // F as well: the same way
+            wave_lds_order();
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    *reinterpret_cast<float4*>(tile + col * SROW + (mt * 32 + g * 8 + half * 4) * 4) =
+                        make_float4(acc[mt][4 * g], acc[mt][4 * g + 1], acc[mt][4 * g + 2], acc[mt][4 * g + 3]);
+            wave_lds_order();
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const long long r = blk * 32 + 4 * i + sp;
+                const f32x4v v = *reinterpret_cast<const f32x4v*>(tile + (4 * i + sp) * SROW + su * 16);
+                if (r < a.m) __builtin_nontemporal_store(v, reinterpret_cast<f32x4v*>(la.feat + r * D + f_wave) + su);
+            }
+        }
+        wave_lds_order();  // the tile's reads are done before the next target rows land in it
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = nacc[mt];
+        cur ^= 1;  // red[cur] is rewritten two blocks later, after every wave passed the next barrier
     }
-    if (lane == 0) {
-        red[0][wave] = l1_acc;
-        red[1][wave] = lc_acc;
+    // per-pixel loss terms were added by the lanes of wave 0: sum them in lane order
+    if (wave == 0) {
+        lred[0][lane] = l1_acc;
+        lred[1][lane] = lc_acc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         CSum s0{}, s1{};
-        for (int w = 0; w < nwaves; ++w) {
-            s0.add(red[0][w]);
-            s1.add(red[1][w]);
+        for (int l = 0; l < 64; ++l) {
+            s0.add(lred[0][l]);
+            s1.add(lred[1][l]);
         }
         la.partial[2 * blockIdx.x] = s0;
         la.partial[2 * blockIdx.x + 1] = s1;
@@ -596,7 +621,7 @@ static int launch_decode_loss(DecodeLossArgs la, hipStream_t stream) {
     DecodeArgs& a = la.d;
     a.FC = a.D;
     a.nchunks = 1;
-    const size_t lds = (size_t)2 * 32 * (a.D * 4 + 16);  // two F tiles
+    const size_t lds = (size_t)(a.D / 64) * 32 * (64 * 4 + 16);  // one staging tile per wave
     static bool attr = false;
     if (!attr) {
         if (hipFuncSetAttribute((const void*)k_decode_loss_f32<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
