@@ -386,12 +386,12 @@ struct SortSmem {
 // depth half mapped linearly onto the bucket's depth range (if every depth is
 // equal, its id half onto the id range).  Every key of a lower bin is then
 // smaller than every key of a higher one.  A histogram and its scan give each
-// bin its place, and the keys are scattered there.  The thread that owns a
-// bin in the scan sorts it in place by insertion, comparing whole 64-bit
-// keys, so ties of depth are ordered by id with no extra step.  Bins of more
-// than kBinSortMax keys (depths clustered more tightly than the bin width)
-// are instead sorted one after another by the whole workgroup with the
-// bitonic network in LDS.
+// bin its place, and the keys are scattered there.  A key of a short bin
+// then goes to its bin's start plus the number of the bin's keys below it,
+// comparing whole 64-bit keys, so ties of depth are ordered by id with no
+// extra step.  Bins of more than kBinSortMax keys (depths clustered more
+// tightly than the bin width) are instead sorted one after another by the
+// whole workgroup with the bitonic network in LDS.
 //
 // Called by the whole workgroup; the caller orders earlier LDS use of sm
 // before the call, and the call ends with an LDS barrier (the global writes
@@ -408,10 +408,10 @@ __device__ __forceinline__ unsigned short* pay_sorted(SortSmem& sm, int cnt) {
 static_assert(kPayCap * (sizeof(unsigned long long) + 2 * sizeof(unsigned short)) + 8 <= sizeof(SortSmem::xbuf),
               "keys, payloads and a 4-mask read past the sorted payload fit the key buffer");
 
-__device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long* src, unsigned long long* dst,
-                                         int cnt, const unsigned short* pay_src = nullptr) {
+template <int ITEMS>  // 64-key chunks per wave, at most: cnt <= 64 kSortWaves ITEMS
+__device__ __forceinline__ void sort_lds_n(SortSmem& sm, const unsigned long long* src, unsigned long long* dst,
+                                           int cnt, const unsigned short* pay_src) {
     constexpr int NW = kSortWaves;
-    constexpr int ITEMS = kSortCap / (64 * NW);  // chunks per wave, at most
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nchunk = (cnt + 63) >> 6;
     const int cpw = (nchunk + NW - 1) / NW;
@@ -525,25 +525,36 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
             if (pay) pay[slot] = pay_in[(c0 + c) * 64 + lane];
         }
     __syncthreads();
-    // 4. the short bins, sorted by insertion: thread t takes bins t, t + T, ...
-    // (neighbouring lanes work on neighbouring bins, so their LDS accesses
-    // fall in different banks); the cursors now hold each bin's end
-    for (int bi = threadIdx.x; bi < nb; bi += blockDim.x) {
-        const int b0 = bi ? (int)bins[bi - 1] : 0, b1 = (int)bins[bi];
-        if (b1 - b0 > kBinSortMax) continue;
-        for (int i = b0 + 1; i < b1; ++i) {
-            const unsigned long long v = sm.xbuf[i];
-            const unsigned short pv = pay ? pay[i] : 0;
-            int j = i - 1;
-            while (j >= b0 && sm.xbuf[j] > v) {
-                sm.xbuf[j + 1] = sm.xbuf[j];
-                if (pay) pay[j + 1] = pay[j];
-                --j;
+    // 4. a key of a short bin goes to its bin's start plus the number of the
+    // bin's keys below it (the cursors now hold each bin's end).  The first
+    // four places of the bin are read at once, so most keys need one LDS
+    // round trip; every read is done before any key moves.
+    unsigned fp[ITEMS];
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c) {
+        fp[c] = 0xffffffffu;
+        if (c < mine && (c0 + c) * 64 + lane < cnt) {
+            const unsigned b = bin_of(key[c]);
+            const int b0 = b ? (int)bins[b - 1] : 0, n = (int)bins[b] - b0;
+            if (n <= kBinSortMax) {
+                unsigned r = 0u;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const unsigned long long v = sm.xbuf[min(b0 + j, cnt - 1)];
+                    r += (j < n && v < key[c]) ? 1u : 0u;
+                }
+                for (int j = 4; j < n; ++j) r += sm.xbuf[b0 + j] < key[c] ? 1u : 0u;
+                fp[c] = (unsigned)b0 + r;
             }
-            sm.xbuf[j + 1] = v;
-            if (pay) pay[j + 1] = pv;
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < ITEMS; ++c)
+        if (fp[c] != 0xffffffffu) {
+            sm.xbuf[fp[c]] = key[c];
+            if (pay) pay[fp[c]] = pay_in[(c0 + c) * 64 + lane];
+        }
     // 5. long bins, one at a time, by the whole workgroup (each network ends
     // with a workgroup barrier; they touch disjoint ranges, none a short bin)
     const unsigned nbig = sm.nbig;  // stored before the last barrier
@@ -555,11 +566,22 @@ __device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long*
     for (int p = threadIdx.x; p < cnt; p += blockDim.x) dst[p] = sm.xbuf[p];
 }
 
+// Buckets of up to 9 x 1024 keys (all but the largest) hold 9 keys per
+// thread in registers instead of 16.
+constexpr int kSortSmallItems = 9;
+__device__ __forceinline__ void sort_lds(SortSmem& sm, const unsigned long long* src, unsigned long long* dst,
+                                         int cnt, const unsigned short* pay_src = nullptr) {
+    if (cnt <= 64 * kSortWaves * kSortSmallItems)
+        sort_lds_n<kSortSmallItems>(sm, src, dst, cnt, pay_src);
+    else
+        sort_lds_n<kSortCap / (64 * kSortWaves)>(sm, src, dst, cnt, pay_src);
+}
+
 // A bucket beyond kSortCap keys: split into the scratch copy by a digit over
 // its depth range and return the number of LDS-sized chunks (their key offsets
 // in sm.chunk_start); 0 if it was sorted here instead, with the global bitonic
 // network (no room for the scratch copy, or one digit bin beyond kSortCap).
-__device__ int split_bucket(const BinArgs& a, SortSmem& sm, unsigned long long* g, int cnt) {
+__device__ __forceinline__ int split_bucket(const BinArgs& a, SortSmem& sm, unsigned long long* g, int cnt) {
     const long long total = a.meta->sb_total;
     if (2 * total > a.max_pairs) {  // no room for the scratch copy
         flip_bitonic<false>(g, cnt);
