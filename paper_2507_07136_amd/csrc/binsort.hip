@@ -123,24 +123,12 @@ __global__ void k_bin_zero(unsigned* __restrict__ p, long long n) {
         p[i] = 0u;
 }
 
-// Superblock rectangle of Gaussian i; optionally stores its tile rectangle
-// (x0, y0, x1, y1), or an empty one (0xffff, 0xffff, 0, 0) if culled.
-__device__ __forceinline__ bool sb_rect_of(const BinArgs& a, int i, int& sx0, int& sy0, int& sx1, int& sy1,
-                                           int& x0, int& y0, int& x1, int& y1, bool store) {
-    bool vis = false;
+// Tile rectangle (x0, y0, x1, y1) of a Gaussian from its radius and mean,
+// with the projection's rule; false (and an empty rectangle) if it covers no
+// tile.
+__device__ __forceinline__ bool gauss_rect(const BinArgs& a, int r, float2 m, int& x0, int& y0, int& x1, int& y1) {
     x0 = 0, y0 = 0, x1 = -1, y1 = -1;
-    const int r = a.radius[i];
-    if (r > 0) {
-        const float2 m = reinterpret_cast<const float2*>(a.mean2d)[i];
-        vis = tile_rect(m.x, m.y, r, a.cam.tx, a.cam.ty, x0, y0, x1, y1);
-    }
-    if (store)
-        a.rect[i] = vis ? make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1, (unsigned short)y1)
-                        : make_ushort4(0xffff, 0xffff, 0, 0);
-    if (!vis) return false;
-    const int sh = __builtin_ctz((unsigned)a.S);
-    sx0 = x0 >> sh; sy0 = y0 >> sh; sx1 = x1 >> sh; sy1 = y1 >> sh;
-    return true;
+    return r > 0 && tile_rect(m.x, m.y, r, a.cam.tx, a.cam.ty, x0, y0, x1, y1);
 }
 
 constexpr int kBinThreads = 1024;
@@ -155,15 +143,31 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
     __syncthreads();
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
     const int S = a.S;
-    unsigned long long my_area = 0;
+    const int sh = __builtin_ctz((unsigned)S);
+    // every global read at once (the mean is read whatever the radius)
+    int rad[kBinPerThread];
+    float2 mean[kBinPerThread];
+#pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
         const int i = base + q * kBinThreads + threadIdx.x;
-        int sx0, sy0, sx1, sy1, x0, y0, x1, y1;
-        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, x0, y0, x1, y1, true)) {
+        rad[q] = i < a.n ? a.radius[i] : 0;
+        mean[q] = i < a.n ? reinterpret_cast<const float2*>(a.mean2d)[i] : make_float2(0.f, 0.f);
+    }
+    unsigned long long my_area = 0;
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int i = base + q * kBinThreads + threadIdx.x;
+        int x0, y0, x1, y1;
+        const bool vis = gauss_rect(a, rad[q], mean[q], x0, y0, x1, y1);
+        if (i < a.n)  // the rectangle for the later passes; culled: an empty one
+            a.rect[i] = vis ? make_ushort4((unsigned short)x0, (unsigned short)y0, (unsigned short)x1,
+                                           (unsigned short)y1)
+                            : make_ushort4(0xffff, 0xffff, 0, 0);
+        if (vis) {
             my_area += (unsigned long long)(x1 - x0 + 1) * (unsigned long long)(y1 - y0 + 1);
-            for (int sy = sy0; sy <= sy1; ++sy) {
+            for (int sy = y0 >> sh; sy <= (y1 >> sh); ++sy) {
                 const int h = min(y1, sy * S + S - 1) - max(y0, sy * S) + 1;
-                for (int sx = sx0; sx <= sx1; ++sx) {
+                for (int sx = x0 >> sh; sx <= (x1 >> sh); ++sx) {
                     const int w = min(x1, sx * S + S - 1) - max(x0, sx * S) + 1;
                     atomicAdd(&hist[sy * a.sbx + sx], 1u);
                     atomicAdd(&area[sy * a.sbx + sx], (unsigned)(w * h));  // the pairs inside the superblock
@@ -272,40 +276,50 @@ __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
-    if (a.meta->overflow) return;  // the lists will not be filled
-    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
-    __syncthreads();
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
+    const int sh = __builtin_ctz((unsigned)a.S);
+    // every global read at once: the tile rectangles stored by the count pass
+    // (culled Gaussians have an empty one), the depths, the overflow flag
+    ushort4 r[kBinPerThread];
+    float dep[kBinPerThread];
+#pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
         const int i = base + q * kBinThreads + threadIdx.x;
-        int sx0, sy0, sx1, sy1, x0, y0, x1, y1;
-        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, x0, y0, x1, y1, false))
-            for (int sy = sy0; sy <= sy1; ++sy)
-                for (int sx = sx0; sx <= sx1; ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
+        r[q] = i < a.n ? a.rect[i] : make_ushort4(0xffff, 0xffff, 0, 0);
+        dep[q] = i < a.n ? a.depth[i] : 0.0f;
     }
+    const bool over = a.meta->overflow != 0;
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
+    __syncthreads();
+    if (over) return;  // the lists will not be filled (the same decision in every thread)
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q)
+        if (r[q].x <= r[q].z)
+            for (int sy = r[q].y >> sh; sy <= (r[q].w >> sh); ++sy)
+                for (int sx = r[q].x >> sh; sx <= (r[q].z >> sh); ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
     __syncthreads();
     // reserve this workgroup's range in every touched bucket; hist becomes the cursor
     for (int s = threadIdx.x; s < a.nsb; s += kBinThreads)
         if (hist[s]) hist[s] = atomicAdd(&a.sb_cursor[s], hist[s]);
     __syncthreads();
+#pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
+        if (r[q].x > r[q].z) continue;
         const int i = base + q * kBinThreads + threadIdx.x;
-        int sx0, sy0, sx1, sy1, x0, y0, x1, y1;
-        if (i < a.n && sb_rect_of(a, i, sx0, sy0, sx1, sy1, x0, y0, x1, y1, false)) {
-            const unsigned long long key = ((unsigned long long)__float_as_uint(a.depth[i]) << 32) | (unsigned)i;
-            for (int sy = sy0; sy <= sy1; ++sy)
-                for (int sx = sx0; sx <= sx1; ++sx) {
-                    const unsigned pos = atomicAdd(&hist[sy * a.sbx + sx], 1u);
-                    a.pool[pos] = key;
-                    if (a.S == 4) {  // the tiles of the superblock the rectangle covers
-                        const int cx0 = max(x0 - 4 * sx, 0), cx1 = min(x1 - 4 * sx, 3);
-                        const int cy0 = max(y0 - 4 * sy, 0), cy1 = min(y1 - 4 * sy, 3);
-                        const unsigned cols = ((2u << cx1) - 1u) & ~((1u << cx0) - 1u);
-                        const unsigned rows = 0x1111u & ((1u << (4 * cy1 + 4)) - 1u) & ~((1u << (4 * cy0)) - 1u);
-                        a.cov[pos] = (unsigned short)(cols * rows);
-                    }
+        const unsigned long long key = ((unsigned long long)__float_as_uint(dep[q]) << 32) | (unsigned)i;
+        const int x0 = r[q].x, y0 = r[q].y, x1 = r[q].z, y1 = r[q].w;
+        for (int sy = y0 >> sh; sy <= (y1 >> sh); ++sy)
+            for (int sx = x0 >> sh; sx <= (x1 >> sh); ++sx) {
+                const unsigned pos = atomicAdd(&hist[sy * a.sbx + sx], 1u);
+                a.pool[pos] = key;
+                if (a.S == 4) {  // the tiles of the superblock the rectangle covers
+                    const int cx0 = max(x0 - 4 * sx, 0), cx1 = min(x1 - 4 * sx, 3);
+                    const int cy0 = max(y0 - 4 * sy, 0), cy1 = min(y1 - 4 * sy, 3);
+                    const unsigned cols = ((2u << cx1) - 1u) & ~((1u << cx0) - 1u);
+                    const unsigned rows = 0x1111u & ((1u << (4 * cy1 + 4)) - 1u) & ~((1u << (4 * cy0)) - 1u);
+                    a.cov[pos] = (unsigned short)(cols * rows);
                 }
-        }
+            }
     }
 }
 
