@@ -289,6 +289,28 @@ def test_long_tile_lists(orc):
     _check_lists(orc, cam, g2)
 
 
+@pytest.mark.parametrize("n,keep_keys,lo,hi", [(8500, False, 0, 9216), (9800, True, 9216, 10240),
+                                               (9800, False, 9216, 10240), (12000, False, 10240, 16384),
+                                               (20000, False, 16384, 1 << 30)])
+def test_bucket_size_tiers(orc, n, keep_keys, lo, hi):
+    """One superblock (a 64 x 64 image) holding every Gaussian, at bucket sizes
+    that take each path of the sort kernel: up to 9216 keys (9 per thread,
+    coverage masks sorted along), up to 10240 (16 per thread, masks along),
+    up to 16384 (masks gathered from the rectangles) and beyond (the bucket is
+    split over its depth range); with and without the keys output.  Lists
+    bit-exact."""
+    rng = np.random.default_rng(40 + n)
+    scene = gen.make_scene(40 + n, n, D=128)
+    scene.means[:] = rng.normal(0, 0.05, (n, 3)).astype(np.float32)
+    scene.scales[:] = 0.004
+    cam = gen.make_camera(64, 64)
+    g = run_forward(cam, scene, keep_keys=keep_keys)
+    vis = int((g["radius"] > 0).sum())
+    assert lo < vis <= hi, vis  # every visible Gaussian is in the one bucket
+    assert (g["keys"] is not None) == keep_keys
+    _check_lists(orc, cam, g)
+
+
 def test_large_bucket_depths_across_exponents(orc):
     """40000 Gaussians in one superblock with depths from 1.5 to 4.5, across
     three float exponents: the bucket is split into bins over its depth range
