@@ -414,6 +414,29 @@ int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const float* coef, 
                             size_t workspace_bytes, hipStream_t stream);
 
 /*
+ * ls2_decode_loss_backward -- ls2_decode_feature_loss and
+ * ls2_dict_decode_backward in one pass (float32): F = W S (Eq. 7), the loss
+ * of ls2_feature_loss against the target (Section 4.1), dL/dF, and both
+ * gradients of the decode, d_coef = dL/dF S^T and d_dict = coef^T dL/dF,
+ * with dL/dF kept on the chip (never written to memory).  Each product takes
+ * the same operands in the same order as the two-call chain, so the outputs
+ * equal that chain's bit for bit whenever the two use the same number of
+ * workgroups (one per compute unit, at most 512 and at most one per 32
+ * pixels, in both).
+ *
+ * In:  coef [m,L], dict [L,D], target [m,D], all f32, 16-byte aligned.
+ * Out: loss (device, one double); d_coef [m,L]; d_dict [L,D] (both
+ *      overwritten).
+ * workspace: at least ls2_decode_loss_backward_workspace() bytes, 16-byte
+ *      aligned (dS partial sums and the loss partials).
+ * Supported: L in {32, 64}; D in {128, 256, 384, 512}; m >= 1.
+ */
+int ls2_decode_loss_backward_workspace(int64_t m, int32_t L, int32_t D, size_t* bytes);
+int ls2_decode_loss_backward(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                             const float* target, double* loss, float* d_coef, float* d_dict, void* workspace,
+                             size_t workspace_bytes, hipStream_t stream);
+
+/*
  * ls2_query_backward -- d_feat = d_rel * dr/dF for the relevancy of
  * ls2_query (Section 3.2, LERF form).  The minimum over negatives selects the
  * first negative of largest similarity; its (sub)gradient is used.

@@ -76,6 +76,8 @@ def _load():
         "ls2_query_backward": ([i64, i32, P, i32, P, i32, P, ctypes.c_float, P, P, P], ctypes.c_int),
         "ls2_decode_feature_loss_workspace": ([i64, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_decode_feature_loss": ([i64, i32, i32, P, P, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
+        "ls2_decode_loss_backward_workspace": ([i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ls2_decode_loss_backward": ([i64, i32, i32, P, P, P, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_dict_decode_backward_workspace": ([i64, i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_dict_decode_backward": ([i64, i32, i32, P, P, i32, P, P, P, P, ctypes.c_size_t, P], ctypes.c_int),
         "ls2_splat_sparse_backward": ([cam, i32, i32, i32, i32] + [P] * 15, ctypes.c_int),
@@ -450,6 +452,24 @@ def ls2_decode_feature_loss(coef, dictionary, target, loss, d_feat, workspace, f
                                       _ptr(d_feat, f32, "d_feat", m * D), _ptr(feat, f32, "feat", m * D, allow_none=True),
                                       _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
     _check("ls2_decode_feature_loss", st)
+
+
+def ls2_decode_loss_backward_workspace(m, L, D) -> int:
+    b = ctypes.c_size_t(0)
+    _check("ls2_decode_loss_backward_workspace",
+           _lib.ls2_decode_loss_backward_workspace(int(m), int(L), int(D), ctypes.byref(b)))
+    return int(b.value)
+
+
+def ls2_decode_loss_backward(coef, dictionary, target, loss, d_coef, d_dict, workspace, stream=None):
+    L, D = dictionary.shape
+    m = coef.numel() // L
+    f32 = torch.float32
+    st = _lib.ls2_decode_loss_backward(m, L, D, _ptr(coef, f32, "coef", m * L), _ptr(dictionary, f32, "dict", L * D),
+                                       _ptr(target, f32, "target", m * D), _ptr(loss, torch.float64, "loss", 1),
+                                       _ptr(d_coef, f32, "d_coef", m * L), _ptr(d_dict, f32, "d_dict", L * D),
+                                       _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
+    _check("ls2_decode_loss_backward", st)
 
 
 def ls2_query_backward(feat, pos, neg, d_rel, d_feat, tau=1.0, stream=None):

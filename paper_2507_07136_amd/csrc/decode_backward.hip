@@ -497,6 +497,376 @@ static int launch_decode_bw(DecodeBwArgs a, hipStream_t stream) {
     return LS2_OK;
 }
 
+static int num_cus_bw() {
+    static int n_cus = 0;
+    if (n_cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        n_cus = n;
+    }
+    return n_cus;
+}
+
+// ---------------------------------------------------------------------------
+// Decode, feature loss and both decode gradients in one pass (L in {32, 64},
+// D a multiple of 128 up to 512): the float32 training objective of Section
+// 4.1 on F = W S (Eq. 7), with dL/dF consumed on the chip instead of being
+// written and read back.  A workgroup of D / 64 waves walks 32-pixel blocks;
+// wave w owns features [64 w, 64 w + 64), keeps its slice of S (forward
+// operand layout) in VGPRs and its dS = W^T dL/dF partial in the matrix
+// accumulators across blocks.  Per block:
+//   1. F = W S over its slice (W from a double-buffered LDS tile loaded a
+//      block ahead) while the block's target rows arrive;
+//   2. the per-pixel sums of the loss (|F - Y|, F.Y, F.F, Y.Y over the slice),
+//      exchanged between the waves through LDS;
+//   3. dL/dF, in the accumulator registers and in the wave's LDS tile;
+//   4. the dW partial dL/dF S^T over the slice, from the registers: one
+//      v_permlane32_swap per register pair gives the B operands in which step
+//      x pairs feature x with x + 32, as the separate backward reads them;
+//      the A operands (S rows) stream from L2, the first half issued before
+//      the exchange;
+//   5. dS += W^T dL/dF from the tile;
+//   6. the dW partials through the tiles, summed in wave order and stored.
+// Every product takes the same operands in the same order as
+// ls2_decode_feature_loss followed by ls2_dict_decode_backward (and the loss
+// formulas are the same), so with the same workgroup count d_coef, d_dict and
+// the loss equal that chain's bit for bit.
+struct DecodeLossBwArgs {
+    long long m, nblocks;
+    int D;
+    const float* coef;    // W [m, L]
+    const float* dict;    // S [L, D]
+    const float* target;  // Y [m, D]
+    float* d_coef;        // [m, L]
+    float* ws;            // [gridDim.x][L][D]: dS partials
+    CSum* partial;        // [gridDim.x][2]: loss partials
+    float inv_md, inv_m;
+};
+
+typedef float f32x4l __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float loss_sign(float e) { return e > 0.f ? 1.f : (e < 0.f ? -1.f : 0.f); }
+
+constexpr int kLbRow = 68;  // row stride (floats) of the per-wave tiles and the W tiles
+
+template <int L, int WPT>
+__global__ __launch_bounds__(512, 1) void k_decode_loss_bw(DecodeLossBwArgs a) {
+    constexpr int TL = L / 32;      // atom tiles of 32
+    constexpr int KS = L / 2;       // forward k-steps
+    constexpr int W4 = 32 * L / 4;  // float4s in a W tile
+    extern __shared__ float4 lds4[];
+    __shared__ float4 red[2][8][32];  // per block parity, wave, pixel: (l1, fy, ff, yy) over the wave's slice
+    __shared__ CSum lred[2][64];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int D = a.D;
+    const int nwaves = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 31, half = lane >> 5;
+    const int f_wave = wave * 64;
+    float* tile = lds + wave * (32 * kLbRow);        // [32 px][kLbRow]: target, then dL/dF, then the dW partial
+    float* wtiles = lds + nwaves * (32 * kLbRow);    // [2][32 px][kLbRow]: W of the current and the next block
+    // the second feature tile's forward operands: [KS / 4][64 lanes] float4 per wave
+    float4* sa1 = reinterpret_cast<float4*>(wtiles + 2 * (32 * kLbRow)) + wave * (KS / 4) * 64;
+    const int sp = lane >> 4, su = lane & 15;        // row-segment access: rows 4 i + sp, 16-byte unit su
+    const float inv_md = a.inv_md, inv_m = a.inv_m;
+    CSum l1_acc{}, lc_acc{};
+
+    // forward A operand S[half KS + s][f_wave + 32 mt + col]: the first
+    // feature tile's in VGPRs, the second's in LDS (four k-steps per float4)
+    float sa[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) sa[s] = a.dict[(size_t)(half * KS + s) * D + f_wave + col];
+#pragma unroll
+    for (int q = 0; q < KS / 4; ++q) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = a.dict[(size_t)(half * KS + 4 * q + e) * D + f_wave + 32 + col];
+        sa1[q * 64 + lane] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    // dW A operand rows: S[32 tl + col][f_wave + 32 half + x]
+    const float* srow = a.dict + (size_t)col * D + f_wave + 32 * half;
+
+    f32x16b accd[TL][2];
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) accd[tl][mt] = (f32x16b){};
+
+    // W tile: float4 number threadIdx.x + k blockDim.x of the tile (row-major)
+    auto load_w = [&](long long bk, float4 (&w)[WPT]) {
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int idx = threadIdx.x + k * blockDim.x;
+            const int wr = idx / (L / 4), wc4 = idx - wr * (L / 4);
+            const long long p = bk * 32 + wr;
+            w[k] = (idx < W4 && bk < a.nblocks && p < a.m) ? reinterpret_cast<const float4*>(a.coef + p * L)[wc4]
+                                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto store_w = [&](float* wt, const float4 (&w)[WPT]) {
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            const int idx = threadIdx.x + k * blockDim.x;
+            const int wr = idx / (L / 4), wc4 = idx - wr * (L / 4);
+            if (idx < W4) *reinterpret_cast<float4*>(wt + wr * kLbRow + 4 * wc4) = w[k];
+        }
+    };
+
+    long long blk = blockIdx.x;
+    const long long bstep = gridDim.x;
+    float4 wpf[WPT];
+    load_w(blk, wpf);
+    store_w(wtiles, wpf);
+    load_w(blk + bstep, wpf);
+    lds_barrier();
+    int cur = 0;
+    for (; blk < a.nblocks; blk += bstep) {
+        const long long p0 = blk * 32;
+        const float* wt = wtiles + cur * (32 * kLbRow);
+        // 1. the block's target rows, then F = W S on the matrix cores
+        f32x4l yr[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const long long row = p0 + 4 * i + sp;
+            yr[i] = row < a.m
+                        ? __builtin_nontemporal_load(reinterpret_cast<const f32x4l*>(a.target + row * D + f_wave) + su)
+                        : (f32x4l){0.f, 0.f, 0.f, 0.f};
+        }
+        f32x16b acc[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) acc[mt] = (f32x16b){};
+#pragma unroll
+        for (int q = 0; q < KS / 4; ++q) {  // B operand: pixel col, atoms half KS + 4 q .. + 3
+            const float4 w4 = *reinterpret_cast<const float4*>(wt + col * kLbRow + half * KS + 4 * q);
+            const float4 s4 = sa1[q * 64 + lane];
+            const float wq[4] = {w4.x, w4.y, w4.z, w4.w};
+            const float s1[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[4 * q + e], wq[e], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(s1[e], wq[e], acc[1], 0, 0, 0);
+            }
+        }
+        // the target through the tile into the accumulator layout
+#pragma unroll
+        for (int i = 0; i < 8; ++i) *reinterpret_cast<f32x4l*>(tile + (4 * i + sp) * kLbRow + 4 * su) = yr[i];
+        // the first dW A operands, in flight during the exchange
+        constexpr int SBA = 2;  // groups of four k-steps loaded ahead
+        float4 sbq[8][TL];
+#pragma unroll
+        for (int j4 = 0; j4 < SBA; ++j4)
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl)
+                sbq[j4][tl] = *reinterpret_cast<const float4*>(srow + (size_t)(32 * tl) * D + 4 * j4);
+        wave_lds_order();
+        // 2. per-pixel partial sums over the slice (lane: pixel col, features
+        //    32 mt + 8 g + 4 half + [0, 4))
+        auto ytile = [&](int mt, int g) -> float4* {
+            return reinterpret_cast<float4*>(tile + col * kLbRow + mt * 32 + g * 8 + half * 4);
+        };
+        float l1 = 0.f, fy = 0.f, ff = 0.f, yy = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float f0 = acc[mt][4 * g], f1 = acc[mt][4 * g + 1], f2 = acc[mt][4 * g + 2], f3 = acc[mt][4 * g + 3];
+                const float4 yv = *ytile(mt, g);
+                l1 += fabsf(f0 - yv.x) + fabsf(f1 - yv.y) + fabsf(f2 - yv.z) + fabsf(f3 - yv.w);
+                fy = fmaf(f0, yv.x, fmaf(f1, yv.y, fmaf(f2, yv.z, fmaf(f3, yv.w, fy))));
+                ff = fmaf(f0, f0, fmaf(f1, f1, fmaf(f2, f2, fmaf(f3, f3, ff))));
+                yy = fmaf(yv.x, yv.x, fmaf(yv.y, yv.y, fmaf(yv.z, yv.z, fmaf(yv.w, yv.w, yy))));
+            }
+        l1 += __shfl_xor(l1, 32);
+        fy += __shfl_xor(fy, 32);
+        ff += __shfl_xor(ff, 32);
+        yy += __shfl_xor(yy, 32);
+        if (half == 0) red[cur][wave][col] = make_float4(l1, fy, ff, yy);
+        lds_barrier();
+        // the next block's W tile: every wave finished reading that buffer
+        // before the barrier that closed the previous block
+        store_w(wtiles + (cur ^ 1) * (32 * kLbRow), wpf);
+        load_w(blk + 2 * bstep, wpf);
+        // 3. the row sums, the loss terms and dL/dF (registers and tile)
+        float4 t = red[cur][0][col];
+        for (int w = 1; w < nwaves; ++w) {
+            const float4 u = red[cur][w][col];
+            t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
+        }
+        const float nf = sqrtf(t.z), ny = sqrtf(t.w);
+        const float gf = fmaxf(nf, 1e-12f), gy = fmaxf(ny, 1e-12f);
+        const float cs = t.y / (gf * gy);
+        if (wave == 0 && half == 0 && p0 + col < a.m) {
+            l1_acc.add(t.x);
+            lc_acc.add(1.0f - cs);
+        }
+        const float ay = inv_m / (gf * gy);
+        const float bf = nf > 1e-12f ? inv_m * t.y / (nf * nf * nf * gy) : 0.f;
+        const bool rok = p0 + col < a.m;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const float f0 = acc[mt][4 * g], f1 = acc[mt][4 * g + 1], f2 = acc[mt][4 * g + 2], f3 = acc[mt][4 * g + 3];
+                const float4 yv = *ytile(mt, g);
+                float4 o;
+                o.x = loss_sign(f0 - yv.x) * inv_md - ay * yv.x + bf * f0;
+                o.y = loss_sign(f1 - yv.y) * inv_md - ay * yv.y + bf * f1;
+                o.z = loss_sign(f2 - yv.z) * inv_md - ay * yv.z + bf * f2;
+                o.w = loss_sign(f3 - yv.w) * inv_md - ay * yv.w + bf * f3;
+                if (!rok) o = make_float4(0.f, 0.f, 0.f, 0.f);  // rows past m: no gradient
+                *ytile(mt, g) = o;  // in place: this lane alone reads and writes these 16 bytes
+                acc[mt][4 * g] = o.x;
+                acc[mt][4 * g + 1] = o.y;
+                acc[mt][4 * g + 2] = o.z;
+                acc[mt][4 * g + 3] = o.w;
+            }
+        // 4. dW partial: B operand of step x (ascending) = features x (half 0)
+        //    and 32 + x (half 1) of pixel col.  After the swap, sw[0][r] holds
+        //    x = 8 (r / 4) + r % 4 and sw[1][r] holds x = 8 (r / 4) + 4 + r % 4.
+        float sw[2][16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const auto pr = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[0][r]), __float_as_uint(acc[1][r]),
+                                                             false, false);
+            sw[0][r] = __uint_as_float(pr[0]);
+            sw[1][r] = __uint_as_float(pr[1]);
+        }
+        f32x16b accc[TL];
+#pragma unroll
+        for (int tl = 0; tl < TL; ++tl) accc[tl] = (f32x16b){};
+#pragma unroll
+        for (int j4 = 0; j4 < 8; ++j4) {
+            if (j4 + SBA < 8) {
+#pragma unroll
+                for (int tl = 0; tl < TL; ++tl)
+                    sbq[j4 + SBA][tl] = *reinterpret_cast<const float4*>(srow + (size_t)(32 * tl) * D + 4 * (j4 + SBA));
+            }
+            const int g = j4 >> 1, c = j4 & 1;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float bx = sw[c][4 * g + e];
+#pragma unroll
+                for (int tl = 0; tl < TL; ++tl) {
+                    const float4 s4 = sbq[j4][tl];
+                    const float av = e == 0 ? s4.x : (e == 1 ? s4.y : (e == 2 ? s4.z : s4.w));
+                    accc[tl] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bx, accc[tl], 0, 0, 0);
+                }
+            }
+        }
+        wave_lds_order();  // dL/dF in the tile before the dS reads
+        // 5. dS += W^T dL/dF: step s pairs pixel q(s) (half 0) with q(s) + 8 (half 1)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int q = (s >> 3) * 16 + (s & 7) + 8 * half;
+            float w[TL], gv[2];
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl) w[tl] = wt[q * kLbRow + 32 * tl + col];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) gv[mt] = tile[q * kLbRow + 32 * mt + col];
+#pragma unroll
+            for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+                for (int mt = 0; mt < 2; ++mt)
+                    accd[tl][mt] = __builtin_amdgcn_mfma_f32_32x32x2f32(w[tl], gv[mt], accd[tl][mt], 0, 0, 0);
+        }
+        wave_lds_order();  // the tile's dS reads are done before the dW partial overwrites it
+        // 6. the dW partial (lane: atoms 32 tl + 8 g + 4 half + [0, 4) of pixel col)
+#pragma unroll
+        for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                *reinterpret_cast<float4*>(tile + col * kLbRow + 32 * tl + 8 * g + 4 * half) =
+                    make_float4(accc[tl][4 * g], accc[tl][4 * g + 1], accc[tl][4 * g + 2], accc[tl][4 * g + 3]);
+        lds_barrier();
+        for (int t4 = threadIdx.x; t4 < W4; t4 += blockDim.x) {
+            const int px = t4 / (L / 4), a4 = t4 - px * (L / 4);
+            float4 s4 = *reinterpret_cast<const float4*>(lds + px * kLbRow + 4 * a4);
+            for (int w = 1; w < nwaves; ++w) {
+                const float4 v = *reinterpret_cast<const float4*>(lds + w * (32 * kLbRow) + px * kLbRow + 4 * a4);
+                s4.x += v.x;
+                s4.y += v.y;
+                s4.z += v.z;
+                s4.w += v.w;
+            }
+            const long long p = p0 + px;
+            if (p < a.m) *reinterpret_cast<float4*>(a.d_coef + p * L + 4 * a4) = s4;
+        }
+        lds_barrier();  // the tiles are free for the next block's target; its W tile is complete
+        cur ^= 1;
+    }
+    float* out = a.ws + (size_t)blockIdx.x * L * D;
+#pragma unroll
+    for (int tl = 0; tl < TL; ++tl)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 32 * tl + 8 * (r >> 2) + 4 * half + (r & 3);
+                out[(size_t)row * D + f_wave + 32 * mt + col] = accd[tl][mt][r];
+            }
+    // per-pixel loss terms were added by the lanes of wave 0: sum them in lane order
+    if (wave == 0) {
+        lred[0][lane] = l1_acc;
+        lred[1][lane] = lc_acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        CSum s0{}, s1{};
+        for (int l = 0; l < 64; ++l) {
+            s0.add(lred[0][l]);
+            s1.add(lred[1][l]);
+        }
+        a.partial[2 * blockIdx.x] = s0;
+        a.partial[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+constexpr int kLossBwMaxParts = 512;  // workgroups (dS and loss partials) at most
+
+static size_t loss_bw_lds(int L, int D) {
+    return (size_t)(D / 64 + 2) * 32 * kLbRow * sizeof(float) + (size_t)(D / 64) * (L / 8) * 64 * sizeof(float4);
+}
+
+static long long loss_bw_grid(long long m) {
+    const long long nblk = (m + 31) / 32;
+    long long grid = num_cus_bw();
+    if (grid > kLossBwMaxParts) grid = kLossBwMaxParts;
+    if (grid > nblk) grid = nblk;
+    return grid < 1 ? 1 : grid;
+}
+
+static size_t loss_bw_dsum_bytes(long long m, int L, int D) {
+    const long long nblk = (m + 31) / 32;
+    const long long parts = nblk < kLossBwMaxParts ? nblk : kLossBwMaxParts;
+    return (size_t)(parts < 1 ? 1 : parts) * L * D * sizeof(float);
+}
+
+template <int L>
+static int launch_decode_loss_bw(DecodeLossBwArgs a, long long grid, hipStream_t stream) {
+    const int threads = (a.D / 64) * 64;
+    const int wpt = (32 * L / 4 + threads - 1) / threads;
+    const size_t lds = loss_bw_lds(L, a.D);
+    const void* kern = wpt <= 1 ? (const void*)k_decode_loss_bw<L, 1>
+                                : (wpt <= 2 ? (const void*)k_decode_loss_bw<L, 2> : (const void*)k_decode_loss_bw<L, 4>);
+    static bool attr[2][3] = {};
+    bool& done = attr[L == 64][wpt <= 1 ? 0 : (wpt <= 2 ? 1 : 2)];
+    if (!done) {
+        if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(150 * 1024)) != hipSuccess)
+            return LS2_ERR_DEVICE;
+        done = true;
+    }
+    if (wpt <= 1)
+        hipLaunchKernelGGL((k_decode_loss_bw<L, 1>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+    else if (wpt <= 2)
+        hipLaunchKernelGGL((k_decode_loss_bw<L, 2>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+    else
+        hipLaunchKernelGGL((k_decode_loss_bw<L, 4>), dim3((unsigned)grid), dim3(threads), lds, stream, a);
+    LS2_LAUNCH_CHECK();
+    return LS2_OK;
+}
+
 static bool decode_bw_supported(int L, int D) {
     return (L == 32 || L == 64 || L == 128) && D % 128 == 0 && D >= 128 && (D <= 512 || D == 1024);
 }
@@ -550,4 +920,42 @@ extern "C" int ls2_dict_decode_backward(int64_t m, int32_t L, int32_t D, const f
         case 64: return launch_decode_bw<64>(a, stream);
         default: return launch_decode_bw<128>(a, stream);
     }
+}
+
+extern "C" int ls2_decode_loss_backward_workspace(int64_t m, int32_t L, int32_t D, size_t* bytes) {
+    if (!bytes || m < 1 || L < 1 || D < 1) return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64) || D % 128 != 0 || D > 512) return LS2_ERR_UNSUPPORTED;
+    *bytes = loss_bw_dsum_bytes(m, L, D) + (size_t)kLossBwMaxParts * 2 * sizeof(CSum);
+    return LS2_OK;
+}
+
+extern "C" int ls2_decode_loss_backward(int64_t m, int32_t L, int32_t D, const float* coef, const float* dict,
+                                        const float* target, double* loss, float* d_coef, float* d_dict,
+                                        void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (m < 1 || L < 1 || D < 1 || !coef || !dict || !target || !loss || !d_coef || !d_dict || !workspace)
+        return LS2_ERR_ARG;
+    if (!(L == 32 || L == 64) || D % 128 != 0 || D > 512) return LS2_ERR_UNSUPPORTED;
+    if (!aligned16(coef) || !aligned16(dict) || !aligned16(target) || !aligned16(d_coef) || !aligned16(workspace))
+        return LS2_ERR_ARG;
+    const size_t dsum = loss_bw_dsum_bytes(m, L, D);
+    if (workspace_bytes < dsum + (size_t)kLossBwMaxParts * 2 * sizeof(CSum)) return LS2_ERR_ARG;
+    DecodeLossBwArgs a;
+    a.m = m;
+    a.nblocks = (m + 31) / 32;
+    a.D = D;
+    a.coef = coef;
+    a.dict = dict;
+    a.target = target;
+    a.d_coef = d_coef;
+    a.ws = static_cast<float*>(workspace);
+    a.partial = reinterpret_cast<CSum*>(static_cast<char*>(workspace) + dsum);
+    a.inv_md = loss_inv_md(m, D);
+    a.inv_m = loss_inv_m(m);
+    const long long grid = loss_bw_grid(m);
+    const int rc = L == 32 ? launch_decode_loss_bw<32>(a, grid, stream) : launch_decode_loss_bw<64>(a, grid, stream);
+    if (rc != LS2_OK) return rc;
+    const int LD = L * D;
+    hipLaunchKernelGGL(k_ddict_reduce, dim3((LD + 63) / 64), dim3(1024), 0, stream, a.ws, (int)grid, LD, d_dict);
+    LS2_LAUNCH_CHECK();
+    return launch_loss_final(a.partial, (int)grid, m, D, loss, stream);
 }

@@ -167,6 +167,19 @@ def test_backward_argument_validation_without_device(L):
     assert L.ls2_decode_feature_loss(10, 64, 512, V(16), V(16), V(16), V(16), None, None, V(16), 1 << 20,
                                      None) == -1
     assert L.ls2_decode_feature_loss(10, 64, 512, *fa, None, V(16), 8, None) == -1
+    # decode + loss + decode backward in one pass: unsupported L / D, null
+    # output, empty input, misalignment, small workspace
+    assert L.ls2_decode_loss_backward_workspace(1000, 64, 512, ctypes.byref(b)) == 0 and b.value >= 64 * 512 * 4
+    assert L.ls2_decode_loss_backward_workspace(1000, 128, 512, ctypes.byref(b)) == -3
+    assert L.ls2_decode_loss_backward_workspace(0, 64, 512, ctypes.byref(b)) == -1
+    la = [V(16)] * 6
+    assert L.ls2_decode_loss_backward(10, 128, 512, *la, V(16), 1 << 24, None) == -3
+    assert L.ls2_decode_loss_backward(10, 64, 1024, *la, V(16), 1 << 24, None) == -3
+    assert L.ls2_decode_loss_backward(10, 64, 64, *la, V(16), 1 << 24, None) == -3
+    assert L.ls2_decode_loss_backward(10, 64, 512, *la[:5], None, V(16), 1 << 24, None) == -1
+    assert L.ls2_decode_loss_backward(0, 64, 512, *la, V(16), 1 << 24, None) == -1
+    assert L.ls2_decode_loss_backward(10, 64, 512, V(4), *la[1:], V(16), 1 << 24, None) == -1
+    assert L.ls2_decode_loss_backward(10, 64, 512, *la, V(16), 64, None) == -1
     # feature loss: empty input, unsupported D, small workspace
     assert L.ls2_feature_loss_workspace(1000, ctypes.byref(b)) == 0 and b.value >= 16
     assert L.ls2_feature_loss(0, 512, V(16), V(16), V(16), None, V(16), 1 << 20, None) == -1

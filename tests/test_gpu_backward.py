@@ -239,6 +239,59 @@ def test_decode_feature_loss_fused(orc, m, L, D):
     assert np.abs(dF_f.cpu().numpy() - dF_ref).max() <= 1e-3 * np.abs(dF_ref).max()
 
 
+@pytest.mark.parametrize("m,L,D", [(3000, 64, 512), (100003, 64, 512), (1001, 32, 256), (40009, 64, 384),
+                                   (33, 64, 128), (1, 32, 512), (9001, 32, 128), (70001, 32, 512)])
+def test_decode_loss_backward_fused(orc, m, L, D):
+    """Decode + loss + both decode gradients in one pass equal the two-call
+    chain (ls2_decode_feature_loss, then ls2_dict_decode_backward on its
+    dL/dF) bit for bit, and the oracle's gradients of its own loss."""
+    import paper_2507_07136_amd as ls2
+    rng = np.random.default_rng(m + 3 * L + D)
+    coef = (rng.random((m, L)) * (rng.random((m, L)) < 0.3)).astype(np.float32)
+    dct = rng.standard_normal((L, D)).astype(np.float32)
+    dct /= np.linalg.norm(dct, axis=1, keepdims=True)
+    Y = (rng.standard_normal((m, D)) * 0.1).astype(np.float32)
+    if m > 2:
+        coef[1] = 0.0                        # zero feature: cosine guard
+    tc, td, tY = (torch.from_numpy(x).cuda() for x in (coef, dct, Y))
+    # the chain
+    loss_c = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    dF = torch.empty((m, D), device="cuda")
+    ws1 = torch.empty((ls2.ls2_decode_feature_loss_workspace(m, D),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_decode_feature_loss(tc, td, tY, loss_c, dF, ws1)
+    dc_c = torch.empty((m, L), device="cuda")
+    ds_c = torch.empty((L, D), device="cuda")
+    ws2 = torch.empty((ls2.ls2_dict_decode_backward_workspace(m, L, D),), dtype=torch.uint8, device="cuda")
+    ls2.ls2_dict_decode_backward(tc, td, dF, dc_c, ds_c, ws2)
+    # one pass, twice (deterministic)
+    ws = torch.empty((ls2.ls2_decode_loss_backward_workspace(m, L, D),), dtype=torch.uint8, device="cuda")
+    outs = []
+    for _ in range(2):
+        loss_f = torch.zeros((1,), dtype=torch.float64, device="cuda")
+        dc_f = torch.full((m, L), 7.0, device="cuda")
+        ds_f = torch.full((L, D), 7.0, device="cuda")
+        ls2.ls2_decode_loss_backward(tc, td, tY, loss_f, dc_f, ds_f, ws)
+        outs.append((loss_f, dc_f, ds_f))
+    torch.cuda.synchronize()
+    (loss_f, dc_f, ds_f), (loss_g, dc_g, ds_g) = outs
+    assert torch.equal(dc_f, dc_c)
+    assert torch.equal(ds_f, ds_c)
+    assert torch.equal(dc_f, dc_g) and torch.equal(ds_f, ds_g) and loss_f.item() == loss_g.item()
+    # the loss partials follow the workgroups: equal to the chain's where the
+    # two launch the same number (one per compute unit at D = 512), else a
+    # few float32 roundings of the compensated total apart
+    if D == 512:
+        assert loss_f.item() == loss_c.item()
+    else:
+        assert abs(loss_f.item() - loss_c.item()) <= 1e-6 * abs(loss_c.item())
+    loss_ref, dF_ref = orc.loss_l1cos(orc.decode(coef, dct), Y)
+    assert abs(loss_f.item() - loss_ref) <= 1e-5 * abs(loss_ref)
+    dc_ref, ds_ref = orc.decode_backward(coef, dct, dF_ref)
+    for got, ref in ((dc_f, dc_ref), (ds_f, ds_ref)):
+        g = got.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(g - ref) <= 1e-4 * np.linalg.norm(ref), (np.linalg.norm(g - ref), np.linalg.norm(ref))
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("m,D,n_neg,tau", [(5000, 512, 4, 1.0), (300, 128, 1, 10.0), (99, 1024, 8, 3.0)])
 def test_query_backward_parity(orc, dtype, m, D, n_neg, tau):
