@@ -197,10 +197,13 @@ def c4_oracle_errors(samples):
     return out
 
 
-def train_step_timing(args, torch, np, gen, ls2):
+def train_step_timing(args, torch, np, gen, ls2, onepass=True):
     """Forward + backward of the feature-map objective on the differentiation
-    workload (float32 throughout): project, bin_sort, splat, decode, loss,
-    then decode / splat / projection backward.  Per-stage HIP events."""
+    workload (float32 throughout): project, bin_sort, splat, then decode +
+    loss + decode backward in one pass (dL/dF kept on chip), splat and
+    projection backward; with onepass=False the decode + loss and the decode
+    backward run as two kernels with dL/dF through HBM.  Per-stage HIP
+    events."""
     cfg = gen.CONFIGS[args.train_config]
     scene, cam = gen.config_scene(args.train_config)
     zup, Pf = gen.make_target_factors(cfg["seed"] * 100, cfg["height"], cfg["width"], D=cfg["D"])
@@ -210,7 +213,9 @@ def train_step_timing(args, torch, np, gen, ls2):
     t = ls2.to_device(scene)
     tr = ls2.Trainer(cam, scene.n, levels=scene.levels, K=scene.K, L=scene.L, D=scene.D)
     tr.forward_loss(t, Y, sync=True)          # sizes the pair buffers
-    names = ["project", "bin_sort", "splat", "decode_loss", "decode_bw", "splat_bw", "project_bw"]
+    onepass = onepass and tr.fused_loss
+    names = ["project", "bin_sort", "splat"] + (["decode_loss_bw"] if onepass else ["decode_loss", "decode_bw"]) + [
+        "splat_bw", "project_bw"]
 
     def step(ev=None):
         def mark(i):
@@ -223,20 +228,26 @@ def train_step_timing(args, torch, np, gen, ls2):
         mark(2)
         tr.splat(t["opacity"], t["topk_idx"], t["topk_w"])
         mark(3)
-        tr.decode_loss(t["dictionary"], Y)      # float32 decode fused with the loss (F stays on chip)
-        mark(4)
         g = tr.grad
         m = tr.levels * tr.H * tr.W
-        ls2.ls2_dict_decode_backward(tr.coef.view(m, tr.L), t["dictionary"], tr.d_feat.view(m, tr.D),
-                                     g.coef.view(m, tr.L), g.dictionary, tr.dec_ws)
-        mark(5)
+        if onepass:
+            ls2.ls2_decode_loss_backward(tr.coef.view(m, tr.L), t["dictionary"], Y.view(m, tr.D), tr.loss,
+                                         g.coef.view(m, tr.L), g.dictionary, tr.onepass_ws)
+            k = 4
+        else:
+            tr.decode_loss(t["dictionary"], Y)      # float32 decode fused with the loss (F stays on chip)
+            mark(4)
+            ls2.ls2_dict_decode_backward(tr.coef.view(m, tr.L), t["dictionary"], tr.d_feat.view(m, tr.D),
+                                         g.coef.view(m, tr.L), g.dictionary, tr.dec_ws)
+            k = 5
+        mark(k)
         ls2.ls2_splat_sparse_backward(tr.cam, tr.levels, tr.K, tr.L, tr.tile_ranges, tr.ids, tr.mean2d, tr.conic,
                                       t["opacity"], t["topk_idx"], t["topk_w"], tr.final_T, tr.last, g.coef,
                                       g.mean2d, g.conic, g.opacity, g.topk_w)
-        mark(6)
+        mark(k + 1)
         ls2.ls2_project_backward(tr.cam, t["means"], t["scales"], t["quats"], tr.radius, g.mean2d, g.conic,
                                  g.means, g.scales, g.quats)
-        mark(7)
+        mark(k + 2)
 
     steps = max(5, args.steps // 2)
     for _ in range(3):
@@ -252,15 +263,19 @@ def train_step_timing(args, torch, np, gen, ls2):
            for i in range(len(names))}
     ms = 1000.0 * wall / steps
     m = scene.levels * cam.height * cam.width
-    dec_bw_flops = 4.0 * m * scene.L * scene.D
-    log("fwd+bwd: %.3f ms/step, stages %s, loss %.6f" % (ms, per, tr.loss.item()))
+    # matrix-core work of the decode stages: 2 m L D flops per product
+    stage, prods = ("decode_loss_bw", 3.0) if onepass else ("decode_bw", 2.0)
+    dec_flops = prods * 2.0 * m * scene.L * scene.D
+    tf = dec_flops / (per[stage] * 1e-3) / 1e12
+    log("fwd+bwd (%s): %.3f ms/step, stages %s, loss %.6f" % ("one pass" if onepass else "two pass", ms, per,
+                                                              tr.loss.item()))
     return dict(ms=ms, steps=steps, workload="%s: %d Gaussians, %dx%d, L=%d, K=%d, D=%d, L1+cosine loss vs a smooth "
                 "random 512-D target, float32" % (args.train_config, scene.n, cam.width, cam.height, scene.L,
                                                    scene.K, scene.D),
+                decode=("decode + loss + decode backward in one pass (dL/dF on chip)" if onepass else
+                        "decode + loss, then decode backward (dL/dF through HBM)"),
                 stages_ms=per, loss=tr.loss.item(),
-                decode_bw_tflops=round(dec_bw_flops / (per["decode_bw"] * 1e-3) / 1e12, 2),
-                decode_bw_frac_f32_peak=round(dec_bw_flops / (per["decode_bw"] * 1e-3) / 1e12 / F32_MFMA_PEAK_TFLOPS,
-                                              4))
+                **{stage + "_tflops": round(tf, 2), stage + "_frac_f32_peak": round(tf / F32_MFMA_PEAK_TFLOPS, 4)})
 
 
 def full_form(args, torch, np, gen, ls2, steps=2):
@@ -298,8 +313,7 @@ def full_form(args, torch, np, gen, ls2, steps=2):
             getattr(total, name).zero_()
         for j in range(8):
             tr.set_camera(cams[j])
-            tr.forward_loss(t, targets[j], sync=False)
-            tr.backward(t)
+            tr.step(t, targets[j], sync=False)   # one-pass decode + loss + decode backward
             tr.accumulate_into(total)
 
     step()
@@ -310,15 +324,14 @@ def full_form(args, torch, np, gen, ls2, steps=2):
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / steps
     # algorithmic HBM bytes of one step (per view: projection, lists, splat,
-    # fused decode + loss, decode / splat / projection backward)
+    # one-pass decode + loss + decode backward, splat / projection backward)
     n, L, K, M = scene.n, scene.L, scene.K, levels * H * W
     per_view = []
     for P in pairs:
         b = algorithmic_bytes("project", n, P, H, W, L, D, K, levels, 4)
         b += algorithmic_bytes("bin_sort", n, P, H, W, L, D, K, levels, 4)
         b += algorithmic_bytes("splat", n, P, H, W, L, D, K, levels, 4)
-        b += M * L * 4 + 2 * M * D * 4                      # decode + loss: W in, Y in, dL/dF out
-        b += 2 * M * D * 4 + 2 * M * L * 4                  # decode backward: G twice, W in, dW out
+        b += 2 * M * L * 4 + M * D * 4                      # decode + loss + decode backward: W in, Y in, dW out
         b += M * L * 4 + H * W * 8 + P * 4 + n * (8 + 12 + 4 + levels * K * 8) + n * levels * K * 4 + n * 24
         b += n * (40 + 20 + 40)                             # projection backward
         per_view.append(b)
@@ -744,6 +757,9 @@ def main():
         del pipe, pipe16
         torch.cuda.empty_cache()
         train = train_step_timing(args, torch, np, gen, ls2)
+        train_two_pass = train_step_timing(args, torch, np, gen, ls2, onepass=False)
+        train["two_pass_ms"] = round(train_two_pass["ms"], 4)
+        train["two_pass_stages_ms"] = train_two_pass["stages_ms"]
 
     ablation = None if args.no_ablation else dense_ablation(args, torch, np, gen, ls2)
     precision, prec_samples = (None, None) if args.no_precision else precision_form(args, torch, np, gen, ls2)

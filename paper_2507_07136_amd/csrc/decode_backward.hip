@@ -653,7 +653,7 @@ __global__ __launch_bounds__(512, 1) void k_decode_loss_bw(DecodeLossBwArgs a) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) *reinterpret_cast<f32x4l*>(tile + (4 * i + sp) * kLbRow + 4 * su) = yr[i];
         // the first dW A operands, in flight during the exchange
-        constexpr int SBA = 2;  // groups of four k-steps loaded ahead
+        constexpr int SBA = 4;  // groups of four k-steps loaded ahead
         float4 sbq[8][TL];
 #pragma unroll
         for (int j4 = 0; j4 < SBA; ++j4)

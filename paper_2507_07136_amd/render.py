@@ -242,6 +242,9 @@ class Trainer(Pipeline):
         if self.fused_loss:
             self.fused_ws = torch.empty((_lib.ls2_decode_feature_loss_workspace(m, D),), dtype=torch.uint8,
                                         device=dev)
+            # decode + loss + decode backward in one pass (step(): dL/dF stays on chip)
+            self.onepass_ws = torch.empty((_lib.ls2_decode_loss_backward_workspace(m, L, D),), dtype=torch.uint8,
+                                          device=dev)
         self.topk_idx = None   # codes formed from logits (codes())
         self.topk_w = None
         self.d_logits = None
@@ -303,6 +306,11 @@ class Trainer(Pipeline):
         G = (self.d_feat if d_feat is None else d_feat).view(m, self.D)
         _lib.ls2_dict_decode_backward(st.coef.view(m, self.L), scene["dictionary"], G, g.coef.view(m, self.L),
                                       g.dictionary, self.dec_ws)
+        return self._backward_render(scene, st)
+
+    def _backward_render(self, scene, st):
+        """splat, projection (and code) backward from g.coef = dL/dcoef."""
+        g = self.grad
         _lib.ls2_splat_sparse_backward(st.cam, self.levels, self.K, self.L, st.tile_ranges, st.ids,
                                        st.mean2d, st.conic, scene["opacity"], scene["topk_idx"],
                                        scene["topk_w"], st.final_T, st.last, g.coef, g.mean2d, g.conic,
@@ -329,8 +337,23 @@ class Trainer(Pipeline):
             _lib.ls2_accumulate(getattr(self.grad, name), getattr(total, name))
 
     def step(self, scene, target, sync=True):
-        loss = self.forward_loss(scene, target, sync=sync)
-        return loss, self.backward(scene)
+        """One training step: the loss and every gradient (into ``self.grad``).
+        Where the one-pass kernel exists (L <= 64, D <= 512) the decode, the
+        loss and the decode gradients are formed together and dL/dF is not
+        materialised (``self.d_feat`` is then not updated)."""
+        if not self.fused_loss:
+            loss = self.forward_loss(scene, target, sync=sync)
+            return loss, self.backward(scene)
+        if "logits" in scene:
+            scene["topk_idx"], scene["topk_w"] = self.codes(scene["logits"])
+        self.project(scene["means"], scene["scales"], scene["quats"])
+        self.bin_sort(sync=sync)
+        self.splat(scene["opacity"], scene["topk_idx"], scene["topk_w"])
+        m = self.levels * self.H * self.W
+        g = self.grad
+        _lib.ls2_decode_loss_backward(self.coef.view(m, self.L), scene["dictionary"], target.view(m, self.D),
+                                      self.loss, g.coef.view(m, self.L), g.dictionary, self.onepass_ws)
+        return self.loss, self._backward_render(scene, self.state())
 
 
 def _render_forward(ctx, trainer, scene):

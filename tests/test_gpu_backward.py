@@ -565,3 +565,32 @@ def test_autograd_logits_chain(orc):
     _grad_close(tl.grad.cpu().numpy().reshape(scene.n, scene.L), d_logits, "d_logits", floor=CHAIN_FLOOR)
     for name in ["means", "scales", "quats", "opacity", "dictionary"]:
         _grad_close(params[name].grad.cpu().numpy(), ref[name], "d_" + name, floor=CHAIN_FLOOR)
+
+
+@pytest.mark.parametrize("levels,D", [(1, 512), (2, 256)])
+def test_trainer_step_one_pass(levels, D):
+    """Trainer.step (decode + loss + decode backward in one pass) against
+    Trainer.forward_loss + backward (dL/dF through memory): the decode
+    gradients bit for bit, the loss bit for bit where both launch the same
+    workgroups (D = 512) and the rest of the chain, whose float atomics may
+    add in another order, to float32 rounding."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(21 + levels, 3000, 200, 136, levels=levels, D=D)
+    rng = np.random.default_rng(5)
+    tY = torch.from_numpy((rng.standard_normal((levels, cam.height, cam.width, D)) * 0.1).astype(np.float32)).cuda()
+    t = ls2.to_device(scene)
+    tr = ls2.Trainer(cam, scene.n, levels=levels, D=D)
+    loss_a = tr.forward_loss(t, tY).clone()
+    ga = {k: getattr(tr.backward(t), k).clone() for k in ("coef", "dictionary", "means", "scales", "quats",
+                                                          "opacity", "topk_w")}
+    loss_b, gb = tr.step(t, tY)
+    torch.cuda.synchronize()
+    assert torch.equal(gb.coef, ga["coef"])
+    assert torch.equal(gb.dictionary, ga["dictionary"])
+    if D == 512:
+        assert loss_b.item() == loss_a.item()
+    else:
+        assert abs(loss_b.item() - loss_a.item()) <= 1e-6 * abs(loss_a.item())
+    for k in ("means", "scales", "quats", "opacity", "topk_w"):
+        a, b = ga[k].double(), getattr(gb, k).double()
+        assert torch.linalg.norm(a - b).item() <= 1e-5 * torch.linalg.norm(a).item() + 1e-30, k
