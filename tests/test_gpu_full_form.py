@@ -21,6 +21,8 @@ parity tests (each stage consumes the GPU's own float32 upstream state):
     so a row's gradient is the oracle's gradient over the sampled rows times
     n_sampled / M) within 1e-5 of the row's max|dL/dF|, elements whose residual F - Y
     is within 1e-5 of zero (the sign of the L1 term may flip) excluded;
+  - the training step's one-pass decode + loss + decode backward against
+    the two-call chain on the whole map: bit for bit;
   - decode backward with dL/dF zero outside 2000 sampled rows: d_dict over
     the whole map against the oracle's over those rows, |dg| <= 1e-5 |A||B|;
     the sampled rows' d_coef likewise; every other row exactly zero;
@@ -157,6 +159,30 @@ def test_full_form_decode_loss_sampled(orc, c5):
           "sign flip)" % (err.max(), np.abs(ref).max(), int(flip.sum())))
     assert err.max() <= 1e-5
     assert np.isfinite(tr.loss.item()) and tr.loss.item() > 0
+
+
+def test_full_form_one_pass_loss_backward(c5):
+    """The training step's one-pass decode + loss + decode backward at full
+    size (3.2e9 feature elements, past 2^31) equals the two-call chain bit for
+    bit: d_coef, d_dict and, with one workgroup per compute unit in both, the
+    loss."""
+    import paper_2507_07136_amd as ls2
+    scene, cam, tr, t, Y, g = c5
+    M, L, D = scene.levels * cam.height * cam.width, scene.L, scene.D
+    loss_c = tr.decode_loss(t["dictionary"], Y).clone()
+    dc_c = torch.empty((M, L), device="cuda")
+    ds_c = torch.empty((L, D), device="cuda")
+    ls2.ls2_dict_decode_backward(tr.coef.view(M, L), t["dictionary"], tr.d_feat.view(M, D), dc_c, ds_c, tr.dec_ws)
+    loss_f = torch.zeros((1,), dtype=torch.float64, device="cuda")
+    dc_f = torch.empty((M, L), device="cuda")
+    ds_f = torch.empty((L, D), device="cuda")
+    ls2.ls2_decode_loss_backward(tr.coef.view(M, L), t["dictionary"], Y.view(M, D), loss_f, dc_f, ds_f,
+                                 tr.onepass_ws)
+    torch.cuda.synchronize()
+    assert torch.equal(dc_f, dc_c)
+    assert torch.equal(ds_f, ds_c)
+    assert loss_f.item() == loss_c.item()
+    del dc_c, dc_f
 
 
 def test_full_form_decode_backward_sparse_upstream(orc, c5):
