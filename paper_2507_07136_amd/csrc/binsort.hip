@@ -13,14 +13,16 @@
 //                   tiles inside that superblock, aggregated per workgroup in
 //                   LDS histograms (one global atomic per workgroup and
 //                   superblock); also the exact pair count P;
-//   2. k_sb_scan  : one workgroup: superblock bucket offsets and list
-//                   offsets, the overflow decision, and the processing order;
-//   3. k_sb_emit  : per Gaussian, the 64-bit key (depth bits << 32 | id) into
-//                   each touched superblock's bucket (LDS histogram again, one
-//                   reserving atomic per workgroup and superblock, LDS cursors);
-//   4. k_sb_sort  : one workgroup per superblock sorts its bucket in LDS
-//                   (keys binned over the bucket's depth range, each short
-//                   bin sorted by insertion, long bins by a bitonic network;
+//   2. k_sb_emit  : every workgroup first scans the superblock entry counts
+//                   into bucket offsets (in LDS; the first workgroup also
+//                   writes the list offsets, the overflow decision and the
+//                   processing order for pass 3), then puts each Gaussian's
+//                   64-bit key (depth bits << 32 | id) into each touched
+//                   superblock's bucket (LDS histogram again, one reserving
+//                   atomic per workgroup and superblock, LDS cursors);
+//   3. k_sb_sort  : one workgroup per superblock sorts its bucket in LDS
+//                   (keys binned over the bucket's depth range, each key of
+//                   a short bin placed by its rank, long bins by a bitonic network;
 //                   buckets beyond the LDS capacity are first split into 256
 //                   bins over their depth range, and runs of bins are sorted
 //                   in LDS; only a single over-full bin falls back to a
@@ -65,10 +67,10 @@ inline Geo geo(const CamK& k) {
 }
 
 struct Layout {
-    size_t meta, sb_count, sb_pairs, sb_start, sb_pstart, sb_cursor, sb_order, rect, pool, cov, total;
+    size_t meta, sb_count, sb_pairs, sb_cursor, sb_start, sb_pstart, sb_order, rect, pool, cov, total;
 };
 
-// meta, sb_count and sb_pairs come first: they are zeroed every call.
+// meta, sb_count, sb_pairs and sb_cursor come first: they are zeroed every call.
 inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     const Geo g = geo(k);
     Layout l;
@@ -76,9 +78,9 @@ inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
     l.meta = off; off = align_up(off + sizeof(Meta));
     l.sb_count = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_pairs = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
+    l.sb_cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_start = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_pstart = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
-    l.sb_cursor = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.sb_order = off; off = align_up(off + sizeof(unsigned) * (size_t)g.nsb);
     l.rect = off; off = align_up(off + sizeof(ushort4) * (size_t)(n > 0 ? n : 1));
     l.pool = off; off = align_up(off + sizeof(unsigned long long) * (size_t)(max_pairs > 0 ? max_pairs : 1));
@@ -101,7 +103,7 @@ struct BinArgs {
     unsigned* sb_pairs;   // (tile, Gaussian) pairs inside each superblock
     unsigned* sb_start;   // bucket offset of each superblock in the pool
     unsigned* sb_pstart;  // first list position of each superblock's tiles
-    unsigned* sb_cursor;
+    unsigned* sb_cursor;  // entries reserved so far in each bucket
     unsigned* sb_order;  // superblocks by decreasing bucket size (size classes)
     ushort4* rect;
     unsigned long long* pool;
@@ -239,15 +241,16 @@ __device__ __forceinline__ int size_class(unsigned c) {
     return c < 8192u ? (int)(c >> 8) : 32 + (int)min(31u, (c - 8192u) >> 10);
 }
 
-__global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
+// The sort kernel's inputs, written by the emission pass's first workgroup
+// (every workgroup of that pass forms the bucket offsets itself, in LDS):
+// bucket and list offsets in global memory, the totals and the overflow
+// decision, and the processing order.
+__device__ void sort_plan(const BinArgs& a, const unsigned* start, long long total, long long P, bool over) {
     __shared__ unsigned cls[64];
-    const long long total = block_scan(a.sb_count, a.sb_start, 1, nullptr, a.nsb);
+    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) a.sb_start[s] = start[s];
     // P is exact in 64 bits; the per-superblock pair counts are exact whenever
     // P fits the lists, which is the only case in which their offsets are used
-    const long long P = (long long)a.meta->P_rect;
-    const bool over = P > a.max_pairs;  // sb_total <= P: covers the pool too
     block_scan(a.sb_pairs, a.sb_pstart, 1, nullptr, a.nsb);
-    for (int s = threadIdx.x; s < a.nsb; s += blockDim.x) a.sb_cursor[s] = a.sb_start[s];
     if (threadIdx.x == 0) {
         a.meta->sb_total = total;
         a.meta->sb_overflow = total > a.max_pairs ? 1 : 0;
@@ -276,6 +279,7 @@ __global__ __launch_bounds__(1024) void k_sb_scan(BinArgs a) {
 
 __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
+    __shared__ unsigned start[kMaxSB];
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
     const int sh = __builtin_ctz((unsigned)a.S);
     // every global read at once: the tile rectangles stored by the count pass
@@ -288,7 +292,12 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
         r[q] = i < a.n ? a.rect[i] : make_ushort4(0xffff, 0xffff, 0, 0);
         dep[q] = i < a.n ? a.depth[i] : 0.0f;
     }
-    const bool over = a.meta->overflow != 0;
+    // the bucket offsets: an exclusive scan of the entry counts, in every
+    // workgroup (the counts are complete: the count pass has finished)
+    const long long total = block_scan(a.sb_count, start, 1, nullptr, a.nsb);
+    const long long P = (long long)a.meta->P_rect;
+    const bool over = P > a.max_pairs;  // sb_total <= P: covers the pool too
+    if (blockIdx.x == 0) sort_plan(a, start, total, P, over);
     for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) hist[s] = 0u;
     __syncthreads();
     if (over) return;  // the lists will not be filled (the same decision in every thread)
@@ -300,7 +309,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
     __syncthreads();
     // reserve this workgroup's range in every touched bucket; hist becomes the cursor
     for (int s = threadIdx.x; s < a.nsb; s += kBinThreads)
-        if (hist[s]) hist[s] = atomicAdd(&a.sb_cursor[s], hist[s]);
+        if (hist[s]) hist[s] = start[s] + atomicAdd(&a.sb_cursor[s], hist[s]);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
@@ -1058,7 +1067,7 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.ranges = tile_ranges;
     a.ids = ids;
     a.keys = reinterpret_cast<unsigned long long*>(keys);
-    // zero meta and the superblock entry and pair counts (contiguous)
+    // zero meta, the superblock entry and pair counts and the cursors (contiguous)
     const long long zw = (long long)((lay.sb_start - lay.meta) / sizeof(unsigned));
     const long long zb = (zw + 255) / 256;
     hipLaunchKernelGGL(k_bin_zero, dim3((unsigned)(zb < 1024 ? zb : 1024)), dim3(256), 0, stream,
@@ -1070,12 +1079,9 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
         hipLaunchKernelGGL(k_sb_count, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_sb_scan, dim3(1), dim3(1024), 0, stream, a);
+    // the emission also writes the sort kernel's plan: it runs even with no Gaussians
+    hipLaunchKernelGGL(k_sb_emit, dim3(gblocks > 0 ? gblocks : 1), dim3(kBinThreads), 0, stream, a);
     LS2_LAUNCH_CHECK();
-    if (n > 0 && max_pairs > 0) {
-        hipLaunchKernelGGL(k_sb_emit, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
-        LS2_LAUNCH_CHECK();
-    }
     // every superblock writes its tiles' ranges (empty ones included)
     hipLaunchKernelGGL(k_sb_sort, dim3(g.nsb), dim3(kSortWaves * 64), 0, stream, a);
     LS2_LAUNCH_CHECK();
