@@ -582,34 +582,41 @@ def main():
     log("P =", P, "pairs")
 
     def frame(p_, compute, out_dtype, ev=None, query=False, fused=False, one_pass=False, keep_feat=True,
-              sync=False):
-        def mark(i):
+              sync=False, pb=False):
+        k = [0]
+
+        def mark():
             if ev is not None:
-                ev[i].record()
-        mark(0)
-        p_.project(t["means"], t["scales"], t["quats"])
-        mark(1)
-        p_.bin_sort(sync=sync)  # sync: the pair count is read back to the host (one round trip)
-        mark(2)
+                ev[k[0]].record()
+            k[0] += 1
+        mark()
+        if pb:  # projection and binning in one call (the binning's first pass projects)
+            p_.project_bin_sort(t["means"], t["scales"], t["quats"], sync=sync)
+            mark()
+        else:
+            p_.project(t["means"], t["scales"], t["quats"])
+            mark()
+            p_.bin_sort(sync=sync)  # sync: the pair count is read back to the host (one round trip)
+            mark()
         if one_pass:  # splat and bf16 decode in one kernel: the coefficient map stays on chip
             if query:  # and the relevancy formed in the same pass
                 p_.splat_decode_query(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"], post, negt,
                                       keep_feat=keep_feat)
             else:
                 p_.splat_decode(t["opacity"], t["topk_idx"], t["topk_w"], t["dictionary"])
-            mark(3)
+            mark()
             return
         p_.splat(t["opacity"], t["topk_idx"], t["topk_w"])
-        mark(3)
+        mark()
         if fused:  # bf16 decode with the relevancy formed in its epilogue
             p_.decode_query(t["dictionary"], post, negt)
-            mark(4)
+            mark()
             return
         p_.decode(t["dictionary"], compute, out_dtype)
-        mark(4)
+        mark()
         if query:
             p_.query(post, negt)
-            mark(5)
+            mark()
 
     stages = ["project", "bin_sort", "splat", "decode", "query"]
 
@@ -617,8 +624,9 @@ def main():
             sync=False):
         """Wall-clock rate over `steps` uninstrumented frames, then the same
         number of frames with HIP events between the stages (per-stage
-        times; these frames are not part of the rate)."""
-        kw = dict(query=query, fused=fused, one_pass=one_pass, keep_feat=keep_feat, sync=sync)
+        times; these frames are not part of the rate).  One-pass frames
+        project and bin in one call (ls2_project_bin_sort)."""
+        kw = dict(query=query, fused=fused, one_pass=one_pass, keep_feat=keep_feat, sync=sync, pb=one_pass)
         for _ in range(warmup):
             frame(p_, compute, out_dtype, **kw)
         torch.cuda.synchronize()
@@ -631,7 +639,7 @@ def main():
         for s in range(steps):
             frame(p_, compute, out_dtype, evs[s], **kw)
         torch.cuda.synchronize()
-        names = (["project", "bin_sort", "splat_decode_query" if query else "splat_decode"] if one_pass
+        names = (["project_bin_sort", "splat_decode_query" if query else "splat_decode"] if one_pass
                  else stages[:5 if (query and not fused) else 4])
         per = {names[i]: float(np.mean([evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(steps)]))
                for i in range(len(names))}

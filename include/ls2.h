@@ -135,8 +135,25 @@ int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2d, const in
                  const float* depth, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
                  uint32_t* tile_ranges, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
                  hipStream_t stream);
-/* P of the last ls2_bin_sort that used this workspace (synchronises stream). */
+/* P of the last ls2_bin_sort (or ls2_project_bin_sort) that used this
+ * workspace (synchronises stream). */
 int ls2_bin_sort_count(const void* workspace, int64_t* num_pairs, hipStream_t stream);
+
+/*
+ * ls2_project_bin_sort -- ls2_project followed by ls2_bin_sort (Section 3.1,
+ * Eqs. 1-2, then the depth-ordered tile lists of Eq. 3) with one launch fewer:
+ * the binning's first pass projects each Gaussian itself, with the same
+ * instructions as ls2_project, writes the projection's outputs and takes the
+ * tile rectangle from the results in registers.  Every output equals that of
+ * the two calls bit for bit.  Arguments as in ls2_project (mean2d, conic,
+ * depth, radius out; tiles_touched optional) and ls2_bin_sort (the same
+ * workspace, from ls2_bin_sort_workspace).
+ */
+int ls2_project_bin_sort(const ls2_camera* cam, int32_t n, const float* means, const float* scales,
+                         const float* quats, float* mean2d, float* conic, float* depth, int32_t* radius,
+                         int32_t* tiles_touched, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
+                         uint32_t* tile_ranges, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream);
 
 /*
  * ls2_splat_sparse -- efficient sparse coefficient splatting.

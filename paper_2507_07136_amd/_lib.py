@@ -54,6 +54,8 @@ def _load():
         "ls2_bin_sort": ([cam, i32, P, P, P, i64, P, P, P, ctypes.POINTER(ctypes.c_int64), P, ctypes.c_size_t, P],
                          ctypes.c_int),
         "ls2_bin_sort_count": ([P, ctypes.POINTER(ctypes.c_int64), P], ctypes.c_int),
+        "ls2_project_bin_sort": ([cam, i32] + [P] * 8 + [i64, P, P, P, ctypes.POINTER(ctypes.c_int64), P,
+                                                       ctypes.c_size_t, P], ctypes.c_int),
         "ls2_splat_sparse": ([cam, i32, i32, i32, i32, P, P, P, P, P, P, P, P, i32, P, P, P], ctypes.c_int),
         "ls2_splat_decode_workspace": ([i32, i32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ls2_splat_decode": ([cam, i32, i32, i32, i32, i32] + [P] * 13 + [ctypes.c_size_t, P], ctypes.c_int),
@@ -209,6 +211,31 @@ def ls2_bin_sort(cam, mean2d, radius, depth, max_pairs, keys, ids, tile_ranges, 
         err.num_pairs = int(P.value)
         raise err
     _check("ls2_bin_sort", st)
+    return int(P.value) if sync else None
+
+
+def ls2_project_bin_sort(cam, means, scales, quats, mean2d, conic, depth, radius, max_pairs, keys, ids, tile_ranges,
+                         workspace, tiles_touched=None, sync=True, stream=None):
+    """ls2_project then ls2_bin_sort in one call (one launch fewer); returns
+    P if sync, else None, as ls2_bin_sort."""
+    n = means.shape[0]
+    c = make_camera(cam) if not isinstance(cam, ls2_camera) else cam
+    f32, i32 = torch.float32, torch.int32
+    P = ctypes.c_int64(-1)
+    ntiles = ((c.width + TILE - 1) // TILE) * ((c.height + TILE - 1) // TILE)
+    st = _lib.ls2_project_bin_sort(
+        ctypes.byref(c), n, _ptr(means, f32, "means", 3 * n), _ptr(scales, f32, "scales", 3 * n),
+        _ptr(quats, f32, "quats", 4 * n), _ptr(mean2d, f32, "mean2d", 2 * n), _ptr(conic, f32, "conic", 3 * n),
+        _ptr(depth, f32, "depth", n), _ptr(radius, i32, "radius", n),
+        _ptr(tiles_touched, i32, "tiles_touched", n, allow_none=True), int(max_pairs),
+        _ptr(keys, torch.int64, "keys", int(max_pairs), allow_none=True), _ptr(ids, i32, "ids", int(max_pairs)),
+        _ptr(tile_ranges, i32, "tile_ranges", 2 * ntiles), ctypes.byref(P) if sync else None,
+        _ptr(workspace, torch.uint8, "workspace"), workspace.numel(), _stream(stream))
+    if st == LS2_ERR_CAPACITY:
+        err = LS2Error("ls2_project_bin_sort", st)
+        err.num_pairs = int(P.value)
+        raise err
+    _check("ls2_project_bin_sort", st)
     return int(P.value) if sync else None
 
 

@@ -31,7 +31,7 @@
 //                   subsequence of the sorted bucket whose rectangles cover
 //                   the tile, an order-preserving ballot compaction, so every
 //                   list comes out already in (depth, id) order.
-#include "ls2_internal.h"
+#include "project_common.h"
 
 namespace ls2 {
 
@@ -91,6 +91,19 @@ inline Layout layout(const CamK& k, int n, int64_t max_pairs) {
 
 }  // namespace
 
+// The projection's inputs and outputs when the count pass also projects
+// (ls2_project_bin_sort); means is null otherwise.
+struct ProjIO {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    float* mean2d;
+    float* conic;
+    float* depth;
+    int* radius;
+    int* touched;
+};
+
 struct BinArgs {
     CamK cam;
     int n, S, sbx, nsb;
@@ -111,6 +124,7 @@ struct BinArgs {
     unsigned* ranges;
     unsigned* ids;
     unsigned long long* keys;
+    ProjIO pj;
 };
 
 // Orders this wave's earlier shared/global writes before its later reads.
@@ -136,6 +150,10 @@ __device__ __forceinline__ bool gauss_rect(const BinArgs& a, int r, float2 m, in
 constexpr int kBinThreads = 1024;
 constexpr int kBinPerThread = 2;  // Gaussians per thread in the histogram passes (147 workgroups at 300k)
 
+// PROJ: each Gaussian is projected here first (the same instructions as
+// ls2_project, whose outputs are written too) and its rectangle taken from
+// the results in registers.
+template <bool PROJ>
 __global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
     __shared__ unsigned area[kMaxSB];
@@ -146,14 +164,29 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_count(BinArgs a) {
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
     const int S = a.S;
     const int sh = __builtin_ctz((unsigned)S);
-    // every global read at once (the mean is read whatever the radius)
     int rad[kBinPerThread];
     float2 mean[kBinPerThread];
+    if constexpr (PROJ) {
 #pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int i = base + q * kBinThreads + threadIdx.x;
-        rad[q] = i < a.n ? a.radius[i] : 0;
-        mean[q] = i < a.n ? reinterpret_cast<const float2*>(a.mean2d)[i] : make_float2(0.f, 0.f);
+        for (int q = 0; q < kBinPerThread; ++q) {
+            const int i = base + q * kBinThreads + threadIdx.x;
+            rad[q] = 0;
+            mean[q] = make_float2(0.f, 0.f);
+            if (i < a.n) {
+                const ProjOut o = project_one(a.cam, a.pj.means, a.pj.scales, a.pj.quats, i);
+                store_proj(o, i, a.pj.mean2d, a.pj.conic, a.pj.depth, a.pj.radius, a.pj.touched);
+                rad[q] = o.r;
+                mean[q] = make_float2(o.u, o.v);
+            }
+        }
+    } else {
+        // every global read at once (the mean is read whatever the radius)
+#pragma unroll
+        for (int q = 0; q < kBinPerThread; ++q) {
+            const int i = base + q * kBinThreads + threadIdx.x;
+            rad[q] = i < a.n ? a.radius[i] : 0;
+            mean[q] = i < a.n ? reinterpret_cast<const float2*>(a.mean2d)[i] : make_float2(0.f, 0.f);
+        }
     }
     unsigned long long my_area = 0;
 #pragma unroll
@@ -1030,10 +1063,10 @@ extern "C" int ls2_bin_sort_workspace(const ls2_camera* cam, int32_t n, int64_t 
     return LS2_OK;
 }
 
-extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2d, const int32_t* radius,
-                            const float* depth, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
-                            uint32_t* tile_ranges, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
-                            hipStream_t stream) {
+static int bin_sort_impl(const ls2_camera* cam, int32_t n, const float* mean2d, const int32_t* radius,
+                         const float* depth, const ProjIO& pj, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
+                         uint32_t* tile_ranges, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
     if (!cam_valid(cam) || n < 0 || max_pairs < 0 || !tile_ranges || !workspace) return LS2_ERR_ARG;
     if (n > 0 && (!mean2d || !radius || !depth)) return LS2_ERR_ARG;
     if (max_pairs > 0 && !ids) return LS2_ERR_ARG;
@@ -1067,6 +1100,7 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     a.ranges = tile_ranges;
     a.ids = ids;
     a.keys = reinterpret_cast<unsigned long long*>(keys);
+    a.pj = pj;
     // zero meta, the superblock entry and pair counts and the cursors (contiguous)
     const long long zw = (long long)((lay.sb_start - lay.meta) / sizeof(unsigned));
     const long long zb = (zw + 255) / 256;
@@ -1076,7 +1110,10 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
     const int per_block = kBinThreads * kBinPerThread;
     const int gblocks = (n + per_block - 1) / per_block;
     if (n > 0) {
-        hipLaunchKernelGGL(k_sb_count, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
+        if (pj.means)
+            hipLaunchKernelGGL(k_sb_count<true>, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_sb_count<false>, dim3(gblocks), dim3(kBinThreads), 0, stream, a);
         LS2_LAUNCH_CHECK();
     }
     // the emission also writes the sort kernel's plan: it runs even with no Gaussians
@@ -1094,6 +1131,27 @@ extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2
         if (h.overflow) return LS2_ERR_CAPACITY;
     }
     return LS2_OK;
+}
+
+extern "C" int ls2_bin_sort(const ls2_camera* cam, int32_t n, const float* mean2d, const int32_t* radius,
+                            const float* depth, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
+                            uint32_t* tile_ranges, int64_t* num_pairs, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+    const ProjIO none{};
+    return bin_sort_impl(cam, n, mean2d, radius, depth, none, max_pairs, keys, ids, tile_ranges, num_pairs,
+                         workspace, workspace_bytes, stream);
+}
+
+extern "C" int ls2_project_bin_sort(const ls2_camera* cam, int32_t n, const float* means, const float* scales,
+                                    const float* quats, float* mean2d, float* conic, float* depth, int32_t* radius,
+                                    int32_t* tiles_touched, int64_t max_pairs, uint64_t* keys, uint32_t* ids,
+                                    uint32_t* tile_ranges, int64_t* num_pairs, void* workspace,
+                                    size_t workspace_bytes, hipStream_t stream) {
+    if (n > 0 && (!means || !scales || !quats || !conic)) return LS2_ERR_ARG;
+    ProjIO pj{};
+    if (n > 0) pj = ProjIO{means, scales, quats, mean2d, conic, depth, radius, tiles_touched};
+    return bin_sort_impl(cam, n, mean2d, radius, depth, pj, max_pairs, keys, ids, tile_ranges, num_pairs,
+                         workspace, workspace_bytes, stream);
 }
 
 extern "C" int ls2_bin_sort_count(const void* workspace, int64_t* num_pairs, hipStream_t stream) {

@@ -76,6 +76,22 @@ class Pipeline:
                     raise
                 self._alloc_pairs(int(e.num_pairs * 1.25) + 1024)
 
+    def project_bin_sort(self, means, scales, quats, sync: bool = True):
+        """project() then bin_sort() in one call (the binning's first pass
+        projects; the same outputs bit for bit, one launch fewer)."""
+        while True:
+            try:
+                P = _lib.ls2_project_bin_sort(self.cam, means, scales, quats, self.mean2d, self.conic, self.depth,
+                                              self.radius, self.max_pairs, self.keys, self.ids, self.tile_ranges,
+                                              self.workspace, tiles_touched=self.tiles_touched, sync=sync)
+                if sync:
+                    self.num_pairs = P
+                return P
+            except LS2Error as e:
+                if e.status != _lib.LS2_ERR_CAPACITY:
+                    raise
+                self._alloc_pairs(int(e.num_pairs * 1.25) + 1024)
+
     def splat(self, opacity, topk_idx, topk_w):
         _lib.ls2_splat_sparse(self.cam, self.levels, self.K, self.L, self.tile_ranges, self.ids, self.mean2d,
                               self.conic, opacity, topk_idx, topk_w, self.coef, self.final_T, self.last)

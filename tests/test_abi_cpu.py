@@ -123,6 +123,18 @@ def test_bin_sort_workspace_and_validation(L):
                           V(257), b.value, None) == -1
     assert L.ls2_bin_sort(ctypes.byref(c), 10, V(256), V(256), V(256), 1000, None, V(256), V(256), ctypes.byref(P),
                           V(256), 16, None) == -1
+    # the projecting form: missing projection inputs, then the same workspace checks
+    pb = [V(256)] * 8
+    assert L.ls2_project_bin_sort(ctypes.byref(c), 10, None, *pb[1:], 1000, None, V(256), V(256), ctypes.byref(P),
+                                  V(256), b.value, None) == -1
+    assert L.ls2_project_bin_sort(ctypes.byref(c), 10, *pb[:6], None, V(256), 1000, None, V(256), V(256),
+                                  ctypes.byref(P), V(256), b.value, None) == -1
+    assert L.ls2_project_bin_sort(ctypes.byref(c), 10, *pb, 1000, None, V(256), V(256), ctypes.byref(P),
+                                  V(257), b.value, None) == -1
+    assert L.ls2_project_bin_sort(ctypes.byref(c), 10, *pb, 1000, None, V(256), V(256), ctypes.byref(P),
+                                  V(256), 16, None) == -1
+    assert L.ls2_project_bin_sort(None, 10, *pb, 1000, None, V(256), V(256), ctypes.byref(P), V(256), b.value,
+                                  None) == -1
 
 
 def test_backward_argument_validation_without_device(L):

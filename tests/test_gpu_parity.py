@@ -751,3 +751,69 @@ def test_large_image_superblock_geometry(orc):
     gT = pipe.final_T.reshape(-1).index_select(0, sel).cpu().numpy()
     gl = pipe.last.reshape(-1).index_select(0, sel).cpu().numpy()
     flip_check_gpu_lists(orc, cam, scene, g, coef_close(gc, gT, gl, ATOL), pix=pix, label="4160x4160 sampled")
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "ragged", "culled", "empty", "overflow", "large_image"])
+def test_project_bin_sort_fused(orc, case):
+    """ls2_project_bin_sort (the binning's first pass projects) equals
+    ls2_project followed by ls2_bin_sort bit for bit: every projection output,
+    P, the keys, ids and tile ranges, the overflow path included; and its
+    lists equal the oracle's."""
+    import paper_2507_07136_amd as ls2
+    max_pairs = None
+    if case in ("c1", "c2"):
+        scene, cam = gen.config_scene(case)
+    elif case == "ragged":
+        scene, cam = small_scene(31, 4000, 203, 117)
+    elif case == "culled":
+        scene, cam = small_scene(32, 3000, 160, 96)
+        scene.means[:500, 2] = -5.0
+        scene.means[500:700, 0] = np.nan
+    elif case == "empty":
+        scene, cam = small_scene(33, 0, 64, 48)
+    elif case == "overflow":
+        scene, cam = gen.config_scene("c1")
+        max_pairs = 100
+    else:  # beyond 4096 superblocks of 4x4 tiles: 8x8-tile superblocks
+        scene, cam = small_scene(34, 2000, 4200, 4200)
+    t = ls2.to_device(scene)
+    pa = ls2.Pipeline(cam, scene.n, keep_keys=True, max_pairs=max_pairs)
+    pb = ls2.Pipeline(cam, scene.n, keep_keys=True, max_pairs=max_pairs)
+    for p_ in (pa, pb):  # garbage in every output, so nothing unwritten passes
+        for buf in (p_.mean2d, p_.conic, p_.depth):
+            buf.fill_(-7.0)
+        for buf in (p_.radius, p_.tiles_touched, p_.ids, p_.tile_ranges, p_.keys):
+            buf.fill_(-7)
+    pa.project(t["means"], t["scales"], t["quats"])
+    if case == "overflow":
+        Pa = ls2.ls2_bin_sort(pa.cam, pa.mean2d, pa.radius, pa.depth, 100, pa.keys, pa.ids, pa.tile_ranges,
+                              pa.workspace, sync=False)
+        Pb = ls2.ls2_project_bin_sort(pb.cam, t["means"], t["scales"], t["quats"], pb.mean2d, pb.conic, pb.depth,
+                                      pb.radius, 100, pb.keys, pb.ids, pb.tile_ranges, pb.workspace,
+                                      tiles_touched=pb.tiles_touched, sync=False)
+        with pytest.raises(ls2.LS2Error) as e:
+            ls2.ls2_project_bin_sort(pb.cam, t["means"], t["scales"], t["quats"], pb.mean2d, pb.conic, pb.depth,
+                                     pb.radius, 100, pb.keys, pb.ids, pb.tile_ranges, pb.workspace,
+                                     tiles_touched=pb.tiles_touched, sync=True)
+        assert e.value.status == ls2.LS2_ERR_CAPACITY
+        Pa = Pb = ls2.ls2_bin_sort_count(pa.workspace)
+        assert ls2.ls2_bin_sort_count(pb.workspace) == Pa == e.value.num_pairs > 100
+    else:
+        Pa = pa.bin_sort(sync=True)
+        Pb = pb.project_bin_sort(t["means"], t["scales"], t["quats"], sync=True)
+    torch.cuda.synchronize()
+    assert Pa == Pb
+    for name in ("mean2d", "conic", "depth", "radius", "tiles_touched", "tile_ranges"):
+        a, b = getattr(pa, name), getattr(pb, name)
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32)), name   # bits, NaN-safe
+    if case != "overflow":
+        assert torch.equal(pa.ids[:Pa], pb.ids[:Pb]) and torch.equal(pa.keys[:Pa], pb.keys[:Pb])
+    else:
+        assert int(pb.tile_ranges.abs().sum().item()) == 0
+    if case in ("c1", "ragged", "culled", "large_image"):
+        g = dict(P=Pb, mean2d=pb.mean2d.cpu().numpy(), radius=pb.radius.cpu().numpy(),
+                 depth=pb.depth.cpu().numpy(), ranges=pb.tile_ranges.cpu().numpy().view(np.uint32),
+                 ids=pb.ids[:Pb].cpu().numpy().view(np.uint32), keys=pb.keys[:Pb].cpu().numpy().view(np.uint64))
+        keys, ids, ranges = orc.tile_lists(cam, g["mean2d"], g["radius"], g["depth"])
+        diff = compare_tile_lists(g, keys, ids, ranges, cam.tiles_x, cam.tiles_y)
+        assert diff is None, diff
