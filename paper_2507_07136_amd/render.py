@@ -191,13 +191,15 @@ class Pipeline:
     def feature_map(self, means, scales, quats, opacity, topk_idx, topk_w, dictionary, compute=LS2_BF16,
                     out_dtype=torch.bfloat16, sync: bool = True, fused: bool = False):
         """One feature-map frame: project, bin and sort, splat, decode (with
-        fused=True: bf16 compute and output, splat and decode in one pass)."""
-        self.project(means, scales, quats)
-        self.bin_sort(sync=sync)
+        fused=True: bf16 compute and output, projection and binning in one
+        call, splat and decode in one pass)."""
         if fused:
             if compute != LS2_BF16 or out_dtype != torch.bfloat16:
                 raise ValueError("the fused frame computes and writes bfloat16")
+            self.project_bin_sort(means, scales, quats, sync=sync)
             return self.splat_decode(opacity, topk_idx, topk_w, dictionary)
+        self.project(means, scales, quats)
+        self.bin_sort(sync=sync)
         self.splat(opacity, topk_idx, topk_w)
         return self.decode(dictionary, compute, out_dtype)
 
@@ -362,8 +364,7 @@ class Trainer(Pipeline):
             return loss, self.backward(scene)
         if "logits" in scene:
             scene["topk_idx"], scene["topk_w"] = self.codes(scene["logits"])
-        self.project(scene["means"], scene["scales"], scene["quats"])
-        self.bin_sort(sync=sync)
+        self.project_bin_sort(scene["means"], scene["scales"], scene["quats"], sync=sync)
         self.splat(scene["opacity"], scene["topk_idx"], scene["topk_w"])
         m = self.levels * self.H * self.W
         g = self.grad
