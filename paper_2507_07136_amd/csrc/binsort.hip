@@ -619,7 +619,8 @@ __device__ __forceinline__ void sort_lds_n(SortSmem& sm, const unsigned long lon
         flip_bitonic<true>(sm.xbuf + (e & 0x7fffu), (int)(e >> 15), pay ? pay + (e & 0x7fffu) : nullptr);
     }
     lds_barrier();
-    for (int p = threadIdx.x; p < cnt; p += blockDim.x) dst[p] = sm.xbuf[p];
+    if (dst)  // the sorted keys back to global memory (chunks of a split bucket)
+        for (int p = threadIdx.x; p < cnt; p += blockDim.x) dst[p] = sm.xbuf[p];
 }
 
 // Buckets of up to 9 x 1024 keys (all but the largest) hold 9 keys per
@@ -1042,7 +1043,9 @@ __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
     const bool lds_fill = in_lds && a.S == 4 && cnt <= kPayCap;
     for (int u = 0; u < nunits; ++u) {
         const int b0 = in_lds ? 0 : (int)sm.chunk_start[u], b1 = in_lds ? cnt : (int)sm.chunk_start[u + 1];
-        if (b1 > b0) sort_lds(sm, src + b0, g + b0, b1 - b0, lds_fill ? a.cov + a.sb_start[sb] : nullptr);
+        // a bucket sorted whole stays in LDS for the fill: no copy back
+        if (b1 > b0)
+            sort_lds(sm, src + b0, in_lds ? nullptr : g + b0, b1 - b0, lds_fill ? a.cov + a.sb_start[sb] : nullptr);
     }
     if (lds_fill) {
         fill_tiles_lds(a, sm, sb, cnt);  // starts after sort_lds's closing LDS barrier
