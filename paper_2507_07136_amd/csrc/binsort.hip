@@ -478,13 +478,16 @@ __device__ __forceinline__ void sort_lds_n(SortSmem& sm, const unsigned long lon
     unsigned* const bins = &sm.ctr[0][0];  // NW * 256 = 4096 counters
 
     unsigned long long key[ITEMS];
+    unsigned short pv[ITEMS];  // the payload of each key (pay_src given), loaded with it
     unsigned hlo = 0xffffffffu, hhi = 0u, ilo = 0xffffffffu, ihi = 0u;
 #pragma unroll
     for (int c = 0; c < ITEMS; ++c) {
         key[c] = 0ull;
+        pv[c] = 0;
         const int p = (c0 + c) * 64 + lane;
         if (c < mine && p < cnt) {
             key[c] = src[p];
+            if (pay_src) pv[c] = pay_src[p];
             const unsigned h = (unsigned)(key[c] >> 32), id = (unsigned)key[c];
             hlo = min(hlo, h);
             hhi = max(hhi, h);
@@ -494,18 +497,8 @@ __device__ __forceinline__ void sort_lds_n(SortSmem& sm, const unsigned long lon
     }
     for (int i = threadIdx.x; i < nb; i += blockDim.x) bins[i] = 0u;
     if (threadIdx.x == 0) sm.nbig = 0u;
-    // payload (cnt <= kPayCap): staged in bucket order, then moved with the keys
+    // payload (cnt <= kPayCap): moved with the keys, from registers
     unsigned short* const pay = pay_src ? pay_sorted(sm, cnt) : nullptr;
-    unsigned short* const pay_in = pay ? pay + cnt : nullptr;
-    if (pay)
-        for (int p0 = threadIdx.x; p0 < cnt; p0 += 4 * (int)blockDim.x) {  // four loads in flight
-            unsigned short v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q] = pay_src[min(p0 + q * (int)blockDim.x, cnt - 1)];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (p0 + q * (int)blockDim.x < cnt) pay_in[p0 + q * (int)blockDim.x] = v[q];
-        }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         hlo = min(hlo, (unsigned)__shfl_xor((int)hlo, off));
@@ -578,7 +571,7 @@ __device__ __forceinline__ void sort_lds_n(SortSmem& sm, const unsigned long lon
         if (c < mine && (c0 + c) * 64 + lane < cnt) {
             const unsigned slot = atomicAdd(&bins[bin_of(key[c])], 1u);
             sm.xbuf[slot] = key[c];
-            if (pay) pay[slot] = pay_in[(c0 + c) * 64 + lane];
+            if (pay) pay[slot] = pv[c];
         }
     __syncthreads();
     // 4. a key of a short bin goes to its bin's start plus the number of the
@@ -609,7 +602,7 @@ __device__ __forceinline__ void sort_lds_n(SortSmem& sm, const unsigned long lon
     for (int c = 0; c < ITEMS; ++c)
         if (fp[c] != 0xffffffffu) {
             sm.xbuf[fp[c]] = key[c];
-            if (pay) pay[fp[c]] = pay_in[(c0 + c) * 64 + lane];
+            if (pay) pay[fp[c]] = pv[c];
         }
     // 5. long bins, one at a time, by the whole workgroup (each network ends
     // with a workgroup barrier; they touch disjoint ranges, none a short bin)
@@ -790,7 +783,7 @@ __device__ __forceinline__ void emit_slice(const unsigned long long* s, const us
     }
 }
 
-__device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, int sb,
+__device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, int sb, unsigned pstart,
                                               const unsigned long long* s, int cnt) {
     const int S = a.S, nsub = S >> 2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -861,7 +854,7 @@ __device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, in
             const unsigned y = __shfl_up(incl, off);
             if (lane >= off) incl += y;
         }
-        unsigned run = a.sb_pstart[sb] + incl - loc;
+        unsigned run = pstart + incl - loc;
         for (int q = 0; q < per; ++q) {
             const int t = lane * per + q;
             if (t >= nt) break;
@@ -910,7 +903,7 @@ __device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, in
 // ballot, the lane's rank among the covering lanes, one store), so every
 // tile list is the ordered subsequence of the sorted bucket.  Masks and keys
 // come from LDS: nothing is gathered.
-__device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, int sb, int cnt) {
+__device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, int sb, unsigned pstart, int cnt) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tx0 = (sb % a.sbx) * 4, ty0 = (sb / a.sbx) * 4;
     const unsigned short* const cov = pay_sorted(sm, cnt);
@@ -944,7 +937,7 @@ __device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, i
             const unsigned y = __shfl_up(incl, off, 16);
             if (lane >= off) incl += y;
         }
-        const unsigned start = a.sb_pstart[sb] + incl - tot;
+        const unsigned start = pstart + incl - tot;
         sm.tcnt[lane] = start;
         sm.big[lane] = start + tot;
         const int x = tx0 + (lane & 3), y = ty0 + (lane >> 2);
@@ -1020,16 +1013,19 @@ __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
     __shared__ SortSmem sm;
     if ((int)blockIdx.x >= a.nsb) return;
     const int sb = (int)a.sb_order[blockIdx.x];
-    if (a.meta->overflow) {
+    // every per-superblock value at once (one round trip)
+    const bool over = a.meta->overflow != 0;
+    const int cnt = (int)a.sb_count[sb];
+    const unsigned gstart = a.sb_start[sb], pstart = a.sb_pstart[sb];
+    if (over) {
         empty_sb_ranges(a, sb, 0u);
         return;
     }
-    const int cnt = (int)a.sb_count[sb];
     if (cnt == 0) {
-        empty_sb_ranges(a, sb, a.sb_pstart[sb]);
+        empty_sb_ranges(a, sb, pstart);
         return;
     }
-    unsigned long long* g = a.pool + a.sb_start[sb];
+    unsigned long long* g = a.pool + gstart;
     // units sorted in LDS: the whole bucket, or the chunks of a split bucket
     const unsigned long long* src = g;
     int nunits = 1;
@@ -1037,7 +1033,7 @@ __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
     if (cnt > kSortCap) {
         in_lds = false;
         nunits = split_bucket(a, sm, g, cnt);
-        src = a.pool + a.meta->sb_total + a.sb_start[sb];
+        src = a.pool + a.meta->sb_total + gstart;
     }
     // S = 4 buckets of at most kPayCap keys sort their coverage masks along
     const bool lds_fill = in_lds && a.S == 4 && cnt <= kPayCap;
@@ -1045,14 +1041,14 @@ __global__ __launch_bounds__(kSortWaves * 64) void k_sb_sort(BinArgs a) {
         const int b0 = in_lds ? 0 : (int)sm.chunk_start[u], b1 = in_lds ? cnt : (int)sm.chunk_start[u + 1];
         // a bucket sorted whole stays in LDS for the fill: no copy back
         if (b1 > b0)
-            sort_lds(sm, src + b0, in_lds ? nullptr : g + b0, b1 - b0, lds_fill ? a.cov + a.sb_start[sb] : nullptr);
+            sort_lds(sm, src + b0, in_lds ? nullptr : g + b0, b1 - b0, lds_fill ? a.cov + gstart : nullptr);
     }
     if (lds_fill) {
-        fill_tiles_lds(a, sm, sb, cnt);  // starts after sort_lds's closing LDS barrier
+        fill_tiles_lds(a, sm, sb, pstart, cnt);  // starts after sort_lds's closing LDS barrier
         return;
     }
     if (!in_lds) __threadfence_block();  // the global writes, before the fill reads g
-    fill_sb_lists(a, sm, sb, in_lds ? sm.xbuf : g, cnt);  // starts with a workgroup barrier
+    fill_sb_lists(a, sm, sb, pstart, in_lds ? sm.xbuf : g, cnt);  // starts with a workgroup barrier
 }
 
 }  // namespace ls2
