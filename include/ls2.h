@@ -436,10 +436,11 @@ int ls2_decode_feature_loss(int64_t m, int32_t L, int32_t D, const float* coef, 
  * of ls2_feature_loss against the target (Section 4.1), dL/dF, and both
  * gradients of the decode, d_coef = dL/dF S^T and d_dict = coef^T dL/dF,
  * with dL/dF kept on the chip (never written to memory).  Each product takes
- * the same operands in the same order as the two-call chain, so the outputs
- * equal that chain's bit for bit whenever the two use the same number of
- * workgroups (one per compute unit, at most 512 and at most one per 32
- * pixels, in both).
+ * the same operands in the same order as the two-call chain, so d_coef and
+ * d_dict equal that chain's bit for bit; the loss, whose partial sums follow
+ * the workgroups, does too when ls2_decode_feature_loss launches the same
+ * number of them (one per compute unit at D = 512) and is otherwise a few
+ * float32 roundings of its compensated total away.
  *
  * In:  coef [m,L], dict [L,D], target [m,D], all f32, 16-byte aligned.
  * Out: loss (device, one double); d_coef [m,L]; d_dict [L,D] (both
