@@ -514,7 +514,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed frames before each timed run (the clocks settle within about 100 frames)")
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-frac", type=float, default=1.0,
                     help="pixel fraction the CPU oracle composites and decodes (default: the whole frame, a few "
