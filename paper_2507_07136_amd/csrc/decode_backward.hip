@@ -514,9 +514,10 @@ static int num_cus_bw() {
 // D a multiple of 128 up to 512): the float32 training objective of Section
 // 4.1 on F = W S (Eq. 7), with dL/dF consumed on the chip instead of being
 // written and read back.  A workgroup of D / 64 waves walks 32-pixel blocks;
-// wave w owns features [64 w, 64 w + 64), keeps its slice of S (forward
-// operand layout) in VGPRs and its dS = W^T dL/dF partial in the matrix
-// accumulators across blocks.  Per block:
+// wave w owns features [64 w, 64 w + 64), keeps its slice of S in the
+// forward operand layout (the first feature tile in VGPRs, the second in LDS:
+// the registers would not hold both) and its dS = W^T dL/dF partial in the
+// matrix accumulators across blocks.  Per block:
 //   1. F = W S over its slice (W from a double-buffered LDS tile loaded a
 //      block ahead) while the block's target rows arrive;
 //   2. the per-pixel sums of the loss (|F - Y|, F.Y, F.F, Y.Y over the slice),
