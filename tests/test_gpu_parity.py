@@ -810,6 +810,13 @@ def test_project_bin_sort_fused(orc, case):
         assert torch.equal(pa.ids[:Pa], pb.ids[:Pb]) and torch.equal(pa.keys[:Pa], pb.keys[:Pb])
     else:
         assert int(pb.tile_ranges.abs().sum().item()) == 0
+    if case == "ragged":  # tiles_touched is optional: the same lists without it
+        ids_b = pb.ids[:Pb].clone()
+        pb.ids.fill_(-7)
+        Pc = ls2.ls2_project_bin_sort(pb.cam, t["means"], t["scales"], t["quats"], pb.mean2d, pb.conic, pb.depth,
+                                      pb.radius, pb.max_pairs, pb.keys, pb.ids, pb.tile_ranges, pb.workspace,
+                                      tiles_touched=None, sync=True)
+        assert Pc == Pb and torch.equal(pb.ids[:Pc], ids_b)
     if case in ("c1", "ragged", "culled", "large_image"):
         g = dict(P=Pb, mean2d=pb.mean2d.cpu().numpy(), radius=pb.radius.cpu().numpy(),
                  depth=pb.depth.cpu().numpy(), ranges=pb.tile_ranges.cpu().numpy().view(np.uint32),
