@@ -594,3 +594,27 @@ def test_trainer_step_one_pass(levels, D):
     for k in ("means", "scales", "quats", "opacity", "topk_w"):
         a, b = ga[k].double(), getattr(gb, k).double()
         assert torch.linalg.norm(a - b).item() <= 1e-5 * torch.linalg.norm(a).item() + 1e-30, k
+
+
+def test_trainer_step_one_pass_logits():
+    """The one-pass Trainer.step with codes given as logits: the codes are
+    formed first and dL/dlogits closes the chain, as with forward_loss +
+    backward (float atomics of the splat backward: float32 rounding)."""
+    import paper_2507_07136_amd as ls2
+    scene, cam = small_scene(41, 2000, 160, 104, D=512)
+    rng = np.random.default_rng(9)
+    tY = torch.from_numpy((rng.standard_normal((1, cam.height, cam.width, 512)) * 0.1).astype(np.float32)).cuda()
+    t = ls2.to_device(scene)
+    t["logits"] = torch.from_numpy((rng.standard_normal((scene.n, 1, scene.L)) * 2.0).astype(np.float32)).cuda()
+    tr = ls2.Trainer(cam, scene.n, D=512)
+    loss_a = tr.forward_loss(t, tY).clone()
+    tr.backward(t)
+    idx_a, dl_a = t["topk_idx"].clone(), tr.d_logits.clone()
+    gd_a = tr.grad.dictionary.clone()
+    loss_b, _ = tr.step(t, tY)
+    torch.cuda.synchronize()
+    assert torch.equal(t["topk_idx"], idx_a)
+    assert loss_b.item() == loss_a.item()
+    assert torch.equal(tr.grad.dictionary, gd_a)
+    a, b = dl_a.double(), tr.d_logits.double()
+    assert torch.linalg.norm(a - b).item() <= 1e-5 * torch.linalg.norm(a).item() + 1e-30
