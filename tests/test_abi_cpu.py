@@ -184,6 +184,11 @@ def test_backward_argument_validation_without_device(L):
     assert L.ls2_decode_loss_backward_workspace(1000, 64, 512, ctypes.byref(b)) == 0 and b.value >= 64 * 512 * 4
     assert L.ls2_decode_loss_backward_workspace(1000, 128, 512, ctypes.byref(b)) == -3
     assert L.ls2_decode_loss_backward_workspace(0, 64, 512, ctypes.byref(b)) == -1
+    # the dS partials: one [L, D] slice per workgroup, at most one per 32 pixels
+    # and at most 512, plus 512 pairs of compensated loss partials (8 bytes each)
+    for m_, parts in ((1, 1), (32, 1), (33, 2), (32 * 300, 300), (32 * 512 + 1, 512), (10 ** 8, 512)):
+        assert L.ls2_decode_loss_backward_workspace(m_, 64, 512, ctypes.byref(b)) == 0
+        assert b.value == parts * 64 * 512 * 4 + 512 * 2 * 8, (m_, b.value)
     la = [V(16)] * 6
     assert L.ls2_decode_loss_backward(10, 128, 512, *la, V(16), 1 << 24, None) == -3
     assert L.ls2_decode_loss_backward(10, 64, 1024, *la, V(16), 1 << 24, None) == -3
