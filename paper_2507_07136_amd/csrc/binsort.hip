@@ -310,9 +310,18 @@ __device__ void sort_plan(const BinArgs& a, const unsigned* start, long long tot
         a.sb_order[atomicAdd(&cls[size_class(a.sb_count[s])], 1u)] = (unsigned)s;
 }
 
+// Entries a workgroup of the emission pass stages in LDS (about 9500 at
+// 1440x1080: 2048 Gaussians of 4.7 superblocks each); a workgroup with more
+// writes them in place instead.
+constexpr int kEmitCap = 10240;
+
 __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
     __shared__ unsigned hist[kMaxSB];
     __shared__ unsigned start[kMaxSB];
+    // the workgroup's entries grouped by superblock, then copied out in runs
+    __shared__ unsigned long long skey[kEmitCap];
+    __shared__ unsigned short smask[kEmitCap];
+    __shared__ unsigned short ssb[kEmitCap];
     const int base = blockIdx.x * kBinThreads * kBinPerThread;
     const int sh = __builtin_ctz((unsigned)a.S);
     // every global read at once: the tile rectangles stored by the count pass
@@ -340,9 +349,16 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
             for (int sy = r[q].y >> sh; sy <= (r[q].w >> sh); ++sy)
                 for (int sx = r[q].x >> sh; sx <= (r[q].z >> sh); ++sx) atomicAdd(&hist[sy * a.sbx + sx], 1u);
     __syncthreads();
-    // reserve this workgroup's range in every touched bucket; hist becomes the cursor
+    // reserve this workgroup's range in every touched bucket (start becomes
+    // the range's first place), then the local places: an exclusive scan of
+    // the counts (hist becomes the local cursor); start - local start maps a
+    // local place to its place in the pool
     for (int s = threadIdx.x; s < a.nsb; s += kBinThreads)
-        if (hist[s]) hist[s] = start[s] + atomicAdd(&a.sb_cursor[s], hist[s]);
+        if (hist[s]) start[s] += atomicAdd(&a.sb_cursor[s], hist[s]);
+    __syncthreads();
+    const long long mine = block_scan(hist, hist, 1, nullptr, a.nsb);  // in place: each thread rewrites what it read
+    const bool staged = mine <= kEmitCap;  // the same decision in every thread
+    for (int s = threadIdx.x; s < a.nsb; s += kBinThreads) start[s] -= hist[s];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
@@ -352,16 +368,35 @@ __global__ __launch_bounds__(kBinThreads) void k_sb_emit(BinArgs a) {
         const int x0 = r[q].x, y0 = r[q].y, x1 = r[q].z, y1 = r[q].w;
         for (int sy = y0 >> sh; sy <= (y1 >> sh); ++sy)
             for (int sx = x0 >> sh; sx <= (x1 >> sh); ++sx) {
-                const unsigned pos = atomicAdd(&hist[sy * a.sbx + sx], 1u);
-                a.pool[pos] = key;
+                const int s = sy * a.sbx + sx;
+                const unsigned lp = atomicAdd(&hist[s], 1u);
+                unsigned short mask = 0;
                 if (a.S == 4) {  // the tiles of the superblock the rectangle covers
                     const int cx0 = max(x0 - 4 * sx, 0), cx1 = min(x1 - 4 * sx, 3);
                     const int cy0 = max(y0 - 4 * sy, 0), cy1 = min(y1 - 4 * sy, 3);
                     const unsigned cols = ((2u << cx1) - 1u) & ~((1u << cx0) - 1u);
                     const unsigned rows = 0x1111u & ((1u << (4 * cy1 + 4)) - 1u) & ~((1u << (4 * cy0)) - 1u);
-                    a.cov[pos] = (unsigned short)(cols * rows);
+                    mask = (unsigned short)(cols * rows);
+                }
+                if (staged) {
+                    skey[lp] = key;
+                    smask[lp] = mask;
+                    ssb[lp] = (unsigned short)s;
+                } else {
+                    const unsigned pos = start[s] + lp;
+                    a.pool[pos] = key;
+                    if (a.S == 4) a.cov[pos] = mask;
                 }
             }
+    }
+    if (!staged) return;
+    __syncthreads();
+    // copy-out: consecutive local places of one superblock are consecutive
+    // places in the pool, so neighbouring lanes write neighbouring words
+    for (int j = threadIdx.x; j < (int)mine; j += kBinThreads) {
+        const unsigned pos = start[ssb[j]] + (unsigned)j;
+        a.pool[pos] = skey[j];
+        if (a.S == 4) a.cov[pos] = smask[j];
     }
 }
 
