@@ -824,3 +824,16 @@ def test_project_bin_sort_fused(orc, case):
         keys, ids, ranges = orc.tile_lists(cam, g["mean2d"], g["radius"], g["depth"])
         diff = compare_tile_lists(g, keys, ids, ranges, cam.tiles_x, cam.tiles_y)
         assert diff is None, diff
+
+
+@pytest.mark.parametrize("mix", [False, True])
+def test_emission_staging_overflow(orc, mix):
+    """Large Gaussians (about 6 superblocks each): the emission workgroups
+    hold more entries than they stage in LDS (12.7k against 10240) and write
+    them in place; with mix, only the first workgroup's Gaussians are large,
+    so one workgroup writes in place and the other stages.  The lists stay
+    bit-exact against the oracle."""
+    scene, cam = small_scene(51, 4096, 640, 480)
+    scene.scales[: 2048 if mix else 4096] *= 3.0
+    g = run_forward(cam, scene, keep_keys=True)
+    _check_lists(orc, cam, g)
