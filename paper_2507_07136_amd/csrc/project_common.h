@@ -12,10 +12,24 @@ struct ProjOut {
     int r, cnt;  // radius (0: culled) and the number of tiles its rectangle covers
 };
 
-__device__ __forceinline__ ProjOut project_one(const CamK& cam, const float* __restrict__ means,
-                                               const float* __restrict__ scales, const float* __restrict__ quats,
-                                               int i) {
-    const float mx = means[3 * i], my = means[3 * i + 1], mz = means[3 * i + 2];
+// The inputs of one Gaussian, loaded apart from the arithmetic so that a
+// thread can issue the loads of several Gaussians at once.
+struct ProjIn {
+    float mx, my, mz, s0, s1, s2, qw, qx, qy, qz;
+};
+
+__device__ __forceinline__ ProjIn load_proj(const float* __restrict__ means, const float* __restrict__ scales,
+                                            const float* __restrict__ quats, int i) {
+    return ProjIn{means[3 * i],     means[3 * i + 1],  means[3 * i + 2],  scales[3 * i],     scales[3 * i + 1],
+                  scales[3 * i + 2], quats[4 * i],      quats[4 * i + 1],  quats[4 * i + 2],  quats[4 * i + 3]};
+}
+
+__device__ __forceinline__ ProjOut project_in(const CamK& cam, const ProjIn& g) {
+    // multiply-adds are fused only inside one expression, never by the code
+    // generator across statements: the result then does not depend on the
+    // kernel this is inlined into, so every caller produces the same bits
+#pragma clang fp contract(on)
+    const float mx = g.mx, my = g.my, mz = g.mz;
     // camera-space mean p = R mu + t
     const float x = cam.R[0] * mx + cam.R[1] * my + cam.R[2] * mz + cam.t[0];
     const float y = cam.R[3] * mx + cam.R[4] * my + cam.R[5] * mz + cam.t[1];
@@ -27,13 +41,13 @@ __device__ __forceinline__ ProjOut project_one(const CamK& cam, const float* __r
     if (ok) {
         // Eq. 2: Sigma = R(q) S S^T R(q)^T; in camera space
         // Sigma_c = (Rc R(q) S)(Rc R(q) S)^T.
-        float qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+        float qw = g.qw, qx = g.qx, qy = g.qy, qz = g.qz;
         const float qn = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
         qw *= qn; qx *= qn; qy *= qn; qz *= qn;
         const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
                              2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
                              2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
-        const float s[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+        const float s[3] = {g.s0, g.s1, g.s2};
         float T[9];  // Rc * Rq * diag(s)
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -83,6 +97,12 @@ __device__ __forceinline__ ProjOut project_one(const CamK& cam, const float* __r
         cnt = 0;
     }
     return ProjOut{u, v, A, B, C, zout, r, cnt};
+}
+
+__device__ __forceinline__ ProjOut project_one(const CamK& cam, const float* __restrict__ means,
+                                               const float* __restrict__ scales, const float* __restrict__ quats,
+                                               int i) {
+    return project_in(cam, load_proj(means, scales, quats, i));
 }
 
 // The projection's outputs for Gaussian i (tiles_touched optional).
