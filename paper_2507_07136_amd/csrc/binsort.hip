@@ -938,7 +938,7 @@ __device__ __forceinline__ void fill_sb_lists(const BinArgs& a, SortSmem& sm, in
 // ballot, the lane's rank among the covering lanes, one store), so every
 // tile list is the ordered subsequence of the sorted bucket.  Masks and keys
 // come from LDS: nothing is gathered.
-__device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, int sb, unsigned pstart, int cnt) {
+__device__ __forceinline__ void fill_tiles_slices(const BinArgs& a, SortSmem& sm, int sb, unsigned pstart, int cnt) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tx0 = (sb % a.sbx) * 4, ty0 = (sb / a.sbx) * 4;
     const unsigned short* const cov = pay_sorted(sm, cnt);
@@ -1023,6 +1023,84 @@ __device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, i
             if (lane == t) cur = out;
         }
     }
+}
+
+// The same lists, for small buckets.  Wave t builds the list of tile t
+// alone: it counts the bucket's entries whose mask has bit t (one ballot per
+// 64 entries), the 16 counts give each tile its start, and a second walk
+// over the bucket emits the covering entries in order (one ballot, the
+// lane's rank among the covering lanes, one store per 64 entries).  The
+// tile, its cursor and its list end stay wave-uniform, and there is one
+// workgroup barrier.
+static_assert(kSortWaves == 16, "one wave per tile of a 4 x 4-tile superblock");
+__device__ __forceinline__ void fill_tiles_per_wave(const BinArgs& a, SortSmem& sm, int sb, unsigned pstart, int cnt) {
+    const int lane = threadIdx.x & 63;
+    const int t = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int x = (sb % a.sbx) * 4 + (t & 3), y = (sb / a.sbx) * 4 + (t >> 2);
+    const unsigned bit = 1u << t;
+    const unsigned short* const cov = pay_sorted(sm, cnt);
+    // 1. entries of tile t
+    unsigned c = 0u;
+    for (int e = 0; e < cnt; e += 64 * kFillGroups) {
+        unsigned cv[kFillGroups];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) cv[q] = e + 64 * q + lane < cnt ? cov[e + 64 * q + lane] : 0u;
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q)
+            c += (unsigned)__builtin_popcountll(__builtin_amdgcn_ballot_w64((cv[q] & bit) != 0u));
+    }
+    if (lane == 0) sm.tcnt[t] = c;
+    __syncthreads();
+    // 2. the tile's list: after the lists of the superblock's tiles before it (row-major)
+    unsigned start = pstart;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) start += v < t ? sm.tcnt[v] : 0u;
+    const unsigned tend = min(start + c, (unsigned)a.max_pairs);  // P <= max_pairs here; the clamp only guards
+    if (lane == 0 && x < a.cam.tx && y < a.cam.ty) {
+        a.ranges[2 * (y * a.cam.tx + x)] = start;
+        a.ranges[2 * (y * a.cam.tx + x) + 1] = start + c;
+    }
+    // 3. emit the covering entries in bucket order
+    const unsigned long long tk = (unsigned long long)(y * a.cam.tx + x) << 32;
+    unsigned* __restrict__ const ids = a.ids;
+    unsigned long long* __restrict__ const keys = a.keys;
+    const bool with_keys = keys != nullptr;
+    unsigned out = start;
+    for (int e = 0; e < cnt; e += 64 * kFillGroups) {
+        unsigned cv[kFillGroups];
+        unsigned long long kk[kFillGroups];
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) {
+            const int ee = e + 64 * q + lane;
+            cv[q] = ee < cnt ? cov[ee] : 0u;
+            kk[q] = sm.xbuf[min(ee, cnt - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < kFillGroups; ++q) {
+            const bool hit = (cv[q] & bit) != 0u;
+            const unsigned long long mask = __builtin_amdgcn_ballot_w64(hit);
+            const unsigned pos = out + __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            if (hit && pos < tend) {  // the count above uses the same test: pos < tend always
+                ids[pos] = (unsigned)(kk[q] & 0xffffffffull);
+                if (with_keys) keys[pos] = tk | (kk[q] >> 32);
+            }
+            out += (unsigned)__builtin_popcountll(mask);
+        }
+    }
+}
+
+// Tile lists from a bucket sorted in LDS with its masks.  Every wave of the
+// per-tile form reads the whole bucket, so its time grows with 16 cnt; the
+// slice form reads each entry once but pays two barriers and a 16-tile
+// bookkeeping per 64 entries, which dominates small buckets.  The small
+// buckets are the ones the sort kernel's last workgroups take.
+constexpr int kPerWaveFillMax = 2048;
+__device__ __forceinline__ void fill_tiles_lds(const BinArgs& a, SortSmem& sm, int sb, unsigned pstart, int cnt) {
+    if (cnt <= kPerWaveFillMax)
+        fill_tiles_per_wave(a, sm, sb, pstart, cnt);
+    else
+        fill_tiles_slices(a, sm, sb, pstart, cnt);
 }
 
 // Empty tile ranges for every tile of superblock sb: [first, first).
