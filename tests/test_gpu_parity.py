@@ -837,3 +837,19 @@ def test_emission_staging_overflow(orc, mix):
     scene.scales[: 2048 if mix else 4096] *= 3.0
     g = run_forward(cam, scene, keep_keys=True)
     _check_lists(orc, cam, g)
+
+
+@pytest.mark.parametrize("n", [1, 2048, 2049, 10240, 10241, 16384, 16385])
+def test_single_superblock_bucket_sizes(orc, n):
+    """A 64 x 64 image is one superblock of 4 x 4 tiles, and every Gaussian of
+    the scene projects inside it (means within [-1, 1]^3 seen from z = -3
+    with a 60 degree field of view), so the superblock's bucket holds exactly
+    n keys.  The sizes sit on both sides of each change of method in the
+    sort kernel: the per-tile list fill (at most 2048 keys), the slice fill
+    with the coverage masks sorted along (at most 10240), the fill from the
+    stored rectangles, and the split of buckets beyond 16384 keys.  Lists,
+    keys and ranges bit-exact against the oracle."""
+    scene, cam = small_scene(57, n, 64, 64)
+    g = run_forward(cam, scene, keep_keys=True)
+    assert int((g["radius"] > 0).sum()) == n
+    _check_lists(orc, cam, g)
