@@ -1062,9 +1062,13 @@ __device__ __forceinline__ void fill_tiles_per_wave(const BinArgs& a, SortSmem& 
     }
     // 3. emit the covering entries in bucket order
     const unsigned long long tk = (unsigned long long)(y * a.cam.tx + x) << 32;
-    unsigned* __restrict__ const ids = a.ids;
-    unsigned long long* __restrict__ const keys = a.keys;
-    const bool with_keys = keys != nullptr;
+    const bool with_keys = a.keys != nullptr;
+    // the list bases in vector registers: the scalar file is full here, and
+    // scalar copies would be restored from spill lanes before every store
+    __attribute__((address_space(1))) unsigned* ids = (__attribute__((address_space(1))) unsigned*)a.ids;
+    __attribute__((address_space(1))) unsigned long long* keys =
+        (__attribute__((address_space(1))) unsigned long long*)a.keys;
+    asm volatile("" : "+v"(ids), "+v"(keys));
     unsigned out = start;
     for (int e = 0; e < cnt; e += 64 * kFillGroups) {
         unsigned cv[kFillGroups];
